@@ -1,0 +1,169 @@
+/*
+ * rpp.h -- C ABI of the MI355X Vietoris-Rips persistence library.
+ *
+ * The library computes Vietoris-Rips persistence barcodes of a finite metric
+ * space given by its distance matrix, as described in "GPU-Accelerated
+ * Computation of Vietoris-Rips Persistence Barcodes" (arXiv 2003.07989).
+ * The data-parallel stages run as HIP kernels on one AMD Instinct MI355X
+ * (gfx950): distance staging and the enclosing radius, H0 by edge sort and
+ * union-find, enumeration of p-simplices in combinatorial-number-system
+ * order with the threshold and clearing filter, the apparent-pair test, the
+ * partition of columns and the key sorts.  The residual reduction of the
+ * non-apparent columns over Z/2 runs on host threads.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Distance matrix.  The condensed LOWER triangle, n*(n-1)/2 IEEE-754 binary32
+ * values in edge combinatorial-index order: entry i*(i-1)/2 + j holds d(i,j)
+ * for i > j (paper, Background: D[i,i] = 0 is implied; the experiments read
+ * a lower-triangular matrix).  Entries must be finite and >= 0; -0.0 is read
+ * as 0.  The triangle inequality is not required.
+ *
+ * Threshold.  Inclusive: a simplex is in the complex iff its diameter (its
+ * largest pairwise distance) is <= threshold (paper, definition of Rips_t).
+ * +INFINITY means no threshold; the library then truncates at the enclosing
+ * radius R = min_x max_y d(x,y), which leaves every nonzero interval
+ * unchanged (paper, proposition on the enclosing radius), unless
+ * RPP_NO_ENCLOSING_RADIUS is given.  NaN or a negative threshold is an error.
+ *
+ * Result.  Dimensions 0..maxdim.  Each bar is [birth, death) with birth and
+ * death equal to entries of the distance matrix (or 0 for H0 births);
+ * zero-length intervals (birth == death) are omitted; essential classes have
+ * death = +INFINITY.  Bars of a dimension are sorted by birth, then death,
+ * +INFINITY last; zeros are written as +0.0.  Results are allocated by the
+ * library and released with rpp_result_free.
+ *
+ * Simplices are identified by their combinatorial index (paper, section on
+ * the combinatorial number system): the simplex with vertices
+ * v_p > ... > v_0 has cidx = C(v_p, p+1) + ... + C(v_0, 1).
+ *
+ * Errors.  Every function returning int returns RPP_OK (0) or a negative
+ * RPP_E_* code; on error *out is left NULL and rpp_last_error() describes
+ * the failure (thread-local text).
+ */
+#ifndef RPP_H
+#define RPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RPP_MAX_DIM 4
+
+enum {
+    RPP_OK = 0,
+    RPP_E_INVAL = -1,  /* null pointer, n < 1, maxdim outside 0..RPP_MAX_DIM, bad threshold */
+    RPP_E_DATA = -2,   /* NaN, infinite or negative distance entry */
+    RPP_E_RANGE = -3,  /* C(n, maxdim+2) does not fit the index type, or n too large */
+    RPP_E_NOMEM = -4,  /* host or device allocation failed, or workspace too small */
+    RPP_E_DEVICE = -5, /* HIP runtime error */
+};
+
+/* flags for rpp_barcodes_device / rpp_barcodes_ex */
+#define RPP_NO_ENCLOSING_RADIUS 0x1u /* use the threshold as given, even if +inf */
+#define RPP_WANT_PAIRS 0x2u          /* also return every persistence pair */
+
+/* Per-dimension counters (paper, tables of apparent pairs and of the
+ * clearing / threshold accounting).  For p >= 1:
+ *   n_candidates = n_thresholded + n_cleared + n_kept          (dense path)
+ *   n_kept       = n_apparent + n_nonapparent
+ *   n_simplices  = p-simplices with diameter <= threshold
+ * For p = 0, n_kept = n and n_apparent = n_nonapparent = 0. */
+typedef struct {
+    int64_t n_candidates;   /* simplices examined by the filter */
+    int64_t n_simplices;    /* p-simplices with diameter <= threshold */
+    int64_t n_thresholded;  /* removed by the threshold */
+    int64_t n_cleared;      /* removed by the clearing lemma */
+    int64_t n_kept;         /* columns of the dimension-p coboundary matrix */
+    int64_t n_apparent;     /* apparent pairs (sigma, tau) found on the GPU */
+    int64_t n_nonapparent;  /* columns handed to the host reduction */
+    int64_t n_host_pairs;   /* pairs found by the host reduction */
+    int64_t n_essential;    /* essential classes */
+    int64_t n_bars;         /* reported intervals, essential included */
+    int64_t n_column_adds;  /* column additions done by the host reduction */
+    float ms_gpu;           /* device time of the dimension's GPU stages */
+    float ms_host;          /* host reduction wall time */
+} rpp_dim_stats;
+
+typedef struct {
+    int32_t dim;
+    int64_t count;
+    float *birth;
+    float *death;
+} rpp_bars;
+
+/* Only filled with RPP_WANT_PAIRS: every persistence pair (sigma, tau) of
+ * dimension dim (zero-length pairs included), sigma a dim-simplex and tau a
+ * (dim+1)-simplex, as combinatorial indices.  For dim 0 sigma is the vertex
+ * index and tau the edge.  Order: unspecified. */
+typedef struct {
+    int32_t dim;
+    int64_t count;
+    uint64_t *sigma;
+    uint64_t *tau;
+} rpp_pairs;
+
+typedef struct {
+    int32_t maxdim;
+    int32_t n;
+    float threshold_used;   /* threshold after enclosing-radius truncation */
+    float enclosing_radius;
+    rpp_bars *dims;         /* maxdim + 1 entries */
+    rpp_dim_stats *stats;   /* maxdim + 1 entries */
+    rpp_pairs *pairs;       /* maxdim + 1 entries, or NULL */
+} rpp_result;
+
+/* Barcodes of a host-resident distance matrix.
+ *   dist      condensed lower triangle (host memory, read only, n*(n-1)/2
+ *             floats; may be NULL when n == 1)
+ *   n         number of points, >= 1
+ *   maxdim    highest homology dimension, 0..RPP_MAX_DIM
+ *   threshold inclusive diameter threshold, or +INFINITY
+ *   out       receives a library-allocated result
+ * Uses device 0's current HIP device and its null stream. */
+int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
+                 rpp_result **out);
+
+/* As rpp_barcodes, for a distance matrix already resident in device memory
+ * (HBM).  Work is issued on hip_stream (a hipStream_t, NULL = null stream)
+ * of the current device; the call returns after the result is complete.
+ * workspace_dev / workspace_bytes: caller-provided device scratch, or
+ * NULL / 0 to let the library use its own per-device cache.  flags: RPP_*. */
+int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
+                        void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                        uint32_t flags, rpp_result **out);
+
+/* Upper bound of the device workspace that rpp_barcodes_device needs for a
+ * matrix of n points, dimensions 0..maxdim (0 on invalid arguments). */
+size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold);
+
+/* Apparent pairs of dimension (p, p+1) over EVERY p-simplex with diameter
+ * <= threshold (no clearing), by the apparent pairs lemma, on the GPU
+ * (paper, algorithm for finding apparent pairs).  dist_dev is a device
+ * condensed matrix.  Writes at most cap pairs (sigma_cidx, tau_cidx) in
+ * increasing sigma order into host arrays sigma_out / tau_out (either may be
+ * NULL when cap == 0) and stores the number of apparent pairs in *count and
+ * the number of p-simplices examined in *n_columns. */
+int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float threshold,
+                       void *hip_stream, uint64_t *sigma_out, uint64_t *tau_out,
+                       int64_t cap, int64_t *count, int64_t *n_columns);
+
+void rpp_result_free(rpp_result *r);
+
+/* Static text for an RPP_E_* code. */
+const char *rpp_strerror(int code);
+
+/* Text describing the last error raised on the calling thread. */
+const char *rpp_last_error(void);
+
+/* Library version string. */
+const char *rpp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPP_H */
