@@ -62,7 +62,7 @@ enum {
     RPP_E_DEVICE = -5, /* HIP runtime error */
 };
 
-/* flags for rpp_barcodes_device / rpp_barcodes_ex */
+/* flags for rpp_barcodes_device */
 #define RPP_NO_ENCLOSING_RADIUS 0x1u /* use the threshold as given, even if +inf */
 #define RPP_WANT_PAIRS 0x2u          /* also return every persistence pair */
 
@@ -84,8 +84,15 @@ typedef struct {
     int64_t n_essential;    /* essential classes */
     int64_t n_bars;         /* reported intervals, essential included */
     int64_t n_column_adds;  /* column additions done by the host reduction */
+    int64_t n_scanned;      /* cofacet candidates examined by the apparent test
+                               (sum over columns; only when the environment
+                               variable RPP_COUNT_SCANS=1, else 0) */
     float ms_gpu;           /* device time of the dimension's GPU stages */
     float ms_host;          /* host reduction wall time */
+    float ms_enumerate;     /* device time: enumeration + filter + compaction */
+    float ms_apparent;      /* device time: apparent-pair kernel */
+    float ms_partition;     /* device time: partition */
+    float ms_sort;          /* device time: key sorts and clearing bitmap */
 } rpp_dim_stats;
 
 typedef struct {
@@ -97,8 +104,9 @@ typedef struct {
 
 /* Only filled with RPP_WANT_PAIRS: every persistence pair (sigma, tau) of
  * dimension dim (zero-length pairs included), sigma a dim-simplex and tau a
- * (dim+1)-simplex, as combinatorial indices.  For dim 0 sigma is the vertex
- * index and tau the edge.  Order: unspecified. */
+ * (dim+1)-simplex, as combinatorial indices.  For dim 0 tau is the edge of
+ * each spanning-forest merge and sigma is UINT64_MAX (the vertex side is not
+ * tracked).  Order: unspecified. */
 typedef struct {
     int32_t dim;
     int64_t count;

@@ -1,0 +1,17 @@
+"""Vietoris-Rips persistence barcodes on the AMD Instinct MI355X.
+
+The data-parallel hot path of arXiv 2003.07989 (Ripser++) -- enumeration
+of simplices in combinatorial-number-system order, the threshold and
+clearing filter, the apparent-pair test, the column key sorts and H0 by
+union-find -- runs as hand-written HIP kernels for gfx950 in ``librpp.so``
+behind the C ABI of ``include/rpp.h``.  This package is the thin Python
+binding.  Importing it does not load the library; the first call does,
+and fails loudly if ``librpp.so`` has not been built.
+"""
+from ._binding import (RPP_MAX_DIM, RPP_NO_ENCLOSING_RADIUS, RPP_WANT_PAIRS, Barcodes,
+                       RppError, apparent_pairs, barcodes, barcodes_device, barcodes_host,
+                       load, strerror, version, workspace_bytes)
+
+__all__ = ["RPP_MAX_DIM", "RPP_NO_ENCLOSING_RADIUS", "RPP_WANT_PAIRS", "Barcodes",
+           "RppError", "apparent_pairs", "barcodes", "barcodes_device", "barcodes_host",
+           "load", "strerror", "version", "workspace_bytes"]

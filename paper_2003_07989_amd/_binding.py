@@ -1,0 +1,247 @@
+"""ctypes binding of the C ABI in include/rpp.h (argument marshalling only).
+
+Every stage of the computation runs inside librpp.so on the GPU (and its
+host residual reduction); this module only moves pointers and sizes across
+the boundary and copies results into numpy arrays.  PyTorch supplies device
+memory and streams.  torch is imported before the library is loaded so that
+both share one HIP runtime (torch's runtime carries the same soname).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading librpp.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpp.so")
+
+RPP_MAX_DIM = 4
+RPP_NO_ENCLOSING_RADIUS = 0x1
+RPP_WANT_PAIRS = 0x2
+
+ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
+          -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE"}
+
+
+class RppError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n_candidates", "n_simplices", "n_thresholded", "n_cleared", "n_kept",
+        "n_apparent", "n_nonapparent", "n_host_pairs", "n_essential", "n_bars",
+        "n_column_adds", "n_scanned")] + [(name, ctypes.c_float) for name in (
+        "ms_gpu", "ms_host", "ms_enumerate", "ms_apparent", "ms_partition", "ms_sort")]
+
+
+class _Bars(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("birth", ctypes.POINTER(ctypes.c_float)),
+                ("death", ctypes.POINTER(ctypes.c_float))]
+
+
+class _Pairs(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("sigma", ctypes.POINTER(ctypes.c_uint64)),
+                ("tau", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("maxdim", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("threshold_used", ctypes.c_float), ("enclosing_radius", ctypes.c_float),
+                ("dims", ctypes.POINTER(_Bars)), ("stats", ctypes.POINTER(_Stats)),
+                ("pairs", ctypes.POINTER(_Pairs))]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load librpp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("librpp.so is missing at %s: run __graft_entry__.build() "
+                           "(or python -m paper_2003_07989_amd.build) first" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.rpp_barcodes.argtypes = [P(ctypes.c_float), ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_float, P(P(_Result))]
+    lib.rpp_barcodes.restype = ctypes.c_int
+    lib.rpp_barcodes_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_uint32, P(P(_Result))]
+    lib.rpp_barcodes_device.restype = ctypes.c_int
+    lib.rpp_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_float]
+    lib.rpp_workspace_bytes.restype = ctypes.c_size_t
+    lib.rpp_apparent_pairs.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_float, ctypes.c_void_p, P(ctypes.c_uint64),
+                                       P(ctypes.c_uint64), ctypes.c_int64, P(ctypes.c_int64),
+                                       P(ctypes.c_int64)]
+    lib.rpp_apparent_pairs.restype = ctypes.c_int
+    lib.rpp_result_free.argtypes = [P(_Result)]
+    lib.rpp_result_free.restype = None
+    lib.rpp_strerror.argtypes = [ctypes.c_int]
+    lib.rpp_strerror.restype = ctypes.c_char_p
+    lib.rpp_last_error.argtypes = []
+    lib.rpp_last_error.restype = ctypes.c_char_p
+    lib.rpp_version.argtypes = []
+    lib.rpp_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise RppError(rc, load().rpp_last_error().decode())
+
+
+@dataclass
+class Barcodes:
+    """Result of one cloud: bars[p] = (birth, death) float32 arrays."""
+    n: int
+    maxdim: int
+    threshold_used: float
+    enclosing_radius: float
+    bars: list
+    stats: list
+    pairs: list = field(default=None)
+
+
+def _collect(res: "ctypes.POINTER(_Result)") -> Barcodes:
+    r = res.contents
+    bars, stats, pairs = [], [], None
+    for p in range(r.maxdim + 1):
+        b = r.dims[p]
+        cnt = int(b.count)
+        if cnt:
+            birth = np.ctypeslib.as_array(b.birth, shape=(cnt,)).copy()
+            death = np.ctypeslib.as_array(b.death, shape=(cnt,)).copy()
+        else:
+            birth = np.zeros(0, np.float32)
+            death = np.zeros(0, np.float32)
+        bars.append((birth, death))
+        s = r.stats[p]
+        stats.append({name: getattr(s, name) for name, _ in _Stats._fields_})
+    if bool(r.pairs):
+        pairs = []
+        for p in range(r.maxdim + 1):
+            q = r.pairs[p]
+            cnt = int(q.count)
+            if cnt:
+                pairs.append((np.ctypeslib.as_array(q.sigma, shape=(cnt,)).copy(),
+                              np.ctypeslib.as_array(q.tau, shape=(cnt,)).copy()))
+            else:
+                pairs.append((np.zeros(0, np.uint64), np.zeros(0, np.uint64)))
+    return Barcodes(int(r.n), int(r.maxdim), float(r.threshold_used),
+                    float(r.enclosing_radius), bars, stats, pairs)
+
+
+def _n_from_len(m: int) -> int:
+    n = int((1 + math.isqrt(1 + 8 * m)) // 2)
+    if n * (n - 1) // 2 != m:
+        raise ValueError("length %d is not n*(n-1)/2" % m)
+    return n
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def barcodes_device(dist: torch.Tensor, maxdim: int, threshold: float = math.inf,
+                    n: int = None, flags: int = 0, stream=None) -> Barcodes:
+    """rpp_barcodes_device on a contiguous float32 CUDA tensor holding the
+    condensed lower triangle."""
+    if not (isinstance(dist, torch.Tensor) and dist.is_cuda and dist.dtype == torch.float32
+            and dist.is_contiguous()):
+        raise TypeError("dist must be a contiguous float32 CUDA tensor")
+    if n is None:
+        n = _n_from_len(dist.numel())
+    lib = load()
+    out = ctypes.POINTER(_Result)()
+    rc = lib.rpp_barcodes_device(ctypes.c_void_p(dist.data_ptr() if dist.numel() else 0),
+                                 int(n), int(maxdim), ctypes.c_float(threshold), None, 0,
+                                 ctypes.c_void_p(_stream_handle(stream)), int(flags),
+                                 ctypes.byref(out))
+    _check(rc)
+    try:
+        return _collect(out)
+    finally:
+        lib.rpp_result_free(out)
+
+
+def barcodes(dist, maxdim: int, threshold: float = math.inf, n: int = None,
+             flags: int = 0, stream=None) -> Barcodes:
+    """Barcodes of a condensed distance array (numpy array or tensor); host
+    data are copied to the current CUDA device first."""
+    if isinstance(dist, torch.Tensor) and dist.is_cuda:
+        t = dist.to(torch.float32).contiguous()
+    else:
+        a = np.ascontiguousarray(np.asarray(dist), dtype=np.float32)
+        t = torch.from_numpy(a).cuda()
+    return barcodes_device(t, maxdim, threshold, n=n, flags=flags, stream=stream)
+
+
+def barcodes_host(dist: np.ndarray, maxdim: int, threshold: float = math.inf,
+                  n: int = None) -> Barcodes:
+    """rpp_barcodes on a host array (the library copies it to the device)."""
+    a = np.ascontiguousarray(dist, dtype=np.float32)
+    if n is None:
+        n = _n_from_len(a.size)
+    lib = load()
+    out = ctypes.POINTER(_Result)()
+    ptr = a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a.size else None
+    _check(lib.rpp_barcodes(ptr, int(n), int(maxdim), ctypes.c_float(threshold),
+                            ctypes.byref(out)))
+    try:
+        return _collect(out)
+    finally:
+        lib.rpp_result_free(out)
+
+
+def apparent_pairs(dist, p: int, threshold: float = math.inf, n: int = None, stream=None):
+    """(sigma, tau, n_columns): apparent pairs of dimension (p, p+1) over all
+    p-simplices with diameter <= threshold, in increasing sigma order."""
+    if isinstance(dist, torch.Tensor) and dist.is_cuda:
+        t = dist.to(torch.float32).contiguous()
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(dist), dtype=np.float32)).cuda()
+    if n is None:
+        n = _n_from_len(t.numel())
+    lib = load()
+    cnt, ncols = ctypes.c_int64(0), ctypes.c_int64(0)
+    h = ctypes.c_void_p(_stream_handle(stream))
+    _check(lib.rpp_apparent_pairs(ctypes.c_void_p(t.data_ptr()), int(n), int(p),
+                                  ctypes.c_float(threshold), h, None, None, 0,
+                                  ctypes.byref(cnt), ctypes.byref(ncols)))
+    k = cnt.value
+    s = np.zeros(max(k, 1), np.uint64)
+    u = np.zeros(max(k, 1), np.uint64)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(lib.rpp_apparent_pairs(ctypes.c_void_p(t.data_ptr()), int(n), int(p),
+                                  ctypes.c_float(threshold), h, s.ctypes.data_as(P64),
+                                  u.ctypes.data_as(P64), k, ctypes.byref(cnt),
+                                  ctypes.byref(ncols)))
+    return s[:k], u[:k], int(ncols.value)
+
+
+def workspace_bytes(n: int, maxdim: int, threshold: float = math.inf) -> int:
+    return int(load().rpp_workspace_bytes(int(n), int(maxdim), ctypes.c_float(threshold)))
+
+
+def version() -> str:
+    return load().rpp_version().decode()
+
+
+def strerror(code: int) -> str:
+    return load().rpp_strerror(int(code)).decode()

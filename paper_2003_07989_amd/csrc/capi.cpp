@@ -1,0 +1,269 @@
+// capi.cpp -- the extern "C" boundary declared in include/rpp.h.
+//
+// Validates arguments, moves host input to the device when needed, runs the
+// pipeline and turns its output into a library-owned rpp_result with
+// canonically sorted bars.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/rpp.h"
+#include "pipeline.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// Argument checks common to every entry point.
+int check_args(int32_t n, int32_t maxdim, float threshold, rpp_result **out)
+{
+    if (!out)
+        return fail(RPP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1)
+        return fail(RPP_E_INVAL, "n must be >= 1");
+    if (maxdim < 0 || maxdim > RPP_MAX_DIM)
+        return fail(RPP_E_INVAL, "maxdim must be in 0..RPP_MAX_DIM");
+    if (isnan(threshold) || threshold < 0.0f)
+        return fail(RPP_E_INVAL, "threshold must be >= 0 or +inf");
+    if (n > 1 && rpp::binom_sat(n, std::min<int>(n, maxdim + 2)) >= (uint64_t)INT64_MAX)
+        return fail(RPP_E_RANGE, "C(n, maxdim+2) exceeds the 63-bit index range");
+    if ((int64_t)n * n > (int64_t)1 << 31)
+        return fail(RPP_E_RANGE, "n too large for the dense distance matrix");
+    return RPP_OK;
+}
+
+template <typename T>
+T *dup(const std::vector<T> &v)
+{
+    T *p = static_cast<T *>(malloc(std::max<size_t>(1, v.size()) * sizeof(T)));
+    if (p && !v.empty())
+        memcpy(p, v.data(), v.size() * sizeof(T));
+    return p;
+}
+
+int build_result(const rpp::RunOut &ro, int n, int maxdim, uint32_t flags, rpp_result **out)
+{
+    rpp_result *r = static_cast<rpp_result *>(calloc(1, sizeof(rpp_result)));
+    if (!r)
+        return fail(RPP_E_NOMEM, "result allocation failed");
+    r->maxdim = maxdim;
+    r->n = n;
+    r->threshold_used = ro.thr_used;
+    r->enclosing_radius = ro.radius;
+    r->dims = static_cast<rpp_bars *>(calloc(maxdim + 1, sizeof(rpp_bars)));
+    r->stats = static_cast<rpp_dim_stats *>(calloc(maxdim + 1, sizeof(rpp_dim_stats)));
+    if (flags & RPP_WANT_PAIRS)
+        r->pairs = static_cast<rpp_pairs *>(calloc(maxdim + 1, sizeof(rpp_pairs)));
+    if (!r->dims || !r->stats || ((flags & RPP_WANT_PAIRS) && !r->pairs)) {
+        rpp_result_free(r);
+        return fail(RPP_E_NOMEM, "result allocation failed");
+    }
+    for (int p = 0; p <= maxdim; ++p) {
+        const rpp::DimOut &D = ro.dims[p];
+        // canonical order: birth, then death (+inf last); zeros as +0.0
+        std::vector<size_t> idx(D.birth.size());
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            if (D.birth[x] != D.birth[y])
+                return D.birth[x] < D.birth[y];
+            return D.death[x] < D.death[y];
+        });
+        std::vector<float> b(idx.size()), d(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) {
+            b[i] = D.birth[idx[i]] + 0.0f;
+            d[i] = D.death[idx[i]] + 0.0f;
+        }
+        r->dims[p].dim = p;
+        r->dims[p].count = (int64_t)b.size();
+        r->dims[p].birth = dup(b);
+        r->dims[p].death = dup(d);
+        r->stats[p] = D.st;
+        if (!r->dims[p].birth || !r->dims[p].death) {
+            rpp_result_free(r);
+            return fail(RPP_E_NOMEM, "result allocation failed");
+        }
+        if (r->pairs) {
+            r->pairs[p].dim = p;
+            r->pairs[p].count = (int64_t)D.pair_sigma.size();
+            r->pairs[p].sigma = dup(D.pair_sigma);
+            r->pairs[p].tau = dup(D.pair_tau);
+            if (!r->pairs[p].sigma || !r->pairs[p].tau) {
+                rpp_result_free(r);
+                return fail(RPP_E_NOMEM, "result allocation failed");
+            }
+        }
+    }
+    *out = r;
+    return RPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
+                        void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                        uint32_t flags, rpp_result **out)
+{
+    int rc = check_args(n, maxdim, threshold, out);
+    if (rc)
+        return rc;
+    if (n > 1 && !dist_dev)
+        return fail(RPP_E_INVAL, "dist_dev is NULL");
+    (void)workspace_dev;
+    (void)workspace_bytes;
+    try {
+        rpp::RunArgs a;
+        a.dcond_dev = dist_dev;
+        a.n = n;
+        a.maxdim = maxdim;
+        a.threshold = threshold;
+        a.flags = flags;
+        a.stream = static_cast<hipStream_t>(hip_stream);
+        const char *g = getenv("RPP_APPARENT_GROUP");
+        a.apparent_group = g ? atoi(g) : 0;
+        const char *cs = getenv("RPP_COUNT_SCANS");
+        a.count_scans = cs && atoi(cs) != 0;
+        rpp::RunOut ro;
+        std::string err;
+        rc = rpp::run_pipeline(a, ro, err);
+        if (rc)
+            return fail(rc, err);
+        return build_result(ro, n, maxdim, flags, out);
+    } catch (const std::bad_alloc &) {
+        return fail(RPP_E_NOMEM, "host allocation failed");
+    }
+}
+
+int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
+                 rpp_result **out)
+{
+    int rc = check_args(n, maxdim, threshold, out);
+    if (rc)
+        return rc;
+    if (n > 1 && !dist)
+        return fail(RPP_E_INVAL, "dist is NULL");
+    const size_t m = (size_t)n * (n - 1) / 2;
+    for (size_t i = 0; i < m; ++i)
+        if (!(dist[i] >= 0.0f) || isinf(dist[i]))
+            return fail(RPP_E_DATA, "distance matrix holds a NaN, infinite or negative entry");
+    float *d = nullptr;
+    if (m) {
+        hipError_t e = hipMalloc(&d, m * sizeof(float));
+        if (e != hipSuccess)
+            return fail(RPP_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        e = hipMemcpy(d, dist, m * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(RPP_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+    }
+    rc = rpp_barcodes_device(d, n, maxdim, threshold, nullptr, 0, nullptr, 0, out);
+    if (d)
+        (void)hipFree(d);
+    return rc;
+}
+
+size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold)
+{
+    (void)threshold;
+    if (n < 1 || maxdim < 0 || maxdim > RPP_MAX_DIM)
+        return 0;
+    return rpp::workspace_bytes(n, maxdim);
+}
+
+int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float threshold,
+                       void *hip_stream, uint64_t *sigma_out, uint64_t *tau_out, int64_t cap,
+                       int64_t *count, int64_t *n_columns)
+{
+    if (!count || !n_columns)
+        return fail(RPP_E_INVAL, "count / n_columns is NULL");
+    if (n < 2 || p < 1 || p > RPP_MAX_DIM)
+        return fail(RPP_E_INVAL, "need n >= 2 and 1 <= p <= RPP_MAX_DIM");
+    if (!dist_dev)
+        return fail(RPP_E_INVAL, "dist_dev is NULL");
+    if (isnan(threshold) || threshold < 0.0f)
+        return fail(RPP_E_INVAL, "threshold must be >= 0 or +inf");
+    if (cap > 0 && (!sigma_out || !tau_out))
+        return fail(RPP_E_INVAL, "output arrays are NULL");
+    if (rpp::binom_sat(n, std::min<int>(n, p + 2)) >= (uint64_t)INT64_MAX)
+        return fail(RPP_E_RANGE, "C(n, p+2) exceeds the 63-bit index range");
+    try {
+        std::vector<uint64_t> s, t;
+        int64_t ncols = 0;
+        std::string err;
+        int rc = rpp::run_apparent_only(dist_dev, n, p, threshold,
+                                        static_cast<hipStream_t>(hip_stream), s, t, ncols, err);
+        if (rc)
+            return fail(rc, err);
+        *count = (int64_t)s.size();
+        *n_columns = ncols;
+        const int64_t k = std::min<int64_t>(cap, (int64_t)s.size());
+        if (k > 0) {
+            memcpy(sigma_out, s.data(), (size_t)k * 8);
+            memcpy(tau_out, t.data(), (size_t)k * 8);
+        }
+        return RPP_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RPP_E_NOMEM, "host allocation failed");
+    }
+}
+
+void rpp_result_free(rpp_result *r)
+{
+    if (!r)
+        return;
+    if (r->dims)
+        for (int p = 0; p <= r->maxdim; ++p) {
+            free(r->dims[p].birth);
+            free(r->dims[p].death);
+        }
+    if (r->pairs)
+        for (int p = 0; p <= r->maxdim; ++p) {
+            free(r->pairs[p].sigma);
+            free(r->pairs[p].tau);
+        }
+    free(r->dims);
+    free(r->stats);
+    free(r->pairs);
+    free(r);
+}
+
+const char *rpp_strerror(int code)
+{
+    switch (code) {
+    case RPP_OK: return "success";
+    case RPP_E_INVAL: return "invalid argument";
+    case RPP_E_DATA: return "invalid distance entry (NaN, infinite or negative)";
+    case RPP_E_RANGE: return "problem size outside the supported index range";
+    case RPP_E_NOMEM: return "out of memory";
+    case RPP_E_DEVICE: return "HIP runtime error";
+    default: return "unknown error";
+    }
+}
+
+const char *rpp_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *rpp_version(void)
+{
+    return "rpp-mi355x 0.1 (gfx950)";
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// device_common.h -- index arithmetic shared by the gfx950 kernels.
+//
+// Simplices are named by their combinatorial index (paper, section on the
+// combinatorial number system): vertices v_p > ... > v_0 map to
+// cidx = C(v_p, p+1) + ... + C(v_0, 1).  Ordering simplices by cidx is the
+// colexicographic order on increasing vertex tuples.
+//
+// Binomial coefficients come from a table binom[k * stride + v] = C(v, k),
+// k = 0..kmax, v = 0..n, built once per point count on the host (paper:
+// cofacets are generated from the distance matrix and a small binomial
+// coefficient table).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpp {
+
+constexpr uint64_t NONE = ~0ull;
+constexpr int WAVE = 64;
+
+struct Binom {
+    const uint64_t *__restrict__ t;
+    int stride;  // n + 1
+    __device__ __forceinline__ uint64_t operator()(int v, int k) const
+    {
+        return t[(int64_t)k * stride + v];
+    }
+};
+
+// Largest v in [k-1, hi) with C(v, k) <= c.  C(k-1, k) = 0 <= c always.
+__device__ __forceinline__ int top_vertex(const Binom &B, uint64_t c, int k, int hi)
+{
+    if (k == 1)
+        return (int)c;
+    int lo = k - 1, h = hi - 1;
+    while (lo < h) {
+        int mid = (lo + h + 1) >> 1;
+        if (B(mid, k) <= c)
+            lo = mid;
+        else
+            h = mid - 1;
+    }
+    return lo;
+}
+
+// Vertices of a p-simplex in decreasing order: v[0] > v[1] > ... > v[P].
+template <int P>
+__device__ __forceinline__ void decode(const Binom &B, uint64_t c, int n, int (&v)[P + 1])
+{
+    int hi = n;
+#pragma unroll
+    for (int pos = 0; pos <= P; ++pos) {
+        const int k = P + 1 - pos;
+        int x = top_vertex(B, c, k, hi);
+        v[pos] = x;
+        c -= B(x, k);
+        hi = x;
+    }
+}
+
+// Edge (a > b) from its index c = C(a,2) + b, without the table.
+__device__ __forceinline__ void decode_edge(uint64_t c, int &a, int &b)
+{
+    int x = (int)floor((1.0 + sqrt(1.0 + 8.0 * (double)c)) * 0.5);
+    while ((uint64_t)x * (x - 1) / 2 > c)
+        --x;
+    while ((uint64_t)(x + 1) * x / 2 <= c)
+        ++x;
+    a = x;
+    b = (int)(c - (uint64_t)x * (x - 1) / 2);
+}
+
+// cidx of sigma + {w} where sigma = v[0] > ... > v[P] and w is not in sigma:
+// with j = #{i : v_i < w}, cidx = sum_{v_i < w} C(v_i, rank+1) + C(w, j+1)
+// + sum_{v_i > w} C(v_i, rank+2) (ranks counted from the bottom).
+template <int P>
+__device__ __forceinline__ uint64_t cofacet_index(const Binom &B, const int (&v)[P + 1], int w)
+{
+    uint64_t c = 0;
+    int r = 0;
+    bool placed = false;
+#pragma unroll
+    for (int i = P; i >= 0; --i) {
+        if (!placed && w < v[i]) {
+            c += B(w, r + 1);
+            ++r;
+            placed = true;
+        }
+        c += B(v[i], r + 1);
+        ++r;
+    }
+    if (!placed)
+        c += B(w, r + 1);
+    return c;
+}
+
+// Distance through the square matrix (row-major, n x n, zero diagonal).
+__device__ __forceinline__ float dsq_at(const float *__restrict__ dsq, int n, int a, int b)
+{
+    return dsq[(int64_t)a * n + b];
+}
+
+// Bit pattern of a non-negative float, -0.0 folded to +0.0: monotone in the
+// value, so unsigned comparison of the patterns orders the diameters.
+__device__ __forceinline__ uint32_t diam_bits(float d)
+{
+    return __float_as_uint(d + 0.0f);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    return (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+}
+
+}  // namespace rpp

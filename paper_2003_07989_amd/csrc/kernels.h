@@ -1,0 +1,98 @@
+// kernels.h -- host-side launchers of the gfx950 kernels (kernels.hip).
+//
+// Every launcher enqueues work on `stream` and returns immediately; sizes
+// that the host needs afterwards are left in device memory for the caller
+// to copy back.  Pointers are device pointers unless stated otherwise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rpp {
+
+// ---- a1: staging -------------------------------------------------------
+// Square n x n copy (zero diagonal, -0 folded to +0), per-row maxima, and a
+// validity flag (bit 0 set when an entry is NaN, infinite or negative).
+void launch_stage(const float *dcond, int n, float *dsq, float *rowmax, uint32_t *bad,
+                  hipStream_t s);
+// out[0] = min over rows of rowmax (the enclosing radius).
+void launch_min(const float *x, int n, float *out, hipStream_t s);
+
+// ---- device-wide helpers --------------------------------------------------
+void launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
+// Exclusive scan of u32 counts into u64 offsets; out has len+1 entries and
+// out[len] is the total.  scratch must hold scan_scratch_words(len) u64.
+int64_t scan_scratch_words(int64_t len);
+void launch_exclusive_scan(const uint32_t *in, int64_t len, uint64_t *out, uint64_t *scratch,
+                           hipStream_t s);
+
+// ---- a3 + a4: enumeration with threshold and clearing --------------------
+constexpr int64_t COMPACT_TILE = 4096;  // candidates per workgroup
+inline int64_t compact_tiles(int64_t count) { return (count + COMPACT_TILE - 1) / COMPACT_TILE; }
+
+struct EnumArgs {
+    const float *dcond;        // condensed distances (edge cidx order)
+    int n;
+    int p;                     // simplex dimension, 1..4
+    float thr;                 // inclusive threshold
+    const uint64_t *binom;     // C(v,k) table, stride n+1
+    const uint32_t *clear;     // clearing bitmap over C(n,p+1) cidx, or null
+    uint64_t ncand;            // C(n, p+1)
+};
+// Pass 1: kept count per tile; stats[0] += thresholded, stats[1] += cleared.
+void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts,
+                       unsigned long long *stats, hipStream_t s);
+// Pass 2: write kept simplices (diameter, cidx) in increasing cidx order.
+void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float *out_diam,
+                         uint64_t *out_cidx, hipStream_t s);
+
+// ---- a5: apparent-pair test -----------------------------------------------
+// tau_out[i] = cidx of the apparent partner of column i, or ~0 when the
+// column is not apparent.  group = lanes cooperating on one column.  When
+// scan_count is not null (SCAN_COUNTERS u64 slots, zeroed by the caller)
+// the number of cofacet candidates each column examines in decreasing
+// vertex order, up to and including the first equal-diameter cofacet (all
+// n-p-1 when there is none), is added to it.
+constexpr int SCAN_COUNTERS = 1024;
+void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                     const float *dsq, int n, int p, const uint64_t *binom, int group,
+                     uint64_t *tau_out, unsigned long long *scan_count, hipStream_t s);
+
+// ---- a6: partition --------------------------------------------------------
+// Pass 1: apparent columns per tile.
+void launch_partition_count(const uint64_t *tau, int64_t ncols, uint32_t *tile_counts,
+                            hipStream_t s);
+// Pass 2: apparent -> (tau, sigma) pairs; non-apparent -> (key, cidx) with
+// key = ~bits(diameter), both in increasing column (cidx) order.
+void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
+                              const uint64_t *col_cidx, int64_t ncols,
+                              const uint64_t *tile_offsets, uint64_t *app_tau,
+                              uint64_t *app_sigma, uint64_t *na_key, uint64_t *na_cidx,
+                              hipStream_t s);
+// key[i] = ~bits(diam[i]) (descending-diameter radix key).
+void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s);
+
+// ---- a7: clearing bitmap ---------------------------------------------------
+void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s);
+
+// ---- a2: H0 by union-find ---------------------------------------------------
+// Edges sorted in coboundary order (diameter descending, cidx ascending);
+// processed from the back, i.e. in filtration order.  Sets the MST bit of
+// each spanning-forest edge, writes the nonzero death diameters to deaths
+// and counters[0] = #deaths, counters[1] = #merges.  uf_scratch: 2n ints,
+// used when the union-find arrays do not fit in LDS.
+void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
+                    uint32_t *mst_bits, float *deaths, int *counters, int *uf_scratch,
+                    hipStream_t s);
+
+// ---- a6: LDS radix sort -------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).  The
+// sorted data end up in either the input or the alternate buffers; the
+// return value is 0 when they are in (keys, vals), 1 when in (keys_alt,
+// vals_alt).  scratch must hold radix_scratch_words(count) u64.
+int64_t radix_scratch_words(int64_t count);
+int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
+                     int64_t count, int bits, uint64_t *scratch, hipStream_t s);
+
+}  // namespace rpp

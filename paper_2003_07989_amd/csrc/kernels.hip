@@ -1,0 +1,945 @@
+// kernels.hip -- gfx950 kernels of the Vietoris-Rips hot path.
+//
+// Wave64 throughout: compaction ranks come from 64-bit ballots and
+// popcounts, the apparent-pair scan uses sub-wave groups that read
+// contiguous runs of a distance-matrix row, and the sort ranks digits with
+// wave-level match masks staged in LDS.  No MFMA: nothing here is a dense
+// contraction.
+#include "device_common.h"
+#include "kernels.h"
+
+#include <limits.h>
+
+namespace rpp {
+
+// ===========================================================================
+// block-level helpers
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        T t = __shfl_up(v, o, WAVE);
+        if (lane >= o)
+            v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Exclusive scan across the block (blockDim.x = NT); *total gets the sum.
+// `sh` must hold NT/64 + 1 elements.  Contains barriers: call from all
+// threads.
+template <int NT, typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *total, T *sh)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    constexpr int NW = NT / WAVE;
+    T inc = wave_inclusive_scan(v);
+    if (lane == WAVE - 1)
+        sh[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < NW; ++w) {
+            T t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[NW] = run;
+    }
+    __syncthreads();
+    T out = sh[wave] + inc - v;
+    *total = sh[NW];
+    __syncthreads();
+    return out;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    constexpr int NW = NT / WAVE;
+    v = wave_sum(v);
+    if (lane == 0)
+        sh[wave] = v;
+    __syncthreads();
+    T s = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NW; ++w)
+            s += sh[w];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// ===========================================================================
+// a1: staging -- square matrix, row maxima, validation
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dcond, int n,
+                                               float *__restrict__ dsq,
+                                               float *__restrict__ rowmax,
+                                               uint32_t *__restrict__ bad)
+{
+    __shared__ float sh[5];
+    const int i = blockIdx.x;
+    float mx = 0.0f;
+    uint32_t flag = 0;
+    const int64_t rowi = (int64_t)i * (i - 1) / 2;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        float d;
+        if (j == i)
+            d = 0.0f;
+        else if (j < i)
+            d = dcond[rowi + j];
+        else
+            d = dcond[(int64_t)j * (j - 1) / 2 + i];
+        if (!(d >= 0.0f) || isinf(d))
+            flag = 1;
+        d = d + 0.0f;
+        dsq[(int64_t)i * n + j] = d;
+        mx = fmaxf(mx, d);
+    }
+    // block max
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0)
+        sh[wave] = mx;
+    if (flag)
+        atomicOr(bad, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            m = fmaxf(m, sh[w]);
+        rowmax[i] = m;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_min(const float *__restrict__ x, int n,
+                                              float *__restrict__ out)
+{
+    __shared__ float sh[16];
+    float m = INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        m = fminf(m, x[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        m = fminf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            r = fminf(r, sh[w]);
+        out[0] = r;
+    }
+}
+
+void launch_stage(const float *dcond, int n, float *dsq, float *rowmax, uint32_t *bad,
+                  hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage, dim3(n), dim3(256), 0, s, dcond, n, dsq, rowmax, bad);
+}
+
+void launch_min(const float *x, int n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, s, x, n, out);
+}
+
+// ===========================================================================
+// fill and device-wide exclusive scan (u32 counts -> u64 offsets)
+// ===========================================================================
+__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t value)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride)
+        p[i] = value;
+}
+
+void launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s)
+{
+    if (count <= 0)
+        return;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, value);
+}
+
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_I = 4;
+constexpr int64_t SCAN_CHUNK = SCAN_T * SCAN_I;
+
+int64_t scan_scratch_words(int64_t len)
+{
+    return (len + SCAN_CHUNK - 1) / SCAN_CHUNK + 2;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_partial(const uint32_t *__restrict__ in,
+                                                         int64_t len,
+                                                         uint64_t *__restrict__ part)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        if (i < len)
+            s += in[i];
+    }
+    s = block_sum<SCAN_T>(s, sh);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_top(uint64_t *__restrict__ part, int nb)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    uint64_t carry = 0;
+    for (int start = 0; start < nb; start += SCAN_T) {
+        int i = start + threadIdx.x;
+        uint64_t v = (i < nb) ? part[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_exclusive_scan<SCAN_T>(v, &tot, sh);
+        if (i < nb)
+            part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        part[nb] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const uint32_t *__restrict__ in,
+                                                       int64_t len,
+                                                       const uint64_t *__restrict__ part, int nb,
+                                                       uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    uint64_t carry = part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        uint64_t v = (i < len) ? in[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_exclusive_scan<SCAN_T>(v, &tot, sh);
+        if (i < len)
+            out[i] = carry + ex;
+        carry += tot;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        out[len] = part[nb];
+}
+
+void launch_exclusive_scan(const uint32_t *in, int64_t len, uint64_t *out, uint64_t *scratch,
+                           hipStream_t s)
+{
+    int nb = (int)((len + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    if (nb == 0) {
+        (void)hipMemsetAsync(out, 0, sizeof(uint64_t), s);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, in, len, scratch);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, scratch, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, s, in, len, scratch, nb, out);
+}
+
+// ===========================================================================
+// a3 + a4: dense enumeration in cidx order, threshold and clearing filter
+// ===========================================================================
+constexpr int CT = 256;
+constexpr int CI = (int)(COMPACT_TILE / CT);
+
+// Condensed lookup d(a, b) for a > b.
+__device__ __forceinline__ float dc_at(const float *__restrict__ dcond, int a, int b)
+{
+    return dcond[(int64_t)a * (a - 1) / 2 + b];
+}
+
+// 0 = kept, 1 = removed by the threshold, 2 = removed by clearing.
+template <int P>
+__device__ __forceinline__ int enum_eval(const EnumArgs &a, const Binom &B, uint64_t c,
+                                         float &diam)
+{
+    float d;
+    if (P == 1) {
+        d = a.dcond[c];
+    } else {
+        int v[P + 1];
+        decode<P>(B, c, a.n, v);
+        d = 0.0f;
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = i + 1; j <= P; ++j)
+                d = fmaxf(d, dc_at(a.dcond, v[i], v[j]));
+    }
+    d = d + 0.0f;
+    diam = d;
+    if (!(d <= a.thr))
+        return 1;
+    if (a.clear && ((a.clear[c >> 5] >> (c & 31)) & 1u))
+        return 2;
+    return 0;
+}
+
+template <int P>
+__global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a, uint32_t *__restrict__ tile_counts,
+                                                   unsigned long long *__restrict__ stats)
+{
+    __shared__ uint32_t sh[CT / WAVE + 1];
+    const Binom B{a.binom, a.n + 1};
+    const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
+    uint32_t keep = 0, nthr = 0, nclr = 0;
+#pragma unroll 4
+    for (int k = 0; k < CI; ++k) {
+        uint64_t c = base + (uint64_t)k * CT + threadIdx.x;
+        if (c < a.ncand) {
+            float d;
+            int r = enum_eval<P>(a, B, c, d);
+            keep += (r == 0);
+            nthr += (r == 1);
+            nclr += (r == 2);
+        }
+    }
+    uint32_t sk = block_sum<CT>(keep, sh);
+    uint32_t st = block_sum<CT>(nthr, sh);
+    uint32_t sc = block_sum<CT>(nclr, sh);
+    if (threadIdx.x == 0) {
+        tile_counts[blockIdx.x] = sk;
+        if (st)
+            atomicAdd(&stats[0], (unsigned long long)st);
+        if (sc)
+            atomicAdd(&stats[1], (unsigned long long)sc);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a,
+                                                     const uint64_t *__restrict__ tile_offsets,
+                                                     float *__restrict__ out_diam,
+                                                     uint64_t *__restrict__ out_cidx)
+{
+    __shared__ uint32_t wsum[CT / WAVE];
+    const Binom B{a.binom, a.n + 1};
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
+    uint64_t running = tile_offsets[blockIdx.x];
+    for (int k = 0; k < CI; ++k) {
+        uint64_t c = base + (uint64_t)k * CT + threadIdx.x;
+        float d = 0.0f;
+        bool keep = (c < a.ncand) && enum_eval<P>(a, B, c, d) == 0;
+        uint64_t m = __ballot(keep);
+        if (lane == 0)
+            wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < CT / WAVE; ++w) {
+            uint32_t x = wsum[w];
+            pre += (w < wave) ? x : 0;
+            tot += x;
+        }
+        if (keep) {
+            uint64_t pos = running + pre + (uint32_t)__popcll(m & lanemask_lt());
+            out_diam[pos] = d;
+            out_cidx[pos] = c;
+        }
+        running += tot;
+        __syncthreads();
+    }
+}
+
+#define RPP_DISPATCH_P(p, F, ...)                                                        \
+    switch (p) {                                                                         \
+    case 1: F<1> __VA_ARGS__; break;                                                     \
+    case 2: F<2> __VA_ARGS__; break;                                                     \
+    case 3: F<3> __VA_ARGS__; break;                                                     \
+    default: F<4> __VA_ARGS__; break;                                                    \
+    }
+
+void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts, unsigned long long *stats,
+                       hipStream_t s)
+{
+    int64_t tiles = compact_tiles((int64_t)a.ncand);
+    if (tiles == 0)
+        return;
+    dim3 g((unsigned)tiles), b(CT);
+    switch (a.p) {
+    case 1: hipLaunchKernelGGL(k_enum_count<1>, g, b, 0, s, a, tile_counts, stats); break;
+    case 2: hipLaunchKernelGGL(k_enum_count<2>, g, b, 0, s, a, tile_counts, stats); break;
+    case 3: hipLaunchKernelGGL(k_enum_count<3>, g, b, 0, s, a, tile_counts, stats); break;
+    default: hipLaunchKernelGGL(k_enum_count<4>, g, b, 0, s, a, tile_counts, stats); break;
+    }
+}
+
+void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float *out_diam,
+                         uint64_t *out_cidx, hipStream_t s)
+{
+    int64_t tiles = compact_tiles((int64_t)a.ncand);
+    if (tiles == 0)
+        return;
+    dim3 g((unsigned)tiles), b(CT);
+    switch (a.p) {
+    case 1: hipLaunchKernelGGL(k_enum_scatter<1>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
+    case 2: hipLaunchKernelGGL(k_enum_scatter<2>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
+    case 3: hipLaunchKernelGGL(k_enum_scatter<3>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
+    default: hipLaunchKernelGGL(k_enum_scatter<4>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
+    }
+}
+
+// ===========================================================================
+// a5: apparent-pair test (apparent pairs lemma)
+//
+// Column sigma = (v_0 > ... > v_P) of diameter d.
+//  1. Oldest cofacet: scanning w = n-1 down to 0 visits the cofacets
+//     sigma + {w} in decreasing cidx; the first w (not in sigma) with
+//     d(w, v_i) <= d for all i gives the lexicographically greatest cofacet
+//     of equal diameter.  None: the oldest cofacet is strictly larger in
+//     diameter and sigma is not apparent.
+//  2. Youngest facet: the other facets of tau are sigma - {u} + {w}; such a
+//     facet precedes sigma in cidx order exactly when u > w, and is younger
+//     than sigma exactly when, in addition, its diameter equals d.
+// G lanes cooperate on one column: in each step they test the G vertices
+// top, top-1, ..., top-G+1 with contiguous reads of the rows of the square
+// matrix, and a ballot picks the largest hit.
+// ===========================================================================
+template <int P, int G>
+__global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_diam,
+                                                  const uint64_t *__restrict__ col_cidx,
+                                                  int64_t ncols, const float *__restrict__ dsq,
+                                                  int n, const uint64_t *__restrict__ binom,
+                                                  uint64_t *__restrict__ tau_out,
+                                                  unsigned long long *__restrict__ scan_count)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = lane & (G - 1);
+    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (col >= ncols)
+        return;  // whole groups leave together
+    const Binom B{binom, n + 1};
+    const float d = col_diam[col];
+    const uint64_t c = col_cidx[col];
+    int v[P + 1];
+    decode<P>(B, c, n, v);
+    const float *row[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        row[i] = dsq + (int64_t)v[i] * n;
+
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    int w = -1;
+    for (int top = n - 1; top >= 0; top -= G) {
+        const int u = top - g;
+        bool ok = u >= 0;
+        if (ok) {
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                ok = ok && (u != v[i]) && (row[i][u] <= d);
+        }
+        const uint64_t m = __ballot(ok) & gmask;
+        if (m) {
+            w = top - (__ffsll((unsigned long long)m) - 1 - gbase);
+            break;
+        }
+    }
+    uint64_t tau = NONE;
+    if (w >= 0) {
+        bool apparent = true;
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            if (v[j] > w && apparent) {
+                // facet sigma - {v_j} + {w}
+                float fd = 0.0f;
+#pragma unroll
+                for (int a = 0; a <= P; ++a) {
+                    if (a == j)
+                        continue;
+                    fd = fmaxf(fd, row[a][w]);
+#pragma unroll
+                    for (int b = a + 1; b <= P; ++b)
+                        if (b != j)
+                            fd = fmaxf(fd, row[a][v[b]]);
+                }
+                if (fd == d)
+                    apparent = false;
+            }
+        }
+        if (apparent)
+            tau = cofacet_index<P>(B, v, w);
+    }
+    if (g == 0) {
+        tau_out[col] = tau;
+        if (scan_count) {
+            // candidates w not in sigma, visited from n-1 down to w*
+            long long sc = n - P - 1;
+            if (w >= 0) {
+                sc = (n - 1) - w + 1;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    sc -= (v[i] > w);
+            }
+            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)sc);
+        }
+    }
+}
+
+template <int P>
+static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
+                              const float *dsq, int n, const uint64_t *binom, int group,
+                              uint64_t *tau, unsigned long long *sc, hipStream_t s)
+{
+    const int64_t threads = ncols * group;
+    dim3 g((unsigned)((threads + 255) / 256)), b(256);
+    switch (group) {
+    case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    case 16: hipLaunchKernelGGL((k_apparent<P, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    case 32: hipLaunchKernelGGL((k_apparent<P, 32>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    case 64: hipLaunchKernelGGL((k_apparent<P, 64>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    default: hipLaunchKernelGGL((k_apparent<P, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    }
+}
+
+void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                     const float *dsq, int n, int p, const uint64_t *binom, int group,
+                     uint64_t *tau_out, unsigned long long *scan_count, hipStream_t s)
+{
+    if (ncols <= 0)
+        return;
+    switch (p) {
+    case 1: launch_apparent_p<1>(col_diam, col_cidx, ncols, dsq, n, binom, group, tau_out, scan_count, s); break;
+    case 2: launch_apparent_p<2>(col_diam, col_cidx, ncols, dsq, n, binom, group, tau_out, scan_count, s); break;
+    case 3: launch_apparent_p<3>(col_diam, col_cidx, ncols, dsq, n, binom, group, tau_out, scan_count, s); break;
+    default: launch_apparent_p<4>(col_diam, col_cidx, ncols, dsq, n, binom, group, tau_out, scan_count, s); break;
+    }
+}
+
+// ===========================================================================
+// a6: partition into apparent pairs and non-apparent columns
+// ===========================================================================
+__global__ __launch_bounds__(CT) void k_partition_count(const uint64_t *__restrict__ tau,
+                                                        int64_t ncols,
+                                                        uint32_t *__restrict__ tile_counts)
+{
+    __shared__ uint32_t sh[CT / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
+    uint32_t cnt = 0;
+#pragma unroll 4
+    for (int k = 0; k < CI; ++k) {
+        int64_t i = base + (int64_t)k * CT + threadIdx.x;
+        if (i < ncols)
+            cnt += (tau[i] != NONE);
+    }
+    cnt = block_sum<CT>(cnt, sh);
+    if (threadIdx.x == 0)
+        tile_counts[blockIdx.x] = cnt;
+}
+
+__global__ __launch_bounds__(CT) void k_partition_scatter(
+    const uint64_t *__restrict__ tau, const float *__restrict__ col_diam,
+    const uint64_t *__restrict__ col_cidx, int64_t ncols,
+    const uint64_t *__restrict__ tile_offsets, uint64_t *__restrict__ app_tau,
+    uint64_t *__restrict__ app_sigma, uint64_t *__restrict__ na_key,
+    uint64_t *__restrict__ na_cidx)
+{
+    __shared__ uint32_t wsum[CT / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
+    uint64_t run_a = tile_offsets[blockIdx.x];
+    uint64_t run_n = (uint64_t)base - run_a;
+    for (int k = 0; k < CI; ++k) {
+        int64_t i = base + (int64_t)k * CT + threadIdx.x;
+        const bool valid = i < ncols;
+        uint64_t t = valid ? tau[i] : NONE;
+        const bool app = valid && t != NONE;
+        const bool non = valid && t == NONE;
+        uint64_t ma = __ballot(app), mv = __ballot(valid);
+        if (lane == 0)
+            wsum[wave] = (uint32_t)__popcll(ma) | ((uint32_t)__popcll(mv) << 16);
+        __syncthreads();
+        uint32_t pa = 0, pv = 0, ta = 0, tv = 0;
+#pragma unroll
+        for (int w = 0; w < CT / WAVE; ++w) {
+            uint32_t x = wsum[w];
+            uint32_t xa = x & 0xffffu, xv = x >> 16;
+            if (w < wave) {
+                pa += xa;
+                pv += xv;
+            }
+            ta += xa;
+            tv += xv;
+        }
+        const uint32_t la = (uint32_t)__popcll(ma & lanemask_lt());
+        const uint32_t lv = (uint32_t)__popcll(mv & lanemask_lt());
+        if (app) {
+            uint64_t pos = run_a + pa + la;
+            app_tau[pos] = t;
+            app_sigma[pos] = col_cidx[i];
+        } else if (non) {
+            // rank among non-apparent = rank among valid - rank among apparent
+            uint64_t pos = run_n + (pv - pa) + (lv - la);
+            na_key[pos] = (uint64_t)(~diam_bits(col_diam[i]));
+            na_cidx[pos] = col_cidx[i];
+        }
+        run_a += ta;
+        run_n += tv - ta;
+        __syncthreads();
+    }
+}
+
+void launch_partition_count(const uint64_t *tau, int64_t ncols, uint32_t *tile_counts,
+                            hipStream_t s)
+{
+    int64_t tiles = compact_tiles(ncols);
+    if (tiles == 0)
+        return;
+    hipLaunchKernelGGL(k_partition_count, dim3((unsigned)tiles), dim3(CT), 0, s, tau, ncols,
+                       tile_counts);
+}
+
+void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
+                              const uint64_t *col_cidx, int64_t ncols,
+                              const uint64_t *tile_offsets, uint64_t *app_tau,
+                              uint64_t *app_sigma, uint64_t *na_key, uint64_t *na_cidx,
+                              hipStream_t s)
+{
+    int64_t tiles = compact_tiles(ncols);
+    if (tiles == 0)
+        return;
+    hipLaunchKernelGGL(k_partition_scatter, dim3((unsigned)tiles), dim3(CT), 0, s, tau,
+                       col_diam, col_cidx, ncols, tile_offsets, app_tau, app_sigma, na_key,
+                       na_cidx);
+}
+
+__global__ void k_desc_keys(const float *__restrict__ diam, int64_t count,
+                            uint64_t *__restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        keys[i] = (uint64_t)(~diam_bits(diam[i]));
+}
+
+void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_desc_keys, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       diam, count, keys);
+}
+
+// ===========================================================================
+// a7: clearing bitmap for the next dimension
+// ===========================================================================
+__global__ void k_mark_bits(const uint64_t *__restrict__ idx, int64_t count,
+                            uint32_t *__restrict__ bits)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        uint64_t t = idx[i];
+        atomicOr(&bits[t >> 5], 1u << (t & 31));
+    }
+}
+
+void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_mark_bits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, idx,
+                       count, bits);
+}
+
+// ===========================================================================
+// a2: H0 -- Kruskal in one workgroup
+//
+// Edges are visited in filtration order in batches of one per thread.  A
+// batch is settled in rounds: each unsettled thread finds the roots of its
+// endpoints; equal roots settle it as a non-tree edge.  Every root claimed
+// by several threads goes to the lowest thread (the oldest edge); a thread
+// that owns both its roots merges them and settles as a tree edge.  Winners
+// touch disjoint components that no older unsettled edge touches, so the
+// outcome equals sequential Kruskal under the strict (diameter, cidx)
+// order.
+// ===========================================================================
+constexpr int KT = 1024;
+
+__device__ __forceinline__ int uf_find(volatile int *parent, int x)
+{
+    while (true) {
+        int p = parent[x];
+        if (p == x)
+            return x;
+        int gp = parent[p];
+        if (gp != p)
+            parent[x] = gp;  // path halving: gp is an ancestor of x
+        x = gp;
+    }
+}
+
+template <bool IN_LDS>
+__global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edge_key,
+                                                const uint64_t *__restrict__ edge_cidx,
+                                                int64_t nedges, int n,
+                                                uint32_t *__restrict__ mst_bits,
+                                                float *__restrict__ deaths,
+                                                int *__restrict__ counters,
+                                                int *__restrict__ uf_scratch)
+{
+    extern __shared__ int smem[];
+    volatile int *parent = IN_LDS ? smem : uf_scratch;
+    int *owner = IN_LDS ? smem + n : uf_scratch + n;
+    __shared__ int s_merges, s_deaths;
+    const int tid = threadIdx.x;
+    for (int v = tid; v < n; v += KT) {
+        parent[v] = v;
+        owner[v] = INT_MAX;
+    }
+    if (tid == 0) {
+        s_merges = 0;
+        s_deaths = 0;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < nedges; base += KT) {
+        if (s_merges >= n - 1)
+            break;  // spanning tree complete: no later edge can merge
+        const int64_t k = base + tid;
+        bool active = k < nedges;
+        int a = 0, b = 0;
+        uint64_t c = 0;
+        float dm = 0.0f;
+        if (active) {
+            const int64_t idx = nedges - 1 - k;  // oldest first
+            c = edge_cidx[idx];
+            dm = __uint_as_float(~(uint32_t)edge_key[idx]);
+            decode_edge(c, a, b);
+        }
+        while (true) {
+            int ra = 0, rb = 0;
+            if (active) {
+                ra = uf_find(parent, a);
+                rb = uf_find(parent, b);
+                if (ra == rb)
+                    active = false;
+            }
+            if (!__syncthreads_or(active))
+                break;
+            if (active) {
+                atomicMin(&owner[ra], tid);
+                atomicMin(&owner[rb], tid);
+            }
+            __syncthreads();
+            const bool win = active && owner[ra] == tid && owner[rb] == tid;
+            __syncthreads();
+            if (active) {
+                owner[ra] = INT_MAX;
+                owner[rb] = INT_MAX;
+            }
+            if (win) {
+                parent[max(ra, rb)] = min(ra, rb);
+                atomicOr(&mst_bits[c >> 5], 1u << (c & 31));
+                if (dm > 0.0f)
+                    deaths[atomicAdd(&s_deaths, 1)] = dm;
+                atomicAdd(&s_merges, 1);
+                active = false;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        counters[0] = s_deaths;
+        counters[1] = s_merges;
+    }
+}
+
+void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
+                    uint32_t *mst_bits, float *deaths, int *counters, int *uf_scratch,
+                    hipStream_t s)
+{
+    const size_t lds = (size_t)2 * n * sizeof(int);
+    if (lds <= 60 * 1024) {
+        hipLaunchKernelGGL(k_kruskal<true>, dim3(1), dim3(KT), lds, s, edge_key, edge_cidx,
+                           nedges, n, mst_bits, deaths, counters, uf_scratch);
+    } else {
+        hipLaunchKernelGGL(k_kruskal<false>, dim3(1), dim3(KT), 0, s, edge_key, edge_cidx,
+                           nedges, n, mst_bits, deaths, counters, uf_scratch);
+    }
+}
+
+// ===========================================================================
+// a6: stable LSD radix sort, 8-bit digits
+//
+// Per pass: (1) per-tile digit histograms (LDS atomics), laid out
+// digit-major so that (2) one exclusive scan yields every tile's global
+// offset per digit; (3) each tile ranks its keys stably -- rounds of 256
+// keys in index order, ranks within a wave from 8 ballots (lanes with the
+// same digit), across waves from LDS counters -- stages the tile in LDS in
+// digit order and writes it out in runs.
+// ===========================================================================
+constexpr int RT = 256;
+constexpr int RI = 8;
+constexpr int RTILE = RT * RI;
+constexpr int RBINS = 256;
+
+int64_t radix_scratch_words(int64_t count)
+{
+    int64_t tiles = (count + RTILE - 1) / RTILE;
+    int64_t hist_words = (tiles * RBINS + 1) / 2 + 1;     // u32 histograms
+    int64_t off_words = tiles * RBINS + 1;                // u64 offsets
+    return hist_words + off_words + scan_scratch_words(tiles * RBINS) + 8;
+}
+
+__global__ __launch_bounds__(RT) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t count,
+                                                int shift, uint32_t *__restrict__ hist,
+                                                int64_t tiles)
+{
+    __shared__ uint32_t h[RBINS];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RTILE;
+#pragma unroll
+    for (int k = 0; k < RI; ++k) {
+        int64_t i = base + (int64_t)k * RT + threadIdx.x;
+        if (i < count)
+            atomicAdd(&h[(keys[i] >> shift) & (RBINS - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RT) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                   const uint64_t *__restrict__ vin,
+                                                   uint64_t *__restrict__ kout,
+                                                   uint64_t *__restrict__ vout, int64_t count,
+                                                   int shift,
+                                                   const uint64_t *__restrict__ offs,
+                                                   int64_t tiles)
+{
+    __shared__ uint64_t sk[RTILE];
+    __shared__ uint64_t sv[RTILE];
+    __shared__ uint32_t wcnt[RT / WAVE][RBINS];
+    __shared__ uint32_t run[RBINS];
+    __shared__ uint32_t loff[RBINS];
+    __shared__ uint32_t scan_sh[RT / WAVE + 1];
+
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * RTILE;
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < RT / WAVE; ++w)
+        wcnt[w][tid] = 0;
+    __syncthreads();
+
+    uint64_t key[RI], val[RI];
+    uint32_t rank[RI];
+    int dig[RI];
+#pragma unroll
+    for (int k = 0; k < RI; ++k) {
+        const int64_t i = base + (int64_t)k * RT + tid;
+        const bool valid = i < count;
+        key[k] = valid ? kin[i] : 0;
+        val[k] = valid ? vin[i] : 0;
+        const int d = valid ? (int)((key[k] >> shift) & (RBINS - 1)) : -1;
+        dig[k] = d;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = valid && ((d >> bit) & 1);
+            const uint64_t bb = __ballot(set);
+            peers &= set ? bb : ~bb;
+        }
+        const uint64_t below = peers & lanemask_lt();
+        if (valid && below == 0)
+            wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = run[d];
+            for (int w = 0; w < wave; ++w)
+                pre += wcnt[w][d];
+            rank[k] = pre + (uint32_t)__popcll(below);
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < RT / WAVE; ++w) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<RT>(run[tid], &total, scan_sh);
+    loff[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RI; ++k) {
+        if (dig[k] >= 0) {
+            const uint32_t pos = loff[dig[k]] + rank[k];
+            sk[pos] = key[k];
+            sv[pos] = val[k];
+        }
+    }
+    __syncthreads();
+    const int64_t cnt = (count - base < RTILE) ? (count - base) : RTILE;
+#pragma unroll
+    for (int k = 0; k < RI; ++k) {
+        const int j = k * RT + tid;
+        if (j < cnt) {
+            const uint64_t kk = sk[j];
+            const int d = (int)((kk >> shift) & (RBINS - 1));
+            const uint64_t g = offs[(int64_t)d * tiles + blockIdx.x] + (uint64_t)(j - loff[d]);
+            kout[g] = kk;
+            vout[g] = sv[j];
+        }
+    }
+}
+
+int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
+                     int64_t count, int bits, uint64_t *scratch, hipStream_t s)
+{
+    if (count <= 1 || bits <= 0)
+        return 0;
+    const int64_t tiles = (count + RTILE - 1) / RTILE;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(scratch);
+    const int64_t hist_words = (tiles * RBINS + 1) / 2 + 1;
+    uint64_t *offs = scratch + hist_words;
+    uint64_t *scan_tmp = offs + tiles * RBINS + 1;
+    uint64_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    int where = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RT), 0, s, ki, count, shift,
+                           hist, tiles);
+        launch_exclusive_scan(hist, tiles * RBINS, offs, scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(RT), 0, s, ki, vi, ko, vo,
+                           count, shift, offs, tiles);
+        uint64_t *t = ki;
+        ki = ko;
+        ko = t;
+        t = vi;
+        vi = vo;
+        vo = t;
+        where ^= 1;
+    }
+    return where;
+}
+
+}  // namespace rpp

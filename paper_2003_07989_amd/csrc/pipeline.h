@@ -1,0 +1,56 @@
+// pipeline.h -- host orchestration of one point cloud through the hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rpp.h"
+
+namespace rpp {
+
+// Per-dimension output gathered by the pipeline before it becomes an
+// rpp_result.
+struct DimOut {
+    std::vector<float> birth, death;     // bars, not yet sorted
+    std::vector<uint64_t> pair_sigma, pair_tau;  // only with RPP_WANT_PAIRS
+    rpp_dim_stats st{};
+};
+
+struct RunOut {
+    float thr_used = 0.0f;
+    float radius = 0.0f;
+    std::vector<DimOut> dims;
+};
+
+struct RunArgs {
+    const float *dcond_dev = nullptr;  // device condensed matrix
+    int n = 0;
+    int maxdim = 0;
+    float threshold = 0.0f;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    int apparent_group = 0;            // lanes per column, 0 = default
+    bool count_scans = false;          // tally cofacet candidates per column
+};
+
+// Returns an RPP_* code; on error `err` holds a message.
+int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);
+
+// Apparent pairs of dimension (p, p+1) over all p-simplices <= threshold.
+int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
+                      std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau,
+                      int64_t &ncols, std::string &err);
+
+// Exact binomial table C(v,k), k = 0..kmax, v = 0..n (saturating at
+// UINT64_MAX).
+std::vector<uint64_t> binomial_table(int n, int kmax);
+
+// C(n, k) with saturation.
+uint64_t binom_sat(int n, int k);
+
+size_t workspace_bytes(int n, int maxdim);
+
+}  // namespace rpp

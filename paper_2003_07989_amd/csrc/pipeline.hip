@@ -1,0 +1,624 @@
+// pipeline.hip -- one point cloud through the Vietoris-Rips hot path.
+//
+// Stage order per cloud (paper, overview of GPU-accelerated computation,
+// with H0 moved to the GPU):
+//   a1  square matrix + enclosing radius             (k_stage, k_min)
+//   a2  H0: edges <= threshold, radix sort, union-find (k_enum_*, sort, k_kruskal)
+//   for p = 1..maxdim:
+//   a3+a4 enumerate p-simplices in cidx order, threshold, clearing
+//   a5  apparent-pair test on every kept column
+//   a6  partition; sort non-apparent columns by (diameter desc, cidx asc)
+//       and apparent pairs by tau
+//   a7  host reduction of the non-apparent columns; clearing bitmap of
+//       dimension p+1 from all dimension-p pivots
+#include "kernels.h"
+#include "pipeline.h"
+#include "residual.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+
+namespace rpp {
+
+// ---------------------------------------------------------------------------
+// binomials
+// ---------------------------------------------------------------------------
+std::vector<uint64_t> binomial_table(int n, int kmax)
+{
+    std::vector<uint64_t> t((size_t)(kmax + 1) * (n + 1));
+    for (int v = 0; v <= n; ++v)
+        for (int k = 0; k <= kmax; ++k) {
+            uint64_t val;
+            if (k == 0)
+                val = 1;
+            else if (v == 0)
+                val = 0;
+            else {
+                uint64_t a = t[(size_t)(k - 1) * (n + 1) + v - 1];
+                uint64_t b = t[(size_t)k * (n + 1) + v - 1];
+                val = (a > UINT64_MAX - b) ? UINT64_MAX : a + b;
+            }
+            t[(size_t)k * (n + 1) + v] = val;
+        }
+    return t;
+}
+
+uint64_t binom_sat(int n, int k)
+{
+    if (k < 0 || k > n)
+        return 0;
+    std::vector<uint64_t> t = binomial_table(n, k);
+    return t[(size_t)k * (n + 1) + n];
+}
+
+static int bit_length(uint64_t x)
+{
+    return x ? 64 - __builtin_clzll(x) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// device workspace: grow-only buffers cached per device
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool ensure(size_t bytes)
+    {
+        if (bytes <= cap && p)
+            return true;
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t b = bytes < 256 ? 256 : bytes;
+        b = (b + 4095) & ~(size_t)4095;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        cap = b;
+        return true;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+struct HostBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool ensure(size_t bytes)
+    {
+        if (bytes <= cap && p)
+            return true;
+        if (p)
+            (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t b = bytes < 256 ? 256 : bytes;
+        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        cap = b;
+        return true;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+struct Workspace {
+    std::mutex mu;
+    DevBuf dsq, rowmax, scal, binom;
+    DevBuf ekey, eval, ekey2, eval2;  // edges for H0
+    DevBuf mst, deaths, ufs;
+    DevBuf tcount, toff, scan;
+    DevBuf cdiam, ccidx, tau;
+    DevBuf akey, aval, akey2, aval2;  // apparent pairs
+    DevBuf nkey, nval, nkey2, nval2;  // non-apparent columns
+    DevBuf clear, next, hostpiv;
+    DevBuf rscratch, scancnt;
+    HostBuf h_app_tau, h_app_sigma, h_na_key, h_na_cidx, h_small;
+    int binom_n = -1, binom_k = -1;
+    std::vector<uint64_t> binom_host;
+};
+
+static std::mutex g_ws_mu;
+static std::map<int, Workspace *> g_ws;
+
+static Workspace &workspace_for_current_device()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace *&w = g_ws[dev];
+    if (!w)
+        w = new Workspace();
+    return *w;
+}
+
+size_t workspace_bytes(int n, int maxdim)
+{
+    if (n < 2)
+        return 4096;
+    uint64_t E = binom_sat(n, 2);
+    uint64_t maxc = E;
+    for (int p = 2; p <= maxdim; ++p)
+        maxc = std::max(maxc, binom_sat(n, p + 1));
+    uint64_t maxbits = binom_sat(n, std::min(maxdim + 1, n) + 1);
+    size_t b = 0;
+    b += (size_t)n * n * 4 + (size_t)n * 4 * 4;
+    b += (size_t)E * 8 * 4;                 // edge keys / values, double buffered
+    b += (size_t)maxc * (4 + 8 + 8);        // kept columns + tau
+    b += (size_t)maxc * 8 * 4 * 2;          // partition outputs, double buffered
+    b += (size_t)(maxc / 32 + 1) * 4 * 2 + (size_t)(maxbits / 32 + 1) * 4;
+    b += (size_t)radix_scratch_words((int64_t)maxc) * 8 * 2;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// error helpers
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return RPP_E_DEVICE;                                                   \
+        }                                                                          \
+    } while (0)
+
+#define ALLOC_TRY(buf, bytes)                                                      \
+    do {                                                                           \
+        if (!(buf).ensure(bytes)) {                                                \
+            err = "allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
+            return RPP_E_NOMEM;                                                    \
+        }                                                                          \
+    } while (0)
+
+struct GpuTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit GpuTimer(hipStream_t st) : s(st)
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~GpuTimer()
+    {
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+    }
+    void start() { (void)hipEventRecord(a, s); }
+    void stop() { (void)hipEventRecord(b, s); }
+    float ms()
+    {
+        float m = 0.0f;
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&m, a, b);
+        return m;
+    }
+};
+
+// Stable compaction of the p-simplices (dense enumeration) into ws.cdiam /
+// ws.ccidx; returns the kept count through *kept and the counters.
+static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int64_t *kept,
+                           uint64_t *nthr, uint64_t *nclr, std::string &err,
+                           GpuTimer *tm = nullptr)
+{
+    const int64_t tiles = compact_tiles((int64_t)ea.ncand);
+    ALLOC_TRY(ws.tcount, (size_t)(tiles + 1) * 4);
+    ALLOC_TRY(ws.toff, (size_t)(tiles + 2) * 8);
+    ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(tiles) * 8);
+    ALLOC_TRY(ws.cdiam, (size_t)(ea.ncand + 1) * 4);
+    ALLOC_TRY(ws.ccidx, (size_t)(ea.ncand + 1) * 8);
+    ALLOC_TRY(ws.h_small, 256);
+    unsigned long long *stats = ws.scal.as<unsigned long long>() + 2;
+    HIP_TRY(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
+    if (tm)
+        tm->start();
+    launch_enum_count(ea, ws.tcount.as<uint32_t>(), stats, s);
+    launch_exclusive_scan(ws.tcount.as<uint32_t>(), tiles, ws.toff.as<uint64_t>(),
+                          ws.scan.as<uint64_t>(), s);
+    launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
+                        ws.ccidx.as<uint64_t>(), s);
+    if (tm)
+        tm->stop();
+    uint64_t *h = ws.h_small.as<uint64_t>();
+    HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 1, stats, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *kept = (int64_t)h[0];
+    *nthr = h[1];
+    *nclr = h[2];
+    return RPP_OK;
+}
+
+// Apparent test + partition of ws.cdiam/ccidx (ncols columns).  Results in
+// ws.akey/aval (tau, sigma), ws.nkey/nval (~bits(diam), cidx).
+static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, int group,
+                                  hipStream_t s, int64_t *napp, std::string &err,
+                                  GpuTimer *t_app = nullptr, GpuTimer *t_part = nullptr,
+                                  int64_t *scanned = nullptr)
+{
+    const int64_t tiles = compact_tiles(ncols);
+    ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.akey, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.aval, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.akey2, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.aval2, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.nkey, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.nval, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.nkey2, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.nval2, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.tcount, (size_t)(tiles + 1) * 4);
+    ALLOC_TRY(ws.toff, (size_t)(tiles + 2) * 8);
+    ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(tiles) * 8);
+    unsigned long long *sc = nullptr;
+    if (scanned) {
+        ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
+        sc = ws.scancnt.as<unsigned long long>();
+        HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+    }
+    if (t_app)
+        t_app->start();
+    launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols, ws.dsq.as<float>(), n,
+                    p, ws.binom.as<uint64_t>(), group, ws.tau.as<uint64_t>(), sc, s);
+    if (t_app)
+        t_app->stop();
+    if (t_part)
+        t_part->start();
+    launch_partition_count(ws.tau.as<uint64_t>(), ncols, ws.tcount.as<uint32_t>(), s);
+    launch_exclusive_scan(ws.tcount.as<uint32_t>(), tiles, ws.toff.as<uint64_t>(),
+                          ws.scan.as<uint64_t>(), s);
+    launch_partition_scatter(ws.tau.as<uint64_t>(), ws.cdiam.as<float>(),
+                             ws.ccidx.as<uint64_t>(), ncols, ws.toff.as<uint64_t>(),
+                             ws.akey.as<uint64_t>(), ws.aval.as<uint64_t>(),
+                             ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(), s);
+    if (t_part)
+        t_part->stop();
+    uint64_t *h = ws.h_small.as<uint64_t>();
+    HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *napp = ncols > 0 ? (int64_t)h[0] : 0;
+    if (scanned) {
+        std::vector<unsigned long long> c(SCAN_COUNTERS);
+        HIP_TRY(hipMemcpy(c.data(), sc, (size_t)SCAN_COUNTERS * 8, hipMemcpyDeviceToHost));
+        int64_t tot = 0;
+        for (unsigned long long x : c)
+            tot += (int64_t)x;
+        *scanned = tot;
+    }
+    return RPP_OK;
+}
+
+static int default_group(int p)
+{
+    (void)p;
+    return 8;
+}
+
+int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
+{
+    const int n = a.n, maxdim = a.maxdim;
+    hipStream_t s = a.stream;
+    out.dims.assign(maxdim + 1, DimOut());
+    if (n == 1) {
+        out.thr_used = a.threshold;
+        out.radius = 0.0f;
+        out.dims[0].birth.push_back(0.0f);
+        out.dims[0].death.push_back(INFINITY);
+        out.dims[0].st.n_simplices = 1;
+        out.dims[0].st.n_kept = 1;
+        out.dims[0].st.n_essential = 1;
+        out.dims[0].st.n_bars = 1;
+        return RPP_OK;
+    }
+    Workspace &ws = workspace_for_current_device();
+    std::lock_guard<std::mutex> lk(ws.mu);
+
+    const uint64_t E = (uint64_t)n * (n - 1) / 2;
+    ALLOC_TRY(ws.dsq, (size_t)n * n * 4);
+    ALLOC_TRY(ws.rowmax, (size_t)n * 4);
+    ALLOC_TRY(ws.scal, 256);
+    ALLOC_TRY(ws.h_small, 256);
+
+    // ---------------- a1: staging --------------------------------------
+    GpuTimer t0(s);
+    t0.start();
+    uint32_t *bad = ws.scal.as<uint32_t>();
+    float *radius = ws.scal.as<float>() + 1;
+    HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
+    launch_stage(a.dcond_dev, n, ws.dsq.as<float>(), ws.rowmax.as<float>(), bad, s);
+    launch_min(ws.rowmax.as<float>(), n, radius, s);
+    uint32_t *hs = ws.h_small.as<uint32_t>();
+    HIP_TRY(hipMemcpyAsync(hs, ws.scal.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs[0]) {
+        err = "distance matrix holds a NaN, infinite or negative entry";
+        return RPP_E_DATA;
+    }
+    float R;
+    memcpy(&R, hs + 1, 4);
+    out.radius = R;
+    float thr = a.threshold;
+    if (isinf(thr) && !(a.flags & RPP_NO_ENCLOSING_RADIUS))
+        thr = R;
+    out.thr_used = thr;
+
+    const int kmax = maxdim + 2;
+    if (ws.binom_n != n || ws.binom_k < kmax) {
+        ws.binom_host = binomial_table(n, kmax);
+        ALLOC_TRY(ws.binom, ws.binom_host.size() * 8);
+        HIP_TRY(hipMemcpyAsync(ws.binom.p, ws.binom_host.data(), ws.binom_host.size() * 8,
+                               hipMemcpyHostToDevice, s));
+        ws.binom_n = n;
+        ws.binom_k = kmax;
+    }
+    const int bstride = n + 1;
+    (void)bstride;
+
+    // host copy of the square matrix for the residual reduction
+    std::vector<float> h_dsq;
+    if (maxdim >= 1) {
+        h_dsq.resize((size_t)n * n);
+        HIP_TRY(hipMemcpyAsync(h_dsq.data(), ws.dsq.p, (size_t)n * n * 4,
+                               hipMemcpyDeviceToHost, s));
+    }
+
+    // ---------------- a2: H0 ---------------------------------------------
+    int64_t nedges = 0;
+    {
+        EnumArgs ea{a.dcond_dev, n, 1, thr, ws.binom.as<uint64_t>(), nullptr, E};
+        uint64_t nthr = 0, nclr = 0;
+        int rc = enumerate_dense(ws, ea, s, &nedges, &nthr, &nclr, err);
+        if (rc)
+            return rc;
+        ALLOC_TRY(ws.ekey, (size_t)(nedges + 1) * 8);
+        ALLOC_TRY(ws.eval, (size_t)(nedges + 1) * 8);
+        ALLOC_TRY(ws.ekey2, (size_t)(nedges + 1) * 8);
+        ALLOC_TRY(ws.eval2, (size_t)(nedges + 1) * 8);
+        ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(nedges) * 8);
+        ALLOC_TRY(ws.mst, (size_t)(E / 32 + 2) * 4);
+        ALLOC_TRY(ws.deaths, (size_t)n * 4);
+        ALLOC_TRY(ws.ufs, (size_t)2 * n * 4 + 64);
+        launch_desc_keys(ws.cdiam.as<float>(), nedges, ws.ekey.as<uint64_t>(), s);
+        HIP_TRY(hipMemcpyAsync(ws.eval.p, ws.ccidx.p, (size_t)nedges * 8,
+                               hipMemcpyDeviceToDevice, s));
+        int where = radix_sort_pairs(ws.ekey.as<uint64_t>(), ws.eval.as<uint64_t>(),
+                                     ws.ekey2.as<uint64_t>(), ws.eval2.as<uint64_t>(), nedges,
+                                     32, ws.rscratch.as<uint64_t>(), s);
+        const uint64_t *sk = where ? ws.ekey2.as<uint64_t>() : ws.ekey.as<uint64_t>();
+        const uint64_t *sv = where ? ws.eval2.as<uint64_t>() : ws.eval.as<uint64_t>();
+        launch_fill_u32(ws.mst.as<uint32_t>(), (int64_t)(E / 32 + 1), 0u, s);
+        int *counters = ws.scal.as<int>() + 8;
+        launch_kruskal(sk, sv, nedges, n, ws.mst.as<uint32_t>(), ws.deaths.as<float>(),
+                       counters, ws.ufs.as<int>(), s);
+        int hc[2];
+        HIP_TRY(hipMemcpyAsync(hc, counters, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        DimOut &d0 = out.dims[0];
+        d0.death.resize(hc[0]);
+        if (hc[0])
+            HIP_TRY(hipMemcpy(d0.death.data(), ws.deaths.p, (size_t)hc[0] * 4,
+                              hipMemcpyDeviceToHost));
+        d0.birth.assign(hc[0], 0.0f);
+        const int ncomp = n - hc[1];
+        for (int i = 0; i < ncomp; ++i) {
+            d0.birth.push_back(0.0f);
+            d0.death.push_back(INFINITY);
+        }
+        d0.st.n_candidates = n;
+        d0.st.n_simplices = n;
+        d0.st.n_kept = n;
+        d0.st.n_host_pairs = hc[1];
+        d0.st.n_essential = ncomp;
+        d0.st.n_bars = (int64_t)d0.birth.size();
+        t0.stop();
+        d0.st.ms_gpu = t0.ms();
+        if (a.flags & RPP_WANT_PAIRS) {
+            // dimension-0 pairs: the edge (tau) of every spanning-forest
+            // merge; the vertex side is not tracked (sigma = UINT64_MAX)
+            std::vector<uint32_t> bits((size_t)(E / 32 + 1));
+            HIP_TRY(hipMemcpy(bits.data(), ws.mst.p, bits.size() * 4, hipMemcpyDeviceToHost));
+            for (uint64_t c = 0; c < E; ++c)
+                if ((bits[c >> 5] >> (c & 31)) & 1u) {
+                    d0.pair_sigma.push_back(UINT64_MAX);
+                    d0.pair_tau.push_back(c);
+                }
+        }
+    }
+
+    // ---------------- dimensions 1..maxdim --------------------------------
+    // clearing set of the current dimension: p = 1 uses the MST bitmap
+    const uint32_t *clear_bits = ws.mst.as<uint32_t>();
+    for (int p = 1; p <= maxdim; ++p) {
+        DimOut &D = out.dims[p];
+        GpuTimer tg(s), t_enum(s), t_app(s), t_part(s), t_sort(s);
+        tg.start();
+        const uint64_t ncand = binom_sat(n, p + 1);
+        EnumArgs ea{a.dcond_dev, n, p, thr, ws.binom.as<uint64_t>(), clear_bits, ncand};
+        int64_t ncols = 0;
+        uint64_t nthr = 0, nclr = 0;
+        int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
+        if (rc)
+            return rc;
+        int64_t napp = 0, scanned = 0;
+        const int group = a.apparent_group > 0 ? a.apparent_group : default_group(p);
+        rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
+                                    a.count_scans ? &scanned : nullptr);
+        if (rc)
+            return rc;
+        t_sort.start();
+        const int64_t nna = ncols - napp;
+
+        // next dimension's clearing bitmap: apparent taus now, host taus later
+        const uint64_t nnext = (p < maxdim) ? binom_sat(n, p + 2) : 0;
+        if (p < maxdim) {
+            ALLOC_TRY(ws.next, (size_t)(nnext / 32 + 2) * 4);
+            launch_fill_u32(ws.next.as<uint32_t>(), (int64_t)(nnext / 32 + 1), 0u, s);
+            launch_mark_bits(ws.akey.as<uint64_t>(), napp, ws.next.as<uint32_t>(), s);
+        }
+        // a6: sorts
+        ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(std::max(napp, nna)) * 8);
+        int wn = radix_sort_pairs(ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(),
+                                  ws.nkey2.as<uint64_t>(), ws.nval2.as<uint64_t>(), nna, 32,
+                                  ws.rscratch.as<uint64_t>(), s);
+        const int tau_bits = bit_length(binom_sat(n, p + 2));
+        int wa = radix_sort_pairs(ws.akey.as<uint64_t>(), ws.aval.as<uint64_t>(),
+                                  ws.akey2.as<uint64_t>(), ws.aval2.as<uint64_t>(), napp,
+                                  tau_bits, ws.rscratch.as<uint64_t>(), s);
+        const uint64_t *d_nk = wn ? ws.nkey2.as<uint64_t>() : ws.nkey.as<uint64_t>();
+        const uint64_t *d_nv = wn ? ws.nval2.as<uint64_t>() : ws.nval.as<uint64_t>();
+        const uint64_t *d_at = wa ? ws.akey2.as<uint64_t>() : ws.akey.as<uint64_t>();
+        const uint64_t *d_as = wa ? ws.aval2.as<uint64_t>() : ws.aval.as<uint64_t>();
+        t_sort.stop();
+        // device -> host handoff
+        ALLOC_TRY(ws.h_na_key, (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_na_cidx, (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
+        ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
+        if (nna) {
+            HIP_TRY(hipMemcpyAsync(ws.h_na_key.p, d_nk, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_na_cidx.p, d_nv, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
+        }
+        if (napp) {
+            HIP_TRY(hipMemcpyAsync(ws.h_app_tau.p, d_at, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_app_sigma.p, d_as, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+        }
+        tg.stop();
+        HIP_TRY(hipStreamSynchronize(s));
+        D.st.ms_gpu = tg.ms();
+        D.st.ms_enumerate = t_enum.ms();
+        D.st.ms_apparent = t_app.ms();
+        D.st.ms_partition = t_part.ms();
+        D.st.ms_sort = t_sort.ms();
+        D.st.n_scanned = scanned;
+
+        // a7: host residual reduction
+        auto h0 = std::chrono::steady_clock::now();
+        ResidualProblem P;
+        P.n = n;
+        P.p = p;
+        P.thr = thr;
+        P.dsq = h_dsq.data();
+        P.binom = ws.binom_host.data();
+        P.ncols = nna;
+        P.col_key = ws.h_na_key.as<uint64_t>();
+        P.col_cidx = ws.h_na_cidx.as<uint64_t>();
+        P.napp = napp;
+        P.app_tau = ws.h_app_tau.as<uint64_t>();
+        P.app_sigma = ws.h_app_sigma.as<uint64_t>();
+        ResidualResult RR;
+        residual_reduce(P, RR);
+        auto h1 = std::chrono::steady_clock::now();
+        D.st.ms_host = std::chrono::duration<float, std::milli>(h1 - h0).count();
+
+        for (size_t i = 0; i < RR.sigma.size(); ++i)
+            if (RR.death[i] > RR.birth[i]) {
+                D.birth.push_back(RR.birth[i]);
+                D.death.push_back(RR.death[i]);
+            }
+        for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
+            D.birth.push_back(RR.ess_birth[i]);
+            D.death.push_back(INFINITY);
+        }
+        D.st.n_candidates = (int64_t)ncand;
+        D.st.n_thresholded = (int64_t)nthr;
+        D.st.n_cleared = (int64_t)nclr;
+        D.st.n_simplices = (int64_t)(ncand - nthr);
+        D.st.n_kept = ncols;
+        D.st.n_apparent = napp;
+        D.st.n_nonapparent = nna;
+        D.st.n_host_pairs = (int64_t)RR.sigma.size();
+        D.st.n_essential = (int64_t)RR.ess_sigma.size();
+        D.st.n_bars = (int64_t)D.birth.size();
+        D.st.n_column_adds = RR.additions;
+        if (a.flags & RPP_WANT_PAIRS) {
+            const uint64_t *at = ws.h_app_tau.as<uint64_t>();
+            const uint64_t *as = ws.h_app_sigma.as<uint64_t>();
+            D.pair_sigma.assign(as, as + napp);
+            D.pair_tau.assign(at, at + napp);
+            D.pair_sigma.insert(D.pair_sigma.end(), RR.sigma.begin(), RR.sigma.end());
+            D.pair_tau.insert(D.pair_tau.end(), RR.tau.begin(), RR.tau.end());
+        }
+
+        if (p < maxdim) {
+            const int64_t nh = (int64_t)RR.tau.size();
+            if (nh) {
+                ALLOC_TRY(ws.hostpiv, (size_t)nh * 8);
+                HIP_TRY(hipMemcpyAsync(ws.hostpiv.p, RR.tau.data(), (size_t)nh * 8,
+                                       hipMemcpyHostToDevice, s));
+                launch_mark_bits(ws.hostpiv.as<uint64_t>(), nh, ws.next.as<uint32_t>(), s);
+            }
+            std::swap(ws.clear, ws.next);
+            clear_bits = ws.clear.as<uint32_t>();
+            // the MST bitmap is no longer needed once p >= 1 has consumed it
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return RPP_OK;
+}
+
+int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
+                      std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau, int64_t &ncols,
+                      std::string &err)
+{
+    Workspace &ws = workspace_for_current_device();
+    std::lock_guard<std::mutex> lk(ws.mu);
+    ALLOC_TRY(ws.dsq, (size_t)n * n * 4);
+    ALLOC_TRY(ws.rowmax, (size_t)n * 4);
+    ALLOC_TRY(ws.scal, 256);
+    ALLOC_TRY(ws.h_small, 256);
+    uint32_t *bad = ws.scal.as<uint32_t>();
+    HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
+    launch_stage(dcond_dev, n, ws.dsq.as<float>(), ws.rowmax.as<float>(), bad, s);
+    uint32_t hb = 0;
+    HIP_TRY(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hb) {
+        err = "distance matrix holds a NaN, infinite or negative entry";
+        return RPP_E_DATA;
+    }
+    const int kmax = p + 2;
+    if (ws.binom_n != n || ws.binom_k < kmax) {
+        ws.binom_host = binomial_table(n, kmax);
+        ALLOC_TRY(ws.binom, ws.binom_host.size() * 8);
+        HIP_TRY(hipMemcpyAsync(ws.binom.p, ws.binom_host.data(), ws.binom_host.size() * 8,
+                               hipMemcpyHostToDevice, s));
+        ws.binom_n = n;
+        ws.binom_k = kmax;
+    }
+    const uint64_t ncand = binom_sat(n, p + 1);
+    EnumArgs ea{dcond_dev, n, p, threshold, ws.binom.as<uint64_t>(), nullptr, ncand};
+    uint64_t nthr = 0, nclr = 0;
+    int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err);
+    if (rc)
+        return rc;
+    int64_t napp = 0;
+    rc = apparent_and_partition(ws, ncols, n, p, default_group(p), s, &napp, err);
+    if (rc)
+        return rc;
+    sigma.resize(napp);
+    tau.resize(napp);
+    if (napp) {
+        HIP_TRY(hipMemcpyAsync(sigma.data(), ws.aval.p, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(tau.data(), ws.akey.p, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return RPP_OK;
+}
+
+}  // namespace rpp

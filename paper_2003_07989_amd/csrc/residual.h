@@ -1,0 +1,42 @@
+// residual.h -- host-side reduction of the non-apparent columns.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace rpp {
+
+// One dimension's leftover coboundary matrix, everything in host memory.
+struct ResidualProblem {
+    int n = 0;
+    int p = 0;                         // column dimension, >= 1
+    float thr = 0.0f;                  // inclusive threshold
+    const float *dsq = nullptr;        // n x n distances, zero diagonal
+    const uint64_t *binom = nullptr;   // C(v,k) at [k * (n+1) + v]
+    // non-apparent columns in coboundary order (diameter desc, cidx asc);
+    // key = ~bits(diameter) in the low 32 bits
+    int64_t ncols = 0;
+    const uint64_t *col_key = nullptr;
+    const uint64_t *col_cidx = nullptr;
+    // apparent pairs (tau, sigma) sorted by tau
+    int64_t napp = 0;
+    const uint64_t *app_tau = nullptr;
+    const uint64_t *app_sigma = nullptr;
+};
+
+struct ResidualResult {
+    std::vector<uint64_t> sigma, tau;  // pairs found by the reduction
+    std::vector<float> birth, death;
+    std::vector<uint64_t> ess_sigma;   // columns reduced to zero
+    std::vector<float> ess_birth;
+    int64_t additions = 0;
+    int64_t lookups_hash = 0, lookups_apparent = 0;
+};
+
+// Oblivious column reduction (paper, Algorithm 2) of every column, in order,
+// with the two-layer pivot store (hash map of pivots found here first, then
+// binary search in the apparent-pair array).
+void residual_reduce(const ResidualProblem &P, ResidualResult &R);
+
+}  // namespace rpp

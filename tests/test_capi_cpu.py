@@ -1,0 +1,105 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/rpp.h declares, and rejects bad arguments before any device
+work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2003_07989_amd as rpp
+from paper_2003_07989_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "rpp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("rpp_barcodes", "rpp_barcodes_device", "rpp_workspace_bytes",
+                 "rpp_apparent_pairs", "rpp_result_free", "rpp_strerror",
+                 "rpp_last_error", "rpp_version"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rpp.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_strings():
+    assert "gfx950" in rpp.version()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert rpp.strerror(code)
+    assert rpp.strerror(-99) == "unknown error"
+
+
+def _call(dist, n, maxdim, thr):
+    lib = rpp.load()
+    out = ctypes.POINTER(B._Result)()
+    ptr = dist.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if dist is not None else None
+    rc = lib.rpp_barcodes(ptr, n, maxdim, ctypes.c_float(thr), ctypes.byref(out))
+    if rc == 0:
+        lib.rpp_result_free(out)
+    else:
+        assert not bool(out), "out must stay NULL on error"
+    return rc
+
+
+@pytest.mark.parametrize("n,maxdim,thr,code", [
+    (0, 1, math.inf, -1),
+    (-3, 1, math.inf, -1),
+    (4, -1, math.inf, -1),
+    (4, 5, math.inf, -1),
+    (4, 1, float("nan"), -1),
+    (4, 1, -0.5, -1),
+])
+def test_invalid_arguments(n, maxdim, thr, code):
+    d = np.ones(max(n, 2) * (max(n, 2) - 1) // 2, np.float32)
+    assert _call(d, n, maxdim, thr) == code
+    assert rpp.load().rpp_last_error()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -1.0])
+def test_bad_distance_entries_are_rejected_on_the_host(bad):
+    d = np.ones(10, np.float32)
+    d[3] = bad
+    assert _call(d, 5, 1, math.inf) == -2
+
+
+def test_null_distance_pointer():
+    assert _call(None, 5, 1, math.inf) == -1
+
+
+def test_index_range_error():
+    # C(n, maxdim+2) beyond 2^63 for n = 60000, maxdim 4 is fine (< 2^63?)
+    # use a case that certainly overflows: n = 40000, maxdim = 4 ->
+    # C(40000, 6) ~ 5.7e24
+    lib = rpp.load()
+    out = ctypes.POINTER(B._Result)()
+    dummy = np.zeros(1, np.float32)
+    rc = lib.rpp_barcodes(dummy.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 40000, 4,
+                          ctypes.c_float(math.inf), ctypes.byref(out))
+    assert rc == -3
+
+
+def test_single_point_needs_no_device():
+    r = rpp.barcodes_host(np.zeros(0, np.float32), 2, n=1)
+    assert r.bars[0][0].tolist() == [0.0]
+    assert r.bars[0][1].tolist() == [math.inf]
+    assert all(len(b[0]) == 0 for b in r.bars[1:])
+
+
+def test_workspace_bound_grows_with_size():
+    a = rpp.workspace_bytes(100, 1)
+    b = rpp.workspace_bytes(400, 2)
+    assert 0 < a < b
+    assert rpp.workspace_bytes(0, 1) == 0

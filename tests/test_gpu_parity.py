@@ -1,0 +1,222 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Barcodes are compared bit for bit: every birth and death is an entry of the
+FP32 distance matrix, never the result of arithmetic, so the tolerance is
+zero.  Persistence pairs are compared as exact sets of combinatorial
+indices.  The apparent-pair kernel is also compared with the literal
+definition, and with the exact counts of the paper's Theorem 1
+constructions.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def rpp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_07989_amd as m
+    m.load()
+    return m
+
+
+def assert_bars_equal(got, exp, label=""):
+    assert len(got) == len(exp), label
+    for p, ((gb, gd), (eb, ed)) in enumerate(zip(got, exp)):
+        ok = (len(gb) == len(eb) and np.array_equal(gb.view(np.uint32), eb.view(np.uint32))
+              and np.array_equal(gd.view(np.uint32), ed.view(np.uint32)))
+        if not ok:
+            msg = "%s dim %d: %d bars vs oracle %d\n gpu %s\n ora %s" % (
+                label, p, len(gb), len(eb), list(zip(gb[:8], gd[:8])), list(zip(eb[:8], ed[:8])))
+            raise AssertionError(msg)
+
+
+def _cases():
+    c = []
+    for n in (5, 8, 12, 20, 33):
+        c.append(("square%d" % n, w.condensed_from_points(w.uniform_square_points(n, 10 + n)),
+                  n, 3 if n <= 12 else 2, math.inf))
+    for n in (48, 64):
+        c.append(("square%d" % n, w.condensed_from_points(w.uniform_square_points(n, 10 + n)),
+                  n, 2, math.inf))
+    for n in (30, 60):
+        c.append(("torus%d" % n, w.condensed_from_points(w.noisy_torus_points(n, 20 + n)),
+                  n, 2, math.inf))
+    for n, vmax in ((8, 2), (16, 3), (30, 5), (45, 4)):
+        c.append(("int%d_%d" % (n, vmax), w.random_integer_metric(n, 30 + n, vmax), n,
+                  3 if n <= 16 else 2, math.inf))
+    c.append(("equal20", w.all_equal_metric(20), 20, 3, math.inf))
+    c.append(("revlex40", w.reverse_lex_metric(40), 40, 2, math.inf))
+    for n in (9, 12, 30):
+        c.append(("cycle%d" % n, w.cycle_graph_metric(n), n, 2, math.inf))
+    c.append(("perm50", w.random_permutation_metric(50, 5), 50, 2, math.inf))
+    # thresholded cases
+    for n, q in ((25, 0.3), (40, 0.5), (64, 0.25)):
+        d = w.condensed_from_points(w.uniform_square_points(n, 40 + n))
+        c.append(("square%d_q%g" % (n, q), d, n, 2, float(np.quantile(d, q))))
+    d = w.random_integer_metric(30, 77, 6)
+    c.append(("int30_thr3", d, 30, 2, 3.0))
+    d = w.condensed_from_points(w.uniform_square_points(40, 91))
+    c.append(("square40_R", d, 40, 2, oracle.enclosing_radius(d, 40)))
+    return c
+
+
+CASES = _cases()
+
+
+def _oracle_bars(d, n, maxdim, thr):
+    return oracle.barcodes(d, n, maxdim, thr, clearing=n > 33)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_barcodes_match_oracle(rpp, case):
+    name, d, n, maxdim, thr = case
+    print("case", name, n, maxdim, thr, flush=True)
+    got = rpp.barcodes(d, maxdim, thr)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+
+
+@pytest.mark.parametrize("case", CASES[:14], ids=[c[0] for c in CASES[:14]])
+def test_pairs_match_oracle(rpp, case):
+    """Apparent pairs (GPU) plus host pairs == the oracle's pivots, as exact
+    (sigma, tau) sets, with the threshold as given (no radius truncation)."""
+    name, d, n, maxdim, thr = case
+    print("case", name, flush=True)
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS)
+    red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+    assert set(got.pairs[0][1].tolist()) == set(red[0]["tau"].tolist())
+    for p in range(1, maxdim + 1):
+        gs = set(zip(got.pairs[p][0].tolist(), got.pairs[p][1].tolist()))
+        es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+        assert gs == es, (name, p, len(gs), len(es))
+
+
+@pytest.mark.parametrize("case", CASES[:10], ids=[c[0] for c in CASES[:10]])
+def test_stats_accounting(rpp, case):
+    """Filter accounting (candidates = thresholded + cleared + kept), the
+    partition (kept = apparent + non-apparent) and the pair identity
+    n_p = P_p + E_p + P_{p-1}."""
+    name, d, n, maxdim, thr = case
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_NO_ENCLOSING_RADIUS)
+    prev_pairs = 0
+    for p, st in enumerate(got.stats):
+        if p >= 1:
+            assert st["n_candidates"] == st["n_thresholded"] + st["n_cleared"] + st["n_kept"]
+            assert st["n_kept"] == st["n_apparent"] + st["n_nonapparent"]
+            assert st["n_cleared"] == prev_pairs
+            assert st["n_simplices"] == oracle.count_simplices(d, n, p, thr)
+        pairs = st["n_apparent"] + st["n_host_pairs"]
+        assert st["n_simplices"] == pairs + st["n_essential"] + prev_pairs
+        prev_pairs = pairs
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("case", range(6))
+def test_apparent_kernel_matches_definition(rpp, p, case):
+    n = (7, 10, 14, 18, 12, 16)[case]
+    if case % 2:
+        d = w.random_integer_metric(n, 600 + case, 2 + case % 3)
+    else:
+        d = w.condensed_from_points(w.uniform_square_points(n, 700 + case))
+    thr = math.inf if case < 4 else float(np.quantile(d, 0.6))
+    s, t, ncols = rpp.apparent_pairs(d, p, thr)
+    es, et = oracle.apparent_pairs(d, n, p, thr)
+    assert ncols == oracle.count_simplices(d, n, p, thr)
+    assert set(zip(s.tolist(), t.tolist())) == set(zip(es.tolist(), et.tolist()))
+
+
+@pytest.mark.parametrize("n,p", [(60, 1), (60, 2), (30, 3), (400, 1), (100, 2)])
+def test_theorem1_upper_bound_all_equal_on_gpu(rpp, n, p):
+    s, _, ncols = rpp.apparent_pairs(w.all_equal_metric(n), p)
+    assert ncols == math.comb(n, p + 1)
+    assert len(s) == math.comb(n - 1, p + 1)
+
+
+@pytest.mark.parametrize("n", [5, 50, 300, 1000])
+def test_theorem1_distinct_diameters_on_gpu(rpp, n):
+    s, _, _ = rpp.apparent_pairs(w.reverse_lex_metric(n), 1)
+    assert len(s) == math.comb(n - 1, 2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_theorem1_lower_bound_on_gpu(rpp, p):
+    s, t, _ = rpp.apparent_pairs(w.random_permutation_metric(p + 2, 3), p)
+    assert len(s) == 1 and int(t[0]) == 0
+
+
+def test_group_sizes_agree(rpp, monkeypatch):
+    d = w.condensed_from_points(w.noisy_torus_points(80, 5))
+    ref = None
+    for g in (1, 4, 8, 16, 32, 64):
+        monkeypatch.setenv("RPP_APPARENT_GROUP", str(g))
+        r = rpp.barcodes(d, 2, flags=rpp.RPP_WANT_PAIRS)
+        key = [set(zip(a.tolist(), b.tolist())) for a, b in r.pairs[1:]]
+        if ref is None:
+            ref = key
+        assert key == ref, g
+
+
+def test_repeat_runs_are_bitwise_identical(rpp):
+    d = w.condensed_from_points(w.noisy_torus_points(120, 9))
+    a = rpp.barcodes(d, 2)
+    b = rpp.barcodes(d, 2)
+    assert_bars_equal(a.bars, b.bars)
+
+
+def test_host_entry_point_matches_device_entry_point(rpp):
+    d = w.condensed_from_points(w.uniform_square_points(50, 3))
+    assert_bars_equal(rpp.barcodes_host(d, 2).bars, rpp.barcodes(d, 2).bars)
+
+
+def test_device_validation_rejects_bad_entries(rpp):
+    d = w.condensed_from_points(w.uniform_square_points(20, 3))
+    d[17] = np.nan
+    with pytest.raises(rpp.RppError) as e:
+        rpp.barcodes(d, 1)
+    assert e.value.code == -2
+
+
+def test_enclosing_radius_reported(rpp):
+    d = w.condensed_from_points(w.uniform_square_points(40, 8))
+    r = rpp.barcodes(d, 1)
+    assert r.enclosing_radius == np.float32(oracle.enclosing_radius(d, 40))
+    assert r.threshold_used == r.enclosing_radius
+
+
+def test_uniform_square_32_matches_oracle(rpp):
+    """32 points i.i.d. uniform in [0,1]^2, dims 0-1, no threshold."""
+    cfg = w.WORKLOADS["square32"]
+    d = cfg["build"]()
+    got = rpp.barcodes(d, cfg["maxdim"], cfg["threshold"])
+    assert_bars_equal(got.bars, oracle.barcodes(d, 32, 1), "square32")
+
+
+def test_torus400_matches_stored_oracle(rpp):
+    """400-point noisy torus, dims 0-2, no threshold: against the oracle's
+    barcodes stored by tests/golden/make_golden.py."""
+    import importlib.util
+    path = os.path.join(GOLDEN, "torus400.bars.txt")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    head, exp = mg.read(path)
+    cfg = w.WORKLOADS["torus400"]
+    d = cfg["build"]()
+    import hashlib
+    assert hashlib.sha256(d.tobytes()).hexdigest() == head["sha256"], "input generator drifted"
+    got = rpp.barcodes(d, cfg["maxdim"], cfg["threshold"])
+    assert_bars_equal(got.bars, exp, "torus400")
+    for p in range(1, 3):
+        st = got.stats[p]
+        assert st["n_apparent"] + st["n_host_pairs"] > 0
