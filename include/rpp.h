@@ -65,6 +65,12 @@ enum {
 /* flags for rpp_barcodes_device */
 #define RPP_NO_ENCLOSING_RADIUS 0x1u /* use the threshold as given, even if +inf */
 #define RPP_WANT_PAIRS 0x2u          /* also return every persistence pair */
+/* Keep the apparent pairs as an array sorted by tau, copied to the host and
+ * binary-searched by the host reduction (the paper's two-layer store).
+ * Default: the host decides whether a row is an apparent pivot by
+ * recomputing the apparent-pair condition from the distance matrix, so the
+ * apparent pairs are neither sorted nor copied.  Results are identical. */
+#define RPP_SORTED_PAIR_STORE 0x4u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:

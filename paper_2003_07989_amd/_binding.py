@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librpp.so")
 RPP_MAX_DIM = 4
 RPP_NO_ENCLOSING_RADIUS = 0x1
 RPP_WANT_PAIRS = 0x2
+RPP_SORTED_PAIR_STORE = 0x4
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
           -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE"}

@@ -73,6 +73,15 @@ void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
 // key[i] = ~bits(diam[i]) (descending-diameter radix key).
 void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s);
 
+// ---- a7: host handoff -------------------------------------------------------
+// For every non-apparent column (key = ~bits(diameter), cidx): its oldest
+// cofacet inside the threshold, i.e. the low of the unreduced coboundary
+// column (smallest diameter, then largest cidx), or ~0 when the coboundary
+// is empty.  One wave per column.
+void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
+                 const float *dsq, int n, int p, float thr, const uint64_t *binom,
+                 uint64_t *low_out, float *low_diam_out, hipStream_t s);
+
 // ---- a7: clearing bitmap ---------------------------------------------------
 void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s);
 

@@ -647,6 +647,80 @@ void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStrea
 }
 
 // ===========================================================================
+// a7: low of every non-apparent column, for the host reduction
+// ===========================================================================
+template <int P>
+__global__ __launch_bounds__(256) void k_lows(const uint64_t *__restrict__ na_key,
+                                              const uint64_t *__restrict__ na_cidx,
+                                              int64_t ncols, const float *__restrict__ dsq,
+                                              int n, float thr,
+                                              const uint64_t *__restrict__ binom,
+                                              uint64_t *__restrict__ low_out,
+                                              float *__restrict__ low_diam_out)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (col >= ncols)
+        return;  // whole waves leave together
+    const Binom B{binom, n + 1};
+    const float d = __uint_as_float(~(uint32_t)na_key[col]);
+    int v[P + 1];
+    decode<P>(B, na_cidx[col], n, v);
+    const float *row[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        row[i] = dsq + (int64_t)v[i] * n;
+    float best = INFINITY;
+    int bw = -1;
+    for (int base = 0; base < n; base += WAVE) {
+        const int w = base + lane;
+        if (w >= n)
+            break;
+        bool ok = true;
+        float m = d;
+#pragma unroll
+        for (int i = 0; i <= P; ++i) {
+            const float e = row[i][w];
+            ok = ok && (w != v[i]) && (e <= thr);
+            m = fmaxf(m, e);
+        }
+        // later w wins ties: larger w gives the larger cofacet cidx
+        if (ok && m <= best) {
+            best = m;
+            bw = w;
+        }
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o, WAVE);
+        const int ow = __shfl_xor(bw, o, WAVE);
+        if (ob < best || (ob == best && ow > bw)) {
+            best = ob;
+            bw = ow;
+        }
+    }
+    if (lane == 0) {
+        low_out[col] = bw >= 0 ? cofacet_index<P>(B, v, bw) : NONE;
+        low_diam_out[col] = best;
+    }
+}
+
+void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
+                 const float *dsq, int n, int p, float thr, const uint64_t *binom,
+                 uint64_t *low_out, float *low_diam_out, hipStream_t s)
+{
+    if (ncols <= 0)
+        return;
+    dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_lows<1>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
+    case 2: hipLaunchKernelGGL(k_lows<2>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
+    case 3: hipLaunchKernelGGL(k_lows<3>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
+    default: hipLaunchKernelGGL(k_lows<4>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
+    }
+}
+
+// ===========================================================================
 // a7: clearing bitmap for the next dimension
 // ===========================================================================
 __global__ void k_mark_bits(const uint64_t *__restrict__ idx, int64_t count,

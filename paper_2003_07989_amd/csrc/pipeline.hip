@@ -127,8 +127,9 @@ struct Workspace {
     DevBuf akey, aval, akey2, aval2;  // apparent pairs
     DevBuf nkey, nval, nkey2, nval2;  // non-apparent columns
     DevBuf clear, next, hostpiv;
+    DevBuf lowc, lowd;               // lows of the non-apparent columns
     DevBuf rscratch, scancnt;
-    HostBuf h_app_tau, h_app_sigma, h_na_key, h_na_cidx, h_small;
+    HostBuf h_app_tau, h_app_sigma, h_na_key, h_na_cidx, h_low, h_lowd, h_small;
     int binom_n = -1, binom_k = -1;
     std::vector<uint64_t> binom_host;
 };
@@ -471,30 +472,48 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             launch_fill_u32(ws.next.as<uint32_t>(), (int64_t)(nnext / 32 + 1), 0u, s);
             launch_mark_bits(ws.akey.as<uint64_t>(), napp, ws.next.as<uint32_t>(), s);
         }
-        // a6: sorts
-        ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(std::max(napp, nna)) * 8);
+        // a6: sort the non-apparent columns into coboundary order (the
+        // partition kept them in cidx order, so a stable sort on the
+        // descending-diameter key yields diameter desc, cidx asc)
+        const bool sorted_store = (a.flags & RPP_SORTED_PAIR_STORE) != 0;
+        const bool want_pairs = (a.flags & RPP_WANT_PAIRS) != 0;
+        ALLOC_TRY(ws.rscratch,
+                  (size_t)radix_scratch_words(sorted_store ? std::max(napp, nna) : nna) * 8);
         int wn = radix_sort_pairs(ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(),
                                   ws.nkey2.as<uint64_t>(), ws.nval2.as<uint64_t>(), nna, 32,
                                   ws.rscratch.as<uint64_t>(), s);
-        const int tau_bits = bit_length(binom_sat(n, p + 2));
-        int wa = radix_sort_pairs(ws.akey.as<uint64_t>(), ws.aval.as<uint64_t>(),
-                                  ws.akey2.as<uint64_t>(), ws.aval2.as<uint64_t>(), napp,
-                                  tau_bits, ws.rscratch.as<uint64_t>(), s);
         const uint64_t *d_nk = wn ? ws.nkey2.as<uint64_t>() : ws.nkey.as<uint64_t>();
         const uint64_t *d_nv = wn ? ws.nval2.as<uint64_t>() : ws.nval.as<uint64_t>();
-        const uint64_t *d_at = wa ? ws.akey2.as<uint64_t>() : ws.akey.as<uint64_t>();
-        const uint64_t *d_as = wa ? ws.aval2.as<uint64_t>() : ws.aval.as<uint64_t>();
+        const uint64_t *d_at = ws.akey.as<uint64_t>();
+        const uint64_t *d_as = ws.aval.as<uint64_t>();
+        if (sorted_store) {
+            const int tau_bits = bit_length(binom_sat(n, p + 2));
+            int wa = radix_sort_pairs(ws.akey.as<uint64_t>(), ws.aval.as<uint64_t>(),
+                                      ws.akey2.as<uint64_t>(), ws.aval2.as<uint64_t>(), napp,
+                                      tau_bits, ws.rscratch.as<uint64_t>(), s);
+            d_at = wa ? ws.akey2.as<uint64_t>() : ws.akey.as<uint64_t>();
+            d_as = wa ? ws.aval2.as<uint64_t>() : ws.aval.as<uint64_t>();
+        }
         t_sort.stop();
+        // a7: lows of the non-apparent columns for the host reduction
+        ALLOC_TRY(ws.lowc, (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.lowd, (size_t)(nna + 1) * 4);
+        launch_lows(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, thr, ws.binom.as<uint64_t>(),
+                    ws.lowc.as<uint64_t>(), ws.lowd.as<float>(), s);
         // device -> host handoff
         ALLOC_TRY(ws.h_na_key, (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_na_cidx, (size_t)(nna + 1) * 8);
-        ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
-        ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
+        ALLOC_TRY(ws.h_low, (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_lowd, (size_t)(nna + 1) * 4);
         if (nna) {
             HIP_TRY(hipMemcpyAsync(ws.h_na_key.p, d_nk, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(ws.h_na_cidx.p, d_nv, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_low.p, ws.lowc.p, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_lowd.p, ws.lowd.p, (size_t)nna * 4, hipMemcpyDeviceToHost, s));
         }
-        if (napp) {
+        if ((sorted_store || want_pairs) && napp) {
+            ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
+            ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
             HIP_TRY(hipMemcpyAsync(ws.h_app_tau.p, d_at, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(ws.h_app_sigma.p, d_as, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
         }
@@ -518,9 +537,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         P.ncols = nna;
         P.col_key = ws.h_na_key.as<uint64_t>();
         P.col_cidx = ws.h_na_cidx.as<uint64_t>();
+        P.col_low = ws.h_low.as<uint64_t>();
+        P.col_low_diam = ws.h_lowd.as<float>();
         P.napp = napp;
-        P.app_tau = ws.h_app_tau.as<uint64_t>();
-        P.app_sigma = ws.h_app_sigma.as<uint64_t>();
+        P.app_tau = sorted_store ? ws.h_app_tau.as<uint64_t>() : nullptr;
+        P.app_sigma = sorted_store ? ws.h_app_sigma.as<uint64_t>() : nullptr;
         ResidualResult RR;
         residual_reduce(P, RR);
         auto h1 = std::chrono::steady_clock::now();

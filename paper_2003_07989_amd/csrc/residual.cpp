@@ -1,10 +1,13 @@
 // residual.cpp -- host reduction of the columns the GPU could not pair.
 //
 // Paper, "Reduction Matrix vs. Oblivious Matrix Reduction" (Algorithm 2)
-// and "Core System Optimizations" (two-layer pair store).  Each column's
+// and "Core System Optimizations" (two-layer pair store).  Columns arrive in
+// coboundary order together with their lows (oldest cofacets), computed on
+// the GPU.  A column whose low is not yet a pivot is paired at once, with no
+// coboundary built (its unreduced column is already reduced).  Otherwise its
 // coboundary is regenerated from the distance matrix (implicit matrix
-// reduction) into a binary heap ordered oldest-first, so the heap top is
-// the column's low.  Z/2 addition pushes the other column's entries; equal
+// reduction) into a binary heap ordered oldest-first, so the heap top is the
+// column's low; Z/2 addition pushes the other column's entries, and equal
 // entries cancel in pairs when the low is taken.
 #include "residual.h"
 
@@ -31,56 +34,101 @@ struct YoungerFirst {
     }
 };
 
+// Working column = Z/2 sum of several coboundaries.  Each added coboundary
+// is kept as its own small heap (a "stream", built in linear time); a heap
+// over the streams' current tops yields the sum's entries oldest-first.
+// Only the entries that reach the top are ever ordered, which is what
+// finding the low needs.
 class Column {
 public:
-    std::vector<Entry> heap;
-    void clear() { heap.clear(); }
-    void push(const Entry &e)
+    void clear()
     {
-        heap.push_back(e);
-        std::push_heap(heap.begin(), heap.end(), YoungerFirst());
+        nstreams = 0;
+        top.clear();
     }
-    Entry pop()
+    void add(const std::vector<Entry> &batch)
     {
-        std::pop_heap(heap.begin(), heap.end(), YoungerFirst());
-        Entry e = heap.back();
-        heap.pop_back();
-        return e;
+        if (batch.empty())
+            return;
+        if (nstreams == streams.size())
+            streams.emplace_back();
+        std::vector<Entry> &h = streams[nstreams];
+        h.assign(batch.begin(), batch.end());
+        std::make_heap(h.begin(), h.end(), YoungerFirst());
+        top_push(h.front(), (uint32_t)nstreams);
+        ++nstreams;
     }
-    // Low of the column over Z/2: drop entries that occur an even number of
-    // times at the top; leave the surviving low in the heap.
+    // Low of the sum over Z/2: entries present in an even number of
+    // streams cancel; the surviving low stays in its stream.
     bool low(Entry &out)
     {
-        while (!heap.empty()) {
-            Entry e = pop();
-            int cnt = 1;
-            while (!heap.empty() && heap.front().cidx == e.cidx) {
-                pop();
-                ++cnt;
+        while (!top.empty()) {
+            const Entry e = top.front().e;
+            hits.clear();
+            while (!top.empty() && top.front().e.cidx == e.cidx) {
+                hits.push_back(top.front().s);
+                top_pop();
             }
-            if (cnt & 1) {
-                push(e);
+            const size_t keep = (hits.size() & 1) ? 1 : 0;
+            for (size_t i = 0; i < hits.size(); ++i) {
+                const uint32_t k = hits[i];
+                if (i < keep) {
+                    top_push(e, k);  // the surviving copy stays put
+                    continue;
+                }
+                std::vector<Entry> &h = streams[k];
+                std::pop_heap(h.begin(), h.end(), YoungerFirst());
+                h.pop_back();
+                if (!h.empty())
+                    top_push(h.front(), k);
+            }
+            if (keep) {
                 out = e;
                 return true;
             }
         }
         return false;
     }
+
+private:
+    struct Top {
+        Entry e;
+        uint32_t s;
+    };
+    struct TopYounger {
+        bool operator()(const Top &a, const Top &b) const { return YoungerFirst()(a.e, b.e); }
+    };
+    void top_push(const Entry &e, uint32_t k)
+    {
+        top.push_back(Top{e, k});
+        std::push_heap(top.begin(), top.end(), TopYounger());
+    }
+    void top_pop()
+    {
+        std::pop_heap(top.begin(), top.end(), TopYounger());
+        top.pop_back();
+    }
+    std::vector<std::vector<Entry>> streams;
+    size_t nstreams = 0;
+    std::vector<Top> top;
+    std::vector<uint32_t> hits;
 };
 
 struct Ctx {
     const ResidualProblem &P;
     int n, p;
+    std::vector<Entry> scratch;
     explicit Ctx(const ResidualProblem &pp) : P(pp), n(pp.n), p(pp.p) {}
 
     uint64_t C(int v, int k) const { return P.binom[(int64_t)k * (n + 1) + v]; }
     float D(int a, int b) const { return P.dsq[(int64_t)a * n + b]; }
 
-    void decode(uint64_t c, int *v) const
+    // vertices of a simplex with q+1 vertices, decreasing
+    void decode(uint64_t c, int q, int *v) const
     {
         int hi = n;
-        for (int pos = 0; pos <= p; ++pos) {
-            const int k = p + 1 - pos;
+        for (int pos = 0; pos <= q; ++pos) {
+            const int k = q + 1 - pos;
             int lo = k - 1, h = hi - 1;
             while (lo < h) {
                 int mid = (lo + h + 1) >> 1;
@@ -95,21 +143,24 @@ struct Ctx {
         }
     }
 
-    // Push every cofacet of sigma with diameter <= threshold.
-    void push_coboundary(uint64_t sigma, float d, Column &col) const
+    // Every cofacet of sigma with diameter <= threshold.
+    const std::vector<Entry> &coboundary(uint64_t sigma, float d)
     {
+        scratch.clear();
         int v[8];
-        decode(sigma, v);
+        decode(sigma, p, v);
+        const float *rows[8];
+        for (int i = 0; i <= p; ++i)
+            rows[i] = P.dsq + (int64_t)v[i] * n;
         // cidx of sigma + {w}: vertices above w move up one rank.  Scan w
         // downward, keeping the two partial sums of the CNS formula.
-        uint64_t above = 0;  // sum over v_i > w of C(v_i, rank+2)
-        uint64_t below = sigma;  // sum over v_i < w of C(v_i, rank+1)
-        int j = p + 1;       // number of sigma's vertices below w
-        int nxt = 0;         // index (in v) of the next vertex at or below w
+        uint64_t above = 0;       // sum over v_i > w of C(v_i, rank+2)
+        uint64_t below = sigma;   // sum over v_i < w of C(v_i, rank+1)
+        int j = p + 1;            // number of sigma's vertices below w
+        int nxt = 0;              // index (in v) of the next vertex at or below w
         for (int w = n - 1; w >= 0; --w) {
             if (nxt <= p && v[nxt] == w) {
-                // w is a vertex of sigma: move it from "below" to "above"
-                const int r = p - nxt;  // its rank from the bottom
+                const int r = p - nxt;  // rank from the bottom
                 below -= C(w, r + 1);
                 above += C(w, r + 2);
                 --j;
@@ -119,17 +170,68 @@ struct Ctx {
             float nd = d;
             bool ok = true;
             for (int i = 0; i <= p; ++i) {
-                const float e = D(w, v[i]);
+                const float e = rows[i][w];
                 if (!(e <= P.thr)) {
                     ok = false;
                     break;
                 }
                 nd = e > nd ? e : nd;
             }
-            if (!ok)
-                continue;
-            col.push(Entry{nd, above + C(w, j + 1) + below});
+            if (ok)
+                scratch.push_back(Entry{nd, above + C(w, j + 1) + below});
         }
+        return scratch;
+    }
+
+    // Implicit second layer: if row tau (diameter dt) is the pivot of an
+    // apparent column, return that column.  The column can only be tau's
+    // youngest facet: among the facets of full diameter dt, the one of
+    // smallest cidx, i.e. tau minus its largest vertex u whose removal keeps
+    // the diameter.  (sigma*, tau) is apparent iff tau is sigma*'s oldest
+    // cofacet: no w > u outside tau has d(w, s) <= dt for all s in sigma*.
+    bool apparent_partner(uint64_t tau, float dt, uint64_t *sigma_out) const
+    {
+        int t[9];
+        decode(tau, p + 1, t);
+        int ui = -1;
+        for (int i = 0; i <= p + 1 && ui < 0; ++i) {
+            float fd = 0.0f;
+            for (int a = 0; a <= p + 1; ++a) {
+                if (a == i)
+                    continue;
+                for (int b = a + 1; b <= p + 1; ++b)
+                    if (b != i) {
+                        const float e = D(t[a], t[b]);
+                        fd = e > fd ? e : fd;
+                    }
+            }
+            if (fd == dt)
+                ui = i;
+        }
+        if (ui < 0)
+            return false;
+        const int u = t[ui];
+        int s[8], q = 0;
+        for (int i = 0; i <= p + 1; ++i)
+            if (i != ui)
+                s[q++] = t[i];
+        int nxt = 0;  // next vertex of tau at or below w (tau is decreasing)
+        for (int w = n - 1; w > u; --w) {
+            if (nxt <= p + 1 && t[nxt] == w) {
+                ++nxt;
+                continue;
+            }
+            bool all = true;
+            for (int i = 0; i <= p && all; ++i)
+                all = P.dsq[(int64_t)s[i] * n + w] <= dt;
+            if (all)
+                return false;
+        }
+        uint64_t c = 0;
+        for (int i = 0; i <= p; ++i)
+            c += C(s[i], p + 1 - i);
+        *sigma_out = c;
+        return true;
     }
 };
 
@@ -141,43 +243,66 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R)
     std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
     pivots.reserve((size_t)P.ncols * 2 + 16);
     Column col;
+
+    // two-layer lookup: the column (and its diameter) whose pivot is row tau
+    auto lookup = [&](uint64_t tau, float dt, uint64_t *other, float *odiam) -> bool {
+        auto it = pivots.find(tau);
+        if (it != pivots.end()) {
+            ++R.lookups_hash;
+            *other = R.sigma[it->second];
+            *odiam = R.birth[it->second];
+            return true;
+        }
+        ++R.lookups_apparent;
+        if (P.app_tau) {
+            const uint64_t *b = P.app_tau, *e = P.app_tau + P.napp;
+            const uint64_t *f = std::lower_bound(b, e, tau);
+            if (f == e || *f != tau)
+                return false;
+            *other = P.app_sigma[f - b];
+        } else if (!X.apparent_partner(tau, dt, other)) {
+            return false;
+        }
+        *odiam = dt;  // an apparent column has the diameter of its tau
+        return true;
+    };
+    auto record_pair = [&](uint64_t sigma, float d, const Entry &lo) {
+        pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
+        R.sigma.push_back(sigma);
+        R.tau.push_back(lo.cidx);
+        R.birth.push_back(d);
+        R.death.push_back(lo.diam);
+    };
+
     for (int64_t j = 0; j < P.ncols; ++j) {
         const uint64_t sigma = P.col_cidx[j];
         const float d = __builtin_bit_cast(float, (uint32_t)~(uint32_t)P.col_key[j]);
+        Entry lo{P.col_low_diam[j], P.col_low[j]};
+        if (lo.cidx == ~0ull) {  // empty coboundary: essential
+            R.ess_sigma.push_back(sigma);
+            R.ess_birth.push_back(d);
+            continue;
+        }
+        uint64_t other;
+        float odiam;
+        if (!lookup(lo.cidx, lo.diam, &other, &odiam)) {
+            record_pair(sigma, d, lo);  // low is free: nothing to add
+            ++R.emergent;
+            continue;
+        }
         col.clear();
-        X.push_coboundary(sigma, d, col);
-        Entry lo;
-        bool nonzero = col.low(lo);
-        while (nonzero) {
-            // first layer: pairs found by this reduction
-            auto it = pivots.find(lo.cidx);
-            uint64_t other;
-            float odiam;
-            if (it != pivots.end()) {
-                ++R.lookups_hash;
-                other = R.sigma[it->second];
-                odiam = R.birth[it->second];
-            } else {
-                // second layer: apparent pairs, sorted by tau
-                const uint64_t *b = P.app_tau, *e = P.app_tau + P.napp;
-                const uint64_t *f = std::lower_bound(b, e, lo.cidx);
-                ++R.lookups_apparent;
-                if (f == e || *f != lo.cidx)
-                    break;  // low is free: (sigma, low) is a new pair
-                other = P.app_sigma[f - b];
-                odiam = lo.diam;  // an apparent column has the diameter of its tau
-            }
+        col.add(X.coboundary(sigma, d));
+        bool nonzero = true;
+        while (true) {
             // Algorithm 2: add the ORIGINAL column of the pivot's owner
-            X.push_coboundary(other, odiam, col);
+            col.add(X.coboundary(other, odiam));
             ++R.additions;
             nonzero = col.low(lo);
+            if (!nonzero || !lookup(lo.cidx, lo.diam, &other, &odiam))
+                break;
         }
         if (nonzero) {
-            pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
-            R.sigma.push_back(sigma);
-            R.tau.push_back(lo.cidx);
-            R.birth.push_back(d);
-            R.death.push_back(lo.diam);
+            record_pair(sigma, d, lo);
         } else {
             R.ess_sigma.push_back(sigma);
             R.ess_birth.push_back(d);

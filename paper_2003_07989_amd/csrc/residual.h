@@ -13,13 +13,20 @@ struct ResidualProblem {
     int p = 0;                         // column dimension, >= 1
     float thr = 0.0f;                  // inclusive threshold
     const float *dsq = nullptr;        // n x n distances, zero diagonal
-    const uint64_t *binom = nullptr;   // C(v,k) at [k * (n+1) + v]
+    const uint64_t *binom = nullptr;   // C(v,k) at [k * (n+1) + v], k <= p+2
     // non-apparent columns in coboundary order (diameter desc, cidx asc);
     // key = ~bits(diameter) in the low 32 bits
     int64_t ncols = 0;
     const uint64_t *col_key = nullptr;
     const uint64_t *col_cidx = nullptr;
-    // apparent pairs (tau, sigma) sorted by tau
+    // low (oldest cofacet) of each unreduced column, ~0 when empty, and its
+    // diameter (computed on the GPU)
+    const uint64_t *col_low = nullptr;
+    const float *col_low_diam = nullptr;
+    // second layer of the pivot store.  Sorted mode: apparent pairs (tau,
+    // sigma) sorted by tau.  Implicit mode (app_tau == nullptr): a row tau is
+    // an apparent pivot iff tau is the oldest cofacet of its youngest facet,
+    // which is recomputed from the distance matrix on demand.
     int64_t napp = 0;
     const uint64_t *app_tau = nullptr;
     const uint64_t *app_sigma = nullptr;
@@ -31,12 +38,13 @@ struct ResidualResult {
     std::vector<uint64_t> ess_sigma;   // columns reduced to zero
     std::vector<float> ess_birth;
     int64_t additions = 0;
+    int64_t emergent = 0;              // columns paired without any addition
     int64_t lookups_hash = 0, lookups_apparent = 0;
 };
 
 // Oblivious column reduction (paper, Algorithm 2) of every column, in order,
-// with the two-layer pivot store (hash map of pivots found here first, then
-// binary search in the apparent-pair array).
+// with the two-layer pivot store: the pivots found here in a hash map first,
+// then the apparent pairs.
 void residual_reduce(const ResidualProblem &P, ResidualResult &R);
 
 }  // namespace rpp

@@ -220,3 +220,28 @@ def test_torus400_matches_stored_oracle(rpp):
     for p in range(1, 3):
         st = got.stats[p]
         assert st["n_apparent"] + st["n_host_pairs"] > 0
+
+
+@pytest.mark.parametrize("case", CASES[::3], ids=[c[0] for c in CASES[::3]])
+def test_sorted_pair_store_mode_matches_oracle(rpp, case):
+    """The paper's two-layer store (apparent pairs sorted by tau, binary
+    searched on the host) gives the same bars and pairs as the default."""
+    name, d, n, maxdim, thr = case
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_SORTED_PAIR_STORE)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+    f = rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    a = rpp.barcodes(d, maxdim, thr, flags=f)
+    b = rpp.barcodes(d, maxdim, thr, flags=f | rpp.RPP_SORTED_PAIR_STORE)
+    for p in range(1, maxdim + 1):
+        assert set(zip(*map(list, a.pairs[p]))) == set(zip(*map(list, b.pairs[p])))
+
+
+def test_torus400_sorted_pair_store(rpp):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    head, exp = mg.read(os.path.join(GOLDEN, "torus400.bars.txt"))
+    d = w.WORKLOADS["torus400"]["build"]()
+    got = rpp.barcodes(d, 2, flags=rpp.RPP_SORTED_PAIR_STORE)
+    assert_bars_equal(got.bars, exp, "torus400 sorted store")
