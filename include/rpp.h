@@ -71,6 +71,13 @@ enum {
  * recomputing the apparent-pair condition from the distance matrix, so the
  * apparent pairs are neither sorted nor copied.  Results are identical. */
 #define RPP_SORTED_PAIR_STORE 0x4u
+/* Enumeration path.  Dense: every C(n, p+1) combinatorial index is examined
+ * in order.  Sparse: p-simplices are grown from the (p-1)-simplices under
+ * the threshold through neighbour bitsets (paper, sparse 1-skeletons).  By
+ * default the sparse path is taken when under a quarter of the edges are
+ * within the threshold.  Results are identical. */
+#define RPP_FORCE_SPARSE 0x8u
+#define RPP_FORCE_DENSE 0x10u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:

@@ -8,12 +8,14 @@ behind the C ABI of ``include/rpp.h``.  This package is the thin Python
 binding.  Importing it does not load the library; the first call does,
 and fails loudly if ``librpp.so`` has not been built.
 """
-from ._binding import (RPP_MAX_DIM, RPP_NO_ENCLOSING_RADIUS, RPP_SORTED_PAIR_STORE,
+from ._binding import (RPP_FORCE_DENSE, RPP_FORCE_SPARSE, RPP_MAX_DIM,
+                       RPP_NO_ENCLOSING_RADIUS, RPP_SORTED_PAIR_STORE,
                        RPP_WANT_PAIRS, Barcodes,
                        RppError, apparent_pairs, barcodes, barcodes_device, barcodes_host,
                        load, strerror, version, workspace_bytes)
 
-__all__ = ["RPP_MAX_DIM", "RPP_NO_ENCLOSING_RADIUS", "RPP_SORTED_PAIR_STORE",
+__all__ = ["RPP_FORCE_DENSE", "RPP_FORCE_SPARSE", "RPP_MAX_DIM",
+           "RPP_NO_ENCLOSING_RADIUS", "RPP_SORTED_PAIR_STORE",
            "RPP_WANT_PAIRS", "Barcodes",
            "RppError", "apparent_pairs", "barcodes", "barcodes_device", "barcodes_host",
            "load", "strerror", "version", "workspace_bytes"]

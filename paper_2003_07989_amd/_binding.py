@@ -23,6 +23,8 @@ RPP_MAX_DIM = 4
 RPP_NO_ENCLOSING_RADIUS = 0x1
 RPP_WANT_PAIRS = 0x2
 RPP_SORTED_PAIR_STORE = 0x4
+RPP_FORCE_SPARSE = 0x8
+RPP_FORCE_DENSE = 0x10
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
           -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE"}

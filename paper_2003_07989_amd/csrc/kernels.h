@@ -82,6 +82,47 @@ void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
                  const float *dsq, int n, int p, float thr, const uint64_t *binom,
                  uint64_t *low_out, float *low_diam_out, hipStream_t s);
 
+// ---- sparse path (a threshold that keeps few edges) -------------------------
+// Neighbour bitsets: bit b of bits[v * words + k] is set iff u = 64k + b is a
+// vertex, u != v and d(u, v) <= thr.
+void launch_nbr_bits(const float *dsq, int n, float thr, uint64_t *bits, int words,
+                     hipStream_t s);
+
+// p-simplices <= thr as one-vertex extensions of the (p-1)-simplices <= thr
+// (paper, enumeration of cofacets for sparse 1-skeletons): prefix
+// (v_p > ... > v_1) extends by every common neighbour v_0 < v_1.  Listing
+// prefixes in cidx order and v_0 upward yields the p-simplices in cidx order.
+struct ExtArgs {
+    const float *dsq;
+    int n;
+    int p;                           // dimension of the produced simplices, >= 2
+    const uint64_t *bits;
+    int words;
+    const uint64_t *binom;
+    const float *pre_diam;           // (p-1)-simplices <= thr, cidx order
+    const uint64_t *pre_cidx;
+    int64_t npre;
+    const uint64_t *clear_sorted;    // cleared p-simplices, sorted cidx (may be null)
+    int64_t nclear;
+};
+// Pass 1: per prefix, the number of extensions and of non-cleared ones.
+void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, uint32_t *cnt_kept, hipStream_t s);
+// Pass 2: write all extensions (when all_cidx is not null) and the kept
+// ones at the given offsets, in cidx order.
+void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, const uint64_t *off_kept,
+                        float *all_diam, uint64_t *all_cidx, float *kept_diam,
+                        uint64_t *kept_cidx, hipStream_t s);
+// Apparent test and lows for the sparse path: candidates are the common
+// neighbours of the column's vertices, scanned 64 at a time from the top.
+void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                            const float *dsq, int n, int p, const uint64_t *bits, int words,
+                            const uint64_t *binom, uint64_t *tau_out,
+                            unsigned long long *scan_count, hipStream_t s);
+void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
+                        const float *dsq, int n, int p, const uint64_t *bits, int words,
+                        const uint64_t *binom, uint64_t *low_out, float *low_diam_out,
+                        hipStream_t s);
+
 // ---- a7: clearing bitmap ---------------------------------------------------
 void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s);
 

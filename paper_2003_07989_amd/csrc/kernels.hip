@@ -720,6 +720,328 @@ void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
     }
 }
 
+
+// ===========================================================================
+// sparse path: neighbour bitsets, extension enumeration, apparent test
+// ===========================================================================
+__global__ void k_nbr_bits(const float *__restrict__ dsq, int n, float thr,
+                           uint64_t *__restrict__ bits, int words)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * words)
+        return;
+    const int v = (int)(t / words), k = (int)(t % words);
+    const float *row = dsq + (int64_t)v * n;
+    uint64_t m = 0;
+    const int base = k * 64;
+    for (int b = 0; b < 64; ++b) {
+        const int u = base + b;
+        if (u < n && u != v && row[u] <= thr)
+            m |= 1ull << b;
+    }
+    bits[t] = m;
+}
+
+void launch_nbr_bits(const float *dsq, int n, float thr, uint64_t *bits, int words, hipStream_t s)
+{
+    const int64_t tot = (int64_t)n * words;
+    hipLaunchKernelGGL(k_nbr_bits, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dsq, n,
+                       thr, bits, words);
+}
+
+__device__ __forceinline__ bool sorted_contains(const uint64_t *__restrict__ a, int64_t len,
+                                                uint64_t key)
+{
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < len && a[lo] == key;
+}
+
+// One wave per prefix, one lane per 64-vertex word of candidates v_0 < v_1.
+template <int P, bool WRITE>
+__global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ cnt_all,
+                                             uint32_t *__restrict__ cnt_kept,
+                                             const uint64_t *__restrict__ off_all,
+                                             const uint64_t *__restrict__ off_kept,
+                                             float *__restrict__ all_diam,
+                                             uint64_t *__restrict__ all_cidx,
+                                             float *__restrict__ kept_diam,
+                                             uint64_t *__restrict__ kept_cidx)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t pre = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (pre >= a.npre)
+        return;
+    const Binom B{a.binom, a.n + 1};
+    int u[P];  // prefix vertices, decreasing; u[P-1] = v_1
+    decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
+    const float pd = a.pre_diam[pre];
+    // cidx of (u, v0) = sum_i C(u_i, P+1-i) + v0
+    uint64_t shifted = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        shifted += B(u[i], P + 1 - i);
+    const int limit = u[P - 1];
+    uint64_t run_all = WRITE ? off_all ? off_all[pre] : 0 : 0;
+    uint64_t run_kept = WRITE ? off_kept[pre] : 0;
+    uint32_t tot_all = 0, tot_kept = 0;
+    for (int wb = 0; wb * 64 < limit; wb += WAVE) {
+        const int word = wb + lane;
+        uint64_t m = 0;
+        if (word * 64 < limit) {
+            m = ~0ull;
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                m &= a.bits[(int64_t)u[i] * a.words + word];
+            const int hi = limit - word * 64;  // keep bits below v_1
+            if (hi < 64)
+                m &= (1ull << hi) - 1;
+        }
+        const uint32_t na = (uint32_t)__popcll(m);
+        uint32_t nk = 0;
+        if (a.clear_sorted) {
+            for (uint64_t r = m; r; r &= r - 1) {
+                const int v0 = word * 64 + __ffsll((unsigned long long)r) - 1;
+                nk += !sorted_contains(a.clear_sorted, a.nclear, shifted + (uint64_t)v0);
+            }
+        } else {
+            nk = na;
+        }
+        if (WRITE) {
+            const uint32_t ia = wave_inclusive_scan(na) - na;
+            const uint32_t ik = wave_inclusive_scan(nk) - nk;
+            uint64_t pa = run_all + ia, pk = run_kept + ik;
+            for (uint64_t r = m; r; r &= r - 1) {
+                const int v0 = word * 64 + __ffsll((unsigned long long)r) - 1;
+                float d = pd;
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    d = fmaxf(d, dsq_at(a.dsq, a.n, u[i], v0));
+                const uint64_t c = shifted + (uint64_t)v0;
+                if (all_cidx) {
+                    all_diam[pa] = d;
+                    all_cidx[pa] = c;
+                    ++pa;
+                }
+                if (!a.clear_sorted || !sorted_contains(a.clear_sorted, a.nclear, c)) {
+                    kept_diam[pk] = d;
+                    kept_cidx[pk] = c;
+                    ++pk;
+                }
+            }
+        }
+        const uint32_t sa = wave_sum(na), sk = wave_sum(nk);
+        run_all += sa;
+        run_kept += sk;
+        tot_all += sa;
+        tot_kept += sk;
+    }
+    if (!WRITE && lane == 0) {
+        cnt_all[pre] = tot_all;
+        cnt_kept[pre] = tot_kept;
+    }
+}
+
+#define RPP_EXT_LAUNCH(WR, ...)                                                                  \
+    switch (a.p) {                                                                               \
+    case 2: hipLaunchKernelGGL((k_ext<2, WR>), g, b, 0, s, a, __VA_ARGS__); break;               \
+    case 3: hipLaunchKernelGGL((k_ext<3, WR>), g, b, 0, s, a, __VA_ARGS__); break;               \
+    default: hipLaunchKernelGGL((k_ext<4, WR>), g, b, 0, s, a, __VA_ARGS__); break;              \
+    }
+
+void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, uint32_t *cnt_kept, hipStream_t s)
+{
+    if (a.npre <= 0)
+        return;
+    dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
+    RPP_EXT_LAUNCH(false, cnt_all, cnt_kept, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)
+}
+
+void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, const uint64_t *off_kept,
+                        float *all_diam, uint64_t *all_cidx, float *kept_diam,
+                        uint64_t *kept_cidx, hipStream_t s)
+{
+    if (a.npre <= 0)
+        return;
+    dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
+    RPP_EXT_LAUNCH(true, nullptr, nullptr, off_all, off_kept, all_diam, all_cidx, kept_diam,
+                   kept_cidx)
+}
+
+// Apparent test over common neighbours: one wave per column; each step
+// covers 64 words (lane 0 = highest word); every lane walks its word's
+// candidates downward and the highest hit across lanes is w.
+template <int P>
+__global__ __launch_bounds__(256) void k_apparent_sparse(
+    const float *__restrict__ col_diam, const uint64_t *__restrict__ col_cidx, int64_t ncols,
+    const float *__restrict__ dsq, int n, const uint64_t *__restrict__ bits, int words,
+    const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
+    unsigned long long *__restrict__ scan_count)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (col >= ncols)
+        return;
+    const Binom B{binom, n + 1};
+    const float d = col_diam[col];
+    int v[P + 1];
+    decode<P>(B, col_cidx[col], n, v);
+    const float *row[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        row[i] = dsq + (int64_t)v[i] * n;
+    int w = -1;
+    long long examined = 0;
+    for (int top = words - 1; top >= 0; top -= WAVE) {
+        const int word = top - lane;
+        int found = -1;
+        if (word >= 0) {
+            uint64_t m = ~0ull;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                m &= bits[(int64_t)v[i] * words + word];
+            while (m) {
+                const int bpos = 63 - __clzll((long long)m);
+                const int x = word * 64 + bpos;
+                bool ok = true;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    ok = ok && row[i][x] <= d;
+                if (scan_count)
+                    ++examined;
+                if (ok) {
+                    found = x;
+                    break;
+                }
+                m &= ~(1ull << bpos);
+            }
+        }
+        const uint64_t bal = __ballot(found >= 0);
+        if (bal) {
+            w = __shfl(found, __ffsll((unsigned long long)bal) - 1, WAVE);
+            break;
+        }
+    }
+    uint64_t tau = NONE;
+    if (w >= 0) {
+        bool apparent = true;
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            if (v[j] > w && apparent) {
+                float fd = 0.0f;
+#pragma unroll
+                for (int a = 0; a <= P; ++a) {
+                    if (a == j)
+                        continue;
+                    fd = fmaxf(fd, row[a][w]);
+#pragma unroll
+                    for (int b = a + 1; b <= P; ++b)
+                        if (b != j)
+                            fd = fmaxf(fd, row[a][v[b]]);
+                }
+                if (fd == d)
+                    apparent = false;
+            }
+        }
+        if (apparent)
+            tau = cofacet_index<P>(B, v, w);
+    }
+    if (scan_count) {
+        const long long tot = wave_sum(examined);
+        if (lane == 0)
+            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)tot);
+    }
+    if (lane == 0)
+        tau_out[col] = tau;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_lows_sparse(
+    const uint64_t *__restrict__ na_key, const uint64_t *__restrict__ na_cidx, int64_t ncols,
+    const float *__restrict__ dsq, int n, const uint64_t *__restrict__ bits, int words,
+    const uint64_t *__restrict__ binom, uint64_t *__restrict__ low_out,
+    float *__restrict__ low_diam_out)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (col >= ncols)
+        return;
+    const Binom B{binom, n + 1};
+    const float d = __uint_as_float(~(uint32_t)na_key[col]);
+    int v[P + 1];
+    decode<P>(B, na_cidx[col], n, v);
+    float best = INFINITY;
+    int bw = -1;
+    for (int word = lane; word < words; word += WAVE) {
+        uint64_t m = ~0ull;
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            m &= bits[(int64_t)v[i] * words + word];
+        for (; m; m &= m - 1) {
+            const int x = word * 64 + __ffsll((unsigned long long)m) - 1;
+            float c = d;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                c = fmaxf(c, dsq_at(dsq, n, v[i], x));
+            if (c <= best) {  // ascending x: later (larger) x wins ties
+                best = c;
+                bw = x;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o, WAVE);
+        const int ow = __shfl_xor(bw, o, WAVE);
+        if (ob < best || (ob == best && ow > bw)) {
+            best = ob;
+            bw = ow;
+        }
+    }
+    if (lane == 0) {
+        low_out[col] = bw >= 0 ? cofacet_index<P>(B, v, bw) : NONE;
+        low_diam_out[col] = best;
+    }
+}
+
+void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                            const float *dsq, int n, int p, const uint64_t *bits, int words,
+                            const uint64_t *binom, uint64_t *tau_out,
+                            unsigned long long *scan_count, hipStream_t s)
+{
+    if (ncols <= 0)
+        return;
+    dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_apparent_sparse<1>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
+    case 2: hipLaunchKernelGGL(k_apparent_sparse<2>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
+    case 3: hipLaunchKernelGGL(k_apparent_sparse<3>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
+    default: hipLaunchKernelGGL(k_apparent_sparse<4>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
+    }
+}
+
+void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
+                        const float *dsq, int n, int p, const uint64_t *bits, int words,
+                        const uint64_t *binom, uint64_t *low_out, float *low_diam_out,
+                        hipStream_t s)
+{
+    if (ncols <= 0)
+        return;
+    dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_lows_sparse<1>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
+    case 2: hipLaunchKernelGGL(k_lows_sparse<2>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
+    case 3: hipLaunchKernelGGL(k_lows_sparse<3>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
+    default: hipLaunchKernelGGL(k_lows_sparse<4>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
+    }
+}
+
 // ===========================================================================
 // a7: clearing bitmap for the next dimension
 // ===========================================================================

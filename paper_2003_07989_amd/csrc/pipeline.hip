@@ -122,7 +122,10 @@ struct Workspace {
     DevBuf dsq, rowmax, scal, binom;
     DevBuf ekey, eval, ekey2, eval2;  // edges for H0
     DevBuf mst, deaths, ufs;
-    DevBuf tcount, toff, scan;
+    DevBuf tcount, toff, scan, tcount2, toff2;
+    DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
+    DevBuf bits;                     // sparse path: neighbour bitsets
+    DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
     DevBuf cdiam, ccidx, tau;
     DevBuf akey, aval, akey2, aval2;  // apparent pairs
     DevBuf nkey, nval, nkey2, nval2;  // non-apparent columns
@@ -223,8 +226,6 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     ALLOC_TRY(ws.tcount, (size_t)(tiles + 1) * 4);
     ALLOC_TRY(ws.toff, (size_t)(tiles + 2) * 8);
     ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(tiles) * 8);
-    ALLOC_TRY(ws.cdiam, (size_t)(ea.ncand + 1) * 4);
-    ALLOC_TRY(ws.ccidx, (size_t)(ea.ncand + 1) * 8);
     ALLOC_TRY(ws.h_small, 256);
     unsigned long long *stats = ws.scal.as<unsigned long long>() + 2;
     HIP_TRY(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
@@ -233,17 +234,61 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     launch_enum_count(ea, ws.tcount.as<uint32_t>(), stats, s);
     launch_exclusive_scan(ws.tcount.as<uint32_t>(), tiles, ws.toff.as<uint64_t>(),
                           ws.scan.as<uint64_t>(), s);
-    launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
-                        ws.ccidx.as<uint64_t>(), s);
-    if (tm)
-        tm->stop();
     uint64_t *h = ws.h_small.as<uint64_t>();
     HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h + 1, stats, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *kept = (int64_t)h[0];
+    *kept = tiles ? (int64_t)h[0] : 0;
     *nthr = h[1];
     *nclr = h[2];
+    ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
+    ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+    launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
+                        ws.ccidx.as<uint64_t>(), s);
+    if (tm)
+        tm->stop();
+    return RPP_OK;
+}
+
+// Sparse enumeration of the p-simplices (p >= 2) from the (p-1)-simplices in
+// ws.skd/skc[cur]: kept columns into ws.cdiam/ccidx, and, when want_all, all
+// p-simplices <= threshold into ws.skd/skc[1-cur] for the next dimension.
+static int enumerate_sparse(Workspace &ws, ExtArgs ea, bool want_all, int cur, hipStream_t s,
+                            int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm)
+{
+    const int64_t np = ea.npre;
+    ALLOC_TRY(ws.tcount, (size_t)(np + 1) * 4);
+    ALLOC_TRY(ws.tcount2, (size_t)(np + 1) * 4);
+    ALLOC_TRY(ws.toff, (size_t)(np + 2) * 8);
+    ALLOC_TRY(ws.toff2, (size_t)(np + 2) * 8);
+    ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(np) * 8);
+    if (tm)
+        tm->start();
+    launch_ext_count(ea, ws.tcount2.as<uint32_t>(), ws.tcount.as<uint32_t>(), s);
+    launch_exclusive_scan(ws.tcount.as<uint32_t>(), np, ws.toff.as<uint64_t>(),
+                          ws.scan.as<uint64_t>(), s);
+    launch_exclusive_scan(ws.tcount2.as<uint32_t>(), np, ws.toff2.as<uint64_t>(),
+                          ws.scan.as<uint64_t>(), s);
+    uint64_t *h = ws.h_small.as<uint64_t>();
+    HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + np, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h + 1, ws.toff2.as<uint64_t>() + np, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *kept = np ? (int64_t)h[0] : 0;
+    *all = np ? (int64_t)h[1] : 0;
+    ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
+    ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+    float *ad = nullptr;
+    uint64_t *ac = nullptr;
+    if (want_all) {
+        ALLOC_TRY(ws.skd[1 - cur], (size_t)(*all + 1) * 4);
+        ALLOC_TRY(ws.skc[1 - cur], (size_t)(*all + 1) * 8);
+        ad = ws.skd[1 - cur].as<float>();
+        ac = ws.skc[1 - cur].as<uint64_t>();
+    }
+    launch_ext_scatter(ea, ws.toff2.as<uint64_t>(), ws.toff.as<uint64_t>(), ad, ac,
+                       ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), s);
+    if (tm)
+        tm->stop();
     return RPP_OK;
 }
 
@@ -252,7 +297,7 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
 static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, int group,
                                   hipStream_t s, int64_t *napp, std::string &err,
                                   GpuTimer *t_app = nullptr, GpuTimer *t_part = nullptr,
-                                  int64_t *scanned = nullptr)
+                                  int64_t *scanned = nullptr, int words = 0)
 {
     const int64_t tiles = compact_tiles(ncols);
     ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
@@ -275,8 +320,14 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     }
     if (t_app)
         t_app->start();
-    launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols, ws.dsq.as<float>(), n,
-                    p, ws.binom.as<uint64_t>(), group, ws.tau.as<uint64_t>(), sc, s);
+    if (words > 0)
+        launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
+                               ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
+                               ws.binom.as<uint64_t>(), ws.tau.as<uint64_t>(), sc, s);
+    else
+        launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
+                        ws.dsq.as<float>(), n, p, ws.binom.as<uint64_t>(), group,
+                        ws.tau.as<uint64_t>(), sc, s);
     if (t_app)
         t_app->stop();
     if (t_part)
@@ -442,32 +493,78 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         }
     }
 
+    // ---------------- path choice --------------------------------------------
+    const bool sparse = maxdim >= 1 && ((a.flags & RPP_FORCE_SPARSE) ||
+                                        (!(a.flags & RPP_FORCE_DENSE) &&
+                                         (double)nedges < 0.25 * (double)E));
+    const int words = (n + 63) / 64;
+    std::vector<uint64_t> h_bits;
+    int cur = 0;
+    int64_t nskel = 0;
+    if (sparse) {
+        // all edges <= thr, in cidx order, are the prefixes of dimension 2
+        ALLOC_TRY(ws.skd[0], (size_t)(nedges + 1) * 4);
+        ALLOC_TRY(ws.skc[0], (size_t)(nedges + 1) * 8);
+        if (nedges) {
+            HIP_TRY(hipMemcpyAsync(ws.skd[0].p, ws.cdiam.p, (size_t)nedges * 4,
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(ws.skc[0].p, ws.ccidx.p, (size_t)nedges * 8,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        nskel = nedges;
+        ALLOC_TRY(ws.bits, (size_t)n * words * 8);
+        launch_nbr_bits(ws.dsq.as<float>(), n, thr, ws.bits.as<uint64_t>(), words, s);
+        h_bits.resize((size_t)n * words);
+        HIP_TRY(hipMemcpyAsync(h_bits.data(), ws.bits.p, h_bits.size() * 8, hipMemcpyDeviceToHost,
+                               s));
+    }
+
     // ---------------- dimensions 1..maxdim --------------------------------
-    // clearing set of the current dimension: p = 1 uses the MST bitmap
+    // clearing set of the current dimension: p = 1 uses the MST bitmap;
+    // later dimensions a bitmap (dense) or a sorted cidx array (sparse)
     const uint32_t *clear_bits = ws.mst.as<uint32_t>();
+    int64_t nclear_sorted = 0;
+    const uint64_t *clear_sorted = nullptr;
     for (int p = 1; p <= maxdim; ++p) {
         DimOut &D = out.dims[p];
         GpuTimer tg(s), t_enum(s), t_app(s), t_part(s), t_sort(s);
         tg.start();
-        const uint64_t ncand = binom_sat(n, p + 1);
-        EnumArgs ea{a.dcond_dev, n, p, thr, ws.binom.as<uint64_t>(), clear_bits, ncand};
-        int64_t ncols = 0;
+        int64_t ncols = 0, ncand = 0;
         uint64_t nthr = 0, nclr = 0;
-        int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
+        int rc;
+        if (!sparse || p == 1) {
+            const uint64_t nc = binom_sat(n, p + 1);
+            EnumArgs ea{a.dcond_dev, n, p, thr, ws.binom.as<uint64_t>(), clear_bits, nc};
+            rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
+            ncand = (int64_t)nc;
+        } else {
+            ExtArgs xa{ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
+                       ws.binom.as<uint64_t>(), ws.skd[cur].as<float>(),
+                       ws.skc[cur].as<uint64_t>(), nskel, clear_sorted, nclear_sorted};
+            int64_t nall = 0;
+            rc = enumerate_sparse(ws, xa, p < maxdim, cur, s, &ncols, &nall, err, &t_enum);
+            ncand = nall;
+            nclr = (uint64_t)(nall - ncols);
+            if (p < maxdim) {
+                cur = 1 - cur;
+                nskel = nall;
+            }
+        }
         if (rc)
             return rc;
         int64_t napp = 0, scanned = 0;
         const int group = a.apparent_group > 0 ? a.apparent_group : default_group(p);
         rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
-                                    a.count_scans ? &scanned : nullptr);
+                                    a.count_scans ? &scanned : nullptr, sparse ? words : 0);
         if (rc)
             return rc;
         t_sort.start();
         const int64_t nna = ncols - napp;
 
-        // next dimension's clearing bitmap: apparent taus now, host taus later
-        const uint64_t nnext = (p < maxdim) ? binom_sat(n, p + 2) : 0;
-        if (p < maxdim) {
+        // next dimension's clearing bitmap (dense): apparent taus now, host
+        // taus after the reduction
+        if (p < maxdim && !sparse) {
+            const uint64_t nnext = binom_sat(n, p + 2);
             ALLOC_TRY(ws.next, (size_t)(nnext / 32 + 2) * 4);
             launch_fill_u32(ws.next.as<uint32_t>(), (int64_t)(nnext / 32 + 1), 0u, s);
             launch_mark_bits(ws.akey.as<uint64_t>(), napp, ws.next.as<uint32_t>(), s);
@@ -498,8 +595,13 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         // a7: lows of the non-apparent columns for the host reduction
         ALLOC_TRY(ws.lowc, (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.lowd, (size_t)(nna + 1) * 4);
-        launch_lows(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, thr, ws.binom.as<uint64_t>(),
-                    ws.lowc.as<uint64_t>(), ws.lowd.as<float>(), s);
+        if (sparse)
+            launch_lows_sparse(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(),
+                               words, ws.binom.as<uint64_t>(), ws.lowc.as<uint64_t>(),
+                               ws.lowd.as<float>(), s);
+        else
+            launch_lows(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, thr, ws.binom.as<uint64_t>(),
+                        ws.lowc.as<uint64_t>(), ws.lowd.as<float>(), s);
         // device -> host handoff
         ALLOC_TRY(ws.h_na_key, (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_na_cidx, (size_t)(nna + 1) * 8);
@@ -511,9 +613,9 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             HIP_TRY(hipMemcpyAsync(ws.h_low.p, ws.lowc.p, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(ws.h_lowd.p, ws.lowd.p, (size_t)nna * 4, hipMemcpyDeviceToHost, s));
         }
+        ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
+        ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
         if ((sorted_store || want_pairs) && napp) {
-            ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
-            ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
             HIP_TRY(hipMemcpyAsync(ws.h_app_tau.p, d_at, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(ws.h_app_sigma.p, d_as, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
         }
@@ -534,6 +636,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         P.thr = thr;
         P.dsq = h_dsq.data();
         P.binom = ws.binom_host.data();
+        P.bits = sparse ? h_bits.data() : nullptr;
+        P.words = sparse ? words : 0;
         P.ncols = nna;
         P.col_key = ws.h_na_key.as<uint64_t>();
         P.col_cidx = ws.h_na_cidx.as<uint64_t>();
@@ -556,10 +660,10 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             D.birth.push_back(RR.ess_birth[i]);
             D.death.push_back(INFINITY);
         }
-        D.st.n_candidates = (int64_t)ncand;
+        D.st.n_candidates = ncand;
         D.st.n_thresholded = (int64_t)nthr;
         D.st.n_cleared = (int64_t)nclr;
-        D.st.n_simplices = (int64_t)(ncand - nthr);
+        D.st.n_simplices = ncand - (int64_t)nthr;
         D.st.n_kept = ncols;
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
@@ -567,7 +671,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.n_essential = (int64_t)RR.ess_sigma.size();
         D.st.n_bars = (int64_t)D.birth.size();
         D.st.n_column_adds = RR.additions;
-        if (a.flags & RPP_WANT_PAIRS) {
+        if (want_pairs) {
             const uint64_t *at = ws.h_app_tau.as<uint64_t>();
             const uint64_t *as = ws.h_app_sigma.as<uint64_t>();
             D.pair_sigma.assign(as, as + napp);
@@ -582,11 +686,33 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                 ALLOC_TRY(ws.hostpiv, (size_t)nh * 8);
                 HIP_TRY(hipMemcpyAsync(ws.hostpiv.p, RR.tau.data(), (size_t)nh * 8,
                                        hipMemcpyHostToDevice, s));
-                launch_mark_bits(ws.hostpiv.as<uint64_t>(), nh, ws.next.as<uint32_t>(), s);
             }
-            std::swap(ws.clear, ws.next);
-            clear_bits = ws.clear.as<uint32_t>();
-            // the MST bitmap is no longer needed once p >= 1 has consumed it
+            if (!sparse) {
+                if (nh)
+                    launch_mark_bits(ws.hostpiv.as<uint64_t>(), nh, ws.next.as<uint32_t>(), s);
+                std::swap(ws.clear, ws.next);
+                clear_bits = ws.clear.as<uint32_t>();
+            } else {
+                // sorted array of every dimension-p pivot row (apparent + host)
+                const int64_t m = napp + nh;
+                ALLOC_TRY(ws.clr, (size_t)(m + 1) * 8);
+                ALLOC_TRY(ws.clr2, (size_t)(m + 1) * 8);
+                ALLOC_TRY(ws.clrv, (size_t)(m + 1) * 8);
+                ALLOC_TRY(ws.clrv2, (size_t)(m + 1) * 8);
+                ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(m) * 8);
+                if (napp)
+                    HIP_TRY(hipMemcpyAsync(ws.clr.p, d_at, (size_t)napp * 8,
+                                           hipMemcpyDeviceToDevice, s));
+                if (nh)
+                    HIP_TRY(hipMemcpyAsync(ws.clr.as<uint64_t>() + napp, ws.hostpiv.p,
+                                           (size_t)nh * 8, hipMemcpyDeviceToDevice, s));
+                int wc = radix_sort_pairs(ws.clr.as<uint64_t>(), ws.clrv.as<uint64_t>(),
+                                          ws.clr2.as<uint64_t>(), ws.clrv2.as<uint64_t>(), m,
+                                          bit_length(binom_sat(n, p + 2)),
+                                          ws.rscratch.as<uint64_t>(), s);
+                clear_sorted = wc ? ws.clr2.as<uint64_t>() : ws.clr.as<uint64_t>();
+                nclear_sorted = m;
+            }
         }
     }
     HIP_TRY(hipStreamSynchronize(s));

@@ -143,12 +143,50 @@ struct Ctx {
         }
     }
 
+    // cidx of sigma + {w} (w not in sigma, v decreasing)
+    uint64_t insert_index(const int *v, int w) const
+    {
+        uint64_t c = 0;
+        int r = 0;
+        bool placed = false;
+        for (int i = p; i >= 0; --i) {
+            if (!placed && w < v[i]) {
+                c += C(w, r + 1);
+                ++r;
+                placed = true;
+            }
+            c += C(v[i], r + 1);
+            ++r;
+        }
+        if (!placed)
+            c += C(w, r + 1);
+        return c;
+    }
+
     // Every cofacet of sigma with diameter <= threshold.
     const std::vector<Entry> &coboundary(uint64_t sigma, float d)
     {
         scratch.clear();
         int v[8];
         decode(sigma, p, v);
+        if (P.bits) {
+            // common neighbours only: every new edge is within the threshold
+            for (int k = 0; k < P.words; ++k) {
+                uint64_t m = ~0ull;
+                for (int i = 0; i <= p; ++i)
+                    m &= P.bits[(int64_t)v[i] * P.words + k];
+                for (; m; m &= m - 1) {
+                    const int w = k * 64 + __builtin_ctzll(m);
+                    float nd = d;
+                    for (int i = 0; i <= p; ++i) {
+                        const float e = D(v[i], w);
+                        nd = e > nd ? e : nd;
+                    }
+                    scratch.push_back(Entry{nd, insert_index(v, w)});
+                }
+            }
+            return scratch;
+        }
         const float *rows[8];
         for (int i = 0; i <= p; ++i)
             rows[i] = P.dsq + (int64_t)v[i] * n;
@@ -215,6 +253,29 @@ struct Ctx {
         for (int i = 0; i <= p + 1; ++i)
             if (i != ui)
                 s[q++] = t[i];
+        if (P.bits) {
+            // candidates: common neighbours of sigma* above u
+            for (int k = P.words - 1; k >= 0 && k * 64 + 63 > u; --k) {
+                uint64_t m = ~0ull;
+                for (int i = 0; i <= p; ++i)
+                    m &= P.bits[(int64_t)s[i] * P.words + k];
+                for (; m; m &= m - 1) {
+                    const int w = k * 64 + __builtin_ctzll(m);
+                    if (w <= u)
+                        continue;
+                    bool all = true;
+                    for (int i = 0; i <= p && all; ++i)
+                        all = P.dsq[(int64_t)s[i] * n + w] <= dt;
+                    if (all)
+                        return false;
+                }
+            }
+            uint64_t c = 0;
+            for (int i = 0; i <= p; ++i)
+                c += C(s[i], p + 1 - i);
+            *sigma_out = c;
+            return true;
+        }
         int nxt = 0;  // next vertex of tau at or below w (tau is decreasing)
         for (int w = n - 1; w > u; --w) {
             if (nxt <= p + 1 && t[nxt] == w) {

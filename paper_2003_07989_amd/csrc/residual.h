@@ -14,6 +14,10 @@ struct ResidualProblem {
     float thr = 0.0f;                  // inclusive threshold
     const float *dsq = nullptr;        // n x n distances, zero diagonal
     const uint64_t *binom = nullptr;   // C(v,k) at [k * (n+1) + v], k <= p+2
+    // optional neighbour bitsets (bit u of row v: u != v, d(u,v) <= thr);
+    // when given, cofacets are found among common neighbours only
+    const uint64_t *bits = nullptr;
+    int words = 0;
     // non-apparent columns in coboundary order (diameter desc, cidx asc);
     // key = ~bits(diameter) in the low 32 bits
     int64_t ncols = 0;

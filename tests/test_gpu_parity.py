@@ -205,12 +205,7 @@ def test_uniform_square_32_matches_oracle(rpp):
 def test_torus400_matches_stored_oracle(rpp):
     """400-point noisy torus, dims 0-2, no threshold: against the oracle's
     barcodes stored by tests/golden/make_golden.py."""
-    import importlib.util
-    path = os.path.join(GOLDEN, "torus400.bars.txt")
-    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
-    mg = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mg)
-    head, exp = mg.read(path)
+    head, exp = _golden("torus400")
     cfg = w.WORKLOADS["torus400"]
     d = cfg["build"]()
     import hashlib
@@ -237,11 +232,63 @@ def test_sorted_pair_store_mode_matches_oracle(rpp, case):
 
 
 def test_torus400_sorted_pair_store(rpp):
-    import importlib.util
-    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(GOLDEN, "make_golden.py"))
-    mg = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mg)
-    head, exp = mg.read(os.path.join(GOLDEN, "torus400.bars.txt"))
+    head, exp = _golden("torus400")
     d = w.WORKLOADS["torus400"]["build"]()
     got = rpp.barcodes(d, 2, flags=rpp.RPP_SORTED_PAIR_STORE)
     assert_bars_equal(got.bars, exp, "torus400 sorted store")
+
+
+SPARSE_CASES = [c for c in CASES if not math.isinf(c[4])] + CASES[:8]
+
+
+@pytest.mark.parametrize("case", SPARSE_CASES, ids=["sp_" + c[0] for c in SPARSE_CASES])
+def test_sparse_path_matches_oracle(rpp, case):
+    """Neighbour-bitset enumeration (forced) gives the oracle's bars and
+    pairs."""
+    name, d, n, maxdim, thr = case
+    print("case", name, flush=True)
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_FORCE_SPARSE)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    g = rpp.barcodes(d, maxdim, thr, flags=f)
+    red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+    for p in range(1, maxdim + 1):
+        gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+        es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+        assert gs == es, (name, p)
+        st = g.stats[p]
+        assert st["n_kept"] == st["n_apparent"] + st["n_nonapparent"]
+        assert st["n_simplices"] == oracle.count_simplices(d, n, p, thr)
+
+
+def test_sparse_and_dense_paths_agree_on_maxdim3(rpp):
+    d = w.condensed_from_points(w.noisy_torus_points(60, 77))
+    thr = float(np.quantile(d, 0.2))
+    a = rpp.barcodes(d, 3, thr, flags=rpp.RPP_FORCE_DENSE)
+    b = rpp.barcodes(d, 3, thr, flags=rpp.RPP_FORCE_SPARSE)
+    assert_bars_equal(a.bars, b.bars, "dense vs sparse")
+    assert_bars_equal(a.bars, oracle.barcodes(d, 60, 3, thr, clearing=True), "vs oracle")
+
+
+def _golden(name):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_golden",
+                                                  os.path.join(GOLDEN, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    return mg.read(os.path.join(GOLDEN, name + ".bars.txt"))
+
+
+def test_sphere4096_matches_stored_oracle(rpp):
+    """4096 points on the unit sphere + noise 0.01, dims 0-2, threshold 0.4
+    (sparse path): against the oracle's stored barcodes."""
+    import hashlib
+    head, exp = _golden("sphere4096")
+    cfg = w.WORKLOADS["sphere4096"]
+    d = cfg["build"]()
+    assert hashlib.sha256(d.tobytes()).hexdigest() == head["sha256"], "input generator drifted"
+    got = rpp.barcodes(d, cfg["maxdim"], cfg["threshold"])
+    assert_bars_equal(got.bars, exp, "sphere4096")
+    for p in range(3):
+        assert got.stats[p]["n_simplices"] == head["dims"][p]["simplices"]
+        assert got.stats[p]["n_apparent"] + got.stats[p]["n_host_pairs"] == head["dims"][p]["pairs"]
