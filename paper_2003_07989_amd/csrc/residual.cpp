@@ -12,6 +12,12 @@
 #include "residual.h"
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 namespace rpp {
@@ -57,6 +63,21 @@ public:
         std::make_heap(h.begin(), h.end(), YoungerFirst());
         top_push(h.front(), (uint32_t)nstreams);
         ++nstreams;
+    }
+    // Add another column's current contents: its streams hold exactly its
+    // Z/2 sum (cancelled pairs were removed together), each a valid heap.
+    void add(const Column &o)
+    {
+        for (size_t k = 0; k < o.nstreams; ++k) {
+            const std::vector<Entry> &src = o.streams[k];
+            if (src.empty())
+                continue;
+            if (nstreams == streams.size())
+                streams.emplace_back();
+            streams[nstreams].assign(src.begin(), src.end());
+            top_push(streams[nstreams].front(), (uint32_t)nstreams);
+            ++nstreams;
+        }
     }
     // Low of the sum over Z/2: entries present in an even number of
     // streams cancel; the surviving low stays in its stream.
@@ -296,74 +317,238 @@ struct Ctx {
     }
 };
 
+// ---------------------------------------------------------------------------
+// A small persistent worker pool for the speculative phase.
+// ---------------------------------------------------------------------------
+class Pool {
+public:
+    static Pool &get()
+    {
+        static Pool pool;
+        return pool;
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    // Runs fn(tid) on every worker and on the calling thread (tid 0), and
+    // returns when all have finished.
+    void run(const std::function<void(int)> &fn)
+    {
+        if (workers_.empty()) {
+            fn(0);
+            return;
+        }
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            job_ = &fn;
+            pending_ = (int)workers_.size();
+            ++epoch_;
+        }
+        cv_.notify_all();
+        fn(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    Pool()
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        int n = (int)(hw ? hw : 1);
+        if (const char *e = getenv("RPP_HOST_THREADS"))
+            n = atoi(e);
+        n = std::max(1, std::min(n, 16));
+        for (int t = 1; t < n; ++t)
+            workers_.emplace_back([this, t] { loop(t); });
+    }
+    ~Pool()
+    {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            stop_ = true;
+            ++epoch_;
+        }
+        cv_.notify_all();
+        for (auto &w : workers_)
+            w.join();
+    }
+    void loop(int tid)
+    {
+        uint64_t seen = 0;
+        while (true) {
+            const std::function<void(int)> *job;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || epoch_ != seen; });
+                if (stop_)
+                    return;
+                seen = epoch_;
+                job = job_;
+            }
+            (*job)(tid);
+            std::unique_lock<std::mutex> lk(mu_);
+            if (--pending_ == 0)
+                done_.notify_one();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    int pending_ = 0;
+    uint64_t epoch_ = 0;
+    bool stop_ = false;
+};
+
 }  // namespace
 
+// Two phases, exact:
+//  A (parallel over columns): reduce each column against the apparent
+//    pivots only -- they are fixed before the reduction starts -- until its
+//    low is not an apparent pivot (or the column is zero).
+//  B (sequential, column order): the true reduction performs exactly the
+//    same additions up to that point, because a row is the pivot of at most
+//    one column, so apparent rows are never host pivots.  If the phase-A low
+//    is not a pivot of an earlier host column, the column is final;
+//    otherwise the reduction resumes from the phase-A state with the full
+//    pivot store.
 void residual_reduce(const ResidualProblem &P, ResidualResult &R)
 {
-    Ctx X(P);
-    std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
-    pivots.reserve((size_t)P.ncols * 2 + 16);
-    Column col;
+    const int64_t ncols = P.ncols;
+    std::vector<Entry> spec_low(ncols);
+    std::vector<uint8_t> spec_nz(ncols, 0);
+    std::vector<int64_t> spec_adds(ncols, 0);
+    std::vector<std::unique_ptr<Column>> state(ncols);
 
-    // two-layer lookup: the column (and its diameter) whose pivot is row tau
-    auto lookup = [&](uint64_t tau, float dt, uint64_t *other, float *odiam) -> bool {
-        auto it = pivots.find(tau);
-        if (it != pivots.end()) {
-            ++R.lookups_hash;
-            *other = R.sigma[it->second];
-            *odiam = R.birth[it->second];
-            return true;
-        }
-        ++R.lookups_apparent;
+    auto apparent_lookup = [&](const Ctx &X, uint64_t tau, float dt, uint64_t *other) -> bool {
         if (P.app_tau) {
             const uint64_t *b = P.app_tau, *e = P.app_tau + P.napp;
             const uint64_t *f = std::lower_bound(b, e, tau);
             if (f == e || *f != tau)
                 return false;
             *other = P.app_sigma[f - b];
-        } else if (!X.apparent_partner(tau, dt, other)) {
-            return false;
+            return true;
         }
-        *odiam = dt;  // an apparent column has the diameter of its tau
-        return true;
+        return X.apparent_partner(tau, dt, other);
     };
-    auto record_pair = [&](uint64_t sigma, float d, const Entry &lo) {
-        pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
-        R.sigma.push_back(sigma);
-        R.tau.push_back(lo.cidx);
-        R.birth.push_back(d);
-        R.death.push_back(lo.diam);
+    auto diam_of_key = [&](int64_t j) {
+        return __builtin_bit_cast(float, (uint32_t)~(uint32_t)P.col_key[j]);
     };
 
-    for (int64_t j = 0; j < P.ncols; ++j) {
-        const uint64_t sigma = P.col_cidx[j];
-        const float d = __builtin_bit_cast(float, (uint32_t)~(uint32_t)P.col_key[j]);
-        Entry lo{P.col_low_diam[j], P.col_low[j]};
-        if (lo.cidx == ~0ull) {  // empty coboundary: essential
-            R.ess_sigma.push_back(sigma);
-            R.ess_birth.push_back(d);
-            continue;
-        }
-        uint64_t other;
-        float odiam;
-        if (!lookup(lo.cidx, lo.diam, &other, &odiam)) {
-            record_pair(sigma, d, lo);  // low is free: nothing to add
-            ++R.emergent;
-            continue;
-        }
-        col.clear();
-        col.add(X.coboundary(sigma, d));
-        bool nonzero = true;
+    // ---- phase A ----------------------------------------------------------
+    Pool &pool = Pool::get();
+    std::atomic<int64_t> next{0};
+    std::atomic<int64_t> look_app{0};
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * pool.size())));
+    pool.run([&](int) {
+        Ctx X(P);
+        int64_t looks = 0;
         while (true) {
-            // Algorithm 2: add the ORIGINAL column of the pivot's owner
-            col.add(X.coboundary(other, odiam));
-            ++R.additions;
-            nonzero = col.low(lo);
-            if (!nonzero || !lookup(lo.cidx, lo.diam, &other, &odiam))
+            const int64_t j0 = next.fetch_add(chunk);
+            if (j0 >= ncols)
                 break;
+            const int64_t j1 = std::min(ncols, j0 + chunk);
+            for (int64_t j = j0; j < j1; ++j) {
+                Entry lo{P.col_low_diam[j], P.col_low[j]};
+                if (lo.cidx == ~0ull)
+                    continue;  // empty coboundary
+                uint64_t other;
+                ++looks;
+                if (!apparent_lookup(X, lo.cidx, lo.diam, &other)) {
+                    spec_low[j] = lo;
+                    spec_nz[j] = 1;
+                    continue;
+                }
+                std::unique_ptr<Column> col(new Column());
+                col->add(X.coboundary(P.col_cidx[j], diam_of_key(j)));
+                bool nz;
+                int64_t adds = 0;
+                while (true) {
+                    // Algorithm 2: add the ORIGINAL column of the pivot's owner
+                    // (an apparent column has the diameter of its tau)
+                    col->add(X.coboundary(other, lo.diam));
+                    ++adds;
+                    nz = col->low(lo);
+                    if (!nz)
+                        break;
+                    ++looks;
+                    if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
+                        break;
+                }
+                spec_low[j] = lo;
+                spec_nz[j] = nz ? 1 : 0;
+                spec_adds[j] = adds;
+                state[j] = std::move(col);
+            }
         }
-        if (nonzero) {
-            record_pair(sigma, d, lo);
+        look_app += looks;
+    });
+    R.lookups_apparent = look_app.load();
+
+    // ---- phase B ----------------------------------------------------------
+    // A finished column that needed additions keeps its heap state: its
+    // streams hold its reduced column R_k, which a later column adds in one
+    // step (the standard algorithm's R_j += R_k) instead of replaying k's
+    // reduction from the original column.  The copied entries are a subset
+    // of what the replay would regenerate, so this is never more work.
+    Ctx X(P);
+    std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
+    pivots.reserve((size_t)ncols * 2 + 16);
+    std::vector<std::unique_ptr<Column>> reduced;  // by index in R.sigma
+    reduced.reserve((size_t)ncols);
+    for (int64_t j = 0; j < ncols; ++j) {
+        const uint64_t sigma = P.col_cidx[j];
+        const float d = diam_of_key(j);
+        int64_t adds = spec_adds[j];
+        bool nz = spec_nz[j] != 0;
+        Entry lo = spec_low[j];
+        std::unique_ptr<Column> col = std::move(state[j]);
+        if (nz) {
+            auto it = pivots.find(lo.cidx);
+            if (it != pivots.end()) {
+                ++R.lookups_hash;
+                if (!col) {
+                    col.reset(new Column());
+                    col->add(X.coboundary(sigma, d));
+                }
+                // owner of the current low: host column k, or apparent column
+                int64_t k = it->second;
+                bool host = true;
+                uint64_t other = 0;
+                while (true) {
+                    if (!host)
+                        col->add(X.coboundary(other, lo.diam));  // diameter of its tau
+                    else if (reduced[k])
+                        col->add(*reduced[k]);
+                    else
+                        col->add(X.coboundary(R.sigma[k], R.birth[k]));
+                    ++adds;
+                    nz = col->low(lo);
+                    if (!nz)
+                        break;
+                    auto f = pivots.find(lo.cidx);
+                    if (f != pivots.end()) {
+                        ++R.lookups_hash;
+                        k = f->second;
+                        host = true;
+                        continue;
+                    }
+                    ++R.lookups_apparent;
+                    if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
+                        break;
+                    host = false;
+                }
+            }
+        }
+        R.additions += adds;
+        if (nz) {
+            if (adds == 0)
+                ++R.emergent;
+            pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
+            R.sigma.push_back(sigma);
+            R.tau.push_back(lo.cidx);
+            R.birth.push_back(d);
+            R.death.push_back(lo.diam);
+            reduced.push_back(adds ? std::move(col) : nullptr);
         } else {
             R.ess_sigma.push_back(sigma);
             R.ess_birth.push_back(d);
