@@ -78,6 +78,8 @@ enum {
  * within the threshold.  Results are identical. */
 #define RPP_FORCE_SPARSE 0x8u
 #define RPP_FORCE_DENSE 0x10u
+/* Fill rpp_bars.birth_edge / death_edge with each bar's critical edges. */
+#define RPP_WANT_CRITICAL_EDGES 0x20u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:
@@ -113,6 +115,13 @@ typedef struct {
     int64_t count;
     float *birth;
     float *death;
+    /* Only with RPP_WANT_CRITICAL_EDGES (else NULL): the edge, as a
+     * combinatorial index, whose length is the bar's birth / death value:
+     * the longest edge of the birth / death simplex, the one of largest
+     * cidx among equally long edges.  UINT64_MAX where there is none (H0
+     * births, essential deaths). */
+    uint64_t *birth_edge;
+    uint64_t *death_edge;
 } rpp_bars;
 
 /* Only filled with RPP_WANT_PAIRS: every persistence pair (sigma, tau) of
@@ -171,6 +180,33 @@ size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold);
 int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float threshold,
                        void *hip_stream, uint64_t *sigma_out, uint64_t *tau_out,
                        int64_t cap, int64_t *count, int64_t *n_columns);
+
+/* Condensed FP32 distance matrix of n points in R^d.  points_dev: n x d
+ * FP32 coordinates, row-major, device memory; dist_dev: n*(n-1)/2 floats,
+ * device memory, written in edge-cidx order.  Each distance is the square
+ * root of the sum of squared coordinate differences, accumulated in FP64 in
+ * coordinate order and rounded once to FP32 (the inputs' own recipe).
+ * Work is issued on hip_stream; the call returns after it completes. */
+int rpp_pdist_device(const float *points_dev, int32_t n, int32_t d, float *dist_dev,
+                     void *hip_stream);
+
+/* Gradient of a loss on the bars with respect to the point coordinates,
+ * through the bars' critical edges (a bar's birth and death values are the
+ * lengths of those edges, and d|x_u - x_v| / dx_u = (x_u - x_v)/|x_u - x_v|).
+ *   points_dev        n x d FP32 coordinates (device, row-major)
+ *   nbars             number of bars
+ *   birth_edge, death_edge   host arrays of nbars edge cidx (UINT64_MAX:
+ *                     no edge, no contribution), e.g. from a result made
+ *                     with RPP_WANT_CRITICAL_EDGES
+ *   grad_birth, grad_death   host arrays of nbars FP32 values dL/dbirth,
+ *                     dL/ddeath (may be NULL for all-zero)
+ *   grad_points_dev   n x d FP32 output (device), overwritten
+ * Each coordinate's gradient is summed in bar order (deterministic).  Edges
+ * of zero length contribute nothing.  Returns after completion. */
+int rpp_backward(const float *points_dev, int32_t n, int32_t d, int64_t nbars,
+                 const uint64_t *birth_edge, const uint64_t *death_edge,
+                 const float *grad_birth, const float *grad_death, float *grad_points_dev,
+                 void *hip_stream);
 
 void rpp_result_free(rpp_result *r);
 

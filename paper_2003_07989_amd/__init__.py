@@ -8,14 +8,15 @@ behind the C ABI of ``include/rpp.h``.  This package is the thin Python
 binding.  Importing it does not load the library; the first call does,
 and fails loudly if ``librpp.so`` has not been built.
 """
-from ._binding import (RPP_FORCE_DENSE, RPP_FORCE_SPARSE, RPP_MAX_DIM,
+from ._binding import (NO_EDGE, RPP_FORCE_DENSE, RPP_FORCE_SPARSE, RPP_MAX_DIM,
                        RPP_NO_ENCLOSING_RADIUS, RPP_SORTED_PAIR_STORE,
-                       RPP_WANT_PAIRS, Barcodes,
-                       RppError, apparent_pairs, barcodes, barcodes_device, barcodes_host,
-                       load, strerror, version, workspace_bytes)
+                       RPP_WANT_CRITICAL_EDGES, RPP_WANT_PAIRS, Barcodes,
+                       PointCloudBarcodes, RppError, apparent_pairs, backward_points, barcodes,
+                       barcodes_device, barcodes_host, load, pdist_device,
+                       point_cloud_barcodes, strerror, version, workspace_bytes)
 
-__all__ = ["RPP_FORCE_DENSE", "RPP_FORCE_SPARSE", "RPP_MAX_DIM",
-           "RPP_NO_ENCLOSING_RADIUS", "RPP_SORTED_PAIR_STORE",
-           "RPP_WANT_PAIRS", "Barcodes",
-           "RppError", "apparent_pairs", "barcodes", "barcodes_device", "barcodes_host",
-           "load", "strerror", "version", "workspace_bytes"]
+__all__ = ["NO_EDGE", "RPP_FORCE_DENSE", "RPP_FORCE_SPARSE", "RPP_MAX_DIM",
+           "RPP_NO_ENCLOSING_RADIUS", "RPP_SORTED_PAIR_STORE", "RPP_WANT_CRITICAL_EDGES",
+           "RPP_WANT_PAIRS", "Barcodes", "PointCloudBarcodes", "RppError", "apparent_pairs",
+           "backward_points", "barcodes", "barcodes_device", "barcodes_host", "load",
+           "pdist_device", "point_cloud_barcodes", "strerror", "version", "workspace_bytes"]

@@ -25,6 +25,8 @@ RPP_WANT_PAIRS = 0x2
 RPP_SORTED_PAIR_STORE = 0x4
 RPP_FORCE_SPARSE = 0x8
 RPP_FORCE_DENSE = 0x10
+RPP_WANT_CRITICAL_EDGES = 0x20
+NO_EDGE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
           -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE"}
@@ -47,7 +49,9 @@ class _Stats(ctypes.Structure):
 class _Bars(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("count", ctypes.c_int64),
                 ("birth", ctypes.POINTER(ctypes.c_float)),
-                ("death", ctypes.POINTER(ctypes.c_float))]
+                ("death", ctypes.POINTER(ctypes.c_float)),
+                ("birth_edge", ctypes.POINTER(ctypes.c_uint64)),
+                ("death_edge", ctypes.POINTER(ctypes.c_uint64))]
 
 
 class _Pairs(ctypes.Structure):
@@ -90,6 +94,13 @@ def load() -> ctypes.CDLL:
                                        P(ctypes.c_uint64), ctypes.c_int64, P(ctypes.c_int64),
                                        P(ctypes.c_int64)]
     lib.rpp_apparent_pairs.restype = ctypes.c_int
+    lib.rpp_pdist_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    lib.rpp_pdist_device.restype = ctypes.c_int
+    lib.rpp_backward.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                 P(ctypes.c_uint64), P(ctypes.c_uint64), P(ctypes.c_float),
+                                 P(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.rpp_backward.restype = ctypes.c_int
     lib.rpp_result_free.argtypes = [P(_Result)]
     lib.rpp_result_free.restype = None
     lib.rpp_strerror.argtypes = [ctypes.c_int]
@@ -117,11 +128,12 @@ class Barcodes:
     bars: list
     stats: list
     pairs: list = field(default=None)
+    edges: list = field(default=None)   # per dim (birth_edge, death_edge), with critical edges
 
 
 def _collect(res: "ctypes.POINTER(_Result)") -> Barcodes:
     r = res.contents
-    bars, stats, pairs = [], [], None
+    bars, stats, pairs, edges = [], [], None, None
     for p in range(r.maxdim + 1):
         b = r.dims[p]
         cnt = int(b.count)
@@ -132,6 +144,14 @@ def _collect(res: "ctypes.POINTER(_Result)") -> Barcodes:
             birth = np.zeros(0, np.float32)
             death = np.zeros(0, np.float32)
         bars.append((birth, death))
+        if bool(b.birth_edge):
+            if edges is None:
+                edges = []
+            if cnt:
+                edges.append((np.ctypeslib.as_array(b.birth_edge, shape=(cnt,)).copy(),
+                              np.ctypeslib.as_array(b.death_edge, shape=(cnt,)).copy()))
+            else:
+                edges.append((np.zeros(0, np.uint64), np.zeros(0, np.uint64)))
         s = r.stats[p]
         stats.append({name: getattr(s, name) for name, _ in _Stats._fields_})
     if bool(r.pairs):
@@ -145,7 +165,7 @@ def _collect(res: "ctypes.POINTER(_Result)") -> Barcodes:
             else:
                 pairs.append((np.zeros(0, np.uint64), np.zeros(0, np.uint64)))
     return Barcodes(int(r.n), int(r.maxdim), float(r.threshold_used),
-                    float(r.enclosing_radius), bars, stats, pairs)
+                    float(r.enclosing_radius), bars, stats, pairs, edges)
 
 
 def _n_from_len(m: int) -> int:
@@ -248,3 +268,82 @@ def version() -> str:
 
 def strerror(code: int) -> str:
     return load().rpp_strerror(int(code)).decode()
+
+
+def pdist_device(points: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """rpp_pdist_device: condensed FP32 distances of an (n, d) float32 CUDA
+    tensor (FP64 accumulation, one rounding)."""
+    if not (points.is_cuda and points.dtype == torch.float32 and points.dim() == 2):
+        raise TypeError("points must be an (n, d) float32 CUDA tensor")
+    pts = points.contiguous()
+    n, d = pts.shape
+    if out is None:
+        out = torch.empty(n * (n - 1) // 2, dtype=torch.float32, device=pts.device)
+    _check(load().rpp_pdist_device(ctypes.c_void_p(pts.data_ptr()), int(n), int(d),
+                                   ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(_stream_handle(stream))))
+    return out
+
+
+def backward_points(points: torch.Tensor, birth_edge, death_edge, grad_birth, grad_death,
+                    stream=None) -> torch.Tensor:
+    """rpp_backward: gradient w.r.t. (n, d) float32 CUDA coordinates of a
+    loss whose gradient w.r.t. each bar's (birth, death) is given."""
+    pts = points.contiguous()
+    n, d = pts.shape
+    be = np.ascontiguousarray(birth_edge, dtype=np.uint64)
+    de = np.ascontiguousarray(death_edge, dtype=np.uint64)
+    gb = np.ascontiguousarray(grad_birth, dtype=np.float32)
+    gd = np.ascontiguousarray(grad_death, dtype=np.float32)
+    out = torch.empty_like(pts)
+    U64, F32 = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_float)
+    _check(load().rpp_backward(ctypes.c_void_p(pts.data_ptr()), int(n), int(d), int(be.size),
+                               be.ctypes.data_as(U64), de.ctypes.data_as(U64),
+                               gb.ctypes.data_as(F32), gd.ctypes.data_as(F32),
+                               ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(_stream_handle(stream))))
+    return out
+
+
+class PointCloudBarcodes(torch.autograd.Function):
+    """Differentiable barcodes of a point cloud: forward returns one (k_p, 2)
+    float32 tensor of (birth, death) per dimension; backward sends each
+    bar's gradient to the endpoints of its critical edges (rpp_backward)."""
+
+    @staticmethod
+    def forward(ctx, points, maxdim, threshold=math.inf, flags=0):
+        pts = points.detach().contiguous()
+        dist = pdist_device(pts)
+        res = barcodes_device(dist, maxdim, threshold, flags=flags | RPP_WANT_CRITICAL_EDGES)
+        ctx.save_for_backward(pts)
+        ctx.edges = res.edges
+        ctx.counts = [len(b) for b, _ in res.bars]
+        outs = tuple(torch.from_numpy(np.stack([b, d], axis=1)).to(points.device)
+                     for b, d in res.bars)
+        return outs
+
+    @staticmethod
+    def backward(ctx, *grads):
+        (pts,) = ctx.saved_tensors
+        be, de, gb, gd = [], [], [], []
+        for p, g in enumerate(grads):
+            e_b, e_d = ctx.edges[p]
+            be.append(e_b)
+            de.append(e_d)
+            if g is None:
+                gb.append(np.zeros(ctx.counts[p], np.float32))
+                gd.append(np.zeros(ctx.counts[p], np.float32))
+            else:
+                gh = g.detach().float().cpu().numpy()
+                gh = np.where(np.isfinite(gh), gh, 0.0).astype(np.float32)
+                gb.append(gh[:, 0])
+                gd.append(gh[:, 1])
+        grad = backward_points(pts, np.concatenate(be), np.concatenate(de),
+                               np.concatenate(gb), np.concatenate(gd))
+        return grad, None, None, None
+
+
+def point_cloud_barcodes(points: torch.Tensor, maxdim: int, threshold: float = math.inf,
+                         flags: int = 0):
+    """Differentiable barcodes (see PointCloudBarcodes)."""
+    return PointCloudBarcodes.apply(points, maxdim, threshold, flags)

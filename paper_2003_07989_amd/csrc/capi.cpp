@@ -83,16 +83,30 @@ int build_result(const rpp::RunOut &ro, int n, int maxdim, uint32_t flags, rpp_r
             return D.death[x] < D.death[y];
         });
         std::vector<float> b(idx.size()), d(idx.size());
+        std::vector<uint64_t> be(idx.size()), de(idx.size());
+        const bool crit = (flags & RPP_WANT_CRITICAL_EDGES) && D.birth_edge.size() == idx.size();
         for (size_t i = 0; i < idx.size(); ++i) {
             b[i] = D.birth[idx[i]] + 0.0f;
             d[i] = D.death[idx[i]] + 0.0f;
+            if (crit) {
+                be[i] = D.birth_edge[idx[i]];
+                de[i] = D.death_edge[idx[i]];
+            }
         }
         r->dims[p].dim = p;
         r->dims[p].count = (int64_t)b.size();
         r->dims[p].birth = dup(b);
         r->dims[p].death = dup(d);
+        if (flags & RPP_WANT_CRITICAL_EDGES) {
+            if (!crit)
+                be.assign(idx.size(), UINT64_MAX), de.assign(idx.size(), UINT64_MAX);
+            r->dims[p].birth_edge = dup(be);
+            r->dims[p].death_edge = dup(de);
+        }
         r->stats[p] = D.st;
-        if (!r->dims[p].birth || !r->dims[p].death) {
+        if (!r->dims[p].birth || !r->dims[p].death ||
+            ((flags & RPP_WANT_CRITICAL_EDGES) &&
+             (!r->dims[p].birth_edge || !r->dims[p].death_edge))) {
             rpp_result_free(r);
             return fail(RPP_E_NOMEM, "result allocation failed");
         }
@@ -223,6 +237,62 @@ int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float thresh
     }
 }
 
+int rpp_pdist_device(const float *points_dev, int32_t n, int32_t d, float *dist_dev,
+                     void *hip_stream)
+{
+    if (n < 1 || d < 1)
+        return fail(RPP_E_INVAL, "need n >= 1 and d >= 1");
+    if (n > 1 && (!points_dev || !dist_dev))
+        return fail(RPP_E_INVAL, "null device pointer");
+    if ((int64_t)n * n > (int64_t)1 << 31)
+        return fail(RPP_E_RANGE, "n too large");
+    std::string err;
+    int rc = rpp::run_pdist(points_dev, n, d, dist_dev, static_cast<hipStream_t>(hip_stream), err);
+    return rc ? fail(rc, err) : RPP_OK;
+}
+
+int rpp_backward(const float *points_dev, int32_t n, int32_t d, int64_t nbars,
+                 const uint64_t *birth_edge, const uint64_t *death_edge,
+                 const float *grad_birth, const float *grad_death, float *grad_points_dev,
+                 void *hip_stream)
+{
+    if (n < 1 || d < 1 || nbars < 0)
+        return fail(RPP_E_INVAL, "need n >= 1, d >= 1, nbars >= 0");
+    if (!points_dev || !grad_points_dev)
+        return fail(RPP_E_INVAL, "null device pointer");
+    if (nbars > 0 && (!birth_edge || !death_edge))
+        return fail(RPP_E_INVAL, "edge arrays are NULL");
+    const uint64_t E = (uint64_t)n * (n - 1) / 2;
+    try {
+        std::vector<uint64_t> edges;
+        std::vector<float> g;
+        edges.reserve((size_t)nbars * 2);
+        g.reserve((size_t)nbars * 2);
+        for (int64_t i = 0; i < nbars; ++i) {
+            const float gb = grad_birth ? grad_birth[i] : 0.0f;
+            const float gd = grad_death ? grad_death[i] : 0.0f;
+            if (birth_edge[i] != UINT64_MAX && gb != 0.0f) {
+                if (birth_edge[i] >= E)
+                    return fail(RPP_E_INVAL, "birth edge index out of range");
+                edges.push_back(birth_edge[i]);
+                g.push_back(gb);
+            }
+            if (death_edge[i] != UINT64_MAX && gd != 0.0f) {
+                if (death_edge[i] >= E)
+                    return fail(RPP_E_INVAL, "death edge index out of range");
+                edges.push_back(death_edge[i]);
+                g.push_back(gd);
+            }
+        }
+        std::string err;
+        int rc = rpp::run_backward(points_dev, n, d, edges, g, grad_points_dev,
+                                   static_cast<hipStream_t>(hip_stream), err);
+        return rc ? fail(rc, err) : RPP_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RPP_E_NOMEM, "host allocation failed");
+    }
+}
+
 void rpp_result_free(rpp_result *r)
 {
     if (!r)
@@ -231,6 +301,8 @@ void rpp_result_free(rpp_result *r)
         for (int p = 0; p <= r->maxdim; ++p) {
             free(r->dims[p].birth);
             free(r->dims[p].death);
+            free(r->dims[p].birth_edge);
+            free(r->dims[p].death_edge);
         }
     if (r->pairs)
         for (int p = 0; p <= r->maxdim; ++p) {

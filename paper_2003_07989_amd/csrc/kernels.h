@@ -130,11 +130,23 @@ void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStr
 // Edges sorted in coboundary order (diameter descending, cidx ascending);
 // processed from the back, i.e. in filtration order.  Sets the MST bit of
 // each spanning-forest edge, writes the nonzero death diameters to deaths
-// and counters[0] = #deaths, counters[1] = #merges.  uf_scratch: 2n ints,
-// used when the union-find arrays do not fit in LDS.
+// (and the edge to death_edges[i]), counters[0] = #deaths, counters[1] =
+// #merges.  uf_scratch: 2n ints, used when the union-find arrays do not fit
+// in LDS.
 void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
-                    uint32_t *mst_bits, float *deaths, int *counters, int *uf_scratch,
-                    hipStream_t s);
+                    uint32_t *mst_bits, float *deaths, uint64_t *death_edges, int *counters,
+                    int *uf_scratch, hipStream_t s);
+
+// ---- distances and gradients ---------------------------------------------
+// Condensed FP32 distances of n points in R^d (row-major FP32 coordinates):
+// squared differences summed in FP64 in coordinate order, FP64 square root,
+// one rounding to FP32.  No contraction into fused multiply-adds.
+void launch_pdist(const float *pts, int n, int d, float *dist, hipStream_t s);
+// grad[u*d + k] = sum over terms t (in order) touching u of
+//   g_t * (x_u - x_v)_k / |x_u - x_v|   (u, v the endpoints of edge e_t),
+// zero-length edges contributing nothing.  One thread per coordinate.
+void launch_edge_grad(const float *pts, int n, int d, const uint64_t *edges, const float *g,
+                      int64_t nterms, float *grad, hipStream_t s);
 
 // ---- a6: LDS radix sort -------------------------------------------------
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).  The

@@ -1096,6 +1096,7 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
                                                 int64_t nedges, int n,
                                                 uint32_t *__restrict__ mst_bits,
                                                 float *__restrict__ deaths,
+                                                uint64_t *__restrict__ death_edges,
                                                 int *__restrict__ counters,
                                                 int *__restrict__ uf_scratch)
 {
@@ -1151,8 +1152,11 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
             if (win) {
                 parent[max(ra, rb)] = min(ra, rb);
                 atomicOr(&mst_bits[c >> 5], 1u << (c & 31));
-                if (dm > 0.0f)
-                    deaths[atomicAdd(&s_deaths, 1)] = dm;
+                if (dm > 0.0f) {
+                    const int slot = atomicAdd(&s_deaths, 1);
+                    deaths[slot] = dm;
+                    death_edges[slot] = c;
+                }
                 atomicAdd(&s_merges, 1);
                 active = false;
             }
@@ -1167,17 +1171,84 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
 }
 
 void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
-                    uint32_t *mst_bits, float *deaths, int *counters, int *uf_scratch,
-                    hipStream_t s)
+                    uint32_t *mst_bits, float *deaths, uint64_t *death_edges, int *counters,
+                    int *uf_scratch, hipStream_t s)
 {
     const size_t lds = (size_t)2 * n * sizeof(int);
     if (lds <= 60 * 1024) {
         hipLaunchKernelGGL(k_kruskal<true>, dim3(1), dim3(KT), lds, s, edge_key, edge_cidx,
-                           nedges, n, mst_bits, deaths, counters, uf_scratch);
+                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch);
     } else {
         hipLaunchKernelGGL(k_kruskal<false>, dim3(1), dim3(KT), 0, s, edge_key, edge_cidx,
-                           nedges, n, mst_bits, deaths, counters, uf_scratch);
+                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch);
     }
+}
+
+// ===========================================================================
+// distances from coordinates, and the critical-edge gradient
+// ===========================================================================
+__global__ void k_pdist(const float *__restrict__ pts, int n, int d, float *__restrict__ dist)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * (n - 1) / 2)
+        return;
+    int a, b;
+    decode_edge((uint64_t)e, a, b);
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double df = __dsub_rn((double)pts[(int64_t)a * d + k], (double)pts[(int64_t)b * d + k]);
+        acc = __dadd_rn(acc, __dmul_rn(df, df));
+    }
+    dist[e] = __double2float_rn(__dsqrt_rn(acc));
+}
+
+void launch_pdist(const float *pts, int n, int d, float *dist, hipStream_t s)
+{
+    const int64_t m = (int64_t)n * (n - 1) / 2;
+    if (m <= 0)
+        return;
+    hipLaunchKernelGGL(k_pdist, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, pts, n, d,
+                       dist);
+}
+
+__global__ void k_edge_grad(const float *__restrict__ pts, int n, int d,
+                            const uint64_t *__restrict__ edges, const float *__restrict__ g,
+                            int64_t nterms, float *__restrict__ grad)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * d)
+        return;
+    const int u = (int)(t / d), k = (int)(t % d);
+    double acc = 0.0;
+    for (int64_t i = 0; i < nterms; ++i) {
+        const uint64_t e = edges[i];
+        if (e == NONE)
+            continue;
+        int a, b;
+        decode_edge(e, a, b);
+        if (a != u && b != u)
+            continue;
+        const int o = (a == u) ? b : a;
+        double len2 = 0.0;
+        for (int q = 0; q < d; ++q) {
+            const double df = (double)pts[(int64_t)u * d + q] - (double)pts[(int64_t)o * d + q];
+            len2 += df * df;
+        }
+        if (len2 > 0.0)
+            acc += (double)g[i] * ((double)pts[(int64_t)u * d + k] - (double)pts[(int64_t)o * d + k]) /
+                   sqrt(len2);
+    }
+    grad[t] = (float)acc;
+}
+
+void launch_edge_grad(const float *pts, int n, int d, const uint64_t *edges, const float *g,
+                      int64_t nterms, float *grad, hipStream_t s)
+{
+    const int64_t m = (int64_t)n * d;
+    if (m <= 0)
+        return;
+    hipLaunchKernelGGL(k_edge_grad, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, pts, n,
+                       d, edges, g, nterms, grad);
 }
 
 // ===========================================================================

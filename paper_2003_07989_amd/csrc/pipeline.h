@@ -15,6 +15,7 @@ namespace rpp {
 // rpp_result.
 struct DimOut {
     std::vector<float> birth, death;     // bars, not yet sorted
+    std::vector<uint64_t> birth_edge, death_edge;  // critical edges (same order)
     std::vector<uint64_t> pair_sigma, pair_tau;  // only with RPP_WANT_PAIRS
     rpp_dim_stats st{};
 };
@@ -43,6 +44,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);
 int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
                       std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau,
                       int64_t &ncols, std::string &err);
+
+int run_pdist(const float *pts, int n, int d, float *dist, hipStream_t s, std::string &err);
+// edges[i] / g[i]: gradient terms (edge cidx or UINT64_MAX, dL/dlength)
+int run_backward(const float *pts, int n, int d, const std::vector<uint64_t> &edges,
+                 const std::vector<float> &g, float *grad, hipStream_t s, std::string &err);
 
 // Exact binomial table C(v,k), k = 0..kmax, v = 0..n (saturating at
 // UINT64_MAX).

@@ -56,6 +56,40 @@ uint64_t binom_sat(int n, int k)
     return t[(size_t)k * (n + 1) + n];
 }
 
+// Longest edge of the q-simplex c (cidx), the one of largest edge cidx
+// among equally long edges.
+static uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, uint64_t c, int q)
+{
+    int v[8];
+    int hi = n;
+    for (int pos = 0; pos <= q; ++pos) {
+        const int k = q + 1 - pos;
+        int lo = k - 1, h = hi - 1;
+        while (lo < h) {
+            const int mid = (lo + h + 1) >> 1;
+            if (binom[(size_t)k * (n + 1) + mid] <= c)
+                lo = mid;
+            else
+                h = mid - 1;
+        }
+        v[pos] = lo;
+        c -= binom[(size_t)k * (n + 1) + lo];
+        hi = lo;
+    }
+    float best = -1.0f;
+    uint64_t be = UINT64_MAX;
+    for (int i = 0; i <= q; ++i)
+        for (int j = i + 1; j <= q; ++j) {
+            const float e = dsq[(size_t)v[i] * n + v[j]];
+            const uint64_t ec = (uint64_t)v[i] * (v[i] - 1) / 2 + (uint64_t)v[j];  // v[i] > v[j]
+            if (e > best || (e == best && ec > be)) {
+                best = e;
+                be = ec;
+            }
+        }
+    return be;
+}
+
 static int bit_length(uint64_t x)
 {
     return x ? 64 - __builtin_clzll(x) : 0;
@@ -121,7 +155,7 @@ struct Workspace {
     std::mutex mu;
     DevBuf dsq, rowmax, scal, binom;
     DevBuf ekey, eval, ekey2, eval2;  // edges for H0
-    DevBuf mst, deaths, ufs;
+    DevBuf mst, deaths, dedges, ufs;
     DevBuf tcount, toff, scan, tcount2, toff2;
     DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
     DevBuf bits;                     // sparse path: neighbour bitsets
@@ -131,6 +165,7 @@ struct Workspace {
     DevBuf nkey, nval, nkey2, nval2;  // non-apparent columns
     DevBuf clear, next, hostpiv;
     DevBuf lowc, lowd;               // lows of the non-apparent columns
+    DevBuf gedges, gvals;            // backward: gradient terms
     DevBuf rscratch, scancnt;
     HostBuf h_app_tau, h_app_sigma, h_na_key, h_na_cidx, h_low, h_lowd, h_small;
     int binom_n = -1, binom_k = -1;
@@ -445,6 +480,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(nedges) * 8);
         ALLOC_TRY(ws.mst, (size_t)(E / 32 + 2) * 4);
         ALLOC_TRY(ws.deaths, (size_t)n * 4);
+        ALLOC_TRY(ws.dedges, (size_t)n * 8);
         ALLOC_TRY(ws.ufs, (size_t)2 * n * 4 + 64);
         launch_desc_keys(ws.cdiam.as<float>(), nedges, ws.ekey.as<uint64_t>(), s);
         HIP_TRY(hipMemcpyAsync(ws.eval.p, ws.ccidx.p, (size_t)nedges * 8,
@@ -457,20 +493,27 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         launch_fill_u32(ws.mst.as<uint32_t>(), (int64_t)(E / 32 + 1), 0u, s);
         int *counters = ws.scal.as<int>() + 8;
         launch_kruskal(sk, sv, nedges, n, ws.mst.as<uint32_t>(), ws.deaths.as<float>(),
-                       counters, ws.ufs.as<int>(), s);
+                       ws.dedges.as<uint64_t>(), counters, ws.ufs.as<int>(), s);
         int hc[2];
         HIP_TRY(hipMemcpyAsync(hc, counters, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         DimOut &d0 = out.dims[0];
         d0.death.resize(hc[0]);
-        if (hc[0])
+        d0.death_edge.resize(hc[0]);
+        if (hc[0]) {
             HIP_TRY(hipMemcpy(d0.death.data(), ws.deaths.p, (size_t)hc[0] * 4,
                               hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(d0.death_edge.data(), ws.dedges.p, (size_t)hc[0] * 8,
+                              hipMemcpyDeviceToHost));
+        }
         d0.birth.assign(hc[0], 0.0f);
+        d0.birth_edge.assign(hc[0], UINT64_MAX);
         const int ncomp = n - hc[1];
         for (int i = 0; i < ncomp; ++i) {
             d0.birth.push_back(0.0f);
             d0.death.push_back(INFINITY);
+            d0.birth_edge.push_back(UINT64_MAX);
+            d0.death_edge.push_back(UINT64_MAX);
         }
         d0.st.n_candidates = n;
         d0.st.n_simplices = n;
@@ -655,10 +698,17 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             if (RR.death[i] > RR.birth[i]) {
                 D.birth.push_back(RR.birth[i]);
                 D.death.push_back(RR.death[i]);
+                D.birth_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
+                                                     RR.sigma[i], p));
+                D.death_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
+                                                     RR.tau[i], p + 1));
             }
         for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
             D.birth.push_back(RR.ess_birth[i]);
             D.death.push_back(INFINITY);
+            D.birth_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
+                                                 RR.ess_sigma[i], p));
+            D.death_edge.push_back(UINT64_MAX);
         }
         D.st.n_candidates = ncand;
         D.st.n_thresholded = (int64_t)nthr;
@@ -715,6 +765,32 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             }
         }
     }
+    HIP_TRY(hipStreamSynchronize(s));
+    return RPP_OK;
+}
+
+int run_pdist(const float *pts, int n, int d, float *dist, hipStream_t s, std::string &err)
+{
+    launch_pdist(pts, n, d, dist, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return RPP_OK;
+}
+
+int run_backward(const float *pts, int n, int d, const std::vector<uint64_t> &edges,
+                 const std::vector<float> &g, float *grad, hipStream_t s, std::string &err)
+{
+    Workspace &ws = workspace_for_current_device();
+    std::lock_guard<std::mutex> lk(ws.mu);
+    const int64_t m = (int64_t)edges.size();
+    ALLOC_TRY(ws.gedges, (size_t)(m + 1) * 8);
+    ALLOC_TRY(ws.gvals, (size_t)(m + 1) * 4);
+    if (m) {
+        HIP_TRY(hipMemcpyAsync(ws.gedges.p, edges.data(), (size_t)m * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ws.gvals.p, g.data(), (size_t)m * 4, hipMemcpyHostToDevice, s));
+    }
+    launch_edge_grad(pts, n, d, ws.gedges.as<uint64_t>(), ws.gvals.as<float>(), m, grad, s);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return RPP_OK;
 }
