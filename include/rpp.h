@@ -80,6 +80,12 @@ enum {
 #define RPP_FORCE_DENSE 0x10u
 /* Fill rpp_bars.birth_edge / death_edge with each bar's critical edges. */
 #define RPP_WANT_CRITICAL_EDGES 0x20u
+/* rpp_barcodes_batch: launch each stage eagerly instead of replaying the
+ * captured graph (results identical). */
+#define RPP_BATCH_NO_GRAPH 0x40u
+/* rpp_barcodes_batch: when no tuned parameters exist for a shape, time the
+ * candidates on this batch first (results identical). */
+#define RPP_BATCH_AUTOTUNE 0x80u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:
@@ -165,6 +171,26 @@ int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
 int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
                         void *workspace_dev, size_t workspace_bytes, void *hip_stream,
                         uint32_t flags, rpp_result **out);
+
+/* One cloud of a batch: a device-resident condensed matrix (as for
+ * rpp_barcodes_device), its size, highest dimension and threshold. */
+typedef struct {
+    const float *dist_dev;
+    int32_t n;
+    int32_t maxdim;
+    float threshold;
+} rpp_request;
+
+/* Barcodes of count clouds at once.  Requests with equal (n, maxdim) form a
+ * shape group: each stage runs as one launch over the whole group, the GPU
+ * stages of a dimension are captured once per shape as a hipGraph and
+ * replayed, and the host reductions of the clouds run in parallel.  Results
+ * are identical to rpp_barcodes_device on each cloud with the dense path.
+ * outs: count pointers, each set to a library-allocated result (free each
+ * with rpp_result_free); on error every out is NULL.  flags: RPP_* (pair
+ * lists are not supported here). */
+int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream, uint32_t flags,
+                       rpp_result **outs);
 
 /* Upper bound of the device workspace that rpp_barcodes_device needs for a
  * matrix of n points, dimensions 0..maxdim (0 on invalid arguments). */

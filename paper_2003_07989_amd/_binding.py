@@ -26,6 +26,8 @@ RPP_SORTED_PAIR_STORE = 0x4
 RPP_FORCE_SPARSE = 0x8
 RPP_FORCE_DENSE = 0x10
 RPP_WANT_CRITICAL_EDGES = 0x20
+RPP_BATCH_NO_GRAPH = 0x40
+RPP_BATCH_AUTOTUNE = 0x80
 NO_EDGE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
@@ -58,6 +60,11 @@ class _Pairs(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("count", ctypes.c_int64),
                 ("sigma", ctypes.POINTER(ctypes.c_uint64)),
                 ("tau", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("dist_dev", ctypes.c_void_p), ("n", ctypes.c_int32), ("maxdim", ctypes.c_int32),
+                ("threshold", ctypes.c_float)]
 
 
 class _Result(ctypes.Structure):
@@ -101,6 +108,9 @@ def load() -> ctypes.CDLL:
                                  P(ctypes.c_uint64), P(ctypes.c_uint64), P(ctypes.c_float),
                                  P(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
     lib.rpp_backward.restype = ctypes.c_int
+    lib.rpp_barcodes_batch.argtypes = [ctypes.c_int32, P(_Request), ctypes.c_void_p,
+                                       ctypes.c_uint32, P(P(_Result))]
+    lib.rpp_barcodes_batch.restype = ctypes.c_int
     lib.rpp_result_free.argtypes = [P(_Result)]
     lib.rpp_result_free.restype = None
     lib.rpp_strerror.argtypes = [ctypes.c_int]
@@ -347,3 +357,37 @@ def point_cloud_barcodes(points: torch.Tensor, maxdim: int, threshold: float = m
                          flags: int = 0):
     """Differentiable barcodes (see PointCloudBarcodes)."""
     return PointCloudBarcodes.apply(points, maxdim, threshold, flags)
+
+
+def barcodes_batch(dists, maxdims, thresholds=None, flags: int = 0, stream=None) -> list:
+    """rpp_barcodes_batch on a list of contiguous float32 CUDA tensors
+    (condensed matrices); maxdims / thresholds: one value or one per cloud.
+    Returns a list of Barcodes in input order."""
+    m = len(dists)
+    if not isinstance(maxdims, (list, tuple)):
+        maxdims = [maxdims] * m
+    if thresholds is None:
+        thresholds = [math.inf] * m
+    elif not isinstance(thresholds, (list, tuple)):
+        thresholds = [thresholds] * m
+    reqs = (_Request * max(m, 1))()
+    for i, t in enumerate(dists):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("each distance array must be a contiguous float32 CUDA tensor")
+        reqs[i].dist_dev = t.data_ptr() if t.numel() else None
+        reqs[i].n = _n_from_len(t.numel())
+        reqs[i].maxdim = int(maxdims[i])
+        reqs[i].threshold = float(thresholds[i])
+    outs = (ctypes.POINTER(_Result) * max(m, 1))()
+    lib = load()
+    _check(lib.rpp_barcodes_batch(m, reqs, ctypes.c_void_p(_stream_handle(stream)), int(flags),
+                                  outs))
+    res = []
+    try:
+        for i in range(m):
+            res.append(_collect(outs[i]))
+    finally:
+        for i in range(m):
+            if bool(outs[i]):
+                lib.rpp_result_free(outs[i])
+    return res

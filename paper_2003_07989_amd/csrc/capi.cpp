@@ -163,6 +163,79 @@ int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float 
     }
 }
 
+int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream, uint32_t flags,
+                       rpp_result **outs)
+{
+    if (count < 0 || (count > 0 && (!reqs || !outs)))
+        return fail(RPP_E_INVAL, "bad batch arguments");
+    for (int32_t i = 0; i < count; ++i)
+        outs[i] = nullptr;
+    if (flags & RPP_WANT_PAIRS)
+        return fail(RPP_E_INVAL, "pair lists are not available for batches");
+    for (int32_t i = 0; i < count; ++i) {
+        rpp_result *dummy = nullptr;
+        int rc = check_args(reqs[i].n, reqs[i].maxdim, reqs[i].threshold, &dummy);
+        if (rc)
+            return rc;
+        if (reqs[i].n > 1 && !reqs[i].dist_dev)
+            return fail(RPP_E_INVAL, "dist_dev is NULL");
+    }
+    try {
+        // shape groups, in first-appearance order
+        std::vector<std::pair<std::pair<int, int>, std::vector<int>>> groups;
+        for (int32_t i = 0; i < count; ++i) {
+            std::pair<int, int> key{reqs[i].n, reqs[i].maxdim};
+            auto it = std::find_if(groups.begin(), groups.end(),
+                                   [&](const auto &g) { return g.first == key; });
+            if (it == groups.end())
+                groups.push_back({key, {i}});
+            else
+                it->second.push_back(i);
+        }
+        std::vector<rpp::RunOut> all(count);
+        for (auto &g : groups) {
+            std::vector<const float *> ptrs;
+            std::vector<float> thr;
+            for (int i : g.second) {
+                ptrs.push_back(reqs[i].dist_dev);
+                thr.push_back(reqs[i].threshold);
+            }
+            rpp::BatchArgs a;
+            a.count = (int)g.second.size();
+            a.n = g.first.first;
+            a.maxdim = g.first.second;
+            a.dist_dev = ptrs.data();
+            a.threshold = thr.data();
+            a.flags = flags;
+            a.stream = static_cast<hipStream_t>(hip_stream);
+            a.use_graph = !(flags & RPP_BATCH_NO_GRAPH);
+            a.tune = (flags & RPP_BATCH_AUTOTUNE) != 0;
+            const char *gs = getenv("RPP_APPARENT_GROUP");
+            a.group = gs ? atoi(gs) : 0;
+            std::vector<rpp::RunOut> outs;
+            std::string err;
+            int rc = rpp::run_batch(a, outs, err);
+            if (rc)
+                return fail(rc, err);
+            for (size_t k = 0; k < g.second.size(); ++k)
+                all[g.second[k]] = std::move(outs[k]);
+        }
+        for (int32_t i = 0; i < count; ++i) {
+            int rc = build_result(all[i], reqs[i].n, reqs[i].maxdim, flags, &outs[i]);
+            if (rc) {
+                for (int32_t j = 0; j < i; ++j) {
+                    rpp_result_free(outs[j]);
+                    outs[j] = nullptr;
+                }
+                return rc;
+            }
+        }
+        return RPP_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RPP_E_NOMEM, "host allocation failed");
+    }
+}
+
 int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
                  rpp_result **out)
 {

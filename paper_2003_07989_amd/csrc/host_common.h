@@ -1,0 +1,156 @@
+// host_common.h -- host-side helpers shared by the single-cloud and the
+// batched pipelines: grow-only device / pinned buffers, event timers, error
+// macros and small index utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rpp.h"
+
+namespace rpp {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool ensure(size_t bytes)
+    {
+        if (bytes <= cap && p)
+            return true;
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t b = bytes < 256 ? 256 : bytes;
+        b = (b + 4095) & ~(size_t)4095;
+        if (hipMalloc(&p, b) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        cap = b;
+        return true;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+struct HostBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool ensure(size_t bytes)
+    {
+        if (bytes <= cap && p)
+            return true;
+        if (p)
+            (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t b = bytes < 256 ? 256 : bytes;
+        if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        cap = b;
+        return true;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// error helpers
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return RPP_E_DEVICE;                                                   \
+        }                                                                          \
+    } while (0)
+
+#define ALLOC_TRY(buf, bytes)                                                      \
+    do {                                                                           \
+        if (!(buf).ensure(bytes)) {                                                \
+            err = "allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
+            return RPP_E_NOMEM;                                                    \
+        }                                                                          \
+    } while (0)
+
+struct GpuTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit GpuTimer(hipStream_t st) : s(st)
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~GpuTimer()
+    {
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+    }
+    void start() { (void)hipEventRecord(a, s); }
+    void stop() { (void)hipEventRecord(b, s); }
+    float ms()
+    {
+        float m = 0.0f;
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&m, a, b);
+        return m;
+    }
+};
+
+// Longest edge of the q-simplex c (cidx), the one of largest edge cidx
+// among equally long edges.
+inline uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, uint64_t c, int q)
+{
+    int v[8];
+    int hi = n;
+    for (int pos = 0; pos <= q; ++pos) {
+        const int k = q + 1 - pos;
+        int lo = k - 1, h = hi - 1;
+        while (lo < h) {
+            const int mid = (lo + h + 1) >> 1;
+            if (binom[(size_t)k * (n + 1) + mid] <= c)
+                lo = mid;
+            else
+                h = mid - 1;
+        }
+        v[pos] = lo;
+        c -= binom[(size_t)k * (n + 1) + lo];
+        hi = lo;
+    }
+    float best = -1.0f;
+    uint64_t be = UINT64_MAX;
+    for (int i = 0; i <= q; ++i)
+        for (int j = i + 1; j <= q; ++j) {
+            const float e = dsq[(size_t)v[i] * n + v[j]];
+            const uint64_t ec = (uint64_t)v[i] * (v[i] - 1) / 2 + (uint64_t)v[j];  // v[i] > v[j]
+            if (e > best || (e == best && ec > be)) {
+                best = e;
+                be = ec;
+            }
+        }
+    return be;
+}
+
+inline int bit_length(uint64_t x)
+{
+    return x ? 64 - __builtin_clzll(x) : 0;
+}
+
+
+}  // namespace rpp

@@ -11,6 +11,23 @@
 
 namespace rpp {
 
+// Batched launches process several clouds at once: cloud c is blockIdx.y
+// (blockIdx.x for one-workgroup-per-cloud kernels), its arrays start
+// c * stride elements in, and its element count is count[c * cstride] when
+// count is set (device memory), else the launch's own count.  The default
+// describes a single cloud.
+struct Batch {
+    const uint64_t *count = nullptr;
+    int64_t cstride = 0;
+    int64_t stride = 0;
+};
+#ifdef __HIPCC__
+__device__ __forceinline__ int64_t batch_count(const Batch &b, int64_t c, int64_t fallback)
+{
+    return b.count ? (int64_t)b.count[c * b.cstride] : fallback;
+}
+#endif
+
 // ---- a1: staging -------------------------------------------------------
 // Square n x n copy (zero diagonal, -0 folded to +0), per-row maxima, and a
 // validity flag (bit 0 set when an entry is NaN, infinite or negative).
@@ -18,6 +35,12 @@ void launch_stage(const float *dcond, int n, float *dsq, float *rowmax, uint32_t
                   hipStream_t s);
 // out[0] = min over rows of rowmax (the enclosing radius).
 void launch_min(const float *x, int n, float *out, hipStream_t s);
+// Batched staging of nb clouds of n points (inputs and outputs packed cloud
+// after cloud), and per-cloud radius / threshold used.
+void launch_stage_b(const float *dcond, int n, int nb, float *dsq, float *rowmax, uint32_t *bad,
+                    hipStream_t s);
+void launch_radius_b(const float *rowmax, int n, int nb, const float *req, int no_radius,
+                     float *radius, float *thr, hipStream_t s);
 
 // ---- device-wide helpers --------------------------------------------------
 void launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
@@ -26,6 +49,10 @@ void launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 int64_t scan_scratch_words(int64_t len);
 void launch_exclusive_scan(const uint32_t *in, int64_t len, uint64_t *out, uint64_t *scratch,
                            hipStream_t s);
+// Batched: nbatch independent scans of len entries each, in cloud after
+// cloud (out: len+1 per cloud; scratch: scan_scratch_words(len) per cloud).
+void launch_exclusive_scan_b(const uint32_t *in, int64_t len, int nbatch, uint64_t *out,
+                             uint64_t *scratch, hipStream_t s);
 
 // ---- a3 + a4: enumeration with threshold and clearing --------------------
 constexpr int64_t COMPACT_TILE = 4096;  // candidates per workgroup
@@ -39,6 +66,13 @@ struct EnumArgs {
     const uint64_t *binom;     // C(v,k) table, stride n+1
     const uint32_t *clear;     // clearing bitmap over C(n,p+1) cidx, or null
     uint64_t ncand;            // C(n, p+1)
+    // batched launches (nbatch clouds of n points, packed one after the
+    // other): per-cloud thresholds, bitmap stride (u32 words) and output
+    // stride (elements); tile counts / offsets are laid out per cloud
+    const float *thr_dev = nullptr;
+    int64_t clear_stride = 0;
+    int64_t out_stride = 0;
+    int nbatch = 1;
 };
 // Pass 1: kept count per tile; stats[0] += thresholded, stats[1] += cleared.
 void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts,
@@ -58,20 +92,25 @@ constexpr int SCAN_COUNTERS = 1024;
 void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                      const float *dsq, int n, int p, const uint64_t *binom, int group,
                      uint64_t *tau_out, unsigned long long *scan_count, hipStream_t s);
+// Batched: cap = per-cloud capacity (grid size); dsq packed n*n per cloud.
+void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
+                       const float *dsq, int n, int p, const uint64_t *binom, int group,
+                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s);
 
 // ---- a6: partition --------------------------------------------------------
 // Pass 1: apparent columns per tile.
 void launch_partition_count(const uint64_t *tau, int64_t ncols, uint32_t *tile_counts,
-                            hipStream_t s);
+                            hipStream_t s, Batch bt = Batch(), int nbatch = 1);
 // Pass 2: apparent -> (tau, sigma) pairs; non-apparent -> (key, cidx) with
 // key = ~bits(diameter), both in increasing column (cidx) order.
 void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
                               const uint64_t *col_cidx, int64_t ncols,
                               const uint64_t *tile_offsets, uint64_t *app_tau,
                               uint64_t *app_sigma, uint64_t *na_key, uint64_t *na_cidx,
-                              hipStream_t s);
+                              hipStream_t s, Batch bt = Batch(), int nbatch = 1);
 // key[i] = ~bits(diam[i]) (descending-diameter radix key).
-void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s);
+void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s,
+                      Batch bt = Batch(), int nbatch = 1);
 
 // ---- a7: host handoff -------------------------------------------------------
 // For every non-apparent column (key = ~bits(diameter), cidx): its oldest
@@ -80,7 +119,8 @@ void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStrea
 // is empty.  One wave per column.
 void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
                  const float *dsq, int n, int p, float thr, const uint64_t *binom,
-                 uint64_t *low_out, float *low_diam_out, hipStream_t s);
+                 uint64_t *low_out, float *low_diam_out, hipStream_t s, Batch bt = Batch(),
+                 int nbatch = 1, const float *thr_dev = nullptr);
 
 // ---- sparse path (a threshold that keeps few edges) -------------------------
 // Neighbour bitsets: bit b of bits[v * words + k] is set iff u = 64k + b is a
@@ -124,7 +164,8 @@ void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t
                         hipStream_t s);
 
 // ---- a7: clearing bitmap ---------------------------------------------------
-void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s);
+void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s,
+                      Batch bt = Batch(), int nbatch = 1, int64_t bits_stride = 0);
 
 // ---- a2: H0 by union-find ---------------------------------------------------
 // Edges sorted in coboundary order (diameter descending, cidx ascending);
@@ -135,7 +176,8 @@ void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStr
 // in LDS.
 void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
                     uint32_t *mst_bits, float *deaths, uint64_t *death_edges, int *counters,
-                    int *uf_scratch, hipStream_t s);
+                    int *uf_scratch, hipStream_t s, Batch bt = Batch(), int nbatch = 1,
+                    int64_t mst_stride = 0);
 
 // ---- distances and gradients ---------------------------------------------
 // Condensed FP32 distances of n points in R^d (row-major FP32 coordinates):
@@ -153,8 +195,12 @@ void launch_edge_grad(const float *pts, int n, int d, const uint64_t *edges, con
 // sorted data end up in either the input or the alternate buffers; the
 // return value is 0 when they are in (keys, vals), 1 when in (keys_alt,
 // vals_alt).  scratch must hold radix_scratch_words(count) u64.
-int64_t radix_scratch_words(int64_t count);
+int64_t radix_scratch_words(int64_t count, int nbatch = 1);
 int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
                      int64_t count, int bits, uint64_t *scratch, hipStream_t s);
+// Batched: count = per-cloud capacity (stride), per-cloud counts in bt.
+int radix_sort_pairs_b(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
+                       int64_t count, int bits, uint64_t *scratch, hipStream_t s, Batch bt,
+                       int nbatch);
 
 }  // namespace rpp

@@ -94,6 +94,13 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dcond, 
 {
     __shared__ float sh[5];
     const int i = blockIdx.x;
+    {   // batched launch: cloud blockIdx.y, arrays packed cloud after cloud
+        const int64_t c = blockIdx.y;
+        dcond += c * ((int64_t)n * (n - 1) / 2);
+        dsq += c * (int64_t)n * n;
+        rowmax += c * n;
+        bad += c;
+    }
     float mx = 0.0f;
     uint32_t flag = 0;
     const int64_t rowi = (int64_t)i * (i - 1) / 2;
@@ -161,6 +168,48 @@ void launch_min(const float *x, int n, float *out, hipStream_t s)
     hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, s, x, n, out);
 }
 
+void launch_stage_b(const float *dcond, int n, int nb, float *dsq, float *rowmax, uint32_t *bad,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage, dim3(n, nb), dim3(256), 0, s, dcond, n, dsq, rowmax, bad);
+}
+
+// Per cloud: radius = min over rows of the row maxima; the threshold used is
+// the radius when the requested one is +inf (unless no_radius), else the
+// requested one.  One block per cloud.
+__global__ __launch_bounds__(1024) void k_radius_b(const float *__restrict__ rowmax, int n,
+                                                  const float *__restrict__ req, int no_radius,
+                                                  float *__restrict__ radius,
+                                                  float *__restrict__ thr)
+{
+    __shared__ float sh[16];
+    const int c = blockIdx.x;
+    float m = INFINITY;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        m = fminf(m, rowmax[(int64_t)c * n + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        m = fminf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            r = fminf(r, sh[w]);
+        radius[c] = r;
+        const float q = req[c];
+        thr[c] = (isinf(q) && !no_radius) ? r : q;
+    }
+}
+
+void launch_radius_b(const float *rowmax, int n, int nb, const float *req, int no_radius,
+                     float *radius, float *thr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_radius_b, dim3(nb), dim3(1024), 0, s, rowmax, n, req, no_radius, radius,
+                       thr);
+}
+
 // ===========================================================================
 // fill and device-wide exclusive scan (u32 counts -> u64 offsets)
 // ===========================================================================
@@ -196,6 +245,8 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_partial(const uint32_t *__restr
                                                          uint64_t *__restrict__ part)
 {
     __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    in += (int64_t)blockIdx.y * len;
+    part += (int64_t)blockIdx.y * (gridDim.x + 2);
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
     uint64_t s = 0;
 #pragma unroll
@@ -212,6 +263,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_partial(const uint32_t *__restr
 __global__ __launch_bounds__(SCAN_T) void k_scan_top(uint64_t *__restrict__ part, int nb)
 {
     __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    part += (int64_t)blockIdx.y * (nb + 2);
     uint64_t carry = 0;
     for (int start = 0; start < nb; start += SCAN_T) {
         int i = start + threadIdx.x;
@@ -232,6 +284,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_apply(const uint32_t *__restric
                                                        uint64_t *__restrict__ out)
 {
     __shared__ uint64_t sh[SCAN_T / WAVE + 1];
+    in += (int64_t)blockIdx.y * len;
+    part += (int64_t)blockIdx.y * (nb + 2);
+    out += (int64_t)blockIdx.y * (len + 1);
     const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
     uint64_t carry = part[blockIdx.x];
 #pragma unroll
@@ -248,17 +303,24 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_apply(const uint32_t *__restric
         out[len] = part[nb];
 }
 
-void launch_exclusive_scan(const uint32_t *in, int64_t len, uint64_t *out, uint64_t *scratch,
-                           hipStream_t s)
+void launch_exclusive_scan_b(const uint32_t *in, int64_t len, int nbatch, uint64_t *out,
+                             uint64_t *scratch, hipStream_t s)
 {
     int nb = (int)((len + SCAN_CHUNK - 1) / SCAN_CHUNK);
     if (nb == 0) {
-        (void)hipMemsetAsync(out, 0, sizeof(uint64_t), s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(out), 2, 0u, s);
         return;
     }
-    hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(SCAN_T), 0, s, in, len, scratch);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, scratch, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, s, in, len, scratch, nb, out);
+    hipLaunchKernelGGL(k_scan_partial, dim3(nb, nbatch), dim3(SCAN_T), 0, s, in, len, scratch);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, nbatch), dim3(SCAN_T), 0, s, scratch, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb, nbatch), dim3(SCAN_T), 0, s, in, len, scratch, nb,
+                       out);
+}
+
+void launch_exclusive_scan(const uint32_t *in, int64_t len, uint64_t *out, uint64_t *scratch,
+                           hipStream_t s)
+{
+    launch_exclusive_scan_b(in, len, 1, out, scratch, s);
 }
 
 // ===========================================================================
@@ -274,6 +336,20 @@ __device__ __forceinline__ float dc_at(const float *__restrict__ dcond, int a, i
 }
 
 // 0 = kept, 1 = removed by the threshold, 2 = removed by clearing.
+// Per-cloud view of the enumeration arguments (batched launches).
+__device__ __forceinline__ EnumArgs enum_view(EnumArgs a)
+{
+    const int64_t c = blockIdx.y;
+    if (c) {
+        a.dcond += c * ((int64_t)a.n * (a.n - 1) / 2);
+        if (a.clear)
+            a.clear += c * a.clear_stride;
+    }
+    if (a.thr_dev)
+        a.thr = a.thr_dev[c];
+    return a;
+}
+
 template <int P>
 __device__ __forceinline__ int enum_eval(const EnumArgs &a, const Binom &B, uint64_t c,
                                          float &diam)
@@ -301,10 +377,13 @@ __device__ __forceinline__ int enum_eval(const EnumArgs &a, const Binom &B, uint
 }
 
 template <int P>
-__global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a, uint32_t *__restrict__ tile_counts,
+__global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__restrict__ tile_counts,
                                                    unsigned long long *__restrict__ stats)
 {
     __shared__ uint32_t sh[CT / WAVE + 1];
+    const EnumArgs a = enum_view(a0);
+    tile_counts += (int64_t)blockIdx.y * gridDim.x;
+    stats += 2 * blockIdx.y;
     const Binom B{a.binom, a.n + 1};
     const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
     uint32_t keep = 0, nthr = 0, nclr = 0;
@@ -332,12 +411,16 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a, uint32_t *__restr
 }
 
 template <int P>
-__global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a,
+__global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
                                                      const uint64_t *__restrict__ tile_offsets,
                                                      float *__restrict__ out_diam,
                                                      uint64_t *__restrict__ out_cidx)
 {
     __shared__ uint32_t wsum[CT / WAVE];
+    const EnumArgs a = enum_view(a0);
+    tile_offsets += (int64_t)blockIdx.y * (gridDim.x + 1);
+    out_diam += (int64_t)blockIdx.y * a.out_stride;
+    out_cidx += (int64_t)blockIdx.y * a.out_stride;
     const Binom B{a.binom, a.n + 1};
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
@@ -381,7 +464,7 @@ void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts, unsigned long l
     int64_t tiles = compact_tiles((int64_t)a.ncand);
     if (tiles == 0)
         return;
-    dim3 g((unsigned)tiles), b(CT);
+    dim3 g((unsigned)tiles, a.nbatch > 0 ? a.nbatch : 1), b(CT);
     switch (a.p) {
     case 1: hipLaunchKernelGGL(k_enum_count<1>, g, b, 0, s, a, tile_counts, stats); break;
     case 2: hipLaunchKernelGGL(k_enum_count<2>, g, b, 0, s, a, tile_counts, stats); break;
@@ -396,7 +479,7 @@ void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float 
     int64_t tiles = compact_tiles((int64_t)a.ncand);
     if (tiles == 0)
         return;
-    dim3 g((unsigned)tiles), b(CT);
+    dim3 g((unsigned)tiles, a.nbatch > 0 ? a.nbatch : 1), b(CT);
     switch (a.p) {
     case 1: hipLaunchKernelGGL(k_enum_scatter<1>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
     case 2: hipLaunchKernelGGL(k_enum_scatter<2>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
@@ -427,11 +510,20 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
                                                   int64_t ncols, const float *__restrict__ dsq,
                                                   int n, const uint64_t *__restrict__ binom,
                                                   uint64_t *__restrict__ tau_out,
-                                                  unsigned long long *__restrict__ scan_count)
+                                                  unsigned long long *__restrict__ scan_count,
+                                                  Batch bt)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int g = lane & (G - 1);
     const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    {
+        const int64_t cl = blockIdx.y;
+        ncols = batch_count(bt, cl, ncols);
+        col_diam += cl * bt.stride;
+        col_cidx += cl * bt.stride;
+        tau_out += cl * bt.stride;
+        dsq += cl * (int64_t)n * n;
+    }
     if (col >= ncols)
         return;  // whole groups leave together
     const Binom B{binom, n + 1};
@@ -505,17 +597,32 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
 template <int P>
 static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
                               const float *dsq, int n, const uint64_t *binom, int group,
-                              uint64_t *tau, unsigned long long *sc, hipStream_t s)
+                              uint64_t *tau, unsigned long long *sc, hipStream_t s,
+                              Batch bt = Batch(), int nbatch = 1)
 {
     const int64_t threads = ncols * group;
-    dim3 g((unsigned)((threads + 255) / 256)), b(256);
+    dim3 g((unsigned)((threads + 255) / 256), nbatch), b(256);
     switch (group) {
-    case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
-    case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
-    case 16: hipLaunchKernelGGL((k_apparent<P, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
-    case 32: hipLaunchKernelGGL((k_apparent<P, 32>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
-    case 64: hipLaunchKernelGGL((k_apparent<P, 64>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
-    default: hipLaunchKernelGGL((k_apparent<P, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+    case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    case 16: hipLaunchKernelGGL((k_apparent<P, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    case 32: hipLaunchKernelGGL((k_apparent<P, 32>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    case 64: hipLaunchKernelGGL((k_apparent<P, 64>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    default: hipLaunchKernelGGL((k_apparent<P, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    }
+}
+
+void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
+                       const float *dsq, int n, int p, const uint64_t *binom, int group,
+                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s)
+{
+    if (cap <= 0)
+        return;
+    switch (p) {
+    case 1: launch_apparent_p<1>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
+    case 2: launch_apparent_p<2>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
+    case 3: launch_apparent_p<3>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
+    default: launch_apparent_p<4>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
     }
 }
 
@@ -538,9 +645,16 @@ void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t nc
 // ===========================================================================
 __global__ __launch_bounds__(CT) void k_partition_count(const uint64_t *__restrict__ tau,
                                                         int64_t ncols,
-                                                        uint32_t *__restrict__ tile_counts)
+                                                        uint32_t *__restrict__ tile_counts,
+                                                        Batch bt)
 {
     __shared__ uint32_t sh[CT / WAVE + 1];
+    {
+        const int64_t cl = blockIdx.y;
+        ncols = batch_count(bt, cl, ncols);
+        tau += cl * bt.stride;
+        tile_counts += cl * gridDim.x;
+    }
     const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
     uint32_t cnt = 0;
 #pragma unroll 4
@@ -559,9 +673,21 @@ __global__ __launch_bounds__(CT) void k_partition_scatter(
     const uint64_t *__restrict__ col_cidx, int64_t ncols,
     const uint64_t *__restrict__ tile_offsets, uint64_t *__restrict__ app_tau,
     uint64_t *__restrict__ app_sigma, uint64_t *__restrict__ na_key,
-    uint64_t *__restrict__ na_cidx)
+    uint64_t *__restrict__ na_cidx, Batch bt)
 {
     __shared__ uint32_t wsum[CT / WAVE];
+    {
+        const int64_t cl = blockIdx.y, st = bt.stride;
+        ncols = batch_count(bt, cl, ncols);
+        tau += cl * st;
+        col_diam += cl * st;
+        col_cidx += cl * st;
+        app_tau += cl * st;
+        app_sigma += cl * st;
+        na_key += cl * st;
+        na_cidx += cl * st;
+        tile_offsets += cl * (gridDim.x + 1);
+    }
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
     uint64_t run_a = tile_offsets[blockIdx.x];
@@ -607,43 +733,46 @@ __global__ __launch_bounds__(CT) void k_partition_scatter(
 }
 
 void launch_partition_count(const uint64_t *tau, int64_t ncols, uint32_t *tile_counts,
-                            hipStream_t s)
+                            hipStream_t s, Batch bt, int nbatch)
 {
     int64_t tiles = compact_tiles(ncols);
     if (tiles == 0)
         return;
-    hipLaunchKernelGGL(k_partition_count, dim3((unsigned)tiles), dim3(CT), 0, s, tau, ncols,
-                       tile_counts);
+    hipLaunchKernelGGL(k_partition_count, dim3((unsigned)tiles, nbatch), dim3(CT), 0, s, tau,
+                       ncols, tile_counts, bt);
 }
 
 void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
                               const uint64_t *col_cidx, int64_t ncols,
                               const uint64_t *tile_offsets, uint64_t *app_tau,
                               uint64_t *app_sigma, uint64_t *na_key, uint64_t *na_cidx,
-                              hipStream_t s)
+                              hipStream_t s, Batch bt, int nbatch)
 {
     int64_t tiles = compact_tiles(ncols);
     if (tiles == 0)
         return;
-    hipLaunchKernelGGL(k_partition_scatter, dim3((unsigned)tiles), dim3(CT), 0, s, tau,
+    hipLaunchKernelGGL(k_partition_scatter, dim3((unsigned)tiles, nbatch), dim3(CT), 0, s, tau,
                        col_diam, col_cidx, ncols, tile_offsets, app_tau, app_sigma, na_key,
-                       na_cidx);
+                       na_cidx, bt);
 }
 
 __global__ void k_desc_keys(const float *__restrict__ diam, int64_t count,
-                            uint64_t *__restrict__ keys)
+                            uint64_t *__restrict__ keys, Batch bt)
 {
+    const int64_t cl = blockIdx.y;
+    count = batch_count(bt, cl, count);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count)
-        keys[i] = (uint64_t)(~diam_bits(diam[i]));
+        keys[cl * bt.stride + i] = (uint64_t)(~diam_bits(diam[cl * bt.stride + i]));
 }
 
-void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s)
+void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s, Batch bt,
+                      int nbatch)
 {
     if (count <= 0)
         return;
-    hipLaunchKernelGGL(k_desc_keys, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
-                       diam, count, keys);
+    hipLaunchKernelGGL(k_desc_keys, dim3((unsigned)((count + 255) / 256), nbatch), dim3(256), 0,
+                       s, diam, count, keys, bt);
 }
 
 // ===========================================================================
@@ -656,67 +785,84 @@ __global__ __launch_bounds__(256) void k_lows(const uint64_t *__restrict__ na_ke
                                               int n, float thr,
                                               const uint64_t *__restrict__ binom,
                                               uint64_t *__restrict__ low_out,
-                                              float *__restrict__ low_diam_out)
+                                              float *__restrict__ low_diam_out, Batch bt,
+                                              const float *__restrict__ thr_dev)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    if (col >= ncols)
-        return;  // whole waves leave together
+    const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    {
+        const int64_t cl = blockIdx.y, st = bt.stride;
+        ncols = batch_count(bt, cl, ncols);
+        na_key += cl * st;
+        na_cidx += cl * st;
+        low_out += cl * st;
+        low_diam_out += cl * st;
+        dsq += cl * (int64_t)n * n;
+        if (thr_dev)
+            thr = thr_dev[cl];
+    }
     const Binom B{binom, n + 1};
-    const float d = __uint_as_float(~(uint32_t)na_key[col]);
-    int v[P + 1];
-    decode<P>(B, na_cidx[col], n, v);
-    const float *row[P + 1];
+    for (int64_t col = wave_id; col < ncols; col += nwaves) {  // whole waves per column
+        const float d = __uint_as_float(~(uint32_t)na_key[col]);
+        int v[P + 1];
+        decode<P>(B, na_cidx[col], n, v);
+        const float *row[P + 1];
 #pragma unroll
-    for (int i = 0; i <= P; ++i)
-        row[i] = dsq + (int64_t)v[i] * n;
-    float best = INFINITY;
-    int bw = -1;
-    for (int base = 0; base < n; base += WAVE) {
-        const int w = base + lane;
-        if (w >= n)
-            break;
-        bool ok = true;
-        float m = d;
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)v[i] * n;
+        float best = INFINITY;
+        int bw = -1;
+        for (int base = 0; base < n; base += WAVE) {
+            const int w = base + lane;
+            if (w >= n)
+                break;
+            bool ok = true;
+            float m = d;
 #pragma unroll
-        for (int i = 0; i <= P; ++i) {
-            const float e = row[i][w];
-            ok = ok && (w != v[i]) && (e <= thr);
-            m = fmaxf(m, e);
+            for (int i = 0; i <= P; ++i) {
+                const float e = row[i][w];
+                ok = ok && (w != v[i]) && (e <= thr);
+                m = fmaxf(m, e);
+            }
+            // later w wins ties: larger w gives the larger cofacet cidx
+            if (ok && m <= best) {
+                best = m;
+                bw = w;
+            }
         }
-        // later w wins ties: larger w gives the larger cofacet cidx
-        if (ok && m <= best) {
-            best = m;
-            bw = w;
-        }
-    }
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const float ob = __shfl_xor(best, o, WAVE);
-        const int ow = __shfl_xor(bw, o, WAVE);
-        if (ob < best || (ob == best && ow > bw)) {
-            best = ob;
-            bw = ow;
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const float ob = __shfl_xor(best, o, WAVE);
+            const int ow = __shfl_xor(bw, o, WAVE);
+            if (ob < best || (ob == best && ow > bw)) {
+                best = ob;
+                bw = ow;
+            }
         }
-    }
-    if (lane == 0) {
-        low_out[col] = bw >= 0 ? cofacet_index<P>(B, v, bw) : NONE;
-        low_diam_out[col] = best;
+        if (lane == 0) {
+            low_out[col] = bw >= 0 ? cofacet_index<P>(B, v, bw) : NONE;
+            low_diam_out[col] = best;
+        }
     }
 }
 
 void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
                  const float *dsq, int n, int p, float thr, const uint64_t *binom,
-                 uint64_t *low_out, float *low_diam_out, hipStream_t s)
+                 uint64_t *low_out, float *low_diam_out, hipStream_t s, Batch bt, int nbatch,
+                 const float *thr_dev)
 {
     if (ncols <= 0)
         return;
-    dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+    int64_t blocks = (ncols * WAVE + 255) / 256;
+    if (bt.count && blocks > 256)
+        blocks = 256;  // batched: counts live on the device; waves loop over columns
+    dim3 g((unsigned)blocks, nbatch), b(256);
     switch (p) {
-    case 1: hipLaunchKernelGGL(k_lows<1>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
-    case 2: hipLaunchKernelGGL(k_lows<2>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
-    case 3: hipLaunchKernelGGL(k_lows<3>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
-    default: hipLaunchKernelGGL(k_lows<4>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out); break;
+    case 1: hipLaunchKernelGGL(k_lows<1>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out, bt, thr_dev); break;
+    case 2: hipLaunchKernelGGL(k_lows<2>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out, bt, thr_dev); break;
+    case 3: hipLaunchKernelGGL(k_lows<3>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out, bt, thr_dev); break;
+    default: hipLaunchKernelGGL(k_lows<4>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, thr, binom, low_out, low_diam_out, bt, thr_dev); break;
     }
 }
 
@@ -1046,21 +1192,24 @@ void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t
 // a7: clearing bitmap for the next dimension
 // ===========================================================================
 __global__ void k_mark_bits(const uint64_t *__restrict__ idx, int64_t count,
-                            uint32_t *__restrict__ bits)
+                            uint32_t *__restrict__ bits, Batch bt, int64_t bits_stride)
 {
+    const int64_t cl = blockIdx.y;
+    count = batch_count(bt, cl, count);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
-        uint64_t t = idx[i];
-        atomicOr(&bits[t >> 5], 1u << (t & 31));
+        uint64_t t = idx[cl * bt.stride + i];
+        atomicOr(&bits[cl * bits_stride + (int64_t)(t >> 5)], 1u << (t & 31));
     }
 }
 
-void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s)
+void launch_mark_bits(const uint64_t *idx, int64_t count, uint32_t *bits, hipStream_t s,
+                      Batch bt, int nbatch, int64_t bits_stride)
 {
     if (count <= 0)
         return;
-    hipLaunchKernelGGL(k_mark_bits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, idx,
-                       count, bits);
+    hipLaunchKernelGGL(k_mark_bits, dim3((unsigned)((count + 255) / 256), nbatch), dim3(256), 0,
+                       s, idx, count, bits, bt, bits_stride);
 }
 
 // ===========================================================================
@@ -1098,9 +1247,21 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
                                                 float *__restrict__ deaths,
                                                 uint64_t *__restrict__ death_edges,
                                                 int *__restrict__ counters,
-                                                int *__restrict__ uf_scratch)
+                                                int *__restrict__ uf_scratch, Batch bt,
+                                                int64_t mst_stride)
 {
     extern __shared__ int smem[];
+    {   // batched launch: one workgroup per cloud
+        const int64_t cl = blockIdx.x;
+        nedges = batch_count(bt, cl, nedges);
+        edge_key += cl * bt.stride;
+        edge_cidx += cl * bt.stride;
+        mst_bits += cl * mst_stride;
+        deaths += cl * n;
+        death_edges += cl * n;
+        counters += 2 * cl;
+        uf_scratch += 2 * (int64_t)n * cl;
+    }
     volatile int *parent = IN_LDS ? smem : uf_scratch;
     int *owner = IN_LDS ? smem + n : uf_scratch + n;
     __shared__ int s_merges, s_deaths;
@@ -1172,15 +1333,17 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
 
 void launch_kruskal(const uint64_t *edge_key, const uint64_t *edge_cidx, int64_t nedges, int n,
                     uint32_t *mst_bits, float *deaths, uint64_t *death_edges, int *counters,
-                    int *uf_scratch, hipStream_t s)
+                    int *uf_scratch, hipStream_t s, Batch bt, int nbatch, int64_t mst_stride)
 {
     const size_t lds = (size_t)2 * n * sizeof(int);
     if (lds <= 60 * 1024) {
-        hipLaunchKernelGGL(k_kruskal<true>, dim3(1), dim3(KT), lds, s, edge_key, edge_cidx,
-                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch);
+        hipLaunchKernelGGL(k_kruskal<true>, dim3(nbatch), dim3(KT), lds, s, edge_key, edge_cidx,
+                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch, bt,
+                           mst_stride);
     } else {
-        hipLaunchKernelGGL(k_kruskal<false>, dim3(1), dim3(KT), 0, s, edge_key, edge_cidx,
-                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch);
+        hipLaunchKernelGGL(k_kruskal<false>, dim3(nbatch), dim3(KT), 0, s, edge_key, edge_cidx,
+                           nedges, n, mst_bits, deaths, death_edges, counters, uf_scratch, bt,
+                           mst_stride);
     }
 }
 
@@ -1266,19 +1429,25 @@ constexpr int RI = 8;
 constexpr int RTILE = RT * RI;
 constexpr int RBINS = 256;
 
-int64_t radix_scratch_words(int64_t count)
+int64_t radix_scratch_words(int64_t count, int nbatch)
 {
     int64_t tiles = (count + RTILE - 1) / RTILE;
-    int64_t hist_words = (tiles * RBINS + 1) / 2 + 1;     // u32 histograms
-    int64_t off_words = tiles * RBINS + 1;                // u64 offsets
-    return hist_words + off_words + scan_scratch_words(tiles * RBINS) + 8;
+    int64_t hist_words = (nbatch * tiles * RBINS + 1) / 2 + 1;   // u32 histograms
+    int64_t off_words = nbatch * (tiles * RBINS + 1);            // u64 offsets
+    return hist_words + off_words + nbatch * scan_scratch_words(tiles * RBINS) + 8;
 }
 
 __global__ __launch_bounds__(RT) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t count,
                                                 int shift, uint32_t *__restrict__ hist,
-                                                int64_t tiles)
+                                                int64_t tiles, Batch bt)
 {
     __shared__ uint32_t h[RBINS];
+    {
+        const int64_t cl = blockIdx.y;
+        count = batch_count(bt, cl, count);
+        keys += cl * bt.stride;
+        hist += cl * tiles * RBINS;
+    }
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RTILE;
@@ -1298,9 +1467,20 @@ __global__ __launch_bounds__(RT) void k_rs_scatter(const uint64_t *__restrict__ 
                                                    uint64_t *__restrict__ vout, int64_t count,
                                                    int shift,
                                                    const uint64_t *__restrict__ offs,
-                                                   int64_t tiles)
+                                                   int64_t tiles, Batch bt)
 {
     __shared__ uint64_t sk[RTILE];
+    {
+        const int64_t cl = blockIdx.y, st = bt.stride;
+        count = batch_count(bt, cl, count);
+        kin += cl * st;
+        vin += cl * st;
+        kout += cl * st;
+        vout += cl * st;
+        offs += cl * (tiles * RBINS + 1);
+    }
+    if ((int64_t)blockIdx.x * RTILE >= count)
+        return;  // no keys of this cloud in this tile (uniform per block)
     __shared__ uint64_t sv[RTILE];
     __shared__ uint32_t wcnt[RT / WAVE][RBINS];
     __shared__ uint32_t run[RBINS];
@@ -1380,24 +1560,30 @@ __global__ __launch_bounds__(RT) void k_rs_scatter(const uint64_t *__restrict__ 
     }
 }
 
-int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
-                     int64_t count, int bits, uint64_t *scratch, hipStream_t s)
+int radix_sort_pairs_b(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
+                       int64_t count, int bits, uint64_t *scratch, hipStream_t s, Batch bt,
+                       int nbatch)
 {
-    if (count <= 1 || bits <= 0)
+    if (count <= 1 && !bt.count)
+        return 0;
+    if (count <= 0 || bits <= 0)
         return 0;
     const int64_t tiles = (count + RTILE - 1) / RTILE;
+    const int64_t per = radix_scratch_words(count);
+    // per-cloud scratch regions: [hist | offsets | scan scratch]
     uint32_t *hist = reinterpret_cast<uint32_t *>(scratch);
-    const int64_t hist_words = (tiles * RBINS + 1) / 2 + 1;
+    const int64_t hist_words = (nbatch * tiles * RBINS + 1) / 2 + 1;
     uint64_t *offs = scratch + hist_words;
-    uint64_t *scan_tmp = offs + tiles * RBINS + 1;
+    uint64_t *scan_tmp = offs + nbatch * (tiles * RBINS + 1);
+    (void)per;
     uint64_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     int where = 0;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RT), 0, s, ki, count, shift,
-                           hist, tiles);
-        launch_exclusive_scan(hist, tiles * RBINS, offs, scan_tmp, s);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(RT), 0, s, ki, vi, ko, vo,
-                           count, shift, offs, tiles);
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles, nbatch), dim3(RT), 0, s, ki, count,
+                           shift, hist, tiles, bt);
+        launch_exclusive_scan_b(hist, tiles * RBINS, nbatch, offs, scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles, nbatch), dim3(RT), 0, s, ki, vi,
+                           ko, vo, count, shift, offs, tiles, bt);
         uint64_t *t = ki;
         ki = ko;
         ko = t;
@@ -1407,6 +1593,14 @@ int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_
         where ^= 1;
     }
     return where;
+}
+
+int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
+                     int64_t count, int bits, uint64_t *scratch, hipStream_t s)
+{
+    if (count <= 1 || bits <= 0)
+        return 0;
+    return radix_sort_pairs_b(keys, vals, keys_alt, vals_alt, count, bits, scratch, s, Batch(), 1);
 }
 
 }  // namespace rpp

@@ -40,6 +40,21 @@ struct RunArgs {
 // Returns an RPP_* code; on error `err` holds a message.
 int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);
 
+// Several clouds with the same n and maxdim, processed together.
+struct BatchArgs {
+    int count = 0;
+    int n = 0;
+    int maxdim = 0;
+    const float *const *dist_dev = nullptr;  // count device pointers
+    const float *threshold = nullptr;         // count requested thresholds (host)
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    bool use_graph = true;                    // capture / replay the GPU chain
+    bool tune = false;                        // time lane-group sizes when untuned
+    int group = 0;                            // fixed lane-group size, 0 = tuned / default
+};
+int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err);
+
 // Apparent pairs of dimension (p, p+1) over all p-simplices <= threshold.
 int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
                       std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau,

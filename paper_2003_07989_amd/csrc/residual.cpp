@@ -401,6 +401,15 @@ private:
 
 }  // namespace
 
+void parallel_for(int64_t n, const std::function<void(int64_t)> &fn)
+{
+    std::atomic<int64_t> next{0};
+    Pool::get().run([&](int) {
+        for (int64_t i = next.fetch_add(1); i < n; i = next.fetch_add(1))
+            fn(i);
+    });
+}
+
 // Two phases, exact:
 //  A (parallel over columns): reduce each column against the apparent
 //    pivots only -- they are fixed before the reduction starts -- until its
@@ -436,10 +445,11 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R)
 
     // ---- phase A ----------------------------------------------------------
     Pool &pool = Pool::get();
+    const int workers = P.parallel ? pool.size() : 1;
     std::atomic<int64_t> next{0};
     std::atomic<int64_t> look_app{0};
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * pool.size())));
-    pool.run([&](int) {
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
+    auto phase_a = [&](int) {
         Ctx X(P);
         int64_t looks = 0;
         while (true) {
@@ -481,7 +491,11 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R)
             }
         }
         look_app += looks;
-    });
+    };
+    if (P.parallel)
+        pool.run(phase_a);
+    else
+        phase_a(0);
     R.lookups_apparent = look_app.load();
 
     // ---- phase B ----------------------------------------------------------

@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 namespace rpp {
@@ -34,6 +35,9 @@ struct ResidualProblem {
     int64_t napp = 0;
     const uint64_t *app_tau = nullptr;
     const uint64_t *app_sigma = nullptr;
+    // run the speculative phase on the shared worker pool (false: on the
+    // calling thread only, e.g. when the caller already runs in parallel)
+    bool parallel = true;
 };
 
 struct ResidualResult {
@@ -50,5 +54,9 @@ struct ResidualResult {
 // with the two-layer pivot store: the pivots found here in a hash map first,
 // then the apparent pairs.
 void residual_reduce(const ResidualProblem &P, ResidualResult &R);
+
+// Runs fn(i) for i in [0, n) on the shared worker pool (dynamic schedule);
+// fn must not itself use the pool.
+void parallel_for(int64_t n, const std::function<void(int64_t)> &fn);
 
 }  // namespace rpp

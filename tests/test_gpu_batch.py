@@ -1,0 +1,113 @@
+"""Batched execution (rpp_barcodes_batch): every cloud's result equals the
+single-cloud path and the oracle, with and without graph replay."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rpp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_07989_amd as m
+    m.load()
+    return m
+
+
+def _same(a, b, label=""):
+    for p, ((b1, d1), (b2, d2)) in enumerate(zip(a.bars, b.bars)):
+        assert np.array_equal(b1.view(np.uint32), b2.view(np.uint32)), (label, p)
+        assert np.array_equal(d1.view(np.uint32), d2.view(np.uint32)), (label, p)
+    if a.edges is not None and b.edges is not None:
+        for p, ((e1, f1), (e2, f2)) in enumerate(zip(a.edges, b.edges)):
+            assert np.array_equal(e1, e2) and np.array_equal(f1, f2), (label, p)
+
+
+def _dev(d):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda()
+
+
+def _mixed():
+    clouds = []
+    for i, n in enumerate((40, 40, 40, 25, 25, 64, 40)):
+        d = w.condensed_from_points(w.noisy_torus_points(n, 1300 + i))
+        maxdim = 2 if n <= 40 else 1
+        thr = math.inf if i % 3 else float(np.quantile(d, 0.5))
+        clouds.append((d, n, maxdim, thr))
+    return clouds
+
+
+@pytest.mark.parametrize("flags_name", ["graph", "eager"])
+def test_mixed_batch_matches_single_and_oracle(rpp, flags_name):
+    flags = rpp.RPP_WANT_CRITICAL_EDGES
+    if flags_name == "eager":
+        flags |= rpp.RPP_BATCH_NO_GRAPH
+    clouds = _mixed()
+    dev = [_dev(d) for d, _, _, _ in clouds]
+    out = rpp.barcodes_batch(dev, [c[2] for c in clouds], [c[3] for c in clouds], flags=flags)
+    for i, ((d, n, maxdim, thr), r) in enumerate(zip(clouds, out)):
+        single = rpp.barcodes_device(dev[i], maxdim, thr,
+                                     flags=rpp.RPP_WANT_CRITICAL_EDGES | rpp.RPP_FORCE_DENSE)
+        _same(r, single, "cloud %d" % i)
+        exp = oracle.barcodes(d, n, maxdim, thr, clearing=True)
+        for p in range(maxdim + 1):
+            assert np.array_equal(r.bars[p][0].view(np.uint32), exp[p][0].view(np.uint32))
+            assert np.array_equal(r.bars[p][1].view(np.uint32), exp[p][1].view(np.uint32))
+
+
+def test_graph_replays_match_eager(rpp):
+    """Replay the captured graph several times, with unrelated eager work and
+    synchronisations in between; every replay equals the eager batch."""
+    import torch
+    clouds = [w.condensed_from_points(w.noisy_circle_points(96, seed=40 + i)) for i in range(12)]
+    dev = [_dev(d) for d in clouds]
+    ref = rpp.barcodes_batch(dev, 1, flags=rpp.RPP_BATCH_NO_GRAPH)
+    other = _dev(w.condensed_from_points(w.uniform_square_points(30, 9)))
+    for rep in range(4):
+        got = rpp.barcodes_batch(dev, 1)
+        rpp.barcodes_device(other, 1)   # eager work between replays
+        torch.cuda.synchronize()
+        for i in range(len(dev)):
+            _same(got[i], ref[i], "replay %d cloud %d" % (rep, i))
+
+
+def test_batch_of_circles_512(rpp):
+    """64 noisy circles of 512 points (FP32 coordinates), dims 0-1."""
+    pts, dists = w.noisy_circle_batch(64, 512)
+    dev = [_dev(d) for d in dists]
+    out = rpp.barcodes_batch(dev, 1, flags=rpp.RPP_WANT_CRITICAL_EDGES)
+    for i in range(0, 64, 9):
+        single = rpp.barcodes_device(dev[i], 1, flags=rpp.RPP_WANT_CRITICAL_EDGES)
+        _same(out[i], single, "circle %d" % i)
+    # one cloud against the oracle
+    exp = oracle.barcodes(dists[5], 512, 1, clearing=True)
+    for p in range(2):
+        assert np.array_equal(out[5].bars[p][0].view(np.uint32), exp[p][0].view(np.uint32))
+        assert np.array_equal(out[5].bars[p][1].view(np.uint32), exp[p][1].view(np.uint32))
+
+
+def test_autotuned_batch_matches(rpp):
+    clouds = [w.condensed_from_points(w.noisy_torus_points(72, 70 + i)) for i in range(5)]
+    dev = [_dev(d) for d in clouds]
+    a = rpp.barcodes_batch(dev, 2, flags=rpp.RPP_BATCH_AUTOTUNE)
+    b = rpp.barcodes_batch(dev, 2, flags=rpp.RPP_BATCH_NO_GRAPH)
+    for i in range(len(dev)):
+        _same(a[i], b[i], "tuned %d" % i)
+        _same(a[i], rpp.barcodes_device(dev[i], 2), "single %d" % i)
+
+
+def test_batch_rejects_bad_entries(rpp):
+    d = w.condensed_from_points(w.uniform_square_points(20, 1))
+    bad = d.copy()
+    bad[3] = -1.0
+    with pytest.raises(rpp.RppError) as e:
+        rpp.barcodes_batch([_dev(d), _dev(bad)], 1)
+    assert e.value.code == -2
