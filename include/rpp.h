@@ -234,6 +234,45 @@ int rpp_backward(const float *points_dev, int32_t n, int32_t d, int64_t nbars,
                  const float *grad_birth, const float *grad_death, float *grad_points_dev,
                  void *hip_stream);
 
+/* ---- serving -------------------------------------------------------------
+ * A server runs requests on `slots` concurrent slots, each with its own HIP
+ * stream and device workspace, so the GPU stages of different requests
+ * overlap and each request's filtration and clearing state stay in HBM until
+ * it finishes.  A request is admitted as soon as a slot is free and its
+ * footprint bound (rpp_workspace_bytes + its input) fits hbm_budget_bytes
+ * next to the requests in flight (a request larger than the whole budget is
+ * admitted alone); the queue is scanned in arrival order.  All functions
+ * are thread-safe. */
+typedef struct rpp_server rpp_server;
+
+typedef struct {
+    int32_t slots;
+    size_t budget_bytes;
+    size_t in_flight_bytes;         /* sum of footprint bounds now running */
+    size_t peak_in_flight_bytes;
+    size_t peak_allocated_bytes;    /* device memory held by the slots */
+    int32_t peak_concurrency;       /* most requests running at once */
+    int64_t admitted, completed, queued;
+} rpp_server_info;
+
+/* slots: 1..64; hbm_budget_bytes: 0 = three quarters of the free device
+ * memory.  Uses the current device. */
+int rpp_server_create(int32_t slots, size_t hbm_budget_bytes, rpp_server **out);
+/* Queue a request; dist is a host condensed matrix, copied before return.
+ * flags: as rpp_barcodes_device (RPP_WANT_PAIRS is ignored).  *ticket
+ * identifies the request for rpp_server_wait. */
+int rpp_server_submit(rpp_server *s, const float *dist, int32_t n, int32_t maxdim,
+                      float threshold, uint32_t flags, uint64_t *ticket);
+/* Block until the request is done; *out receives its result (free with
+ * rpp_result_free).  latency_ms: submission to completion; queue_ms:
+ * submission to admission (either may be NULL).  Returns the request's own
+ * error code if it failed.  Each ticket can be waited for once. */
+int rpp_server_wait(rpp_server *s, uint64_t ticket, rpp_result **out, double *latency_ms,
+                    double *queue_ms);
+int rpp_server_stats(rpp_server *s, rpp_server_info *st);
+/* Finishes the queued requests, then releases everything. */
+void rpp_server_destroy(rpp_server *s);
+
 void rpp_result_free(rpp_result *r);
 
 /* Static text for an RPP_E_* code. */

@@ -67,6 +67,14 @@ class _Request(ctypes.Structure):
                 ("threshold", ctypes.c_float)]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("budget_bytes", ctypes.c_size_t),
+                ("in_flight_bytes", ctypes.c_size_t), ("peak_in_flight_bytes", ctypes.c_size_t),
+                ("peak_allocated_bytes", ctypes.c_size_t), ("peak_concurrency", ctypes.c_int32),
+                ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [("maxdim", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("threshold_used", ctypes.c_float), ("enclosing_radius", ctypes.c_float),
@@ -111,6 +119,19 @@ def load() -> ctypes.CDLL:
     lib.rpp_barcodes_batch.argtypes = [ctypes.c_int32, P(_Request), ctypes.c_void_p,
                                        ctypes.c_uint32, P(P(_Result))]
     lib.rpp_barcodes_batch.restype = ctypes.c_int
+    lib.rpp_server_create.argtypes = [ctypes.c_int32, ctypes.c_size_t, P(ctypes.c_void_p)]
+    lib.rpp_server_create.restype = ctypes.c_int
+    lib.rpp_server_submit.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_float, ctypes.c_uint32,
+                                      P(ctypes.c_uint64)]
+    lib.rpp_server_submit.restype = ctypes.c_int
+    lib.rpp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(P(_Result)),
+                                    P(ctypes.c_double), P(ctypes.c_double)]
+    lib.rpp_server_wait.restype = ctypes.c_int
+    lib.rpp_server_stats.argtypes = [ctypes.c_void_p, P(_ServerStats)]
+    lib.rpp_server_stats.restype = ctypes.c_int
+    lib.rpp_server_destroy.argtypes = [ctypes.c_void_p]
+    lib.rpp_server_destroy.restype = None
     lib.rpp_result_free.argtypes = [P(_Result)]
     lib.rpp_result_free.restype = None
     lib.rpp_strerror.argtypes = [ctypes.c_int]
@@ -391,3 +412,64 @@ def barcodes_batch(dists, maxdims, thresholds=None, flags: int = 0, stream=None)
             if bool(outs[i]):
                 lib.rpp_result_free(outs[i])
     return res
+
+
+class Server:
+    """Continuous-admission barcode server (rpp_server_*): submit host
+    distance arrays, wait for results with per-request latency."""
+
+    def __init__(self, slots: int = 4, hbm_budget_bytes: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        rc = self._lib.rpp_server_create(int(slots), int(hbm_budget_bytes), ctypes.byref(h))
+        if rc != 0:
+            raise RppError(rc, "rpp_server_create failed")
+        self._h = h
+
+    def submit(self, dist, maxdim: int, threshold: float = math.inf, flags: int = 0,
+               n: int = None) -> int:
+        a = np.ascontiguousarray(dist, dtype=np.float32)
+        if n is None:
+            n = _n_from_len(a.size)
+        t = ctypes.c_uint64(0)
+        ptr = a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a.size else None
+        rc = self._lib.rpp_server_submit(self._h, ptr, int(n), int(maxdim),
+                                         ctypes.c_float(threshold), int(flags), ctypes.byref(t))
+        if rc != 0:
+            raise RppError(rc, "rpp_server_submit failed")
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(Barcodes, latency_ms, queue_ms)."""
+        out = ctypes.POINTER(_Result)()
+        lat, q = ctypes.c_double(0), ctypes.c_double(0)
+        rc = self._lib.rpp_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(out),
+                                       ctypes.byref(lat), ctypes.byref(q))
+        if rc != 0:
+            raise RppError(rc, self._lib.rpp_last_error().decode())
+        try:
+            return _collect(out), lat.value, q.value
+        finally:
+            self._lib.rpp_result_free(out)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        self._lib.rpp_server_stats(self._h, ctypes.byref(st))
+        return {name: getattr(st, name) for name, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._lib.rpp_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "librpp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 DEVICE_SOURCES = ["kernels.hip", "pipeline.hip", "batch.hip"]
-HOST_SOURCES = ["residual.cpp", "capi.cpp"]
+HOST_SOURCES = ["residual.cpp", "capi.cpp", "serve.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops", "-munsafe-fp-atomics"]

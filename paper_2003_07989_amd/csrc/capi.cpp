@@ -127,6 +127,17 @@ int build_result(const rpp::RunOut &ro, int n, int maxdim, uint32_t flags, rpp_r
 
 }  // namespace
 
+namespace rpp {
+int build_result_public(const RunOut &ro, int n, int maxdim, uint32_t flags, rpp_result **out)
+{
+    return build_result(ro, n, maxdim, flags, out);
+}
+void set_last_error(const std::string &msg)
+{
+    g_last_error = msg;
+}
+}  // namespace rpp
+
 extern "C" {
 
 int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,

@@ -8,15 +8,36 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rpp.h"
 
 namespace rpp {
 
+// Owning device buffer; grows, never shrinks; movable, not copyable.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), cap(o.cap)
+    {
+        o.p = nullptr;
+        o.cap = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+        return *this;
+    }
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
     bool ensure(size_t bytes)
     {
         if (bytes <= cap && p)
@@ -41,9 +62,29 @@ struct DevBuf {
     }
 };
 
+// Owning pinned host buffer (hipHostMalloc); same rules as DevBuf.
 struct HostBuf {
     void *p = nullptr;
     size_t cap = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    HostBuf(HostBuf &&o) noexcept : p(o.p), cap(o.cap)
+    {
+        o.p = nullptr;
+        o.cap = 0;
+    }
+    HostBuf &operator=(HostBuf &&o) noexcept
+    {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+        return *this;
+    }
+    ~HostBuf()
+    {
+        if (p)
+            (void)hipHostFree(p);
+    }
     bool ensure(size_t bytes)
     {
         if (bytes <= cap && p)

@@ -35,7 +35,13 @@ struct RunArgs {
     hipStream_t stream = nullptr;
     int apparent_group = 0;            // lanes per column, 0 = default
     bool count_scans = false;          // tally cofacet candidates per column
+    void *workspace = nullptr;         // explicit workspace (workspace_new), or the device's
 };
+
+// Device workspaces for concurrent callers (one per serving slot).
+void *workspace_new();
+void workspace_delete(void *w);
+size_t workspace_allocated(void *w);
 
 // Returns an RPP_* code; on error `err` holds a message.
 int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);

@@ -95,6 +95,32 @@ static Workspace &workspace_for_current_device()
     return *w;
 }
 
+void *workspace_new()
+{
+    return new Workspace();
+}
+
+void workspace_delete(void *w)
+{
+    delete static_cast<Workspace *>(w);
+}
+
+size_t workspace_allocated(void *wp)
+{
+    Workspace &w = *static_cast<Workspace *>(wp);
+    size_t t = 0;
+    const DevBuf *bufs[] = {&w.dsq, &w.rowmax, &w.scal, &w.binom, &w.ekey, &w.eval, &w.ekey2,
+                            &w.eval2, &w.mst, &w.deaths, &w.dedges, &w.ufs, &w.tcount, &w.toff,
+                            &w.scan, &w.tcount2, &w.toff2, &w.skd[0], &w.skd[1], &w.skc[0],
+                            &w.skc[1], &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
+                            &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
+                            &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
+                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt};
+    for (const DevBuf *b : bufs)
+        t += b->cap;
+    return t;
+}
+
 size_t workspace_bytes(int n, int maxdim)
 {
     if (n < 2)
@@ -276,7 +302,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         out.dims[0].st.n_bars = 1;
         return RPP_OK;
     }
-    Workspace &ws = workspace_for_current_device();
+    Workspace &ws = a.workspace ? *static_cast<Workspace *>(a.workspace)
+                                : workspace_for_current_device();
     std::lock_guard<std::mutex> lk(ws.mu);
 
     const uint64_t E = (uint64_t)n * (n - 1) / 2;

@@ -329,10 +329,12 @@ public:
     }
     int size() const { return (int)workers_.size() + 1; }
     // Runs fn(tid) on every worker and on the calling thread (tid 0), and
-    // returns when all have finished.
+    // returns when all have finished.  One caller at a time uses the
+    // workers; a concurrent caller runs fn(0) alone on its own thread.
     void run(const std::function<void(int)> &fn)
     {
-        if (workers_.empty()) {
+        std::unique_lock<std::mutex> owner(run_mu_, std::try_to_lock);
+        if (workers_.empty() || !owner.owns_lock()) {
             fn(0);
             return;
         }
@@ -391,6 +393,7 @@ private:
         }
     }
     std::vector<std::thread> workers_;
+    std::mutex run_mu_;
     std::mutex mu_;
     std::condition_variable cv_, done_;
     const std::function<void(int)> *job_ = nullptr;
