@@ -11,6 +11,10 @@ the given threshold that enter the filter (all C(n, p+1) when there is no
 threshold).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torus400]
+Other workloads (their own JSON lines): --workload sphere4096 (4096 points on
+the sphere, threshold 0.4), --workload circles64x512 (batched forward +
+backward), --workload serving512 (Poisson request stream, served vs batched
+vs plain).
 """
 from __future__ import annotations
 
@@ -71,6 +75,336 @@ def cpu_baseline(name: str) -> dict:
             "sample": sample, "seconds": round(el, 3)}
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def bench_circles(args):
+    """64 noisy circles of 512 points, dims 0-1: forward barcodes/s one cloud
+    per call vs one batched call, the backward pass of the total finite H1
+    persistence, and an FP64 central-difference check of the gradient."""
+    import numpy as np
+    import torch
+    import paper_2003_07989_amd as rpp
+    import workloads
+    torch.cuda.set_device(0)
+    rpp.load()
+    pts, dists = workloads.noisy_circle_batch(64, 512)
+    P = [torch.from_numpy(p).cuda() for p in pts]
+    D = [torch.from_numpy(d).cuda() for d in dists]
+    flags = rpp.RPP_WANT_CRITICAL_EDGES
+    for _ in range(args.warmup):
+        rpp.barcodes_batch(D, 1, flags=flags)
+        for d in D[:4]:
+            rpp.barcodes_device(d, 1, flags=flags)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain = [rpp.barcodes_device(d, 1, flags=flags) for d in D]
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batched = rpp.barcodes_batch(D, 1, flags=flags)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    for a, b in zip(plain, batched):
+        for p in range(2):
+            assert np.array_equal(a.bars[p][0].view(np.uint32), b.bars[p][0].view(np.uint32))
+            assert np.array_equal(a.bars[p][1].view(np.uint32), b.bars[p][1].view(np.uint32))
+    # backward of loss = sum over finite H1 bars of (death - birth), per cloud
+    terms = []
+    for r in batched:
+        be, de = r.edges[1]
+        fin = np.isfinite(r.bars[1][1])
+        terms.append((be, de, np.where(fin, -1.0, 0.0).astype(np.float32),
+                      np.where(fin, 1.0, 0.0).astype(np.float32)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grads = [rpp.backward_points(P[i], *terms[i]) for i in range(64)]
+    torch.cuda.synchronize()
+    t_bwd = (time.perf_counter() - t0) / reps
+    print("circles: forward and backward timed; finite-difference check", file=sys.stderr,
+          flush=True)
+    fd = _fd_check(rpp, pts, batched, grads, full=args.fd_full)
+    out = {
+        "metric": "barcodes/sec forward, batched vs plain (64 noisy circles x 512 points, dims 0-1)",
+        "value": round(64 / t_batch, 2), "unit": "barcodes/s", "n_gpus": 1,
+        "steps": reps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": "circles64x512", "clouds": 64, "n": 512,
+                                        "maxdim": 1},
+        "plain_barcodes_per_s": round(64 / t_plain, 2),
+        "batched_speedup": round(t_plain / t_batch, 3),
+        "ms_forward_plain_64": round(t_plain * 1e3, 3),
+        "ms_forward_batched_64": round(t_batch * 1e3, 3),
+        "ms_backward_64": round(t_bwd * 1e3, 3),
+        "fd_check": fd,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_clouds(dists, 512)
+    print(json.dumps(out))
+
+
+def _edge_vertices(e):
+    """Endpoints (a, b), a > b, of the edge with combinatorial index e = C(a,2) + b."""
+    a = int((1 + math.isqrt(1 + 8 * e)) // 2)
+    while a * (a - 1) // 2 > e:
+        a -= 1
+    return (a, e - a * (a - 1) // 2)
+
+
+def _finite_h1_terms(res):
+    import numpy as np
+    be, de = res.edges[1]
+    fin = np.isfinite(res.bars[1][1])
+    return sorted(zip(be[fin].tolist(), de[fin].tolist()))
+
+
+def _fd_check(rpp, pts, batched, grads, full=False, h=1e-4, chunk=32):
+    """Central differences in FP64 of the loss evaluated with the pairing of
+    the unperturbed cloud; a coordinate whose +-h perturbation changes that
+    pairing (a near-tie) is skipped and counted.  Perturbed clouds go through
+    the batched path, 2*chunk clouds per launch.  Default sample: every
+    coordinate of every vertex on a critical edge plus 8 other vertices, for
+    8 of the 64 clouds; full=True checks all 64 x 512 x 3 coordinates."""
+    import numpy as np
+    import torch
+    rng = np.random.Generator(np.random.PCG64(7))
+    checked = skipped = bad = 0
+    worst = 0.0
+    cloud_ids = range(64) if full else range(0, 64, 8)
+    for ci in cloud_ids:
+        x = pts[ci].astype(np.float64)
+        n = x.shape[0]
+        base = _finite_h1_terms(batched[ci])
+        ends = np.array([[*_edge_vertices(ed), *_edge_vertices(eb)] for eb, ed in base],
+                        dtype=np.int64).reshape(-1, 4)
+        g = grads[ci].cpu().numpy()
+        if full:
+            verts = list(range(n))
+        else:
+            touched = sorted(set(ends.ravel().tolist()))
+            others = [v for v in range(n) if v not in set(touched)]
+            verts = touched + sorted(rng.choice(others, size=min(8, len(others)),
+                                                replace=False).tolist())
+        coords = [(i, k) for i in verts for k in range(x.shape[1])]
+
+        def loss64(xx):
+            dd = np.sqrt(np.sum((xx[ends[:, 0]] - xx[ends[:, 1]]) ** 2, axis=1))
+            db = np.sqrt(np.sum((xx[ends[:, 2]] - xx[ends[:, 3]]) ** 2, axis=1))
+            return float(np.sum(dd) - np.sum(db))
+
+        for c0 in range(0, len(coords), chunk):
+            cs = coords[c0:c0 + chunk]
+            xs = []
+            for i, k in cs:
+                for sg in (1.0, -1.0):
+                    xx = x.copy()
+                    xx[i, k] += sg * h
+                    xs.append(xx)
+            dev = [rpp.pdist_device(torch.from_numpy(xx.astype(np.float32)).cuda()) for xx in xs]
+            res = rpp.barcodes_batch(dev, 1, flags=rpp.RPP_WANT_CRITICAL_EDGES)
+            for j, (i, k) in enumerate(cs):
+                if _finite_h1_terms(res[2 * j]) != base or _finite_h1_terms(res[2 * j + 1]) != base:
+                    skipped += 1
+                    continue
+                fd = (loss64(xs[2 * j]) - loss64(xs[2 * j + 1])) / (2 * h)
+                err = abs(float(g[i, k]) - fd)
+                checked += 1
+                worst = max(worst, err / (1e-4 + 1e-3 * abs(fd)))
+                bad += err > 1e-4 + 1e-3 * abs(fd)
+    return {"clouds": len(cloud_ids), "coords_checked": checked,
+            "coords_skipped_near_ties": skipped, "failures": int(bad),
+            "worst_err_over_tol": round(worst, 4), "h": h, "tol": "abs 1e-4 + rel 1e-3",
+            "sample": "all coordinates" if full else
+                      "vertices on critical edges + 8 others, every 8th cloud"}
+
+
+def cpu_baseline_clouds(dists, n):
+    """The oracle on one circle per host thread in parallel (threshold =
+    enclosing radius, clearing mode): barcodes/s over the host cores."""
+    import threading
+    import oracle
+    oracle.build()
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = dists[:cores]
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=lambda d=d: oracle.barcodes(
+        d, n, 1, oracle.enclosing_radius(d, n), threads=1, clearing=True)) for d in sample]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    return {"value": round(len(sample) / el, 4), "unit": "barcodes/s", "cores": cores,
+            "kind": "oracle", "seconds": round(el, 3),
+            "sample": "%d of the 64 circles, one per thread, threshold = enclosing radius"
+                      % len(sample)}
+
+
+def bench_serving(args):
+    """512 Gaussian-mixture requests (n log-uniform in [64, 1024], d in 2..8,
+    maxdim 1 or 2, threshold = enclosing radius) arriving as a Poisson
+    process at rate lam = f x the measured plain serial capacity (f = 0.8 by
+    default, --rates for a sweep); barcodes/s and p50/p99 latency (finish -
+    arrival) for plain serial processing, static batches of 8, and the
+    continuous-admission server."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2003_07989_amd as rpp
+    import workloads
+    torch.cuda.set_device(0)
+    rpp.load()
+    count = args.requests
+    # arrivals at rate 1 scale to any rate lam as t / lam
+    reqs = workloads.serving_stream(count, rate_per_s=1.0)
+    for r in reqs[:3]:
+        rpp.barcodes(r["dist"], r["maxdim"])
+    t0 = time.perf_counter()
+    for r in reqs:
+        rpp.barcodes(r["dist"], r["maxdim"])
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+    capacity = count / serial_s
+    print("serving: plain capacity %.1f barcodes/s" % capacity, file=sys.stderr, flush=True)
+
+    def plain_mode(arrivals):
+        lat, t0 = [], time.perf_counter()
+        for r, a in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            rpp.barcodes(r["dist"], r["maxdim"])
+            lat.append(time.perf_counter() - t0 - a)
+        return lat, time.perf_counter() - t0, {}
+
+    def batched_mode(arrivals, size=8):
+        lat, t0 = [], time.perf_counter()
+        for b in range(0, count, size):
+            idx = list(range(b, min(count, b + size)))
+            now = time.perf_counter() - t0
+            if now < arrivals[idx[-1]]:
+                time.sleep(arrivals[idx[-1]] - now)
+            D = [torch.from_numpy(reqs[i]["dist"]).cuda() for i in idx]
+            rpp.barcodes_batch(D, [reqs[i]["maxdim"] for i in idx])
+            done = time.perf_counter() - t0
+            lat += [done - arrivals[i] for i in idx]
+        return lat, time.perf_counter() - t0, {"batch": size}
+
+    def served_mode(arrivals, slots=4):
+        srv = rpp.Server(slots=slots)
+        tickets = [None] * count
+        late = [0.0] * count   # submission time minus arrival time
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (r, a) in enumerate(zip(reqs, arrivals)):
+                now = time.perf_counter() - t0
+                if now < a:
+                    time.sleep(a - now)
+                late[i] = max(0.0, time.perf_counter() - t0 - a)
+                tickets[i] = srv.submit(r["dist"], r["maxdim"])
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat = []
+        for i in range(count):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            _, ms, _ = srv.wait(tickets[i])
+            lat.append(late[i] + ms / 1e3)
+        th.join()
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, span, {"slots": slots, "admitted": st["admitted"],
+                           "completed": st["completed"],
+                           "peak_concurrency": st["peak_concurrency"],
+                           "budget_bytes": st["budget_bytes"],
+                           "peak_in_flight_bytes": st["peak_in_flight_bytes"],
+                           "peak_allocated_bytes": st["peak_allocated_bytes"]}
+
+    def summary(res):
+        lat, span, extra = res
+        return dict({"barcodes_per_s": round(count / span, 2),
+                     "p50_ms": round(_pct(lat, 50) * 1e3, 2),
+                     "p99_ms": round(_pct(lat, 99) * 1e3, 2)}, **extra)
+
+    rates = [float(f) for f in args.rates.split(",")]
+    sweep = []
+    for f in rates:
+        lam = f * capacity
+        arrivals = np.array([r["arrival_s"] / lam for r in reqs])
+        row = {"rate_factor": f, "arrival_rate_per_s": round(lam, 3)}
+        for name, fn in (("plain", plain_mode), ("batched", batched_mode),
+                         ("served", served_mode)):
+            row[name] = summary(fn(arrivals))
+            print("serving: rate %.2f x capacity, %s done" % (f, name), file=sys.stderr,
+                  flush=True)
+        sweep.append(row)
+    main_row = sweep[0]
+    out = {
+        "metric": "barcodes/sec and p99 latency, served vs batched vs plain (Poisson stream)",
+        "value": main_row["served"]["barcodes_per_s"], "unit": "barcodes/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving%d" % count, "requests": count,
+                   "arrival_rate_per_s": main_row["arrival_rate_per_s"],
+                   "rate_rule": "%.2f x plain serial capacity" % rates[0]},
+        "plain_serial_capacity_per_s": round(capacity, 2),
+        "served": main_row["served"], "batched": main_row["batched"],
+        "plain": main_row["plain"],
+    }
+    if len(sweep) > 1:
+        out["sweep"] = sweep
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_requests(rpp, reqs)
+    print(json.dumps(out))
+
+
+def cpu_baseline_requests(rpp, reqs, n_max=256, k=32):
+    """The oracle on a bounded sample of the request stream -- the first k
+    requests with n <= n_max, one per host thread -- and the plain GPU path
+    on the same sample, both as barcodes/s."""
+    import threading
+    import oracle
+    oracle.build()
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    sample = [r for r in reqs if r["n"] <= n_max][:k]
+    queue = list(range(len(sample)))
+    lock = threading.Lock()
+
+    def worker():
+        while True:
+            with lock:
+                if not queue:
+                    return
+                i = queue.pop(0)
+            r = sample[i]
+            oracle.barcodes(r["dist"], r["n"], r["maxdim"], oracle.enclosing_radius(r["dist"], r["n"]),
+                            threads=1, clearing=True)
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=worker) for _ in range(cores)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for r in sample:
+        rpp.barcodes(r["dist"], r["maxdim"])
+    gpu_el = time.perf_counter() - t0
+    return {"value": round(len(sample) / el, 3), "unit": "barcodes/s", "cores": cores,
+            "kind": "oracle", "seconds": round(el, 3),
+            "sample": "first %d requests of the stream with n <= %d (threshold = enclosing "
+                      "radius, one request per thread)" % (len(sample), n_max),
+            "gpu_plain_same_sample_barcodes_per_s": round(len(sample) / gpu_el, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,11 +412,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="torus400")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rates", default="0.8",
+                    help="serving: arrival rates as multiples of the plain capacity")
+    ap.add_argument("--fd-full", action="store_true",
+                    help="circles: finite-difference check of every coordinate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X and this "
               "build has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "circles64x512":
+        return bench_circles(args)
+    if args.workload.startswith("serving"):
+        return bench_serving(args)
 
     import numpy as np
     import torch
