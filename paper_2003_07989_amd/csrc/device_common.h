@@ -29,10 +29,32 @@ struct Binom {
 };
 
 // Largest v in [k-1, hi) with C(v, k) <= c.  C(k-1, k) = 0 <= c always.
+// For k <= 4 a closed-form root of C(v, k) = c gives a guess within a step
+// or two of the answer (C(v,2) ~ v(v-1)/2, C(v,3) ~ (v-1)^3/6,
+// C(v,4) ~ (v-1.5)^4/24); table comparisons then step to the exact value,
+// so a decode costs a couple of independent loads instead of a dependent
+// binary search.  Larger k use the binary search.
 __device__ __forceinline__ int top_vertex(const Binom &B, uint64_t c, int k, int hi)
 {
     if (k == 1)
         return (int)c;
+    if (k <= 4) {
+        const double cd = (double)c;
+        double g;
+        if (k == 2)
+            g = 0.5 * (1.0 + sqrt(1.0 + 8.0 * cd));
+        else if (k == 3)
+            g = cbrt(6.0 * cd) + 1.0;
+        else
+            g = sqrt(sqrt(24.0 * cd)) + 1.5;
+        int x = (int)fmin(g, (double)(hi - 1));
+        x = x < k - 1 ? k - 1 : x;
+        while (x > k - 1 && B(x, k) > c)
+            --x;
+        while (x + 1 < hi && B(x + 1, k) <= c)
+            ++x;
+        return x;
+    }
     int lo = k - 1, h = hi - 1;
     while (lo < h) {
         int mid = (lo + h + 1) >> 1;

@@ -29,116 +29,222 @@ struct Entry {
     uint64_t cidx;
 };
 
-// Max-heap comparator whose top is the OLDEST entry (smallest diameter,
-// then largest cidx): a < b means a is younger than b.
-struct YoungerFirst {
-    bool operator()(const Entry &a, const Entry &b) const
+// Column entries are packed into one unsigned integer whose order is the
+// filtration order of the cofacets: the diameter's bit pattern (monotone for
+// non-negative floats) above (M - cidx), so a smaller key is older -- smaller
+// diameter, then larger cidx.  K = uint64_t when every cofacet index fits in
+// 32 bits, unsigned __int128 otherwise.
+using u128 = unsigned __int128;
+template <class K> struct KeyFmt;
+template <> struct KeyFmt<uint64_t> {
+    static constexpr int S = 32;
+    static constexpr uint64_t M = 0xffffffffull;
+};
+template <> struct KeyFmt<u128> {
+    static constexpr int S = 64;
+    static constexpr uint64_t M = ~0ull;
+};
+template <class K> inline K pack(float d, uint64_t c)
+{
+    return ((K)__builtin_bit_cast(uint32_t, d) << KeyFmt<K>::S) | (K)(KeyFmt<K>::M - c);
+}
+template <class K> inline Entry unpack(K k)
+{
+    return Entry{__builtin_bit_cast(float, (uint32_t)(k >> KeyFmt<K>::S)),
+                 KeyFmt<K>::M - (uint64_t)(k & (K)KeyFmt<K>::M)};
+}
+
+// Moves the c smallest of a[0..m) (distinct keys) to a[0..c), unordered:
+// quickselect with a median-of-three pivot and a branch-free Lomuto
+// partition (every element is swapped; the split index advances on the
+// comparison result), which keeps the mispredictions of a comparison-driven
+// partition out of the loop.
+template <class K> void select_smallest(K *a, size_t m, size_t c)
+{
+    size_t lo = 0, hi = m;
+    while (hi - lo > 24) {
+        const size_t mid = lo + (hi - lo) / 2;
+        K x = a[lo], y = a[mid], z = a[hi - 1];
+        if (x > y)
+            std::swap(x, y);
+        if (y > z)
+            y = z > x ? z : x;  // median of three
+        // distinct keys and a median pivot: both sides are non-empty
+        size_t j = lo;
+        for (size_t i = lo; i < hi; ++i) {
+            const K t = a[i];
+            const bool lt = t < y;
+            a[i] = a[j];
+            a[j] = t;
+            j += lt ? 1 : 0;
+        }
+        if (c < j)
+            hi = j;
+        else if (c > j)
+            lo = j;
+        else
+            return;
+    }
+    std::sort(a + lo, a + hi);
+}
+
+// One added coboundary, consumed oldest-first.  Only a sorted prefix is
+// kept: the oldest `chunk` remaining keys are selected (linear on average)
+// and sorted; when they run out the next, twice as large, chunk is
+// selected.  A column's low usually lies a few dozen entries into each
+// stream, so most keys are never ordered, and pops read memory in order.
+template <class K> struct Stream {
+    std::vector<K> e;
+    uint32_t pos = 0, sorted = 0, chunk = 32;
+    bool empty() const { return pos >= e.size(); }
+    K front() const { return e[pos]; }
+    void prepare()
     {
-        if (a.diam != b.diam)
-            return a.diam > b.diam;
-        return a.cidx < b.cidx;
+        pos = sorted = 0;
+        chunk = 32;
+        refill();
+    }
+    void refill()
+    {
+        const size_t rem = e.size() - pos;
+        if (rem == 0)
+            return;
+        const size_t c = std::min<size_t>(rem, chunk);
+        if (c < rem)
+            select_smallest(e.data() + pos, rem, c);
+        std::sort(e.begin() + pos, e.begin() + pos + c);
+        sorted = pos + (uint32_t)c;
+        chunk = chunk < (1u << 30) ? chunk * 2 : chunk;
+    }
+    void pop()
+    {
+        if (++pos == sorted)
+            refill();
     }
 };
 
 // Working column = Z/2 sum of several coboundaries.  Each added coboundary
-// is kept as its own small heap (a "stream", built in linear time); a heap
-// over the streams' current tops yields the sum's entries oldest-first.
-// Only the entries that reach the top are ever ordered, which is what
-// finding the low needs.
-class Column {
+// is its own stream; a min-heap over the streams' current fronts yields the
+// sum's entries oldest-first.  Only the entries that reach the front are
+// ever ordered, which is what finding the low needs.
+template <class K> class Column {
 public:
-    void clear()
+    // Storage for the next coboundary: fill it, then commit().
+    std::vector<K> &next_stream()
     {
-        nstreams = 0;
-        top.clear();
-    }
-    void add(const std::vector<Entry> &batch)
-    {
-        if (batch.empty())
-            return;
         if (nstreams == streams.size())
             streams.emplace_back();
-        std::vector<Entry> &h = streams[nstreams];
-        h.assign(batch.begin(), batch.end());
-        std::make_heap(h.begin(), h.end(), YoungerFirst());
-        top_push(h.front(), (uint32_t)nstreams);
+        std::vector<K> &v = streams[nstreams].e;
+        v.clear();
+        return v;
+    }
+    void commit()
+    {
+        Stream<K> &st = streams[nstreams];
+        if (st.e.empty())
+            return;
+        st.prepare();
+        top_push(st.front(), (uint32_t)nstreams);
         ++nstreams;
     }
     // Add another column's current contents: its streams hold exactly its
-    // Z/2 sum (cancelled pairs were removed together), each a valid heap.
+    // Z/2 sum (cancelled pairs were removed together).
     void add(const Column &o)
     {
         for (size_t k = 0; k < o.nstreams; ++k) {
-            const std::vector<Entry> &src = o.streams[k];
+            const Stream<K> &src = o.streams[k];
             if (src.empty())
                 continue;
             if (nstreams == streams.size())
                 streams.emplace_back();
-            streams[nstreams].assign(src.begin(), src.end());
-            top_push(streams[nstreams].front(), (uint32_t)nstreams);
+            Stream<K> &dst = streams[nstreams];
+            dst.e.assign(src.e.begin() + src.pos, src.e.end());
+            dst.pos = 0;
+            dst.sorted = src.sorted - src.pos;
+            dst.chunk = src.chunk;
+            top_push(dst.front(), (uint32_t)nstreams);
             ++nstreams;
         }
     }
-    // Low of the sum over Z/2: entries present in an even number of
-    // streams cancel; the surviving low stays in its stream.
+    // Low of the sum over Z/2: keys present in an even number of streams
+    // cancel.  In the min-heap every copy of the minimum lies in a subtree
+    // containing the root, so a second copy exists iff a child of the root
+    // holds it; pairs are dropped until the minimum is unique.
     bool low(Entry &out)
     {
         while (!top.empty()) {
-            const Entry e = top.front().e;
-            hits.clear();
-            while (!top.empty() && top.front().e.cidx == e.cidx) {
-                hits.push_back(top.front().s);
-                top_pop();
-            }
-            const size_t keep = (hits.size() & 1) ? 1 : 0;
-            for (size_t i = 0; i < hits.size(); ++i) {
-                const uint32_t k = hits[i];
-                if (i < keep) {
-                    top_push(e, k);  // the surviving copy stays put
-                    continue;
-                }
-                std::vector<Entry> &h = streams[k];
-                std::pop_heap(h.begin(), h.end(), YoungerFirst());
-                h.pop_back();
-                if (!h.empty())
-                    top_push(h.front(), k);
-            }
-            if (keep) {
-                out = e;
+            const K e = top[0].k;
+            const size_t m = top.size();
+            const bool dup = (m > 1 && top[1].k == e) || (m > 2 && top[2].k == e);
+            if (!dup) {
+                out = unpack<K>(e);
                 return true;
             }
+            advance_root();  // the other copy becomes the root
+            advance_root();
         }
         return false;
     }
 
 private:
     struct Top {
-        Entry e;
+        K k;
         uint32_t s;
     };
-    struct TopYounger {
-        bool operator()(const Top &a, const Top &b) const { return YoungerFirst()(a.e, b.e); }
-    };
-    void top_push(const Entry &e, uint32_t k)
+    void sift_down(size_t i)
     {
-        top.push_back(Top{e, k});
-        std::push_heap(top.begin(), top.end(), TopYounger());
+        const Top x = top[i];
+        const size_t m = top.size();
+        while (true) {
+            size_t c = 2 * i + 1;
+            if (c >= m)
+                break;
+            if (c + 1 < m && top[c + 1].k < top[c].k)
+                ++c;
+            if (!(top[c].k < x.k))
+                break;
+            top[i] = top[c];
+            i = c;
+        }
+        top[i] = x;
     }
-    void top_pop()
+    void top_push(K k, uint32_t s)
     {
-        std::pop_heap(top.begin(), top.end(), TopYounger());
-        top.pop_back();
+        top.push_back(Top{k, s});
+        size_t i = top.size() - 1;
+        const Top x = top[i];
+        while (i > 0) {
+            const size_t par = (i - 1) / 2;
+            if (!(x.k < top[par].k))
+                break;
+            top[i] = top[par];
+            i = par;
+        }
+        top[i] = x;
     }
-    std::vector<std::vector<Entry>> streams;
+    // Consume the root's entry from its stream and restore the heap.
+    void advance_root()
+    {
+        Stream<K> &st = streams[top[0].s];
+        st.pop();
+        if (!st.empty()) {
+            top[0].k = st.front();
+        } else {
+            top[0] = top.back();
+            top.pop_back();
+            if (top.empty())
+                return;
+        }
+        sift_down(0);
+    }
+    std::vector<Stream<K>> streams;
     size_t nstreams = 0;
     std::vector<Top> top;
-    std::vector<uint32_t> hits;
 };
 
 struct Ctx {
     const ResidualProblem &P;
     int n, p;
-    std::vector<Entry> scratch;
     explicit Ctx(const ResidualProblem &pp) : P(pp), n(pp.n), p(pp.p) {}
 
     uint64_t C(int v, int k) const { return P.binom[(int64_t)k * (n + 1) + v]; }
@@ -184,14 +290,31 @@ struct Ctx {
         return c;
     }
 
-    // Every cofacet of sigma with diameter <= threshold.
-    const std::vector<Entry> &coboundary(uint64_t sigma, float d)
+    // Adds sigma's coboundary to col as a new stream.
+    template <class K> void add_coboundary(Column<K> &col, uint64_t sigma, float d) const
     {
-        scratch.clear();
+        coboundary(sigma, d, col.next_stream());
+        col.commit();
+    }
+
+    // Every cofacet of sigma with diameter <= threshold, appended to out as
+    // packed keys.
+    template <class K> void coboundary(uint64_t sigma, float d, std::vector<K> &out) const
+    {
         int v[8];
         decode(sigma, p, v);
         if (P.bits) {
-            // common neighbours only: every new edge is within the threshold
+            // common neighbours only: every new edge is within the threshold;
+            // count them first so the stream is sized exactly
+            size_t cnt = 0;
+            for (int k = 0; k < P.words; ++k) {
+                uint64_t m = ~0ull;
+                for (int i = 0; i <= p; ++i)
+                    m &= P.bits[(int64_t)v[i] * P.words + k];
+                cnt += (size_t)__builtin_popcountll(m);
+            }
+            out.resize(cnt);
+            K *o = out.data();
             for (int k = 0; k < P.words; ++k) {
                 uint64_t m = ~0ull;
                 for (int i = 0; i <= p; ++i)
@@ -203,43 +326,61 @@ struct Ctx {
                         const float e = D(v[i], w);
                         nd = e > nd ? e : nd;
                     }
-                    scratch.push_back(Entry{nd, insert_index(v, w)});
+                    *o++ = pack<K>(nd, insert_index(v, w));
                 }
             }
-            return scratch;
+            return;
         }
         const float *rows[8];
         for (int i = 0; i <= p; ++i)
             rows[i] = P.dsq + (int64_t)v[i] * n;
-        // cidx of sigma + {w}: vertices above w move up one rank.  Scan w
-        // downward, keeping the two partial sums of the CNS formula.
-        uint64_t above = 0;       // sum over v_i > w of C(v_i, rank+2)
-        uint64_t below = sigma;   // sum over v_i < w of C(v_i, rank+1)
-        int j = p + 1;            // number of sigma's vertices below w
-        int nxt = 0;              // index (in v) of the next vertex at or below w
-        for (int w = n - 1; w >= 0; --w) {
-            if (nxt <= p && v[nxt] == w) {
-                const int r = p - nxt;  // rank from the bottom
-                below -= C(w, r + 1);
-                above += C(w, r + 2);
-                --j;
-                ++nxt;
-                continue;
-            }
-            float nd = d;
-            bool ok = true;
-            for (int i = 0; i <= p; ++i) {
-                const float e = rows[i][w];
-                if (!(e <= P.thr)) {
-                    ok = false;
-                    break;
-                }
-                nd = e > nd ? e : nd;
-            }
-            if (ok)
-                scratch.push_back(Entry{nd, above + C(w, j + 1) + below});
+        out.resize((size_t)n);
+        size_t cnt;
+        switch (p) {
+        case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out.data()); break;
+        case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out.data()); break;
+        case 3: cnt = cob_dense<K, 4>(rows, v, sigma, d, out.data()); break;
+        default: cnt = cob_dense<K, 0>(rows, v, sigma, d, out.data()); break;
         }
-        return scratch;
+        out.resize(cnt);
+    }
+
+    // Dense coboundary: cidx of sigma + {w} = above + C(w, j+1) + below,
+    // where the vertices of sigma above w move up one rank.  Between two
+    // consecutive vertices of sigma, j, above and below are constant, so w
+    // runs over each gap in a tight loop that writes every cofacet and
+    // advances the output only for those within the threshold.
+    template <class K, int NV>
+    size_t cob_dense(const float *const *rows, const int *v, uint64_t sigma, float d, K *out) const
+    {
+        const int nv = NV ? NV : p + 1;
+        const float thr = P.thr;
+        size_t cnt = 0;
+        uint64_t above = 0, below = sigma;
+        int hi = n;
+        for (int idx = 0; idx <= nv; ++idx) {
+            const int lo = idx < nv ? v[idx] : -1;
+            const int j = nv - idx;  // vertices of sigma below w
+            const uint64_t *Cj = P.binom + (int64_t)(j + 1) * (n + 1);
+            const uint64_t base = above + below;
+            for (int w = hi - 1; w > lo; --w) {
+                float mx = rows[0][w];
+                for (int i = 1; i < nv; ++i) {
+                    const float e = rows[i][w];
+                    mx = e > mx ? e : mx;
+                }
+                const float nd = mx > d ? mx : d;
+                out[cnt] = pack<K>(nd, base + Cj[w]);
+                cnt += (mx <= thr) ? 1 : 0;
+            }
+            if (idx < nv) {
+                const int r = nv - 1 - idx;  // rank of v[idx] from the bottom
+                below -= C(lo, r + 1);
+                above += C(lo, r + 2);
+            }
+            hi = lo;
+        }
+        return cnt;
     }
 
     // Implicit second layer: if row tau (diameter dt) is the pivot of an
@@ -423,13 +564,15 @@ void parallel_for(int64_t n, const std::function<void(int64_t)> &fn)
 //    is not a pivot of an earlier host column, the column is final;
 //    otherwise the reduction resumes from the phase-A state with the full
 //    pivot store.
-void residual_reduce(const ResidualProblem &P, ResidualResult &R)
+namespace {
+
+template <class K> void reduce_impl(const ResidualProblem &P, ResidualResult &R)
 {
     const int64_t ncols = P.ncols;
     std::vector<Entry> spec_low(ncols);
     std::vector<uint8_t> spec_nz(ncols, 0);
     std::vector<int64_t> spec_adds(ncols, 0);
-    std::vector<std::unique_ptr<Column>> state(ncols);
+    std::vector<std::unique_ptr<Column<K>>> state(ncols);
 
     auto apparent_lookup = [&](const Ctx &X, uint64_t tau, float dt, uint64_t *other) -> bool {
         if (P.app_tau) {
@@ -471,14 +614,14 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R)
                     spec_nz[j] = 1;
                     continue;
                 }
-                std::unique_ptr<Column> col(new Column());
-                col->add(X.coboundary(P.col_cidx[j], diam_of_key(j)));
+                std::unique_ptr<Column<K>> col(new Column<K>());
+                X.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
                 bool nz;
                 int64_t adds = 0;
                 while (true) {
                     // Algorithm 2: add the ORIGINAL column of the pivot's owner
                     // (an apparent column has the diameter of its tau)
-                    col->add(X.coboundary(other, lo.diam));
+                    X.add_coboundary(*col, other, lo.diam);
                     ++adds;
                     nz = col->low(lo);
                     if (!nz)
@@ -502,75 +645,159 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R)
     R.lookups_apparent = look_app.load();
 
     // ---- phase B ----------------------------------------------------------
+    // Columns become final in column order (the frontier).  A column is
+    // final once every earlier column is final and its low is not the pivot
+    // of one of them.  A column whose low IS a final pivot makes exactly the
+    // addition the sequential algorithm makes at that point (pivots never
+    // change once final), so such columns -- anywhere past the frontier --
+    // are advanced together on the worker pool, each until its low is
+    // neither a final pivot nor apparent.  A waiting column is woken when
+    // its low becomes a final pivot.
+    //
     // A finished column that needed additions keeps its heap state: its
     // streams hold its reduced column R_k, which a later column adds in one
-    // step (the standard algorithm's R_j += R_k) instead of replaying k's
-    // reduction from the original column.  The copied entries are a subset
-    // of what the replay would regenerate, so this is never more work.
-    Ctx X(P);
+    // step (R_j += R_k) instead of replaying k's reduction from the original
+    // column.  The copied entries are a subset of what the replay would
+    // regenerate, so this is never more work.
     std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
     pivots.reserve((size_t)ncols * 2 + 16);
-    std::vector<std::unique_ptr<Column>> reduced;  // by index in R.sigma
+    std::vector<std::unique_ptr<Column<K>>> reduced;  // by index in R.sigma
     reduced.reserve((size_t)ncols);
-    for (int64_t j = 0; j < ncols; ++j) {
+    std::unordered_map<uint64_t, int64_t> whead;  // low -> last waiting column
+    whead.reserve((size_t)ncols * 2 + 16);
+    std::vector<int64_t> wnext(ncols, -1);
+    std::vector<uint8_t> pending(ncols, 0);
+    std::vector<int64_t> work;
+    auto wait_on = [&](int64_t j) {
+        auto r = whead.emplace(spec_low[j].cidx, j);
+        if (!r.second) {
+            wnext[j] = r.first->second;
+            r.first->second = j;
+        } else {
+            wnext[j] = -1;
+        }
+    };
+    for (int64_t j = 0; j < ncols; ++j)
+        if (spec_nz[j])
+            wait_on(j);
+
+    auto finalize = [&](int64_t j) {
         const uint64_t sigma = P.col_cidx[j];
         const float d = diam_of_key(j);
-        int64_t adds = spec_adds[j];
-        bool nz = spec_nz[j] != 0;
-        Entry lo = spec_low[j];
-        std::unique_ptr<Column> col = std::move(state[j]);
-        if (nz) {
-            auto it = pivots.find(lo.cidx);
-            if (it != pivots.end()) {
-                ++R.lookups_hash;
-                if (!col) {
-                    col.reset(new Column());
-                    col->add(X.coboundary(sigma, d));
-                }
-                // owner of the current low: host column k, or apparent column
-                int64_t k = it->second;
-                bool host = true;
-                uint64_t other = 0;
-                while (true) {
-                    if (!host)
-                        col->add(X.coboundary(other, lo.diam));  // diameter of its tau
-                    else if (reduced[k])
-                        col->add(*reduced[k]);
-                    else
-                        col->add(X.coboundary(R.sigma[k], R.birth[k]));
-                    ++adds;
-                    nz = col->low(lo);
-                    if (!nz)
-                        break;
-                    auto f = pivots.find(lo.cidx);
-                    if (f != pivots.end()) {
-                        ++R.lookups_hash;
-                        k = f->second;
-                        host = true;
-                        continue;
-                    }
-                    ++R.lookups_apparent;
-                    if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
-                        break;
-                    host = false;
-                }
-            }
-        }
-        R.additions += adds;
-        if (nz) {
-            if (adds == 0)
-                ++R.emergent;
-            pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
-            R.sigma.push_back(sigma);
-            R.tau.push_back(lo.cidx);
-            R.birth.push_back(d);
-            R.death.push_back(lo.diam);
-            reduced.push_back(adds ? std::move(col) : nullptr);
-        } else {
+        R.additions += spec_adds[j];
+        if (!spec_nz[j]) {
             R.ess_sigma.push_back(sigma);
             R.ess_birth.push_back(d);
+            return;
+        }
+        const Entry lo = spec_low[j];
+        if (spec_adds[j] == 0)
+            ++R.emergent;
+        pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
+        R.sigma.push_back(sigma);
+        R.tau.push_back(lo.cidx);
+        R.birth.push_back(d);
+        R.death.push_back(lo.diam);
+        reduced.push_back(spec_adds[j] ? std::move(state[j]) : nullptr);
+        state[j].reset();
+        auto it = whead.find(lo.cidx);
+        if (it == whead.end())
+            return;
+        for (int64_t k = it->second; k >= 0; k = wnext[k])
+            if (k != j && spec_nz[k] && spec_low[k].cidx == lo.cidx && !pending[k]) {
+                pending[k] = 1;
+                work.push_back(k);
+            }
+        whead.erase(it);
+    };
+
+    // Advance column j from a low that is a final pivot (read-only use of
+    // the pivot store and the finished columns; safe to run concurrently).
+    std::atomic<int64_t> look_hash{0}, look_app_b{0};
+    auto advance = [&](Ctx &Xc, int64_t j) {
+        std::unique_ptr<Column<K>> &col = state[j];
+        if (!col) {
+            col.reset(new Column<K>());
+            Xc.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
+        }
+        Entry lo = spec_low[j];
+        int64_t adds = 0, lh = 0, la = 0;
+        auto f = pivots.find(lo.cidx);
+        ++lh;
+        int64_t k = f->second;
+        bool host = true, nz = true;
+        uint64_t other = 0;
+        while (true) {
+            if (!host)
+                Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
+            else if (reduced[k])
+                col->add(*reduced[k]);
+            else
+                Xc.add_coboundary(*col, R.sigma[k], R.birth[k]);
+            ++adds;
+            nz = col->low(lo);
+            if (!nz)
+                break;
+            auto g = pivots.find(lo.cidx);
+            if (g != pivots.end()) {
+                ++lh;
+                k = g->second;
+                host = true;
+                continue;
+            }
+            ++la;
+            if (!apparent_lookup(Xc, lo.cidx, lo.diam, &other))
+                break;
+            host = false;
+        }
+        spec_low[j] = lo;
+        spec_nz[j] = nz ? 1 : 0;
+        spec_adds[j] += adds;
+        look_hash += lh;
+        look_app_b += la;
+    };
+
+    Ctx X(P);
+    int64_t frontier = 0;
+    std::vector<int64_t> round;
+    while (frontier < ncols) {
+        while (frontier < ncols && !pending[frontier])
+            finalize(frontier++);
+        if (frontier == ncols)
+            break;
+        round.swap(work);
+        work.clear();
+        if (round.size() == 1 || !P.parallel) {
+            for (int64_t j : round)
+                advance(X, j);
+        } else {
+            std::atomic<int64_t> nx{0};
+            pool.run([&](int) {
+                Ctx Xw(P);
+                for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size(); i = nx.fetch_add(1))
+                    advance(Xw, round[i]);
+            });
+        }
+        for (int64_t j : round) {
+            pending[j] = 0;
+            if (spec_nz[j])
+                wait_on(j);
         }
     }
+    R.lookups_hash += look_hash.load();
+    R.lookups_apparent += look_app_b.load();
+}
+
+}  // namespace
+
+void residual_reduce(const ResidualProblem &P, ResidualResult &R)
+{
+    // largest cofacet index + 1 = C(n, p+2)
+    const uint64_t ncof = P.binom[(int64_t)(P.p + 2) * (P.n + 1) + P.n];
+    if (ncof <= (1ull << 32))
+        reduce_impl<uint64_t>(P, R);
+    else
+        reduce_impl<u128>(P, R);
 }
 
 }  // namespace rpp
