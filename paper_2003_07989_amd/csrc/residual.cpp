@@ -172,10 +172,13 @@ public:
     // holds it; pairs are dropped until the minimum is unique.
     bool low(Entry &out)
     {
-        while (!top.empty()) {
-            const K e = top[0].k;
-            const size_t m = top.size();
-            const bool dup = (m > 1 && top[1].k == e) || (m > 2 && top[2].k == e);
+        while (!hk.empty()) {
+            const K e = hk[0];
+            const size_t m = hk.size();
+            const size_t e4 = m < 5 ? m : 5;
+            bool dup = false;
+            for (size_t j = 1; j < e4; ++j)
+                dup |= hk[j] == e;
             if (!dup) {
                 out = unpack<K>(e);
                 return true;
@@ -187,59 +190,73 @@ public:
     }
 
 private:
-    struct Top {
-        K k;
-        uint32_t s;
-    };
+    // 4-ary min-heap, keys and stream ids in separate arrays: half the
+    // levels of a binary heap, a node's four child keys share a cache line,
+    // and the smallest child is picked without branches.
     void sift_down(size_t i)
     {
-        const Top x = top[i];
-        const size_t m = top.size();
+        const K x = hk[i];
+        const uint32_t xs = hs[i];
+        const size_t m = hk.size();
         while (true) {
-            size_t c = 2 * i + 1;
+            const size_t c = 4 * i + 1;
             if (c >= m)
                 break;
-            if (c + 1 < m && top[c + 1].k < top[c].k)
-                ++c;
-            if (!(top[c].k < x.k))
+            size_t best = c;
+            K bk = hk[c];
+            const size_t e = c + 4 < m ? c + 4 : m;
+            for (size_t j = c + 1; j < e; ++j) {
+                const K v = hk[j];
+                const bool lt = v < bk;
+                bk = lt ? v : bk;
+                best = lt ? j : best;
+            }
+            if (!(bk < x))
                 break;
-            top[i] = top[c];
-            i = c;
+            hk[i] = bk;
+            hs[i] = hs[best];
+            i = best;
         }
-        top[i] = x;
+        hk[i] = x;
+        hs[i] = xs;
     }
     void top_push(K k, uint32_t s)
     {
-        top.push_back(Top{k, s});
-        size_t i = top.size() - 1;
-        const Top x = top[i];
+        hk.push_back(k);
+        hs.push_back(s);
+        size_t i = hk.size() - 1;
         while (i > 0) {
-            const size_t par = (i - 1) / 2;
-            if (!(x.k < top[par].k))
+            const size_t par = (i - 1) / 4;
+            if (!(k < hk[par]))
                 break;
-            top[i] = top[par];
+            hk[i] = hk[par];
+            hs[i] = hs[par];
             i = par;
         }
-        top[i] = x;
+        hk[i] = k;
+        hs[i] = s;
     }
     // Consume the root's entry from its stream and restore the heap.
     void advance_root()
     {
-        Stream<K> &st = streams[top[0].s];
+        Stream<K> &st = streams[hs[0]];
         st.pop();
         if (!st.empty()) {
-            top[0].k = st.front();
+            hk[0] = st.front();
         } else {
-            top[0] = top.back();
-            top.pop_back();
-            if (top.empty())
+            hk[0] = hk.back();
+            hs[0] = hs.back();
+            hk.pop_back();
+            hs.pop_back();
+            if (hk.empty())
                 return;
         }
         sift_down(0);
     }
     std::vector<Stream<K>> streams;
     size_t nstreams = 0;
-    std::vector<Top> top;
+    std::vector<K> hk;
+    std::vector<uint32_t> hs;
 };
 
 struct Ctx {
@@ -566,15 +583,26 @@ void parallel_for(int64_t n, const std::function<void(int64_t)> &fn)
 //    pivot store.
 namespace {
 
-template <class K> void reduce_impl(const ResidualProblem &P, ResidualResult &R)
-{
-    const int64_t ncols = P.ncols;
-    std::vector<Entry> spec_low(ncols);
-    std::vector<uint8_t> spec_nz(ncols, 0);
-    std::vector<int64_t> spec_adds(ncols, 0);
-    std::vector<std::unique_ptr<Column<K>>> state(ncols);
+// One dimension's reduction, split so that the speculative phase can run
+// before the previous dimension's pivots (the clearing set) are known: the
+// constructor runs phase A, finish() phase B.
+template <class K> class SpecImpl final : public ResidualSpec {
+public:
+    explicit SpecImpl(const ResidualProblem &p)
+        : P(p), ncols(p.ncols), spec_low(p.ncols), spec_nz(p.ncols, 0), spec_adds(p.ncols, 0),
+          spec_cut(p.ncols, 0), state(p.ncols)
+    {
+        phase_a();
+    }
+    void finish(const uint8_t *drop, ResidualResult &R) override
+    {
+        R.lookups_apparent = looks_a;
+        phase_b(drop, R);
+    }
 
-    auto apparent_lookup = [&](const Ctx &X, uint64_t tau, float dt, uint64_t *other) -> bool {
+private:
+    bool apparent_lookup(const Ctx &X, uint64_t tau, float dt, uint64_t *other) const
+    {
         if (P.app_tau) {
             const uint64_t *b = P.app_tau, *e = P.app_tau + P.napp;
             const uint64_t *f = std::lower_bound(b, e, tau);
@@ -584,220 +612,259 @@ template <class K> void reduce_impl(const ResidualProblem &P, ResidualResult &R)
             return true;
         }
         return X.apparent_partner(tau, dt, other);
-    };
-    auto diam_of_key = [&](int64_t j) {
-        return __builtin_bit_cast(float, (uint32_t)~(uint32_t)P.col_key[j]);
-    };
-
-    // ---- phase A ----------------------------------------------------------
-    Pool &pool = Pool::get();
-    const int workers = P.parallel ? pool.size() : 1;
-    std::atomic<int64_t> next{0};
-    std::atomic<int64_t> look_app{0};
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
-    auto phase_a = [&](int) {
-        Ctx X(P);
-        int64_t looks = 0;
-        while (true) {
-            const int64_t j0 = next.fetch_add(chunk);
-            if (j0 >= ncols)
-                break;
-            const int64_t j1 = std::min(ncols, j0 + chunk);
-            for (int64_t j = j0; j < j1; ++j) {
-                Entry lo{P.col_low_diam[j], P.col_low[j]};
-                if (lo.cidx == ~0ull)
-                    continue;  // empty coboundary
-                uint64_t other;
-                ++looks;
-                if (!apparent_lookup(X, lo.cidx, lo.diam, &other)) {
-                    spec_low[j] = lo;
-                    spec_nz[j] = 1;
-                    continue;
-                }
-                std::unique_ptr<Column<K>> col(new Column<K>());
-                X.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
-                bool nz;
-                int64_t adds = 0;
-                while (true) {
-                    // Algorithm 2: add the ORIGINAL column of the pivot's owner
-                    // (an apparent column has the diameter of its tau)
-                    X.add_coboundary(*col, other, lo.diam);
-                    ++adds;
-                    nz = col->low(lo);
-                    if (!nz)
-                        break;
-                    ++looks;
-                    if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
-                        break;
-                }
-                spec_low[j] = lo;
-                spec_nz[j] = nz ? 1 : 0;
-                spec_adds[j] = adds;
-                state[j] = std::move(col);
-            }
-        }
-        look_app += looks;
-    };
-    if (P.parallel)
-        pool.run(phase_a);
-    else
-        phase_a(0);
-    R.lookups_apparent = look_app.load();
-
-    // ---- phase B ----------------------------------------------------------
-    // Columns become final in column order (the frontier).  A column is
-    // final once every earlier column is final and its low is not the pivot
-    // of one of them.  A column whose low IS a final pivot makes exactly the
-    // addition the sequential algorithm makes at that point (pivots never
-    // change once final), so such columns -- anywhere past the frontier --
-    // are advanced together on the worker pool, each until its low is
-    // neither a final pivot nor apparent.  A waiting column is woken when
-    // its low becomes a final pivot.
-    //
-    // A finished column that needed additions keeps its heap state: its
-    // streams hold its reduced column R_k, which a later column adds in one
-    // step (R_j += R_k) instead of replaying k's reduction from the original
-    // column.  The copied entries are a subset of what the replay would
-    // regenerate, so this is never more work.
-    std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
-    pivots.reserve((size_t)ncols * 2 + 16);
-    std::vector<std::unique_ptr<Column<K>>> reduced;  // by index in R.sigma
-    reduced.reserve((size_t)ncols);
-    std::unordered_map<uint64_t, int64_t> whead;  // low -> last waiting column
-    whead.reserve((size_t)ncols * 2 + 16);
-    std::vector<int64_t> wnext(ncols, -1);
-    std::vector<uint8_t> pending(ncols, 0);
-    std::vector<int64_t> work;
-    auto wait_on = [&](int64_t j) {
-        auto r = whead.emplace(spec_low[j].cidx, j);
-        if (!r.second) {
-            wnext[j] = r.first->second;
-            r.first->second = j;
-        } else {
-            wnext[j] = -1;
-        }
-    };
-    for (int64_t j = 0; j < ncols; ++j)
-        if (spec_nz[j])
-            wait_on(j);
-
-    auto finalize = [&](int64_t j) {
-        const uint64_t sigma = P.col_cidx[j];
-        const float d = diam_of_key(j);
-        R.additions += spec_adds[j];
-        if (!spec_nz[j]) {
-            R.ess_sigma.push_back(sigma);
-            R.ess_birth.push_back(d);
-            return;
-        }
-        const Entry lo = spec_low[j];
-        if (spec_adds[j] == 0)
-            ++R.emergent;
-        pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
-        R.sigma.push_back(sigma);
-        R.tau.push_back(lo.cidx);
-        R.birth.push_back(d);
-        R.death.push_back(lo.diam);
-        reduced.push_back(spec_adds[j] ? std::move(state[j]) : nullptr);
-        state[j].reset();
-        auto it = whead.find(lo.cidx);
-        if (it == whead.end())
-            return;
-        for (int64_t k = it->second; k >= 0; k = wnext[k])
-            if (k != j && spec_nz[k] && spec_low[k].cidx == lo.cidx && !pending[k]) {
-                pending[k] = 1;
-                work.push_back(k);
-            }
-        whead.erase(it);
-    };
-
-    // Advance column j from a low that is a final pivot (read-only use of
-    // the pivot store and the finished columns; safe to run concurrently).
-    std::atomic<int64_t> look_hash{0}, look_app_b{0};
-    auto advance = [&](Ctx &Xc, int64_t j) {
-        std::unique_ptr<Column<K>> &col = state[j];
-        if (!col) {
-            col.reset(new Column<K>());
-            Xc.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
-        }
-        Entry lo = spec_low[j];
-        int64_t adds = 0, lh = 0, la = 0;
-        auto f = pivots.find(lo.cidx);
-        ++lh;
-        int64_t k = f->second;
-        bool host = true, nz = true;
-        uint64_t other = 0;
-        while (true) {
-            if (!host)
-                Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
-            else if (reduced[k])
-                col->add(*reduced[k]);
-            else
-                Xc.add_coboundary(*col, R.sigma[k], R.birth[k]);
-            ++adds;
-            nz = col->low(lo);
-            if (!nz)
-                break;
-            auto g = pivots.find(lo.cidx);
-            if (g != pivots.end()) {
-                ++lh;
-                k = g->second;
-                host = true;
-                continue;
-            }
-            ++la;
-            if (!apparent_lookup(Xc, lo.cidx, lo.diam, &other))
-                break;
-            host = false;
-        }
-        spec_low[j] = lo;
-        spec_nz[j] = nz ? 1 : 0;
-        spec_adds[j] += adds;
-        look_hash += lh;
-        look_app_b += la;
-    };
-
-    Ctx X(P);
-    int64_t frontier = 0;
-    std::vector<int64_t> round;
-    while (frontier < ncols) {
-        while (frontier < ncols && !pending[frontier])
-            finalize(frontier++);
-        if (frontier == ncols)
-            break;
-        round.swap(work);
-        work.clear();
-        if (round.size() == 1 || !P.parallel) {
-            for (int64_t j : round)
-                advance(X, j);
-        } else {
-            std::atomic<int64_t> nx{0};
-            pool.run([&](int) {
-                Ctx Xw(P);
-                for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size(); i = nx.fetch_add(1))
-                    advance(Xw, round[i]);
-            });
-        }
-        for (int64_t j : round) {
-            pending[j] = 0;
-            if (spec_nz[j])
-                wait_on(j);
-        }
     }
-    R.lookups_hash += look_hash.load();
-    R.lookups_apparent += look_app_b.load();
-}
+    float diam_of_key(int64_t j) const
+    {
+        return __builtin_bit_cast(float, (uint32_t)~(uint32_t)P.col_key[j]);
+    }
+
+    void phase_a()
+    {
+        // ---- phase A ----------------------------------------------------------
+        Pool &pool = Pool::get();
+        const int workers = P.parallel ? pool.size() : 1;
+        std::atomic<int64_t> next{0};
+        std::atomic<int64_t> look_app{0};
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
+        const int64_t budget = P.spec_budget;
+        auto phase_a = [&](int) {
+            Ctx X(P);
+            int64_t looks = 0;
+            while (true) {
+                const int64_t j0 = next.fetch_add(chunk);
+                if (j0 >= ncols)
+                    break;
+                const int64_t j1 = std::min(ncols, j0 + chunk);
+                for (int64_t j = j0; j < j1; ++j) {
+                    Entry lo{P.col_low_diam[j], P.col_low[j]};
+                    if (lo.cidx == ~0ull)
+                        continue;  // empty coboundary
+                    uint64_t other;
+                    ++looks;
+                    if (!apparent_lookup(X, lo.cidx, lo.diam, &other)) {
+                        spec_low[j] = lo;
+                        spec_nz[j] = 1;
+                        continue;
+                    }
+                    std::unique_ptr<Column<K>> col(new Column<K>());
+                    X.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
+                    bool nz;
+                    int64_t adds = 0;
+                    bool cut = false;
+                    while (true) {
+                        // Algorithm 2: add the ORIGINAL column of the pivot's owner
+                        // (an apparent column has the diameter of its tau)
+                        X.add_coboundary(*col, other, lo.diam);
+                        ++adds;
+                        nz = col->low(lo);
+                        if (!nz)
+                            break;
+                        ++looks;
+                        if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
+                            break;
+                        if (budget > 0 && adds >= budget) {
+                            cut = true;  // low still apparent: phase B goes on
+                            break;
+                        }
+                    }
+                    spec_low[j] = lo;
+                    spec_nz[j] = nz ? 1 : 0;
+                    spec_adds[j] = adds;
+                    spec_cut[j] = cut ? 1 : 0;
+                    state[j] = std::move(col);
+                }
+            }
+            look_app += looks;
+        };
+        if (P.parallel)
+            pool.run(phase_a);
+        else
+            phase_a(0);
+        looks_a = look_app.load();
+    }
+
+    void phase_b(const uint8_t *drop, ResidualResult &R)
+    {
+        // ---- phase B ----------------------------------------------------------
+        // Columns become final in column order (the frontier).  A column is
+        // final once every earlier column is final and its low is not the pivot
+        // of one of them.  A column whose low IS a final pivot makes exactly the
+        // addition the sequential algorithm makes at that point (pivots never
+        // change once final), so such columns -- anywhere past the frontier --
+        // are advanced together on the worker pool, each until its low is
+        // neither a final pivot nor apparent.  A waiting column is woken when
+        // its low becomes a final pivot.
+        //
+        // A finished column that needed additions keeps its heap state: its
+        // streams hold its reduced column R_k, which a later column adds in one
+        // step (R_j += R_k) instead of replaying k's reduction from the original
+        // column.  The copied entries are a subset of what the replay would
+        // regenerate, so this is never more work.
+        Pool &pool = Pool::get();
+        // columns that clearing removes (pivots of the previous dimension, not
+        // known when the speculative phase ran) take no part: no pair, no class
+        if (drop)
+            for (int64_t j = 0; j < ncols; ++j)
+                if (drop[j])
+                    spec_nz[j] = 0;
+        std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
+        pivots.reserve((size_t)ncols * 2 + 16);
+        std::vector<std::unique_ptr<Column<K>>> reduced;  // by index in R.sigma
+        reduced.reserve((size_t)ncols);
+        std::unordered_map<uint64_t, int64_t> whead;  // low -> last waiting column
+        whead.reserve((size_t)ncols * 2 + 16);
+        std::vector<int64_t> wnext(ncols, -1);
+        std::vector<uint8_t> pending(ncols, 0);
+        std::vector<int64_t> work;
+        auto wait_on = [&](int64_t j) {
+            auto r = whead.emplace(spec_low[j].cidx, j);
+            if (!r.second) {
+                wnext[j] = r.first->second;
+                r.first->second = j;
+            } else {
+                wnext[j] = -1;
+            }
+        };
+        for (int64_t j = 0; j < ncols; ++j) {
+            if (!spec_nz[j])
+                continue;
+            if (spec_cut[j]) {
+                pending[j] = 1;  // resumes in the first round
+                work.push_back(j);
+            } else {
+                wait_on(j);
+            }
+        }
+
+        auto finalize = [&](int64_t j) {
+            if (drop && drop[j])
+                return;
+            const uint64_t sigma = P.col_cidx[j];
+            const float d = diam_of_key(j);
+            R.additions += spec_adds[j];
+            if (!spec_nz[j]) {
+                R.ess_sigma.push_back(sigma);
+                R.ess_birth.push_back(d);
+                return;
+            }
+            const Entry lo = spec_low[j];
+            if (spec_adds[j] == 0)
+                ++R.emergent;
+            pivots.emplace(lo.cidx, (int64_t)R.sigma.size());
+            R.sigma.push_back(sigma);
+            R.tau.push_back(lo.cidx);
+            R.birth.push_back(d);
+            R.death.push_back(lo.diam);
+            reduced.push_back(spec_adds[j] ? std::move(state[j]) : nullptr);
+            state[j].reset();
+            auto it = whead.find(lo.cidx);
+            if (it == whead.end())
+                return;
+            for (int64_t k = it->second; k >= 0; k = wnext[k])
+                if (k != j && spec_nz[k] && spec_low[k].cidx == lo.cidx && !pending[k]) {
+                    pending[k] = 1;
+                    work.push_back(k);
+                }
+            whead.erase(it);
+        };
+
+        // Advance column j from a low that is a final pivot (read-only use of
+        // the pivot store and the finished columns; safe to run concurrently).
+        std::atomic<int64_t> look_hash{0}, look_app_b{0};
+        auto advance = [&](Ctx &Xc, int64_t j) {
+            std::unique_ptr<Column<K>> &col = state[j];
+            if (!col) {
+                col.reset(new Column<K>());
+                Xc.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
+            }
+            Entry lo = spec_low[j];
+            int64_t adds = 0, lh = 0, la = 0;
+            bool nz = true;
+            while (true) {
+                // the owner of the low: a final host column, else an
+                // apparent column, else the column stops here
+                auto f = pivots.find(lo.cidx);
+                if (f != pivots.end()) {
+                    ++lh;
+                    const int64_t k = f->second;
+                    if (reduced[k])
+                        col->add(*reduced[k]);
+                    else
+                        Xc.add_coboundary(*col, R.sigma[k], R.birth[k]);
+                } else {
+                    uint64_t other = 0;
+                    ++la;
+                    if (!apparent_lookup(Xc, lo.cidx, lo.diam, &other))
+                        break;
+                    Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
+                }
+                ++adds;
+                nz = col->low(lo);
+                if (!nz)
+                    break;
+            }
+            spec_low[j] = lo;
+            spec_nz[j] = nz ? 1 : 0;
+            spec_adds[j] += adds;
+            look_hash += lh;
+            look_app_b += la;
+        };
+
+        Ctx X(P);
+        int64_t frontier = 0;
+        std::vector<int64_t> round;
+        while (frontier < ncols) {
+            while (frontier < ncols && !pending[frontier])
+                finalize(frontier++);
+            if (frontier == ncols)
+                break;
+            round.swap(work);
+            work.clear();
+            if (round.size() == 1 || !P.parallel) {
+                for (int64_t j : round)
+                    advance(X, j);
+            } else {
+                std::atomic<int64_t> nx{0};
+                pool.run([&](int) {
+                    Ctx Xw(P);
+                    for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size(); i = nx.fetch_add(1))
+                        advance(Xw, round[i]);
+                });
+            }
+            for (int64_t j : round) {
+                pending[j] = 0;
+                if (spec_nz[j])
+                    wait_on(j);
+            }
+        }
+        R.lookups_hash += look_hash.load();
+        R.lookups_apparent += look_app_b.load();
+    }
+
+    const ResidualProblem P;
+    const int64_t ncols;
+    std::vector<Entry> spec_low;
+    std::vector<uint8_t> spec_nz;
+    std::vector<int64_t> spec_adds;
+    std::vector<uint8_t> spec_cut;  // phase A stopped at its budget, low apparent
+    std::vector<std::unique_ptr<Column<K>>> state;
+    int64_t looks_a = 0;
+};
 
 }  // namespace
 
-void residual_reduce(const ResidualProblem &P, ResidualResult &R)
+std::unique_ptr<ResidualSpec> residual_speculate(const ResidualProblem &P)
 {
     // largest cofacet index + 1 = C(n, p+2)
     const uint64_t ncof = P.binom[(int64_t)(P.p + 2) * (P.n + 1) + P.n];
     if (ncof <= (1ull << 32))
-        reduce_impl<uint64_t>(P, R);
-    else
-        reduce_impl<u128>(P, R);
+        return std::unique_ptr<ResidualSpec>(new SpecImpl<uint64_t>(P));
+    return std::unique_ptr<ResidualSpec>(new SpecImpl<u128>(P));
+}
+
+void residual_reduce(const ResidualProblem &P, ResidualResult &R)
+{
+    residual_speculate(P)->finish(nullptr, R);
 }
 
 }  // namespace rpp

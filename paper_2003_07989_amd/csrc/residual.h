@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <functional>
+#include <memory>
 #include <vector>
 
 namespace rpp {
@@ -38,6 +39,9 @@ struct ResidualProblem {
     // run the speculative phase on the shared worker pool (false: on the
     // calling thread only, e.g. when the caller already runs in parallel)
     bool parallel = true;
+    // at most this many additions per column in the speculative phase
+    // (0: no limit); a column cut off there resumes in the exact phase
+    int64_t spec_budget = 0;
 };
 
 struct ResidualResult {
@@ -54,6 +58,19 @@ struct ResidualResult {
 // with the two-layer pivot store: the pivots found here in a hash map first,
 // then the apparent pairs.
 void residual_reduce(const ResidualProblem &P, ResidualResult &R);
+
+// The same reduction in two steps.  residual_speculate runs the parallel
+// speculative phase (reduction against the apparent pivots only) and may run
+// before the previous dimension's pivots are known; finish() completes the
+// exact reduction, skipping every column j with drop[j] != 0 (columns the
+// clearing lemma removes, which would reduce to zero: no pair, no essential
+// class).  The problem's arrays must stay valid until finish() returns.
+class ResidualSpec {
+public:
+    virtual ~ResidualSpec() = default;
+    virtual void finish(const uint8_t *drop, ResidualResult &R) = 0;
+};
+std::unique_ptr<ResidualSpec> residual_speculate(const ResidualProblem &P);
 
 // Runs fn(i) for i in [0, n) on the shared worker pool (dynamic schedule);
 // fn must not itself use the pool.

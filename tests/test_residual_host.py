@@ -1,0 +1,79 @@
+"""Host residual reduction (csrc/residual.cpp) on the CPU, through a test
+driver that builds the GPU stages' hand-off by brute force: every schedule
+-- plain, with a speculative budget, and the overlapped one that drops the
+previous dimension's host pivots instead of clearing them -- gives the
+oracle's persistence pairs and essential classes exactly."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def driver():
+    out = os.path.join(tempfile.mkdtemp(prefix="rpp_resdrv_"), "residual_driver")
+    cmd = ["g++", "-O2", "-std=c++17", "-pthread", "-o", out,
+           os.path.join(HERE, "host", "residual_driver.cpp"),
+           os.path.join(ROOT, "paper_2003_07989_amd", "csrc", "residual.cpp")]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _run(driver, d, n, maxdim, thr, mode):
+    with tempfile.NamedTemporaryFile(suffix=".f32", delete=False) as f:
+        np.ascontiguousarray(d, dtype=np.float32).tofile(f)
+        path = f.name
+    try:
+        r = subprocess.run([driver, path, str(n), str(maxdim), repr(float(thr)), str(mode)],
+                           check=True, capture_output=True, text=True)
+    finally:
+        os.unlink(path)
+    pairs = {p: set() for p in range(1, maxdim + 1)}
+    ess = {p: set() for p in range(1, maxdim + 1)}
+    for line in r.stdout.splitlines():
+        t = line.split()
+        if t[0] == "P":
+            pairs[int(t[1])].add((int(t[2]), int(t[3])))
+        else:
+            ess[int(t[1])].add(int(t[2]))
+    return pairs, ess
+
+
+def _expected(d, n, maxdim, thr):
+    red = oracle.reduce(d, n, maxdim, thr, clearing=True)
+    pairs = {p: set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+             for p in range(1, maxdim + 1)}
+    ess = {p: set(red[p]["zero_sigma"].tolist()) for p in range(1, maxdim + 1)}
+    return pairs, ess
+
+
+CASES = [
+    ("torus40", lambda: w.condensed_from_points(w.noisy_torus_points(40, 31)), 40, 2, np.inf),
+    ("circle48", lambda: w.condensed_from_points(w.noisy_circle_points(48, seed=5)), 48, 1,
+     np.inf),
+    ("perm24", lambda: w.random_permutation_metric(24, 8), 24, 2, np.inf),
+    ("ties22", lambda: w.random_integer_metric(22, 9, vmax=3), 22, 2, np.inf),
+    ("square30_thr", lambda: w.condensed_from_points(w.uniform_square_points(30, 4)), 30, 2,
+     0.35),
+]
+
+
+@pytest.mark.parametrize("name,build,n,maxdim,thr", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["plain", "budget", "overlap"])
+def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
+    d = build()
+    if np.isinf(thr):
+        thr = oracle.enclosing_radius(d, n)  # the library's truncation; bars unchanged
+    got_p, got_e = _run(driver, d, n, maxdim, thr, mode)
+    exp_p, exp_e = _expected(d, n, maxdim, thr)
+    for p in range(1, maxdim + 1):
+        assert got_p[p] == exp_p[p], (name, mode, p)
+        assert got_e[p] == exp_e[p], (name, mode, p)
