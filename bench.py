@@ -6,15 +6,17 @@ resident in HBM: staging, H0, and for every dimension p >= 1 enumeration
 with threshold and clearing, the apparent-pair test, the partition and key
 sorts, the host reduction of the non-apparent columns and the clearing set
 of the next dimension.  value = simplices per second of whole-step time,
-where simplices = the p-simplices (p = 1..maxdim) of the Rips complex up to
-the given threshold that enter the filter (all C(n, p+1) when there is no
-threshold).
+where simplices = the p-simplices (p = 1..maxdim) of the Rips complex with
+diameter up to the workload's threshold (all C(n, p+1) when the workload has
+no threshold; the library's own truncation at the enclosing radius is an
+optimisation and does not change the count).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torus400]
 Other workloads (their own JSON lines): --workload sphere4096 (4096 points on
 the sphere, threshold 0.4), --workload circles64x512 (batched forward +
 backward), --workload serving512 (Poisson request stream, served vs batched
-vs plain).
+vs plain), --workload perm20000 (dimension-1 apparent test over all edges of
+a random edge order on 20000 points).
 """
 from __future__ import annotations
 
@@ -142,6 +144,8 @@ def bench_circles(args):
         "ms_forward_plain_64": round(t_plain * 1e3, 3),
         "ms_forward_batched_64": round(t_batch * 1e3, 3),
         "ms_backward_64": round(t_bwd * 1e3, 3),
+        "plain_stage_ms_mean": {k: [round(sum(r.stats[p][k] for r in plain) / 64, 4)
+                                    for p in range(2)] for k in ("ms_gpu", "ms_host")},
         "fd_check": fd,
     }
     if not args.no_cpu_baseline:
@@ -405,6 +409,108 @@ def cpu_baseline_requests(rpp, reqs, n_max=256, k=32):
             "gpu_plain_same_sample_barcodes_per_s": round(len(sample) / gpu_el, 2)}
 
 
+def bench_copy(args):
+    """HBM copy calibration: clone of a 1 GiB float32 tensor (1 GiB read +
+    1 GiB written per copy).  Its FETCH_SIZE / WRITE_SIZE counter readings
+    against the known bytes give the scale for the counters of the other
+    kernels."""
+    import torch
+    torch.cuda.set_device(0)
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "HBM copy bandwidth (read + write)", "value": round(2 * nbytes / el / 1e9, 1),
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(el * 1e3, 4), "higher_is_better": True,
+                      "config": {"workload": "copy1g", "bytes_read": nbytes,
+                                 "bytes_written": nbytes}}))
+
+
+# The paper's averages of the dimension-1 apparent fraction of random edge
+# orders (random distance-matrix experiments).
+PAPER_APPARENT_FRACTION = {10000: 0.991127743, 20000: 0.993733522}
+
+
+def bench_perm(args, n0):
+    """Dimension-1 apparent-pair test over all C(n0,2) edges of a matrix
+    whose lower triangle is a random order of distinct FP32 values: columns
+    per second through staging + enumeration + apparent test + partition,
+    the apparent fraction, and the roofline of the apparent kernel."""
+    import numpy as np
+    import torch
+    import paper_2003_07989_amd as rpp
+    import workloads
+    torch.cuda.set_device(0)
+    rpp.load()
+    d_host = workloads.random_permutation_metric(n0, 1006)
+    dist = torch.from_numpy(d_host).cuda()
+    del d_host
+    stream = torch.cuda.current_stream()
+    os.environ["RPP_COUNT_SCANS"] = "1"
+    k, ncols, tally = rpp.apparent_count(dist, 1, n=n0, stream=stream)
+    del os.environ["RPP_COUNT_SCANS"]
+    for _ in range(args.warmup):
+        rpp.apparent_count(dist, 1, n=n0, stream=stream)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 4)
+    acc = {"ms_enumerate": 0.0, "ms_apparent": 0.0, "ms_partition": 0.0, "ms_gpu": 0.0}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        k, ncols, st = rpp.apparent_count(dist, 1, n=n0, stream=stream)
+        for key in acc:
+            acc[key] += st[key] / steps
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    kbytes = algorithmic_bytes_apparent(tally, 1)
+    kms = acc["ms_apparent"]
+    achieved = kbytes / (kms / 1e3) / 1e9
+    out = {
+        "metric": "columns/sec through the dimension-1 apparent-pair test (random edge order)",
+        "value": round(ncols / el, 1), "unit": "columns/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(el * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "perm%d" % n0, "n0": n0, "columns": ncols, "seed": 1006},
+        "apparent_fraction": k / ncols,
+        "paper_average_fraction": PAPER_APPARENT_FRACTION.get(n0),
+        "upper_bound_fraction": (n0 - 2) / n0,
+        "mean_scan": tally["n_scanned"] / ncols,
+        "apparent_group": st["apparent_group"],
+        "gpu_stage_ms": {key: round(v, 4) for key, v in acc.items()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_apparent<1,%d>" % st["apparent_group"], "dim": 1,
+                     "ms": round(kms, 4), "bytes": kbytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_perm()
+    print(json.dumps(out))
+
+
+def cpu_baseline_perm(n0=500):
+    """The oracle's apparent-pair test on a smaller random order (all
+    C(n0,2) edges), one thread, as columns/s.  Its cost per column grows
+    with n0 (every column builds its full coboundary), so the sample is
+    small and the rate is not the same per-column work as at 20000 points."""
+    import oracle
+    import workloads
+    oracle.build()
+    d = workloads.random_permutation_metric(n0, 1006)
+    t0 = time.perf_counter()
+    oracle.apparent_pairs(d, n0, 1)
+    el = time.perf_counter() - t0
+    return {"value": round(n0 * (n0 - 1) / 2 / el, 1), "unit": "columns/s", "cores": 1,
+            "kind": "oracle", "seconds": round(el, 3),
+            "sample": "random order on %d points (all %d edges), dimension 1" % (n0, n0 * (n0 - 1) // 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +529,10 @@ def main():
               "build has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload.startswith("perm"):
+        return bench_perm(args, int(args.workload[4:]))
+    if args.workload == "copy1g":
+        return bench_copy(args)
     if args.workload == "circles64x512":
         return bench_circles(args)
     if args.workload.startswith("serving"):
@@ -464,7 +574,13 @@ def main():
     for k in stage:
         stage[k] = [v / args.steps for v in stage[k]]
 
-    simplices = sum(last.stats[p]["n_candidates"] for p in range(1, maxdim + 1))
+    # p-simplices with diameter <= the workload's threshold, p = 1..maxdim:
+    # every C(n, p+1) without a threshold (the library's truncation at the
+    # enclosing radius is an optimisation, not part of the workload)
+    if math.isinf(thr):
+        simplices = sum(math.comb(n, p + 1) for p in range(1, maxdim + 1))
+    else:
+        simplices = sum(last.stats[p]["n_simplices"] for p in range(1, maxdim + 1))
     value = simplices / (ms_step / 1e3)
     # GPU-only rate through filtration + apparent test + partition + sorts
     gpu_ms = sum(stage["ms_enumerate"][p] + stage["ms_apparent"][p] + stage["ms_partition"][p]

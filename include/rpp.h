@@ -114,6 +114,7 @@ typedef struct {
     float ms_apparent;      /* device time: apparent-pair kernel */
     float ms_partition;     /* device time: partition */
     float ms_sort;          /* device time: key sorts and clearing bitmap */
+    int32_t apparent_group; /* lanes that test one column in the apparent kernel */
 } rpp_dim_stats;
 
 typedef struct {
@@ -197,15 +198,21 @@ int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream,
 size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold);
 
 /* Apparent pairs of dimension (p, p+1) over EVERY p-simplex with diameter
- * <= threshold (no clearing), by the apparent pairs lemma, on the GPU
- * (paper, algorithm for finding apparent pairs).  dist_dev is a device
- * condensed matrix.  Writes at most cap pairs (sigma_cidx, tau_cidx) in
- * increasing sigma order into host arrays sigma_out / tau_out (either may be
- * NULL when cap == 0) and stores the number of apparent pairs in *count and
- * the number of p-simplices examined in *n_columns. */
+ * <= threshold (no clearing, no truncation at the enclosing radius), by the
+ * apparent pairs lemma, on the GPU (paper, algorithm for finding apparent
+ * pairs; the dimension-1 apparent fraction of its random-order experiments).
+ * dist_dev is a device condensed matrix.  Writes at most cap pairs
+ * (sigma_cidx, tau_cidx) in increasing sigma order into host arrays
+ * sigma_out / tau_out (either may be NULL when cap == 0; with cap == 0 the
+ * pairs are only counted and never leave the device) and stores the number
+ * of apparent pairs in *count and the number of p-simplices examined in
+ * *n_columns.  stats (may be NULL) receives the counts, the GPU stage times
+ * and the lanes per column; n_scanned is filled when the environment
+ * variable RPP_COUNT_SCANS=1. */
 int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float threshold,
                        void *hip_stream, uint64_t *sigma_out, uint64_t *tau_out,
-                       int64_t cap, int64_t *count, int64_t *n_columns);
+                       int64_t cap, int64_t *count, int64_t *n_columns,
+                       rpp_dim_stats *stats);
 
 /* Condensed FP32 distance matrix of n points in R^d.  points_dev: n x d
  * FP32 coordinates, row-major, device memory; dist_dev: n*(n-1)/2 floats,

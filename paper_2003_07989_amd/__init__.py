@@ -12,7 +12,8 @@ from ._binding import (NO_EDGE, RPP_BATCH_AUTOTUNE, RPP_BATCH_NO_GRAPH, RPP_FORC
                        RPP_FORCE_SPARSE, RPP_MAX_DIM,
                        RPP_NO_ENCLOSING_RADIUS, RPP_SORTED_PAIR_STORE,
                        RPP_WANT_CRITICAL_EDGES, RPP_WANT_PAIRS, Barcodes,
-                       PointCloudBarcodes, RppError, Server, apparent_pairs, backward_points, barcodes,
+                       PointCloudBarcodes, RppError, Server, apparent_count, apparent_pairs,
+                       backward_points, barcodes,
                        barcodes_batch,
                        barcodes_device, barcodes_host, load, pdist_device,
                        point_cloud_barcodes, strerror, version, workspace_bytes)
@@ -20,6 +21,6 @@ from ._binding import (NO_EDGE, RPP_BATCH_AUTOTUNE, RPP_BATCH_NO_GRAPH, RPP_FORC
 __all__ = ["NO_EDGE", "RPP_BATCH_AUTOTUNE", "RPP_BATCH_NO_GRAPH", "RPP_FORCE_DENSE", "RPP_FORCE_SPARSE", "RPP_MAX_DIM",
            "RPP_NO_ENCLOSING_RADIUS", "RPP_SORTED_PAIR_STORE", "RPP_WANT_CRITICAL_EDGES",
            "RPP_WANT_PAIRS", "Barcodes", "PointCloudBarcodes", "RppError", "Server",
-           "apparent_pairs",
+           "apparent_count", "apparent_pairs",
            "backward_points", "barcodes", "barcodes_batch", "barcodes_device", "barcodes_host", "load",
            "pdist_device", "point_cloud_barcodes", "strerror", "version", "workspace_bytes"]

@@ -45,7 +45,8 @@ class _Stats(ctypes.Structure):
         "n_candidates", "n_simplices", "n_thresholded", "n_cleared", "n_kept",
         "n_apparent", "n_nonapparent", "n_host_pairs", "n_essential", "n_bars",
         "n_column_adds", "n_scanned")] + [(name, ctypes.c_float) for name in (
-        "ms_gpu", "ms_host", "ms_enumerate", "ms_apparent", "ms_partition", "ms_sort")]
+        "ms_gpu", "ms_host", "ms_enumerate", "ms_apparent", "ms_partition", "ms_sort")] + [
+        ("apparent_group", ctypes.c_int32)]
 
 
 class _Bars(ctypes.Structure):
@@ -107,7 +108,7 @@ def load() -> ctypes.CDLL:
     lib.rpp_apparent_pairs.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_float, ctypes.c_void_p, P(ctypes.c_uint64),
                                        P(ctypes.c_uint64), ctypes.c_int64, P(ctypes.c_int64),
-                                       P(ctypes.c_int64)]
+                                       P(ctypes.c_int64), P(_Stats)]
     lib.rpp_apparent_pairs.restype = ctypes.c_int
     lib.rpp_pdist_device.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p]
@@ -263,30 +264,42 @@ def barcodes_host(dist: np.ndarray, maxdim: int, threshold: float = math.inf,
         lib.rpp_result_free(out)
 
 
-def apparent_pairs(dist, p: int, threshold: float = math.inf, n: int = None, stream=None):
-    """(sigma, tau, n_columns): apparent pairs of dimension (p, p+1) over all
-    p-simplices with diameter <= threshold, in increasing sigma order."""
+def _apparent_call(dist, p, threshold, n, stream, cap, s_arr, t_arr, stats):
     if isinstance(dist, torch.Tensor) and dist.is_cuda:
         t = dist.to(torch.float32).contiguous()
     else:
         t = torch.from_numpy(np.ascontiguousarray(np.asarray(dist), dtype=np.float32)).cuda()
     if n is None:
         n = _n_from_len(t.numel())
-    lib = load()
     cnt, ncols = ctypes.c_int64(0), ctypes.c_int64(0)
-    h = ctypes.c_void_p(_stream_handle(stream))
-    _check(lib.rpp_apparent_pairs(ctypes.c_void_p(t.data_ptr()), int(n), int(p),
-                                  ctypes.c_float(threshold), h, None, None, 0,
-                                  ctypes.byref(cnt), ctypes.byref(ncols)))
-    k = cnt.value
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(load().rpp_apparent_pairs(
+        ctypes.c_void_p(t.data_ptr()), int(n), int(p), ctypes.c_float(threshold),
+        ctypes.c_void_p(_stream_handle(stream)),
+        s_arr.ctypes.data_as(P64) if s_arr is not None else None,
+        t_arr.ctypes.data_as(P64) if t_arr is not None else None, int(cap),
+        ctypes.byref(cnt), ctypes.byref(ncols),
+        ctypes.byref(stats) if stats is not None else None))
+    return int(cnt.value), int(ncols.value)
+
+
+def apparent_pairs(dist, p: int, threshold: float = math.inf, n: int = None, stream=None):
+    """(sigma, tau, n_columns): apparent pairs of dimension (p, p+1) over all
+    p-simplices with diameter <= threshold, in increasing sigma order."""
+    k, _ = _apparent_call(dist, p, threshold, n, stream, 0, None, None, None)
     s = np.zeros(max(k, 1), np.uint64)
     u = np.zeros(max(k, 1), np.uint64)
-    P64 = ctypes.POINTER(ctypes.c_uint64)
-    _check(lib.rpp_apparent_pairs(ctypes.c_void_p(t.data_ptr()), int(n), int(p),
-                                  ctypes.c_float(threshold), h, s.ctypes.data_as(P64),
-                                  u.ctypes.data_as(P64), k, ctypes.byref(cnt),
-                                  ctypes.byref(ncols)))
-    return s[:k], u[:k], int(ncols.value)
+    k2, ncols = _apparent_call(dist, p, threshold, n, stream, k, s, u, None)
+    return s[:k2], u[:k2], ncols
+
+
+def apparent_count(dist, p: int, threshold: float = math.inf, n: int = None, stream=None):
+    """Number of apparent pairs of dimension (p, p+1) over all p-simplices
+    with diameter <= threshold, without fetching them: (count, n_columns,
+    stats dict with the GPU stage times and lanes per column)."""
+    st = _Stats()
+    k, ncols = _apparent_call(dist, p, threshold, n, stream, 0, None, None, st)
+    return k, ncols, {name: getattr(st, name) for name, _ in _Stats._fields_}
 
 
 def workspace_bytes(n: int, maxdim: int, threshold: float = math.inf) -> int:

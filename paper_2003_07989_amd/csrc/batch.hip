@@ -170,12 +170,15 @@ struct BatchWs {
     DevBuf rscratch;
     DevBuf poff, pkey, pcidx, plow, plowd;  // packed non-apparent columns
     DevBuf hidx, hcloud;                   // host pivots for the next clearing set
+    HostBuf h_dsq;                         // pinned host copies of the square matrices
     std::vector<uint64_t> binom_host;
     std::map<std::tuple<int, int>, hipGraphExec_t> graphs;  // (p, group) -> graph
     // The batch runs on its own stream (the caller's may be the null stream,
     // which cannot be captured), ordered after the caller's stream.
     hipStream_t own = nullptr;
     hipEvent_t ready = nullptr;
+    int in_use = 0;          // callers holding it (guarded by g_bws_mu)
+    uint64_t last_use = 0;   // for least-recently-used eviction
     ~BatchWs()
     {
         for (auto &kv : graphs)
@@ -190,19 +193,57 @@ struct BatchWs {
 static std::mutex g_bws_mu;
 static std::map<std::tuple<int, int, int, int>, BatchWs *> g_bws;
 
-static BatchWs &batch_ws(int n, int maxdim, int nb)
+// At most this many batch workspaces are cached per device; beyond it the
+// least recently used idle one is freed (a stream of many shapes would
+// otherwise keep every shape's capacity-sized arenas).
+constexpr size_t BATCH_CACHE_ENTRIES = 4;
+static uint64_t g_bws_clock = 0;
+
+// The workspace for a shape, marked in use until batch_ws_release.
+static BatchWs *batch_ws_acquire(int n, int maxdim, int nb)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_bws_mu);
-    BatchWs *&w = g_bws[{dev, n, maxdim, nb}];
-    if (!w) {
-        w = new BatchWs();
-        w->n = n;
-        w->maxdim = maxdim;
-        w->nb = nb;
+    std::vector<BatchWs *> victims;
+    BatchWs *w;
+    {
+        std::lock_guard<std::mutex> lk(g_bws_mu);
+        BatchWs *&slot = g_bws[{dev, n, maxdim, nb}];
+        if (!slot) {
+            slot = new BatchWs();
+            slot->n = n;
+            slot->maxdim = maxdim;
+            slot->nb = nb;
+        }
+        w = slot;
+        ++w->in_use;
+        w->last_use = ++g_bws_clock;
+        while (true) {
+            size_t count = 0;
+            auto lru = g_bws.end();
+            for (auto it = g_bws.begin(); it != g_bws.end(); ++it) {
+                if (std::get<0>(it->first) != dev)
+                    continue;
+                ++count;
+                if (it->second->in_use == 0 &&
+                    (lru == g_bws.end() || it->second->last_use < lru->second->last_use))
+                    lru = it;
+            }
+            if (count <= BATCH_CACHE_ENTRIES || lru == g_bws.end())
+                break;
+            victims.push_back(lru->second);
+            g_bws.erase(lru);
+        }
     }
-    return *w;
+    for (BatchWs *v : victims)
+        delete v;  // idle and unreachable: frees its buffers, graphs and stream
+    return w;
+}
+
+static void batch_ws_release(BatchWs *w)
+{
+    std::lock_guard<std::mutex> lk(g_bws_mu);
+    --w->in_use;
 }
 
 // Sizes of one dimension's stage.
@@ -461,7 +502,12 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
         }
         return RPP_OK;
     }
-    BatchWs &W = batch_ws(n, maxdim, nb);
+    BatchWs *Wp = batch_ws_acquire(n, maxdim, nb);
+    struct Release {
+        BatchWs *w;
+        ~Release() { batch_ws_release(w); }
+    } release{Wp};
+    BatchWs &W = *Wp;
     std::lock_guard<std::mutex> lk(W.mu);
     if (!W.dcond.p) {
         int rc = batch_alloc(W, err);
@@ -478,7 +524,12 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
                                hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.thr_req.p, a.threshold, (size_t)nb * 4, hipMemcpyHostToDevice, s));
 
-    std::vector<float> h_dsq_all((size_t)nb * n * n);  // host copies for the reductions
+    // host copies for the reductions (pinned, kept with the batch workspace)
+    if (maxdim >= 1 && !W.h_dsq.ensure((size_t)nb * n * n * 4)) {
+        err = "hipHostMalloc of the host distance copies failed";
+        return RPP_E_NOMEM;
+    }
+    const float *h_dsq_all = W.h_dsq.as<float>();
     for (int p = 1; p <= maxdim; ++p) {
         const DimShape D = dim_shape(n, p, maxdim);
         int group = a.group > 0 ? a.group : tuned_group(n, p);
@@ -527,7 +578,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
                                    hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(dedges.data(), W.dedges.p, dedges.size() * 8,
                                    hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(h_dsq_all.data(), W.dsq.p, h_dsq_all.size() * 4,
+            HIP_TRY(hipMemcpyAsync(W.h_dsq.p, W.dsq.p, (size_t)nb * n * n * 4,
                                    hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
@@ -600,7 +651,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             P.n = n;
             P.p = p;
             P.thr = outs[c].thr_used;
-            P.dsq = h_dsq_all.data() + (size_t)c * n * n;
+            P.dsq = h_dsq_all + (size_t)c * n * n;
             P.binom = W.binom_host.data();
             P.ncols = (int64_t)nna[c];
             P.col_key = hk.data() + off[c];
@@ -618,7 +669,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
         for (int c = 0; c < nb; ++c) {
             DimOut &Dd = outs[c].dims[p];
             const ResidualResult &R = RR[c];
-            const float *dsq = h_dsq_all.data() + (size_t)c * n * n;
+            const float *dsq = h_dsq_all + (size_t)c * n * n;
             for (size_t i = 0; i < R.sigma.size(); ++i)
                 if (R.death[i] > R.birth[i]) {
                     Dd.birth.push_back(R.birth[i]);
@@ -639,6 +690,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             Dd.st.n_cleared = (int64_t)st[2 * c + 1];
             Dd.st.n_simplices = D.cap - (int64_t)st[2 * c];
             Dd.st.n_kept = kept;
+            Dd.st.apparent_group = group;
             Dd.st.n_apparent = napp;
             Dd.st.n_nonapparent = kept - napp;
             Dd.st.n_host_pairs = (int64_t)R.sigma.size();

@@ -286,7 +286,7 @@ size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold)
 
 int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float threshold,
                        void *hip_stream, uint64_t *sigma_out, uint64_t *tau_out, int64_t cap,
-                       int64_t *count, int64_t *n_columns)
+                       int64_t *count, int64_t *n_columns, rpp_dim_stats *stats)
 {
     if (!count || !n_columns)
         return fail(RPP_E_INVAL, "count / n_columns is NULL");
@@ -302,13 +302,16 @@ int rpp_apparent_pairs(const float *dist_dev, int32_t n, int32_t p, float thresh
         return fail(RPP_E_RANGE, "C(n, p+2) exceeds the 63-bit index range");
     try {
         std::vector<uint64_t> s, t;
-        int64_t ncols = 0;
+        int64_t ncols = 0, napp = 0;
         std::string err;
+        const char *cs = getenv("RPP_COUNT_SCANS");
+        const bool count_scans = stats && cs && atoi(cs) != 0;
         int rc = rpp::run_apparent_only(dist_dev, n, p, threshold,
-                                        static_cast<hipStream_t>(hip_stream), s, t, ncols, err);
+                                        static_cast<hipStream_t>(hip_stream), cap > 0,
+                                        count_scans, s, t, ncols, napp, stats, err);
         if (rc)
             return fail(rc, err);
-        *count = (int64_t)s.size();
+        *count = napp;
         *n_columns = ncols;
         const int64_t k = std::min<int64_t>(cap, (int64_t)s.size());
         if (k > 0) {

@@ -500,10 +500,25 @@ void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float 
 //  2. Youngest facet: the other facets of tau are sigma - {u} + {w}; such a
 //     facet precedes sigma in cidx order exactly when u > w, and is younger
 //     than sigma exactly when, in addition, its diameter equals d.
-// G lanes cooperate on one column: in each step they test the G vertices
-// top, top-1, ..., top-G+1 with contiguous reads of the rows of the square
-// matrix, and a ballot picks the largest hit.
+//
+// A wave owns 64 consecutive columns.  Every lane loads and decodes one of
+// them (coalesced, no redundant decodes); then the wave works through them
+// in G rounds of 64/G columns, G lanes per column: the lanes of a group
+// fetch their column's diameter and vertices from the owner lane by
+// shuffles, test the G vertices top, top-1, ..., top-G+1 per step with
+// contiguous reads of the rows of the square matrix, and a ballot picks the
+// largest hit.  The facet test takes d(v_i, w) from the registers of the
+// lane that hit, and the distances among sigma's own vertices are loaded
+// while the scan runs.  Each tau returns to its owner lane for one
+// coalesced store.
 // ===========================================================================
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, WAVE);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int P, int G>
 __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_diam,
                                                   const uint64_t *__restrict__ col_cidx,
@@ -513,9 +528,13 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
                                                   unsigned long long *__restrict__ scan_count,
                                                   Batch bt)
 {
+    constexpr int CPR = WAVE / G;  // columns per round
     const int lane = threadIdx.x & (WAVE - 1);
     const int g = lane & (G - 1);
-    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * WAVE;
     {
         const int64_t cl = blockIdx.y;
         ncols = batch_count(bt, cl, ncols);
@@ -524,63 +543,96 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
         tau_out += cl * bt.stride;
         dsq += cl * (int64_t)n * n;
     }
-    if (col >= ncols)
-        return;  // whole groups leave together
+    if (base >= ncols)
+        return;  // whole waves leave together
     const Binom B{binom, n + 1};
-    const float d = col_diam[col];
-    const uint64_t c = col_cidx[col];
-    int v[P + 1];
-    decode<P>(B, c, n, v);
-    const float *row[P + 1];
+    const int64_t mycol = base + lane;
+    const bool myvalid = mycol < ncols;
+    float myd = 0.0f;
+    int myv[P + 1];
 #pragma unroll
     for (int i = 0; i <= P; ++i)
-        row[i] = dsq + (int64_t)v[i] * n;
-
-    const int gbase = lane - g;
-    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
-    int w = -1;
-    for (int top = n - 1; top >= 0; top -= G) {
-        const int u = top - g;
-        bool ok = u >= 0;
-        if (ok) {
-#pragma unroll
-            for (int i = 0; i <= P; ++i)
-                ok = ok && (u != v[i]) && (row[i][u] <= d);
-        }
-        const uint64_t m = __ballot(ok) & gmask;
-        if (m) {
-            w = top - (__ffsll((unsigned long long)m) - 1 - gbase);
-            break;
-        }
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        decode<P>(B, col_cidx[mycol], n, myv);
     }
-    uint64_t tau = NONE;
-    if (w >= 0) {
-        bool apparent = true;
+    uint64_t mytau = NONE;
+    for (int r = 0; r < G; ++r) {
+        const int src = r * CPR + grp;
+        const float d = __shfl(myd, src, WAVE);
+        int v[P + 1];
 #pragma unroll
-        for (int j = 0; j <= P; ++j) {
-            if (v[j] > w && apparent) {
-                // facet sigma - {v_j} + {w}
-                float fd = 0.0f;
+        for (int i = 0; i <= P; ++i)
+            v[i] = __shfl(myv[i], src, WAVE);
+        const bool valid = base + src < ncols;  // uniform in the group
+        const float *row[P + 1];
 #pragma unroll
-                for (int a = 0; a <= P; ++a) {
-                    if (a == j)
-                        continue;
-                    fd = fmaxf(fd, row[a][w]);
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)v[i] * n;
+        // distances among sigma's own vertices (facet test), loaded early
+        float dv[P + 1][P + 1];
 #pragma unroll
-                    for (int b = a + 1; b <= P; ++b)
-                        if (b != j)
-                            fd = fmaxf(fd, row[a][v[b]]);
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= P; ++b)
+                dv[a][b] = valid ? row[a][v[b]] : 0.0f;
+        int w = -1;
+        int hit = 0;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = n - 1; top >= 0; top -= G) {
+                const int u = top - g;
+                bool ok = u >= 0;
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        e[i] = row[i][u];
+                        ok = ok && (u != v[i]) && (e[i] <= d);
+                    }
                 }
-                if (fd == d)
-                    apparent = false;
+                const uint64_t m = __ballot(ok) & gmask;
+                if (m) {
+                    hit = __ffsll((unsigned long long)m) - 1;  // lane of the largest u
+                    w = top - (hit - gbase);
+                    break;
+                }
             }
         }
-        if (apparent)
-            tau = cofacet_index<P>(B, v, w);
-    }
-    if (g == 0) {
-        tau_out[col] = tau;
-        if (scan_count) {
+        // d(v_i, w) from the lane that found w (every lane joins the shuffle)
+        float ew[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            ew[i] = __shfl(e[i], w >= 0 ? hit : lane, WAVE);
+        uint64_t tau = NONE;
+        if (w >= 0) {
+            bool apparent = true;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                if (v[j] > w && apparent) {
+                    // facet sigma - {v_j} + {w}
+                    float fd = 0.0f;
+#pragma unroll
+                    for (int a = 0; a <= P; ++a) {
+                        if (a == j)
+                            continue;
+                        fd = fmaxf(fd, ew[a]);
+#pragma unroll
+                        for (int b = a + 1; b <= P; ++b)
+                            if (b != j)
+                                fd = fmaxf(fd, dv[a][b]);
+                    }
+                    if (fd == d)
+                        apparent = false;
+                }
+            }
+            if (apparent)
+                tau = cofacet_index<P>(B, v, w);
+        }
+        if (scan_count && valid && g == 0) {
             // candidates w not in sigma, visited from n-1 down to w*
             long long sc = n - P - 1;
             if (w >= 0) {
@@ -591,7 +643,14 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
             }
             atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)sc);
         }
+        // the owner of column base + r*CPR + k is lane r*CPR + k; group k's
+        // first lane holds its tau
+        const uint64_t t = shfl_u64(tau, (lane % CPR) * G);
+        if (lane / CPR == r)
+            mytau = t;
     }
+    if (myvalid)
+        tau_out[mycol] = mytau;
 }
 
 template <int P>
@@ -600,7 +659,7 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
                               uint64_t *tau, unsigned long long *sc, hipStream_t s,
                               Batch bt = Batch(), int nbatch = 1)
 {
-    const int64_t threads = ncols * group;
+    const int64_t threads = (ncols + WAVE - 1) / WAVE * WAVE;  // one wave per 64 columns
     dim3 g((unsigned)((threads + 255) / 256), nbatch), b(256);
     switch (group) {
     case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;

@@ -62,9 +62,12 @@ struct BatchArgs {
 int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err);
 
 // Apparent pairs of dimension (p, p+1) over all p-simplices <= threshold.
+// copy_pairs: fetch the pairs to sigma / tau; count_scans: tally the cofacet
+// candidates the scans examine; st (may be null): counts and GPU stage times.
 int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
-                      std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau,
-                      int64_t &ncols, std::string &err);
+                      bool copy_pairs, bool count_scans, std::vector<uint64_t> &sigma,
+                      std::vector<uint64_t> &tau, int64_t &ncols, int64_t &napp,
+                      rpp_dim_stats *st, std::string &err);
 
 int run_pdist(const float *pts, int n, int d, float *dist, hipStream_t s, std::string &err);
 // edges[i] / g[i]: gradient terms (edge cidx or UINT64_MAX, dL/dlength)

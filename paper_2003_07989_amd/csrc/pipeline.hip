@@ -23,6 +23,7 @@
 #include <chrono>
 #include <map>
 #include <mutex>
+#include <thread>
 
 namespace rpp {
 
@@ -76,7 +77,11 @@ struct Workspace {
     DevBuf lowc, lowd;               // lows of the non-apparent columns
     DevBuf gedges, gvals;            // backward: gradient terms
     DevBuf rscratch, scancnt;
-    HostBuf h_app_tau, h_app_sigma, h_na_key, h_na_cidx, h_low, h_lowd, h_small;
+    // host hand-off of one dimension; two sets, since the reduction of
+    // dimension p still reads its set while dimension p+1 fills the other
+    HostBuf h_app_tau[2], h_app_sigma[2], h_na_key[2], h_na_cidx[2], h_low[2], h_lowd[2];
+    HostBuf h_small;
+    HostBuf h_dsq, h_bits;           // pinned host copies for the residual reduction
     int binom_n = -1, binom_k = -1;
     std::vector<uint64_t> binom_host;
 };
@@ -280,6 +285,11 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     return RPP_OK;
 }
 
+// Additions per column in the speculative phase before it defers the column
+// to the exact phase (which then drops it, if the previous dimension's host
+// pivots clear it).
+constexpr int64_t SPEC_BUDGET = 16;
+
 static int default_group(int p)
 {
     (void)p;
@@ -347,12 +357,17 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     const int bstride = n + 1;
     (void)bstride;
 
-    // host copy of the square matrix for the residual reduction
-    std::vector<float> h_dsq;
+    // host copy of the square matrix for the residual reduction (pinned,
+    // grow-only: a DMA copy that overlaps nothing on the host)
+    const float *h_dsq = nullptr;
     if (maxdim >= 1) {
-        h_dsq.resize((size_t)n * n);
-        HIP_TRY(hipMemcpyAsync(h_dsq.data(), ws.dsq.p, (size_t)n * n * 4,
-                               hipMemcpyDeviceToHost, s));
+        if (!ws.h_dsq.ensure((size_t)n * n * 4)) {
+            err = "hipHostMalloc of the host distance copy failed";
+            return RPP_E_NOMEM;
+        }
+        h_dsq = ws.h_dsq.as<float>();
+        HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.dsq.p, (size_t)n * n * 4, hipMemcpyDeviceToHost,
+                               s));
     }
 
     // ---------------- a2: H0 ---------------------------------------------
@@ -431,7 +446,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                                         (!(a.flags & RPP_FORCE_DENSE) &&
                                          (double)nedges < 0.25 * (double)E));
     const int words = (n + 63) / 64;
-    std::vector<uint64_t> h_bits;
+    const uint64_t *h_bits = nullptr;
     int cur = 0;
     int64_t nskel = 0;
     if (sparse) {
@@ -447,14 +462,90 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         nskel = nedges;
         ALLOC_TRY(ws.bits, (size_t)n * words * 8);
         launch_nbr_bits(ws.dsq.as<float>(), n, thr, ws.bits.as<uint64_t>(), words, s);
-        h_bits.resize((size_t)n * words);
-        HIP_TRY(hipMemcpyAsync(h_bits.data(), ws.bits.p, h_bits.size() * 8, hipMemcpyDeviceToHost,
-                               s));
+        if (!ws.h_bits.ensure((size_t)n * words * 8)) {
+            err = "hipHostMalloc of the host bitset copy failed";
+            return RPP_E_NOMEM;
+        }
+        h_bits = ws.h_bits.as<uint64_t>();
+        HIP_TRY(hipMemcpyAsync(ws.h_bits.p, ws.bits.p, (size_t)n * words * 8,
+                               hipMemcpyDeviceToHost, s));
     }
 
     // ---------------- dimensions 1..maxdim --------------------------------
+    // Host reduction of each dimension: the speculative phase, then the
+    // exact phase on a host thread that overlaps the next dimension's GPU
+    // stages and speculative phase.
+    struct HostDim {
+        ResidualProblem P;
+        std::unique_ptr<ResidualSpec> spec;
+        std::vector<uint8_t> drop;  // columns the previous dimension's host pivots clear
+        int64_t ndrop = 0;
+        ResidualResult RR;
+        std::thread th;
+        bool failed = false;
+        float ms_spec = 0.0f, ms_exact = 0.0f;
+        int64_t napp = 0;
+        const uint64_t *app_tau = nullptr, *app_sigma = nullptr;
+    };
+    std::vector<HostDim> hd((size_t)maxdim + 1);
+    struct JoinAll {
+        std::vector<HostDim> &h;
+        ~JoinAll()
+        {
+            for (HostDim &x : h)
+                if (x.th.joinable())
+                    x.th.join();
+        }
+    } join_all{hd};
+    const bool want_pairs_all = (a.flags & RPP_WANT_PAIRS) != 0;
+    auto finish_dim = [&](int q) -> int {
+        HostDim &H = hd[(size_t)q];
+        if (H.th.joinable())
+            H.th.join();
+        if (H.failed) {
+            err = "host allocation failed in the residual reduction";
+            return RPP_E_NOMEM;
+        }
+        DimOut &Dq = out.dims[q];
+        const ResidualResult &RR = H.RR;
+        Dq.st.ms_host = H.ms_spec + H.ms_exact;
+        for (size_t i = 0; i < RR.sigma.size(); ++i)
+            if (RR.death[i] > RR.birth[i]) {
+                Dq.birth.push_back(RR.birth[i]);
+                Dq.death.push_back(RR.death[i]);
+                Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+                                                      RR.sigma[i], q));
+                Dq.death_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+                                                      RR.tau[i], q + 1));
+            }
+        for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
+            Dq.birth.push_back(RR.ess_birth[i]);
+            Dq.death.push_back(INFINITY);
+            Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+                                                  RR.ess_sigma[i], q));
+            Dq.death_edge.push_back(UINT64_MAX);
+        }
+        // the dropped columns count as cleared, as if the previous
+        // dimension's host pivots had been in the device clearing set
+        Dq.st.n_cleared += H.ndrop;
+        Dq.st.n_kept -= H.ndrop;
+        Dq.st.n_nonapparent -= H.ndrop;
+        Dq.st.n_host_pairs = (int64_t)RR.sigma.size();
+        Dq.st.n_essential = (int64_t)RR.ess_sigma.size();
+        Dq.st.n_bars = (int64_t)Dq.birth.size();
+        Dq.st.n_column_adds = RR.additions;
+        if (want_pairs_all) {
+            Dq.pair_sigma.assign(H.app_sigma, H.app_sigma + H.napp);
+            Dq.pair_tau.assign(H.app_tau, H.app_tau + H.napp);
+            Dq.pair_sigma.insert(Dq.pair_sigma.end(), RR.sigma.begin(), RR.sigma.end());
+            Dq.pair_tau.insert(Dq.pair_tau.end(), RR.tau.begin(), RR.tau.end());
+        }
+        return RPP_OK;
+    };
+
     // clearing set of the current dimension: p = 1 uses the MST bitmap;
-    // later dimensions a bitmap (dense) or a sorted cidx array (sparse)
+    // later dimensions a bitmap (dense) or a sorted cidx array (sparse) of
+    // the previous dimension's apparent pivots
     const uint32_t *clear_bits = ws.mst.as<uint32_t>();
     int64_t nclear_sorted = 0;
     const uint64_t *clear_sorted = nullptr;
@@ -494,8 +585,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         t_sort.start();
         const int64_t nna = ncols - napp;
 
-        // next dimension's clearing bitmap (dense): apparent taus now, host
-        // taus after the reduction
+        // next dimension's clearing bitmap (dense): this dimension's apparent
+        // taus (its host taus are dropped on the host instead)
         if (p < maxdim && !sparse) {
             const uint64_t nnext = binom_sat(n, p + 2);
             ALLOC_TRY(ws.next, (size_t)(nnext / 32 + 2) * 4);
@@ -535,22 +626,53 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         else
             launch_lows(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, thr, ws.binom.as<uint64_t>(),
                         ws.lowc.as<uint64_t>(), ws.lowd.as<float>(), s);
-        // device -> host handoff
-        ALLOC_TRY(ws.h_na_key, (size_t)(nna + 1) * 8);
-        ALLOC_TRY(ws.h_na_cidx, (size_t)(nna + 1) * 8);
-        ALLOC_TRY(ws.h_low, (size_t)(nna + 1) * 8);
-        ALLOC_TRY(ws.h_lowd, (size_t)(nna + 1) * 4);
+        // device -> host handoff (the set of this dimension's parity)
+        const int hb = p & 1;
+        ALLOC_TRY(ws.h_na_key[hb], (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_na_cidx[hb], (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_low[hb], (size_t)(nna + 1) * 8);
+        ALLOC_TRY(ws.h_lowd[hb], (size_t)(nna + 1) * 4);
         if (nna) {
-            HIP_TRY(hipMemcpyAsync(ws.h_na_key.p, d_nk, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(ws.h_na_cidx.p, d_nv, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(ws.h_low.p, ws.lowc.p, (size_t)nna * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(ws.h_lowd.p, ws.lowd.p, (size_t)nna * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_na_key[hb].p, d_nk, (size_t)nna * 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_na_cidx[hb].p, d_nv, (size_t)nna * 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_low[hb].p, ws.lowc.p, (size_t)nna * 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_lowd[hb].p, ws.lowd.p, (size_t)nna * 4,
+                                   hipMemcpyDeviceToHost, s));
         }
-        ALLOC_TRY(ws.h_app_tau, (size_t)(napp + 1) * 8);
-        ALLOC_TRY(ws.h_app_sigma, (size_t)(napp + 1) * 8);
+        ALLOC_TRY(ws.h_app_tau[hb], (size_t)(napp + 1) * 8);
+        ALLOC_TRY(ws.h_app_sigma[hb], (size_t)(napp + 1) * 8);
         if ((sorted_store || want_pairs) && napp) {
-            HIP_TRY(hipMemcpyAsync(ws.h_app_tau.p, d_at, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(ws.h_app_sigma.p, d_as, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_app_tau[hb].p, d_at, (size_t)napp * 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ws.h_app_sigma[hb].p, d_as, (size_t)napp * 8,
+                                   hipMemcpyDeviceToHost, s));
+        }
+        // next dimension's clearing set on the device: this dimension's
+        // apparent pivots.  Its host pivots are not known yet; the columns
+        // they would clear are dropped from the next reduction instead.
+        if (p < maxdim) {
+            if (!sparse) {
+                std::swap(ws.clear, ws.next);
+                clear_bits = ws.clear.as<uint32_t>();
+            } else {
+                ALLOC_TRY(ws.clr, (size_t)(napp + 1) * 8);
+                ALLOC_TRY(ws.clr2, (size_t)(napp + 1) * 8);
+                ALLOC_TRY(ws.clrv, (size_t)(napp + 1) * 8);
+                ALLOC_TRY(ws.clrv2, (size_t)(napp + 1) * 8);
+                ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(napp) * 8);
+                if (napp)
+                    HIP_TRY(hipMemcpyAsync(ws.clr.p, d_at, (size_t)napp * 8,
+                                           hipMemcpyDeviceToDevice, s));
+                int wc = radix_sort_pairs(ws.clr.as<uint64_t>(), ws.clrv.as<uint64_t>(),
+                                          ws.clr2.as<uint64_t>(), ws.clrv2.as<uint64_t>(), napp,
+                                          bit_length(binom_sat(n, p + 2)),
+                                          ws.rscratch.as<uint64_t>(), s);
+                clear_sorted = wc ? ws.clr2.as<uint64_t>() : ws.clr.as<uint64_t>();
+                nclear_sorted = napp;
+            }
         }
         tg.stop();
         HIP_TRY(hipStreamSynchronize(s));
@@ -560,100 +682,85 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.ms_partition = t_part.ms();
         D.st.ms_sort = t_sort.ms();
         D.st.n_scanned = scanned;
-
-        // a7: host residual reduction
-        auto h0 = std::chrono::steady_clock::now();
-        ResidualProblem P;
-        P.n = n;
-        P.p = p;
-        P.thr = thr;
-        P.dsq = h_dsq.data();
-        P.binom = ws.binom_host.data();
-        P.bits = sparse ? h_bits.data() : nullptr;
-        P.words = sparse ? words : 0;
-        P.ncols = nna;
-        P.col_key = ws.h_na_key.as<uint64_t>();
-        P.col_cidx = ws.h_na_cidx.as<uint64_t>();
-        P.col_low = ws.h_low.as<uint64_t>();
-        P.col_low_diam = ws.h_lowd.as<float>();
-        P.napp = napp;
-        P.app_tau = sorted_store ? ws.h_app_tau.as<uint64_t>() : nullptr;
-        P.app_sigma = sorted_store ? ws.h_app_sigma.as<uint64_t>() : nullptr;
-        ResidualResult RR;
-        residual_reduce(P, RR);
-        auto h1 = std::chrono::steady_clock::now();
-        D.st.ms_host = std::chrono::duration<float, std::milli>(h1 - h0).count();
-
-        for (size_t i = 0; i < RR.sigma.size(); ++i)
-            if (RR.death[i] > RR.birth[i]) {
-                D.birth.push_back(RR.birth[i]);
-                D.death.push_back(RR.death[i]);
-                D.birth_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
-                                                     RR.sigma[i], p));
-                D.death_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
-                                                     RR.tau[i], p + 1));
-            }
-        for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
-            D.birth.push_back(RR.ess_birth[i]);
-            D.death.push_back(INFINITY);
-            D.birth_edge.push_back(critical_edge(h_dsq.data(), n, ws.binom_host.data(),
-                                                 RR.ess_sigma[i], p));
-            D.death_edge.push_back(UINT64_MAX);
-        }
         D.st.n_candidates = ncand;
         D.st.n_thresholded = (int64_t)nthr;
         D.st.n_cleared = (int64_t)nclr;
         D.st.n_simplices = ncand - (int64_t)nthr;
         D.st.n_kept = ncols;
+        D.st.apparent_group = sparse ? 64 : group;  // sparse path: one wave per column
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
-        D.st.n_host_pairs = (int64_t)RR.sigma.size();
-        D.st.n_essential = (int64_t)RR.ess_sigma.size();
-        D.st.n_bars = (int64_t)D.birth.size();
-        D.st.n_column_adds = RR.additions;
-        if (want_pairs) {
-            const uint64_t *at = ws.h_app_tau.as<uint64_t>();
-            const uint64_t *as = ws.h_app_sigma.as<uint64_t>();
-            D.pair_sigma.assign(as, as + napp);
-            D.pair_tau.assign(at, at + napp);
-            D.pair_sigma.insert(D.pair_sigma.end(), RR.sigma.begin(), RR.sigma.end());
-            D.pair_tau.insert(D.pair_tau.end(), RR.tau.begin(), RR.tau.end());
-        }
 
-        if (p < maxdim) {
-            const int64_t nh = (int64_t)RR.tau.size();
-            if (nh) {
-                ALLOC_TRY(ws.hostpiv, (size_t)nh * 8);
-                HIP_TRY(hipMemcpyAsync(ws.hostpiv.p, RR.tau.data(), (size_t)nh * 8,
-                                       hipMemcpyHostToDevice, s));
+        // a7: host residual reduction.  The speculative phase runs now; the
+        // exact phase needs the previous dimension's host pivots (its
+        // clearing set) and runs on a host thread while the next dimension's
+        // GPU stages proceed.
+        HostDim &H = hd[p];
+        H.P.n = n;
+        H.P.p = p;
+        H.P.thr = thr;
+        H.P.dsq = h_dsq;
+        H.P.binom = ws.binom_host.data();
+        H.P.bits = sparse ? h_bits : nullptr;
+        H.P.words = sparse ? words : 0;
+        H.P.ncols = nna;
+        H.P.col_key = ws.h_na_key[hb].as<uint64_t>();
+        H.P.col_cidx = ws.h_na_cidx[hb].as<uint64_t>();
+        H.P.col_low = ws.h_low[hb].as<uint64_t>();
+        H.P.col_low_diam = ws.h_lowd[hb].as<float>();
+        H.P.napp = napp;
+        H.P.app_tau = sorted_store ? ws.h_app_tau[hb].as<uint64_t>() : nullptr;
+        H.P.app_sigma = sorted_store ? ws.h_app_sigma[hb].as<uint64_t>() : nullptr;
+        H.P.spec_budget = SPEC_BUDGET;
+        H.napp = napp;
+        H.app_tau = ws.h_app_tau[hb].as<uint64_t>();
+        H.app_sigma = ws.h_app_sigma[hb].as<uint64_t>();
+        {
+            auto a0 = std::chrono::steady_clock::now();
+            try {
+                H.spec = residual_speculate(H.P);
+            } catch (const std::bad_alloc &) {
+                err = "host allocation failed in the residual reduction";
+                return RPP_E_NOMEM;
             }
-            if (!sparse) {
-                if (nh)
-                    launch_mark_bits(ws.hostpiv.as<uint64_t>(), nh, ws.next.as<uint32_t>(), s);
-                std::swap(ws.clear, ws.next);
-                clear_bits = ws.clear.as<uint32_t>();
-            } else {
-                // sorted array of every dimension-p pivot row (apparent + host)
-                const int64_t m = napp + nh;
-                ALLOC_TRY(ws.clr, (size_t)(m + 1) * 8);
-                ALLOC_TRY(ws.clr2, (size_t)(m + 1) * 8);
-                ALLOC_TRY(ws.clrv, (size_t)(m + 1) * 8);
-                ALLOC_TRY(ws.clrv2, (size_t)(m + 1) * 8);
-                ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(m) * 8);
-                if (napp)
-                    HIP_TRY(hipMemcpyAsync(ws.clr.p, d_at, (size_t)napp * 8,
-                                           hipMemcpyDeviceToDevice, s));
-                if (nh)
-                    HIP_TRY(hipMemcpyAsync(ws.clr.as<uint64_t>() + napp, ws.hostpiv.p,
-                                           (size_t)nh * 8, hipMemcpyDeviceToDevice, s));
-                int wc = radix_sort_pairs(ws.clr.as<uint64_t>(), ws.clrv.as<uint64_t>(),
-                                          ws.clr2.as<uint64_t>(), ws.clrv2.as<uint64_t>(), m,
-                                          bit_length(binom_sat(n, p + 2)),
-                                          ws.rscratch.as<uint64_t>(), s);
-                clear_sorted = wc ? ws.clr2.as<uint64_t>() : ws.clr.as<uint64_t>();
-                nclear_sorted = m;
+            H.ms_spec = std::chrono::duration<float, std::milli>(
+                            std::chrono::steady_clock::now() - a0).count();
+        }
+        // the previous dimension's exact phase must be done: its pivots are
+        // this dimension's dropped columns
+        if (p > 1) {
+            int rc2 = finish_dim(p - 1);
+            if (rc2)
+                return rc2;
+            const std::vector<uint64_t> &prev = hd[p - 1].RR.tau;
+            H.drop.assign((size_t)nna, 0);
+            if (!prev.empty() && nna) {
+                std::vector<uint64_t> sp(prev);
+                std::sort(sp.begin(), sp.end());
+                const uint64_t *cc = H.P.col_cidx;
+                for (int64_t j = 0; j < nna; ++j)
+                    if (std::binary_search(sp.begin(), sp.end(), cc[j])) {
+                        H.drop[(size_t)j] = 1;
+                        ++H.ndrop;
+                    }
             }
         }
+        H.th = std::thread([&H] {
+            auto b0 = std::chrono::steady_clock::now();
+            try {
+                H.spec->finish(H.drop.empty() ? nullptr : H.drop.data(), H.RR);
+            } catch (const std::bad_alloc &) {
+                H.failed = true;
+            }
+            H.spec.reset();
+            H.ms_exact = std::chrono::duration<float, std::milli>(
+                             std::chrono::steady_clock::now() - b0).count();
+        });
+    }
+    if (maxdim >= 1) {
+        int rc2 = finish_dim(maxdim);
+        if (rc2)
+            return rc2;
     }
     HIP_TRY(hipStreamSynchronize(s));
     return RPP_OK;
@@ -686,11 +793,14 @@ int run_backward(const float *pts, int n, int d, const std::vector<uint64_t> &ed
 }
 
 int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hipStream_t s,
-                      std::vector<uint64_t> &sigma, std::vector<uint64_t> &tau, int64_t &ncols,
-                      std::string &err)
+                      bool copy_pairs, bool count_scans, std::vector<uint64_t> &sigma,
+                      std::vector<uint64_t> &tau, int64_t &ncols, int64_t &napp,
+                      rpp_dim_stats *st, std::string &err)
 {
     Workspace &ws = workspace_for_current_device();
     std::lock_guard<std::mutex> lk(ws.mu);
+    GpuTimer t_all(s), t_enum(s), t_app(s), t_part(s);
+    t_all.start();
     ALLOC_TRY(ws.dsq, (size_t)n * n * 4);
     ALLOC_TRY(ws.rowmax, (size_t)n * 4);
     ALLOC_TRY(ws.scal, 256);
@@ -717,20 +827,62 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     const uint64_t ncand = binom_sat(n, p + 1);
     EnumArgs ea{dcond_dev, n, p, threshold, ws.binom.as<uint64_t>(), nullptr, ncand};
     uint64_t nthr = 0, nclr = 0;
-    int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err);
+    int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
     if (rc)
         return rc;
-    int64_t napp = 0;
-    rc = apparent_and_partition(ws, ncols, n, p, default_group(p), s, &napp, err);
+    // Lanes per column from the mean scan length of a sample: inputs whose
+    // oldest equal-diameter cofacet is found within a few candidates (point
+    // clouds) use narrow groups, long scans (e.g. random orders) wide ones.
+    int group = default_group(p);
+    const int64_t probe = 65536;
+    if (ncols >= 16 * probe) {
+        ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
+        ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
+        unsigned long long *sc = ws.scancnt.as<unsigned long long>();
+        HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+        launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), probe, ws.dsq.as<float>(),
+                        n, p, ws.binom.as<uint64_t>(), 8, ws.tau.as<uint64_t>(), sc, s);
+        std::vector<unsigned long long> c(SCAN_COUNTERS);
+        HIP_TRY(hipMemcpyAsync(c.data(), sc, (size_t)SCAN_COUNTERS * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double tot = 0;
+        for (unsigned long long x : c)
+            tot += (double)x;
+        const double sbar = tot / (double)probe;
+        group = sbar > 96 ? 64 : sbar > 40 ? 32 : sbar > 16 ? 16 : 8;
+    }
+    int64_t scanned = 0;
+    rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
+                                count_scans ? &scanned : nullptr);
     if (rc)
         return rc;
-    sigma.resize(napp);
-    tau.resize(napp);
-    if (napp) {
-        HIP_TRY(hipMemcpyAsync(sigma.data(), ws.aval.p, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(tau.data(), ws.akey.p, (size_t)napp * 8, hipMemcpyDeviceToHost, s));
+    t_all.stop();
+    if (copy_pairs) {
+        sigma.resize(napp);
+        tau.resize(napp);
+        if (napp) {
+            HIP_TRY(hipMemcpyAsync(sigma.data(), ws.aval.p, (size_t)napp * 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(tau.data(), ws.akey.p, (size_t)napp * 8,
+                                   hipMemcpyDeviceToHost, s));
+        }
     }
     HIP_TRY(hipStreamSynchronize(s));
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->n_candidates = (int64_t)ncand;
+        st->n_simplices = (int64_t)ncand - (int64_t)nthr;
+        st->n_thresholded = (int64_t)nthr;
+        st->n_kept = ncols;
+        st->n_apparent = napp;
+        st->n_nonapparent = ncols - napp;
+        st->n_scanned = count_scans ? scanned : 0;
+        st->ms_enumerate = t_enum.ms();
+        st->ms_apparent = t_app.ms();
+        st->ms_partition = t_part.ms();
+        st->ms_gpu = t_all.ms();
+        st->apparent_group = group;
+    }
     return RPP_OK;
 }
 

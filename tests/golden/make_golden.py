@@ -12,7 +12,12 @@ line per bar: ``dim birth_hex death_hex birth death`` where *_hex are the
 IEEE-754 binary32 bit patterns (exact) and the decimal values are for
 reading only.
 
-Usage: python tests/golden/make_golden.py torus400 [sphere4096 ...]
+A second kind of fixture, ``perm<n0>.apparent.txt``, holds the oracle's
+dimension-1 apparent pairs of a random edge order on n0 points (all C(n0,2)
+edges, no threshold): the input SHA-256, the number of pairs and the SHA-256
+of the pair arrays (sigma then tau, little-endian u64, increasing sigma).
+
+Usage: python tests/golden/make_golden.py torus400 [sphere4096 perm1500 ...]
 """
 from __future__ import annotations
 
@@ -57,6 +62,43 @@ def write(name: str) -> str:
     return path
 
 
+PERM_SEED = 1006
+
+
+def pair_digest(sigma, tau) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(sigma, dtype="<u8").tobytes())
+    h.update(np.ascontiguousarray(tau, dtype="<u8").tobytes())
+    return h.hexdigest()
+
+
+def write_perm(n0: int) -> str:
+    d = workloads.random_permutation_metric(n0, PERM_SEED)
+    t0 = time.time()
+    sigma, tau = oracle.apparent_pairs(d, n0, 1)
+    secs = time.time() - t0
+    path = os.path.join(HERE, "perm%d.apparent.txt" % n0)
+    with open(path, "w") as f:
+        f.write("# dimension-1 apparent pairs of a random edge order, written by "
+                "tests/golden/make_golden.py\n")
+        f.write("# source: CPU oracle apparent-pair test (%.1f s)\n" % secs)
+        f.write("input_sha256 %s\n" % hashlib.sha256(d.tobytes()).hexdigest())
+        f.write("n0 %d\nseed %d\nedges %d\n" % (n0, PERM_SEED, n0 * (n0 - 1) // 2))
+        f.write("pairs %d\n" % len(sigma))
+        f.write("pairs_sha256 %s\n" % pair_digest(sigma, tau))
+    return path
+
+
+def read_perm(path: str) -> dict:
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        out[k] = v if k.endswith("sha256") else int(v)
+    return out
+
+
 def read(path: str):
     """(header dict, bars list per dimension) from a golden file."""
     head = {"dims": {}}
@@ -86,4 +128,7 @@ def read(path: str):
 
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        print("wrote", write(name), flush=True)
+        if name.startswith("perm"):
+            print("wrote", write_perm(int(name[4:])), flush=True)
+        else:
+            print("wrote", write(name), flush=True)

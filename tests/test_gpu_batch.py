@@ -111,3 +111,18 @@ def test_batch_rejects_bad_entries(rpp):
     with pytest.raises(rpp.RppError) as e:
         rpp.barcodes_batch([_dev(d), _dev(bad)], 1)
     assert e.value.code == -2
+
+
+def test_many_shapes_evict_and_recreate_workspaces(rpp):
+    """More distinct batch shapes than the workspace cache holds, then the
+    first shape again (its workspace was evicted and is rebuilt): every
+    result still equals the single-cloud path."""
+    shapes = [20, 21, 22, 23, 24, 25, 26, 20]
+    for k, n in enumerate(shapes):
+        clouds = [w.condensed_from_points(w.noisy_torus_points(n, 900 + 10 * k + i))
+                  for i in range(2)]
+        dev = [_dev(d) for d in clouds]
+        out = rpp.barcodes_batch(dev, 2)
+        for i in range(2):
+            _same(out[i], rpp.barcodes_device(dev[i], 2, flags=rpp.RPP_FORCE_DENSE),
+                  "shape %d cloud %d" % (n, i))

@@ -7,6 +7,7 @@ indices.  The apparent-pair kernel is also compared with the literal
 definition, and with the exact counts of the paper's Theorem 1
 constructions.
 """
+import hashlib
 import math
 import os
 
@@ -270,13 +271,17 @@ def test_sparse_and_dense_paths_agree_on_maxdim3(rpp):
     assert_bars_equal(a.bars, oracle.barcodes(d, 60, 3, thr, clearing=True), "vs oracle")
 
 
-def _golden(name):
+def _golden_module():
     import importlib.util
     spec = importlib.util.spec_from_file_location("make_golden",
                                                   os.path.join(GOLDEN, "make_golden.py"))
     mg = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mg)
-    return mg.read(os.path.join(GOLDEN, name + ".bars.txt"))
+    return mg
+
+
+def _golden(name):
+    return _golden_module().read(os.path.join(GOLDEN, name + ".bars.txt"))
 
 
 def test_sphere4096_matches_stored_oracle(rpp):
@@ -292,3 +297,49 @@ def test_sphere4096_matches_stored_oracle(rpp):
     for p in range(3):
         assert got.stats[p]["n_simplices"] == head["dims"][p]["simplices"]
         assert got.stats[p]["n_apparent"] + got.stats[p]["n_host_pairs"] == head["dims"][p]["pairs"]
+
+
+# ---------------------------------------------------------------------------
+# Dimension-1 apparent fraction of random orders (the paper's random
+# distance-matrix experiments): every C(n0,2) edge, no threshold.
+# ---------------------------------------------------------------------------
+def test_apparent_count_matches_pairs_and_oracle(rpp):
+    d = w.random_permutation_metric(60, 11)
+    s, t, ncols = rpp.apparent_pairs(d, 1)
+    k, ncols2, st = rpp.apparent_count(d, 1)
+    es, et = oracle.apparent_pairs(d, 60, 1)
+    assert k == len(s) == len(es) and ncols == ncols2 == 60 * 59 // 2
+    assert np.array_equal(s, es) and np.array_equal(t, et)
+    assert st["n_kept"] == ncols and st["n_apparent"] == k
+    assert st["apparent_group"] >= 1
+
+
+def test_random_order_1500_matches_oracle_with_adaptive_lanes(rpp):
+    """1.1e6 edges, large enough for the lanes-per-column probe: the pairs
+    equal the oracle's (stored by tests/golden/make_golden.py as a count and
+    a SHA-256 of the pair arrays), whatever group size the probe picked."""
+    mg = _golden_module()
+    g = mg.read_perm(os.path.join(GOLDEN, "perm1500.apparent.txt"))
+    n0 = g["n0"]
+    d = w.random_permutation_metric(n0, g["seed"])
+    assert hashlib.sha256(d.tobytes()).hexdigest() == g["input_sha256"]
+    s, t, ncols = rpp.apparent_pairs(d, 1)
+    assert ncols == g["edges"]
+    assert len(s) == g["pairs"]
+    assert mg.pair_digest(s, t) == g["pairs_sha256"]
+    _, _, st = rpp.apparent_count(d, 1)
+    assert st["apparent_group"] in (8, 16, 32, 64)
+
+
+def test_random_order_apparent_fraction_10000(rpp):
+    """The paper reports an average dimension-1 apparent fraction of
+    0.991127743 at 10000 points (random orders of the C(n0,2) edge lengths,
+    averaged over samples, with very low variance); one sample must land
+    within 1e-3 of it and below the upper bound (n0-2)/n0 of Theorem 1."""
+    n0 = 10000
+    d = w.random_permutation_metric(n0, 1006)
+    k, ncols, _ = rpp.apparent_count(d, 1)
+    frac = k / ncols
+    assert ncols == n0 * (n0 - 1) // 2
+    assert frac <= (n0 - 2) / n0
+    assert abs(frac - 0.991127743) < 1e-3, frac
