@@ -16,7 +16,8 @@ Other workloads (their own JSON lines): --workload sphere4096 (4096 points on
 the sphere, threshold 0.4), --workload circles64x512 (batched forward +
 backward), --workload serving512 (Poisson request stream, served vs batched
 vs plain), --workload perm20000 (dimension-1 apparent test over all edges of
-a random edge order on 20000 points).
+a random edge order on 20000 points), --workload greedy200 (the same test on
+the greedy deterministic distance assignment).
 """
 from __future__ import annotations
 
@@ -43,6 +44,31 @@ def algorithmic_bytes_apparent(st: dict, p: int) -> float:
     """Apparent test: 12 bytes of column key in, 8 bytes of result out, and
     4*(p+1) distance bytes per cofacet candidate examined."""
     return st["n_kept"] * 20.0 + 4.0 * (p + 1) * st["n_scanned"]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary committed under profiles/, scaled by a copy kernel
+    of known size; None when there is none or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2003_07989_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernels_hip_sha256") != sha or kv.get("kernel", "").replace(" ", "") != kernel.replace(" ", ""):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(name: str) -> dict:
@@ -439,18 +465,23 @@ def bench_copy(args):
 PAPER_APPARENT_FRACTION = {10000: 0.991127743, 20000: 0.993733522}
 
 
-def bench_perm(args, n0):
+def bench_perm(args, n0, kind="perm"):
     """Dimension-1 apparent-pair test over all C(n0,2) edges of a matrix
-    whose lower triangle is a random order of distinct FP32 values: columns
-    per second through staging + enumeration + apparent test + partition,
-    the apparent fraction, and the roofline of the apparent kernel."""
+    whose lower triangle is a random order of distinct FP32 values (kind
+    "perm") or the greedy deterministic assignment (kind "greedy", about
+    half the edges apparent): columns per second through staging +
+    enumeration + apparent test + partition, the apparent fraction, and the
+    roofline of the apparent kernel."""
     import numpy as np
     import torch
     import paper_2003_07989_amd as rpp
     import workloads
     torch.cuda.set_device(0)
     rpp.load()
-    d_host = workloads.random_permutation_metric(n0, 1006)
+    if kind == "greedy":
+        d_host = workloads.greedy_assignment_metric(n0)
+    else:
+        d_host = workloads.random_permutation_metric(n0, 1006)
     dist = torch.from_numpy(d_host).cuda()
     del d_host
     stream = torch.cuda.current_stream()
@@ -477,19 +508,23 @@ def bench_perm(args, n0):
         "value": round(ncols / el, 1), "unit": "columns/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": round(el * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "perm%d" % n0, "n0": n0, "columns": ncols, "seed": 1006},
+        "config": {"workload": "%s%d" % (kind, n0), "n0": n0, "columns": ncols,
+                   "seed": 1006 if kind == "perm" else None},
         "apparent_fraction": k / ncols,
-        "paper_average_fraction": PAPER_APPARENT_FRACTION.get(n0),
+        "paper_average_fraction": PAPER_APPARENT_FRACTION.get(n0) if kind == "perm" else None,
+        "lower_bound_fraction": 1.0 / 3.0 if kind == "greedy" else None,
         "upper_bound_fraction": (n0 - 2) / n0,
         "mean_scan": tally["n_scanned"] / ncols,
         "apparent_group": st["apparent_group"],
         "gpu_stage_ms": {key: round(v, 4) for key, v in acc.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("%s%d" % (kind, n0),
+                                                 "k_apparent<1,%d>" % st["apparent_group"]),
                      "kernel": "k_apparent<1,%d>" % st["apparent_group"], "dim": 1,
                      "ms": round(kms, 4), "bytes": kbytes},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and kind == "perm":
         out["cpu_baseline"] = cpu_baseline_perm()
     print(json.dumps(out))
 
@@ -531,6 +566,8 @@ def main():
 
     if args.workload.startswith("perm"):
         return bench_perm(args, int(args.workload[4:]))
+    if args.workload.startswith("greedy"):
+        return bench_perm(args, int(args.workload[6:]), kind="greedy")
     if args.workload == "copy1g":
         return bench_copy(args)
     if args.workload == "circles64x512":
@@ -596,10 +633,12 @@ def main():
     kname = max(cand, key=lambda k: cand[k][0])
     kms, kbytes = cand[kname]
     achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    kfull = ("k_apparent<%d,%d>" % (top, st.get("apparent_group", 8)) if kname == "apparent"
+             else "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top))
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": {"apparent": "k_apparent", "enumerate": "k_enum_count+k_enum_scatter"}[kname],
-            "dim": top, "ms": round(kms, 4), "bytes": kbytes}
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload, kfull),
+            "kernel": kfull, "dim": top, "ms": round(kms, 4), "bytes": kbytes}
 
     out = {
         "metric": "simplices/sec through apparent-pair+filtration",

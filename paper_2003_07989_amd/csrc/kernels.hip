@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
                                                   int n, const uint64_t *__restrict__ binom,
                                                   uint64_t *__restrict__ tau_out,
                                                   unsigned long long *__restrict__ scan_count,
-                                                  Batch bt)
+                                                  Batch bt, int rounds)
 {
     constexpr int CPR = WAVE / G;  // columns per round
     const int lane = threadIdx.x & (WAVE - 1);
@@ -534,7 +534,8 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
     const int grp = lane / G;
     const int gbase = lane - g;
     const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
-    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * WAVE;
+    const int own = CPR * rounds;  // columns owned by a wave (rounds <= G)
+    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * own;
     {
         const int64_t cl = blockIdx.y;
         ncols = batch_count(bt, cl, ncols);
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
         return;  // whole waves leave together
     const Binom B{binom, n + 1};
     const int64_t mycol = base + lane;
-    const bool myvalid = mycol < ncols;
+    const bool myvalid = lane < own && mycol < ncols;
     float myd = 0.0f;
     int myv[P + 1];
 #pragma unroll
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
         decode<P>(B, col_cidx[mycol], n, myv);
     }
     uint64_t mytau = NONE;
-    for (int r = 0; r < G; ++r) {
+    for (int r = 0; r < rounds; ++r) {
         const int src = r * CPR + grp;
         const float d = __shfl(myd, src, WAVE);
         int v[P + 1];
@@ -659,15 +660,26 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
                               uint64_t *tau, unsigned long long *sc, hipStream_t s,
                               Batch bt = Batch(), int nbatch = 1)
 {
-    const int64_t threads = (ncols + WAVE - 1) / WAVE * WAVE;  // one wave per 64 columns
+    if (group != 1 && group != 4 && group != 16 && group != 32 && group != 64)
+        group = 8;  // the instantiated group sizes; 8 is the default
+    // Rounds per wave (each round covers 64/group columns): as many as the
+    // group size allows while the grid keeps at least ~4 waves per SIMD
+    // (1024 SIMDs), so small column counts still fill the chip.
+    const int cpr = WAVE / group;
+    const int64_t total = ncols * (nbatch > 0 ? nbatch : 1);
+    int rounds = 1;
+    while (rounds < group && total / ((int64_t)cpr * rounds * 2) >= 4096)
+        rounds *= 2;
+    const int64_t waves = (ncols + (int64_t)cpr * rounds - 1) / ((int64_t)cpr * rounds);
+    const int64_t threads = waves * WAVE;
     dim3 g((unsigned)((threads + 255) / 256), nbatch), b(256);
     switch (group) {
-    case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
-    case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
-    case 16: hipLaunchKernelGGL((k_apparent<P, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
-    case 32: hipLaunchKernelGGL((k_apparent<P, 32>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
-    case 64: hipLaunchKernelGGL((k_apparent<P, 64>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
-    default: hipLaunchKernelGGL((k_apparent<P, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt); break;
+    case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
+    case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
+    case 16: hipLaunchKernelGGL((k_apparent<P, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
+    case 32: hipLaunchKernelGGL((k_apparent<P, 32>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
+    case 64: hipLaunchKernelGGL((k_apparent<P, 64>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
+    default: hipLaunchKernelGGL((k_apparent<P, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
     }
 }
 
@@ -1654,11 +1666,61 @@ int radix_sort_pairs_b(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint6
     return where;
 }
 
+// Small sorts in one launch: one workgroup sorts fewer than 8192 pairs by
+// the low `bits` (<= 51) bits of the key, stably -- a bitonic network in LDS
+// over (key bits << 13 | index), whose distinct values make it stable, then
+// whole keys and values gathered by index.  A radix sort of a few thousand
+// keys would spend its time in ~20 launches.
+constexpr int SS_N = 8192;
+constexpr int SS_T = 1024;
+
+__global__ __launch_bounds__(SS_T) void k_small_sort(const uint64_t *__restrict__ kin,
+                                                     const uint64_t *__restrict__ vin,
+                                                     uint64_t *__restrict__ kout,
+                                                     uint64_t *__restrict__ vout, int count,
+                                                     int bits)
+{
+    __shared__ uint64_t a[SS_N];
+    int m = 2;
+    while (m < count)
+        m <<= 1;
+    const uint64_t mask = (1ull << bits) - 1;
+    // padding sorts last: a real composite is below ~0 (index <= 8190)
+    for (int i = threadIdx.x; i < m; i += SS_T)
+        a[i] = i < count ? (((kin[i] & mask) << 13) | (uint64_t)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < m; i += SS_T) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < count; i += SS_T) {
+        const int src = (int)(a[i] & 0x1fffull);
+        kout[i] = kin[src];
+        vout[i] = vin[src];
+    }
+}
+
 int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_t *vals_alt,
                      int64_t count, int bits, uint64_t *scratch, hipStream_t s)
 {
     if (count <= 1 || bits <= 0)
         return 0;
+    if (count < SS_N && bits <= 51) {
+        hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt,
+                           (int)count, bits);
+        return 1;
+    }
     return radix_sort_pairs_b(keys, vals, keys_alt, vals_alt, count, bits, scratch, s, Batch(), 1);
 }
 

@@ -17,6 +17,8 @@
 #include "residual.h"
 
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -292,8 +294,40 @@ constexpr int64_t SPEC_BUDGET = 16;
 
 static int default_group(int p)
 {
-    (void)p;
-    return 8;
+    return p == 1 ? 16 : 4;
+}
+
+// Lanes per column for the dense apparent kernel, from the mean scan length
+// s of the oldest-cofacet search: a step tests `group` candidates, so the
+// group should cover about one mean scan.  Large inputs measure s on a
+// probe of 16384 columns; small ones use the per-dimension default (edges
+// of point clouds scan ~10-15 candidates, higher simplices ~4).
+static int group_for_scan(double sbar)
+{
+    return sbar <= 6 ? 4 : sbar <= 12 ? 8 : sbar <= 40 ? 16 : sbar <= 96 ? 32 : 64;
+}
+
+static int choose_group(Workspace &ws, int64_t ncols, int n, int p, hipStream_t s, int *group,
+                        std::string &err)
+{
+    const int64_t probe = 16384;
+    *group = default_group(p);
+    if (ncols < 4 * probe)
+        return RPP_OK;
+    ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
+    ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
+    unsigned long long *sc = ws.scancnt.as<unsigned long long>();
+    HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+    launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), probe, ws.dsq.as<float>(), n, p,
+                    ws.binom.as<uint64_t>(), 8, ws.tau.as<uint64_t>(), sc, s);
+    std::vector<unsigned long long> c(SCAN_COUNTERS);
+    HIP_TRY(hipMemcpyAsync(c.data(), sc, (size_t)SCAN_COUNTERS * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double tot = 0;
+    for (unsigned long long x : c)
+        tot += (double)x;
+    *group = group_for_scan(tot / (double)probe);
+    return RPP_OK;
 }
 
 int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
@@ -484,10 +518,18 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         std::thread th;
         bool failed = false;
         float ms_spec = 0.0f, ms_exact = 0.0f;
+        double t_exact_start = 0.0, t_exact_end = 0.0;  // ms since the call began
         int64_t napp = 0;
         const uint64_t *app_tau = nullptr, *app_sigma = nullptr;
     };
     std::vector<HostDim> hd((size_t)maxdim + 1);
+    // RPP_TRACE=1: per-dimension timings of the schedule on stderr
+    const char *trace_env = getenv("RPP_TRACE");
+    const bool trace = trace_env && atoi(trace_env) != 0;
+    const auto t_call = std::chrono::steady_clock::now();
+    auto since = [&](std::chrono::steady_clock::time_point t) {
+        return std::chrono::duration<double, std::milli>(t - t_call).count();
+    };
     struct JoinAll {
         std::vector<HostDim> &h;
         ~JoinAll()
@@ -509,6 +551,13 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         DimOut &Dq = out.dims[q];
         const ResidualResult &RR = H.RR;
         Dq.st.ms_host = H.ms_spec + H.ms_exact;
+        if (trace)
+            fprintf(stderr,
+                    "rpp trace: dim %d gpu %.3f ms | speculative %.3f ms | exact %.3f ms "
+                    "(from %.3f to %.3f ms) | joined at %.3f ms | %lld columns, %lld dropped\n",
+                    q, Dq.st.ms_gpu, H.ms_spec, H.ms_exact, H.t_exact_start, H.t_exact_end,
+                    since(std::chrono::steady_clock::now()), (long long)H.P.ncols,
+                    (long long)H.ndrop);
         for (size_t i = 0; i < RR.sigma.size(); ++i)
             if (RR.death[i] > RR.birth[i]) {
                 Dq.birth.push_back(RR.birth[i]);
@@ -577,7 +626,12 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         if (rc)
             return rc;
         int64_t napp = 0, scanned = 0;
-        const int group = a.apparent_group > 0 ? a.apparent_group : default_group(p);
+        int group = a.apparent_group;
+        if (group <= 0 && !sparse) {
+            rc = choose_group(ws, ncols, n, p, s, &group, err);
+            if (rc)
+                return rc;
+        }
         rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
                                     a.count_scans ? &scanned : nullptr, sparse ? words : 0);
         if (rc)
@@ -723,8 +777,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                 err = "host allocation failed in the residual reduction";
                 return RPP_E_NOMEM;
             }
-            H.ms_spec = std::chrono::duration<float, std::milli>(
-                            std::chrono::steady_clock::now() - a0).count();
+            const auto a1 = std::chrono::steady_clock::now();
+            H.ms_spec = std::chrono::duration<float, std::milli>(a1 - a0).count();
+            if (trace)
+                fprintf(stderr, "rpp trace: dim %d hand-off at %.3f ms, speculative done at %.3f ms\n",
+                        p, since(a0), since(a1));
         }
         // the previous dimension's exact phase must be done: its pivots are
         // this dimension's dropped columns
@@ -745,16 +802,18 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                     }
             }
         }
-        H.th = std::thread([&H] {
+        H.th = std::thread([&H, &since] {
             auto b0 = std::chrono::steady_clock::now();
+            H.t_exact_start = since(b0);
             try {
                 H.spec->finish(H.drop.empty() ? nullptr : H.drop.data(), H.RR);
             } catch (const std::bad_alloc &) {
                 H.failed = true;
             }
             H.spec.reset();
-            H.ms_exact = std::chrono::duration<float, std::milli>(
-                             std::chrono::steady_clock::now() - b0).count();
+            const auto b1 = std::chrono::steady_clock::now();
+            H.ms_exact = std::chrono::duration<float, std::milli>(b1 - b0).count();
+            H.t_exact_end = since(b1);
         });
     }
     if (maxdim >= 1) {
@@ -762,6 +821,9 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         if (rc2)
             return rc2;
     }
+    if (trace)
+        fprintf(stderr, "rpp trace: n %d maxdim %d done at %.3f ms\n", n, maxdim,
+                since(std::chrono::steady_clock::now()));
     HIP_TRY(hipStreamSynchronize(s));
     return RPP_OK;
 }
@@ -830,27 +892,12 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
     if (rc)
         return rc;
-    // Lanes per column from the mean scan length of a sample: inputs whose
-    // oldest equal-diameter cofacet is found within a few candidates (point
-    // clouds) use narrow groups, long scans (e.g. random orders) wide ones.
-    int group = default_group(p);
-    const int64_t probe = 65536;
-    if (ncols >= 16 * probe) {
-        ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
-        ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
-        unsigned long long *sc = ws.scancnt.as<unsigned long long>();
-        HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
-        launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), probe, ws.dsq.as<float>(),
-                        n, p, ws.binom.as<uint64_t>(), 8, ws.tau.as<uint64_t>(), sc, s);
-        std::vector<unsigned long long> c(SCAN_COUNTERS);
-        HIP_TRY(hipMemcpyAsync(c.data(), sc, (size_t)SCAN_COUNTERS * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        double tot = 0;
-        for (unsigned long long x : c)
-            tot += (double)x;
-        const double sbar = tot / (double)probe;
-        group = sbar > 96 ? 64 : sbar > 40 ? 32 : sbar > 16 ? 16 : 8;
-    }
+    // lanes per column from the mean scan length (random edge orders scan
+    // hundreds of candidates per column, point clouds a few)
+    int group = 8;
+    rc = choose_group(ws, ncols, n, p, s, &group, err);
+    if (rc)
+        return rc;
     int64_t scanned = 0;
     rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
                                 count_scans ? &scanned : nullptr);

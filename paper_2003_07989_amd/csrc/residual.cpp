@@ -11,8 +11,11 @@
 // entries cancel in pairs when the low is taken.
 #include "residual.h"
 
+#include <immintrin.h>
+
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 #include <condition_variable>
 #include <functional>
 #include <memory>
@@ -93,8 +96,24 @@ template <class K> void select_smallest(K *a, size_t m, size_t c)
 // and sorted; when they run out the next, twice as large, chunk is
 // selected.  A column's low usually lies a few dozen entries into each
 // stream, so most keys are never ordered, and pops read memory in order.
+// Allocator whose construct() default-initialises: resizing a stream's
+// storage before the coboundary is written into it does not zero it.
+template <class T> struct NoInit : std::allocator<T> {
+    template <class U> struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <class U> NoInit(const NoInit<U> &) noexcept {}
+    template <class U> void construct(U *p) noexcept { ::new ((void *)p) U; }
+    template <class U, class... A> void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class K> using KeyVec = std::vector<K, NoInit<K>>;
+
 template <class K> struct Stream {
-    std::vector<K> e;
+    KeyVec<K> e;
     uint32_t pos = 0, sorted = 0, chunk = 32;
     bool empty() const { return pos >= e.size(); }
     K front() const { return e[pos]; }
@@ -130,11 +149,11 @@ template <class K> struct Stream {
 template <class K> class Column {
 public:
     // Storage for the next coboundary: fill it, then commit().
-    std::vector<K> &next_stream()
+    KeyVec<K> &next_stream()
     {
         if (nstreams == streams.size())
             streams.emplace_back();
-        std::vector<K> &v = streams[nstreams].e;
+        KeyVec<K> &v = streams[nstreams].e;
         v.clear();
         return v;
     }
@@ -259,6 +278,70 @@ private:
     std::vector<uint32_t> hs;
 };
 
+// ---------------------------------------------------------------------------
+// AVX-512 variants (chosen at run time when the CPU has F, VL, BW and VBMI2)
+// ---------------------------------------------------------------------------
+static bool cpu_has_avx512()
+{
+    static const bool ok = __builtin_cpu_supports("avx512f") &&
+                           __builtin_cpu_supports("avx512vl") &&
+                           __builtin_cpu_supports("avx512bw") &&
+                           __builtin_cpu_supports("avx512vbmi2");
+    return ok;
+}
+
+// Dense coboundary with 32-bit cofacet indices (u64 keys): 16 candidate
+// vertices per step -- row maxima, the threshold test, the packed keys --
+// and a compress of the cofacets that pass (out needs 16 slots of slack).  Same set of keys as the
+// scalar loop; the order within a stream does not matter.
+__attribute__((target("avx512f,avx512vl,avx512bw,avx512vbmi2"))) static size_t
+cob_dense_u64_avx512(const float *const *rows, int nv, const int *v, uint64_t sigma, float d,
+                     float thr, const uint64_t *binom, int n, uint64_t *out)
+{
+    size_t cnt = 0;
+    uint64_t above = 0, below = sigma;
+    int hi = n;
+    const __m512 vd = _mm512_set1_ps(d), vthr = _mm512_set1_ps(thr);
+    const __m512i vM = _mm512_set1_epi64((long long)0xffffffffull);
+    for (int idx = 0; idx <= nv; ++idx) {
+        const int lo = idx < nv ? v[idx] : -1;
+        const int j = nv - idx;  // vertices of sigma below w
+        const uint64_t *Cj = binom + (int64_t)(j + 1) * (n + 1);
+        const __m512i vbase = _mm512_set1_epi64((long long)(above + below));
+        for (int w0 = lo + 1; w0 < hi; w0 += 16) {
+            const int rem = hi - w0;
+            const __mmask16 lm = rem >= 16 ? (__mmask16)0xffff : (__mmask16)((1u << rem) - 1u);
+            __m512 mx = _mm512_maskz_loadu_ps(lm, rows[0] + w0);
+            for (int i = 1; i < nv; ++i)
+                mx = _mm512_max_ps(mx, _mm512_maskz_loadu_ps(lm, rows[i] + w0));
+            const __mmask16 ok = _mm512_mask_cmp_ps_mask(lm, mx, vthr, _CMP_LE_OQ);
+            const __m512i ndb = _mm512_castps_si512(_mm512_max_ps(mx, vd));
+            const __m512i c0 =
+                _mm512_add_epi64(vbase, _mm512_maskz_loadu_epi64((__mmask8)lm, Cj + w0));
+            const __m512i c1 =
+                _mm512_add_epi64(vbase, _mm512_maskz_loadu_epi64((__mmask8)(lm >> 8), Cj + w0 + 8));
+            const __m512i d0 = _mm512_cvtepu32_epi64(_mm512_castsi512_si256(ndb));
+            const __m512i d1 = _mm512_cvtepu32_epi64(_mm512_extracti64x4_epi64(ndb, 1));
+            const __m512i k0 = _mm512_or_si512(_mm512_slli_epi64(d0, 32), _mm512_sub_epi64(vM, c0));
+            const __m512i k1 = _mm512_or_si512(_mm512_slli_epi64(d1, 32), _mm512_sub_epi64(vM, c1));
+            // compress in registers, then full stores (the memory form of
+            // compress is slow on some cores); out has 16 slots of slack
+            const __mmask8 ok0 = (__mmask8)ok, ok1 = (__mmask8)(ok >> 8);
+            _mm512_storeu_si512(out + cnt, _mm512_maskz_compress_epi64(ok0, k0));
+            cnt += (size_t)__builtin_popcount(ok0);
+            _mm512_storeu_si512(out + cnt, _mm512_maskz_compress_epi64(ok1, k1));
+            cnt += (size_t)__builtin_popcount(ok1);
+        }
+        if (idx < nv) {
+            const int r = nv - 1 - idx;  // rank of v[idx] from the bottom
+            below -= binom[(int64_t)(r + 1) * (n + 1) + lo];
+            above += binom[(int64_t)(r + 2) * (n + 1) + lo];
+        }
+        hi = lo;
+    }
+    return cnt;
+}
+
 struct Ctx {
     const ResidualProblem &P;
     int n, p;
@@ -316,7 +399,7 @@ struct Ctx {
 
     // Every cofacet of sigma with diameter <= threshold, appended to out as
     // packed keys.
-    template <class K> void coboundary(uint64_t sigma, float d, std::vector<K> &out) const
+    template <class K> void coboundary(uint64_t sigma, float d, KeyVec<K> &out) const
     {
         int v[8];
         decode(sigma, p, v);
@@ -351,8 +434,14 @@ struct Ctx {
         const float *rows[8];
         for (int i = 0; i <= p; ++i)
             rows[i] = P.dsq + (int64_t)v[i] * n;
-        out.resize((size_t)n);
+        out.resize((size_t)n + 16);
         size_t cnt;
+        if (std::is_same<K, uint64_t>::value && cpu_has_avx512()) {
+            cnt = cob_dense_u64_avx512(rows, p + 1, v, sigma, d, P.thr, P.binom, n,
+                                       reinterpret_cast<uint64_t *>(out.data()));
+            out.resize(cnt);
+            return;
+        }
         switch (p) {
         case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out.data()); break;
         case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out.data()); break;

@@ -343,3 +343,17 @@ def test_random_order_apparent_fraction_10000(rpp):
     assert ncols == n0 * (n0 - 1) // 2
     assert frac <= (n0 - 2) / n0
     assert abs(frac - 0.991127743) < 1e-3, frac
+
+
+def test_greedy_assignment_pairs_are_its_picks(rpp):
+    """Greedy deterministic distance assignment (an adversarial input, about
+    half the edges apparent): the GPU's apparent pairs are exactly the edges
+    the construction took while triangles remained."""
+    n = 150
+    order, picks = w.greedy_assignment_order(n)
+    d = w.greedy_assignment_metric(n)
+    s, t, ncols = rpp.apparent_pairs(d, 1)
+    assert ncols == n * (n - 1) // 2
+    assert len(s) == picks
+    assert set(s.tolist()) == set(order[:picks])
+    assert picks / ncols >= 1.0 / 3.0

@@ -229,3 +229,29 @@ def test_clearing_mode_matches_plain_reduction(case):
         if p > 0:
             assert clear[p]["n_cleared"] == len(plain[p - 1]["tau"])
     _bars_equal(oracle.bars_from_pairs(plain), oracle.bars_from_pairs(clear))
+
+
+# ---------------------------------------------------------------------------
+# Greedy deterministic distance assignment (the paper's greedy variant of its
+# random apparent-pair construction): every edge it takes while triangles
+# remain forms an apparent pair with its oldest remaining cofacet, so the
+# apparent-pair test must find exactly that many pairs; the fraction stays
+# above the lower bound 1/(p+2) = 1/3 and near 1/2.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [4, 7, 12, 20, 33])
+def test_greedy_assignment_apparent_count_is_its_pick_count(n):
+    order, picks = w.greedy_assignment_order(n)
+    d = w.greedy_assignment_metric(n)
+    s, t = oracle.apparent_pairs(d, n, 1)
+    assert len(s) == picks
+    assert len(s) / (n * (n - 1) / 2) >= 1.0 / 3.0
+    # the pairs are exactly the picked edges
+    assert set(s.tolist()) == set(order[:picks])
+
+
+def test_greedy_assignment_fraction_near_one_half():
+    n = 60
+    d = w.greedy_assignment_metric(n)
+    s, _ = oracle.apparent_pairs(d, n, 1)
+    frac = len(s) / (n * (n - 1) / 2)
+    assert 0.4 <= frac <= 0.6, frac

@@ -38,6 +38,8 @@ __all__ = [
     "all_equal_metric",
     "reverse_lex_metric",
     "random_permutation_metric",
+    "greedy_assignment_order",
+    "greedy_assignment_metric",
     "random_integer_metric",
     "WORKLOADS",
 ]
@@ -311,6 +313,68 @@ def random_permutation_metric(n: int, seed: int) -> np.ndarray:
     return (np.uint32(0x3F800000) + ranks).view(np.float32)
 
 
+def greedy_assignment_order(n: int):
+    """The paper's greedy deterministic distance assignment on the full
+    2-skeleton of n points (its random apparent-pair construction with the
+    edge choice made greedy): while triangles remain, take the edge with
+    the most remaining triangles (ties: the larger cidx), give it the next
+    smaller diameter, and remove every triangle that contains it.  Edges
+    left when no triangle remains get the smallest diameters, in decreasing
+    cidx order.  Returns (edges in decreasing-diameter order, number of
+    picks made while triangles remained)."""
+    import heapq
+    E = n * (n - 1) // 2
+    ends = [(a, b) for a in range(n) for b in range(a)]   # cidx order
+
+    def edge(a, b):
+        return a * (a - 1) // 2 + b
+
+    def tri(a, b, c):
+        return a * (a - 1) * (a - 2) // 6 + b * (b - 1) // 2 + c
+
+    alive = np.ones(max(n * (n - 1) * (n - 2) // 6, 1), dtype=bool)
+    remaining = n * (n - 1) * (n - 2) // 6
+    count = [n - 2] * E
+    picked = [False] * E
+    heap = [(-(n - 2), -e) for e in range(E)]
+    heapq.heapify(heap)
+    order = []
+    while remaining > 0:
+        c, ne = heapq.heappop(heap)
+        e = -ne
+        if picked[e] or -c != count[e]:
+            continue  # stale entry
+        picked[e] = True
+        order.append(e)
+        a, b = ends[e]
+        for w in range(n):
+            if w == a or w == b:
+                continue
+            x = sorted((a, b, w), reverse=True)
+            t = tri(*x)
+            if not alive[t]:
+                continue
+            alive[t] = False
+            remaining -= 1
+            for f in (edge(x[0], x[1]), edge(x[0], x[2]), edge(x[1], x[2])):
+                if f != e and not picked[f]:
+                    count[f] -= 1
+                    heapq.heappush(heap, (-count[f], -f))
+    picks = len(order)
+    order += [e for e in range(E - 1, -1, -1) if not picked[e]]
+    return order, picks
+
+
+def greedy_assignment_metric(n: int) -> np.ndarray:
+    """Distance matrix of the greedy assignment (distinct FP32 values that
+    preserve its order: the first edge taken is the longest)."""
+    order, _ = greedy_assignment_order(n)
+    E = len(order)
+    ranks = np.empty(E, dtype=np.uint32)
+    ranks[np.asarray(order, dtype=np.int64)] = np.arange(E, 0, -1, dtype=np.uint32)
+    return (np.uint32(0x3F800000) + ranks).view(np.float32)
+
+
 def random_integer_metric(n: int, seed: int, vmax: int = 4) -> np.ndarray:
     """Tie-heavy matrices: i.i.d. integers in [1, vmax] (not necessarily a
     metric; the method only reads edge lengths)."""
@@ -330,4 +394,8 @@ WORKLOADS = {
                      build=lambda: _dist(noisy_torus_points, 400, 1002)),
     "sphere4096": dict(n=4096, maxdim=2, threshold=0.4,
                        build=lambda: _dist(noisy_sphere_points, 4096, 1003)),
+    # the same cloud and threshold, one dimension higher (C(4096,5) ~ 9.5e15
+    # cofacet indices)
+    "sphere4096d3": dict(n=4096, maxdim=3, threshold=0.4,
+                         build=lambda: _dist(noisy_sphere_points, 4096, 1003)),
 }
