@@ -326,8 +326,18 @@ def bench_serving(args):
             lat += [done - arrivals[i] for i in idx]
         return lat, time.perf_counter() - t0, {"batch": size}
 
-    def served_mode(arrivals, slots=4):
-        srv = rpp.Server(slots=slots)
+    # One server for the whole sweep, warmed by one closed-loop pass of the
+    # stream -- the plain path's workspace is warm the same way (the capacity
+    # pass above), and a server is long-lived: its slot workspaces grow to
+    # the largest request once, not per measurement.
+    slots = 4
+    srv = rpp.Server(slots=slots)
+    for r in reqs:
+        srv.wait(srv.submit(r["dist"], r["maxdim"]))
+    print("serving: server warmed", file=sys.stderr, flush=True)
+
+    def served_mode(arrivals):
+        st0 = srv.stats()
         tickets = [None] * count
         late = [0.0] * count   # submission time minus arrival time
         t0 = time.perf_counter()
@@ -350,9 +360,8 @@ def bench_serving(args):
         th.join()
         span = time.perf_counter() - t0
         st = srv.stats()
-        srv.close()
-        return lat, span, {"slots": slots, "admitted": st["admitted"],
-                           "completed": st["completed"],
+        return lat, span, {"slots": slots, "admitted": st["admitted"] - st0["admitted"],
+                           "completed": st["completed"] - st0["completed"],
                            "peak_concurrency": st["peak_concurrency"],
                            "budget_bytes": st["budget_bytes"],
                            "peak_in_flight_bytes": st["peak_in_flight_bytes"],
@@ -376,6 +385,7 @@ def bench_serving(args):
             print("serving: rate %.2f x capacity, %s done" % (f, name), file=sys.stderr,
                   flush=True)
         sweep.append(row)
+    srv.close()
     main_row = sweep[0]
     out = {
         "metric": "barcodes/sec and p99 latency, served vs batched vs plain (Poisson stream)",
@@ -504,7 +514,8 @@ def bench_perm(args, n0, kind="perm"):
     kms = acc["ms_apparent"]
     achieved = kbytes / (kms / 1e3) / 1e9
     out = {
-        "metric": "columns/sec through the dimension-1 apparent-pair test (random edge order)",
+        "metric": "columns/sec through the dimension-1 apparent-pair test (%s)"
+                  % ("greedy-assignment edge order" if kind == "greedy" else "random edge order"),
         "value": round(ncols / el, 1), "unit": "columns/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": round(el * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -633,8 +644,13 @@ def main():
     kname = max(cand, key=lambda k: cand[k][0])
     kms, kbytes = cand[kname]
     achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
-    kfull = ("k_apparent<%d,%d>" % (top, st.get("apparent_group", 8)) if kname == "apparent"
-             else "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top))
+    if kname == "apparent":
+        g = st.get("apparent_group", 8)
+        kfull = "k_apparent_sparse<%d>" % top if g == 0 else "k_apparent<%d,%d>" % (top, g)
+    elif st.get("apparent_group", 8) == 0:
+        kfull = "k_ext<%d>" % top  # sparse enumeration (count + scatter passes)
+    else:
+        kfull = "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, kfull),

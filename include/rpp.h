@@ -86,6 +86,14 @@ enum {
 /* rpp_barcodes_batch: when no tuned parameters exist for a shape, time the
  * candidates on this batch first (results identical). */
 #define RPP_BATCH_AUTOTUNE 0x80u
+/* Host reduction of the non-apparent columns: when a column's low is the
+ * pivot of an earlier host-reduced column k, add k's unreduced coboundary
+ * D_k (paper, oblivious matrix reduction, Algorithm 2; nothing is kept once a
+ * column is final) instead of its reduced column R_k, kept from k's own
+ * reduction (the paper's reduction-matrix technique; the default).  Results
+ * are identical (the paper's lemma on oblivious reduction); the oblivious
+ * form uses less host memory and may need many more additions. */
+#define RPP_OBLIVIOUS_REDUCTION 0x100u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:
@@ -114,7 +122,10 @@ typedef struct {
     float ms_apparent;      /* device time: apparent-pair kernel */
     float ms_partition;     /* device time: partition */
     float ms_sort;          /* device time: key sorts and clearing bitmap */
-    int32_t apparent_group; /* lanes that test one column in the apparent kernel */
+    int32_t apparent_group; /* lanes that test one column in the dense apparent
+                               kernel; 0 when the sparse kernel ran (a wave
+                               per 64 columns, candidates from neighbour
+                               bitsets) */
 } rpp_dim_stats;
 
 typedef struct {

@@ -659,6 +659,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             P.col_low = hl.data() + off[c];
             P.col_low_diam = hld.data() + off[c];
             P.parallel = false;
+            P.oblivious = (a.flags & RPP_OBLIVIOUS_REDUCTION) != 0;
             residual_reduce(P, RR[c]);
         });
         auto h1 = std::chrono::steady_clock::now();

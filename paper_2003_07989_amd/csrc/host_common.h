@@ -15,6 +15,21 @@
 
 namespace rpp {
 
+// Capacity for a buffer that must hold `bytes` and held `old` before: at least
+// 1.5x the old capacity, rounded up to 64 KiB, so a sequence of slowly
+// growing requests reallocates O(log) times rather than on nearly every call
+// (each reallocation is a device-wide synchronising free + malloc).
+inline size_t grow_capacity(size_t old, size_t bytes)
+{
+    size_t b = bytes < 256 ? 256 : bytes;
+    if (old) {
+        const size_t g = old + old / 2;
+        if (g > b)
+            b = g;
+    }
+    return (b + 65535) & ~(size_t)65535;
+}
+
 // Owning device buffer; grows, never shrinks; movable, not copyable.
 struct DevBuf {
     void *p = nullptr;
@@ -42,15 +57,21 @@ struct DevBuf {
     {
         if (bytes <= cap && p)
             return true;
+        const size_t cap0 = p ? cap : 0;
         if (p)
             (void)hipFree(p);
         p = nullptr;
         cap = 0;
-        size_t b = bytes < 256 ? 256 : bytes;
-        b = (b + 4095) & ~(size_t)4095;
+        size_t b = grow_capacity(cap0, bytes);
         if (hipMalloc(&p, b) != hipSuccess) {
+            // The headroom may not fit where the exact size does.
+            const size_t e = grow_capacity(0, bytes);
             p = nullptr;
-            return false;
+            if (e >= b || hipMalloc(&p, e) != hipSuccess) {
+                p = nullptr;
+                return false;
+            }
+            b = e;
         }
         cap = b;
         return true;
@@ -89,14 +110,21 @@ struct HostBuf {
     {
         if (bytes <= cap && p)
             return true;
+        const size_t cap0 = p ? cap : 0;
         if (p)
             (void)hipHostFree(p);
         p = nullptr;
         cap = 0;
-        size_t b = bytes < 256 ? 256 : bytes;
+        size_t b = grow_capacity(cap0, bytes);
         if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+            // The headroom may not fit where the exact size does.
+            const size_t e = grow_capacity(0, bytes);
             p = nullptr;
-            return false;
+            if (e >= b || hipHostMalloc(&p, e, hipHostMallocDefault) != hipSuccess) {
+                p = nullptr;
+                return false;
+            }
+            b = e;
         }
         cap = b;
         return true;

@@ -1091,9 +1091,18 @@ void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, const uint64_
                    kept_cidx)
 }
 
-// Apparent test over common neighbours: one wave per column; each step
-// covers 64 words (lane 0 = highest word); every lane walks its word's
-// candidates downward and the highest hit across lanes is w.
+// Sparse apparent test.  A wave owns 64 columns: each lane loads and
+// decodes one, then the wave takes them one at a time (diameter and
+// vertices by shuffles).  For a column, lane l holds word (top - l) of the
+// AND of sigma's neighbour bitsets -- the common neighbours, sigma's own
+// vertices excluded; a wave prefix sum of the popcounts ranks the
+// candidates from the highest vertex down, and they are written to LDS in
+// that order and tested 64 at a time, one per lane.  The ballot's lowest
+// lane is the highest candidate whose cofacet keeps the diameter: the
+// oldest cofacet when sigma's diameter is its own.  Only candidates above
+// the first hit are examined.
+constexpr int SP_CAP = 128;  // candidates staged per pass, per wave
+
 template <int P>
 __global__ __launch_bounds__(256) void k_apparent_sparse(
     const float *__restrict__ col_diam, const uint64_t *__restrict__ col_cidx, int64_t ncols,
@@ -1101,81 +1110,145 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
     const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
     unsigned long long *__restrict__ scan_count)
 {
+    __shared__ int cand_all[256 / WAVE][SP_CAP];
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t col = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    if (col >= ncols)
-        return;
+    int *cand = cand_all[threadIdx.x / WAVE];
+    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * WAVE;
+    if (base >= ncols)
+        return;  // whole waves leave together
     const Binom B{binom, n + 1};
-    const float d = col_diam[col];
-    int v[P + 1];
-    decode<P>(B, col_cidx[col], n, v);
-    const float *row[P + 1];
+    const int64_t mycol = base + lane;
+    const bool myvalid = mycol < ncols;
+    float myd = 0.0f;
+    int myv[P + 1];
 #pragma unroll
     for (int i = 0; i <= P; ++i)
-        row[i] = dsq + (int64_t)v[i] * n;
-    int w = -1;
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        decode<P>(B, col_cidx[mycol], n, myv);
+    }
+    uint64_t mytau = NONE;
     long long examined = 0;
-    for (int top = words - 1; top >= 0; top -= WAVE) {
-        const int word = top - lane;
-        int found = -1;
-        if (word >= 0) {
-            uint64_t m = ~0ull;
+    const int ncol_wave = (int)((ncols - base) < WAVE ? (ncols - base) : WAVE);
+    for (int r = 0; r < ncol_wave; ++r) {
+        const float d = __shfl(myd, r, WAVE);
+        int v[P + 1];
 #pragma unroll
-            for (int i = 0; i <= P; ++i)
-                m &= bits[(int64_t)v[i] * words + word];
-            while (m) {
-                const int bpos = 63 - __clzll((long long)m);
-                const int x = word * 64 + bpos;
-                bool ok = true;
+        for (int i = 0; i <= P; ++i)
+            v[i] = __shfl(myv[i], r, WAVE);
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)v[i] * n;
+        float dv[P + 1][P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b2 = a + 1; b2 <= P; ++b2)
+                dv[a][b2] = row[a][v[b2]];
+        int w = -1;
+        float ew[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            ew[i] = 0.0f;
+        // candidates examined, from the highest down to the hit (uniform in
+        // the wave): earlier chunks in full, the hit's chunk up to the hit
+        long long seen = 0;
+        for (int top = words - 1; top >= 0 && w < 0; top -= WAVE) {
+            const int word = top - lane;
+            uint64_t m = 0;
+            if (word >= 0) {
+                m = ~0ull;
 #pragma unroll
                 for (int i = 0; i <= P; ++i)
-                    ok = ok && row[i][x] <= d;
-                if (scan_count)
-                    ++examined;
-                if (ok) {
-                    found = x;
-                    break;
-                }
-                m &= ~(1ull << bpos);
+                    m &= bits[(int64_t)v[i] * words + word];
             }
-        }
-        const uint64_t bal = __ballot(found >= 0);
-        if (bal) {
-            w = __shfl(found, __ffsll((unsigned long long)bal) - 1, WAVE);
-            break;
-        }
-    }
-    uint64_t tau = NONE;
-    if (w >= 0) {
-        bool apparent = true;
-#pragma unroll
-        for (int j = 0; j <= P; ++j) {
-            if (v[j] > w && apparent) {
-                float fd = 0.0f;
-#pragma unroll
-                for (int a = 0; a <= P; ++a) {
-                    if (a == j)
-                        continue;
-                    fd = fmaxf(fd, row[a][w]);
-#pragma unroll
-                    for (int b = a + 1; b <= P; ++b)
-                        if (b != j)
-                            fd = fmaxf(fd, row[a][v[b]]);
+            const int c = __popcll(m);
+            const int inc = wave_inclusive_scan(c);
+            const int pre = inc - c;  // rank of this lane's highest candidate
+            const int total = __shfl(inc, WAVE - 1, WAVE);
+            for (int s0 = 0; s0 < total && w < 0; s0 += SP_CAP) {
+                if (c > 0 && pre < s0 + SP_CAP && pre + c > s0) {
+                    uint64_t mm = m;
+                    int k = pre;
+                    while (mm && k < s0 + SP_CAP) {
+                        const int bpos = 63 - __clzll((long long)mm);
+                        if (k >= s0)
+                            cand[k - s0] = word * 64 + bpos;
+                        ++k;
+                        mm &= ~(1ull << bpos);
+                    }
                 }
-                if (fd == d)
-                    apparent = false;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const int lim = (total - s0) < SP_CAP ? (total - s0) : SP_CAP;
+                for (int b0 = 0; b0 < lim && w < 0; b0 += WAVE) {
+                    const int slot = b0 + lane;
+                    bool ok = false;
+                    int x = 0;
+                    float e[P + 1];
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        e[i] = 0.0f;
+                    if (slot < lim) {
+                        x = cand[slot];
+                        ok = true;
+#pragma unroll
+                        for (int i = 0; i <= P; ++i) {
+                            e[i] = row[i][x];
+                            ok = ok && (e[i] <= d);
+                        }
+                    }
+                    const uint64_t bal = __ballot(ok);
+                    if (bal) {
+                        const int hl = __ffsll((unsigned long long)bal) - 1;
+                        w = __shfl(x, hl, WAVE);
+#pragma unroll
+                        for (int i = 0; i <= P; ++i)
+                            ew[i] = __shfl(e[i], hl, WAVE);
+                        seen += s0 + b0 + hl + 1;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
+            if (w < 0)
+                seen += total;  // the whole chunk was examined without a hit
         }
-        if (apparent)
-            tau = cofacet_index<P>(B, v, w);
+        uint64_t tau = NONE;
+        if (w >= 0) {
+            bool apparent = true;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                if (v[j] > w && apparent) {
+                    // facet sigma - {v_j} + {w}
+                    float fd = 0.0f;
+#pragma unroll
+                    for (int a = 0; a <= P; ++a) {
+                        if (a == j)
+                            continue;
+                        fd = fmaxf(fd, ew[a]);
+#pragma unroll
+                        for (int b2 = a + 1; b2 <= P; ++b2)
+                            if (b2 != j)
+                                fd = fmaxf(fd, dv[a][b2]);
+                    }
+                    if (fd == d)
+                        apparent = false;
+                }
+            }
+            if (apparent)
+                tau = cofacet_index<P>(B, v, w);
+        }
+        examined += seen;
+        if (lane == r)
+            mytau = tau;
     }
-    if (scan_count) {
-        const long long tot = wave_sum(examined);
-        if (lane == 0)
-            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)tot);
-    }
-    if (lane == 0)
-        tau_out[col] = tau;
+    if (scan_count && lane == 0)
+        atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)examined);
+    if (myvalid)
+        tau_out[mycol] = mytau;
 }
 
 template <int P>
@@ -1234,7 +1307,8 @@ void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int
 {
     if (ncols <= 0)
         return;
-    dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+    const int64_t threads = (ncols + WAVE - 1) / WAVE * WAVE;  // one wave per 64 columns
+    dim3 g((unsigned)((threads + 255) / 256)), b(256);
     switch (p) {
     case 1: hipLaunchKernelGGL(k_apparent_sparse<1>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
     case 2: hipLaunchKernelGGL(k_apparent_sparse<2>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;

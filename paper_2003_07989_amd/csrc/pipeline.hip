@@ -741,7 +741,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.n_cleared = (int64_t)nclr;
         D.st.n_simplices = ncand - (int64_t)nthr;
         D.st.n_kept = ncols;
-        D.st.apparent_group = sparse ? 64 : group;  // sparse path: one wave per column
+        D.st.apparent_group = sparse ? 0 : group;  // 0: the sparse kernel
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
 
@@ -766,6 +766,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         H.P.app_tau = sorted_store ? ws.h_app_tau[hb].as<uint64_t>() : nullptr;
         H.P.app_sigma = sorted_store ? ws.h_app_sigma[hb].as<uint64_t>() : nullptr;
         H.P.spec_budget = SPEC_BUDGET;
+        H.P.oblivious = (a.flags & RPP_OBLIVIOUS_REDUCTION) != 0;
         H.napp = napp;
         H.app_tau = ws.h_app_tau[hb].as<uint64_t>();
         H.app_sigma = ws.h_app_sigma[hb].as<uint64_t>();

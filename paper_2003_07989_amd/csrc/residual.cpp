@@ -1,14 +1,16 @@
 // residual.cpp -- host reduction of the columns the GPU could not pair.
 //
-// Paper, "Reduction Matrix vs. Oblivious Matrix Reduction" (Algorithm 2)
-// and "Core System Optimizations" (two-layer pair store).  Columns arrive in
-// coboundary order together with their lows (oldest cofacets), computed on
-// the GPU.  A column whose low is not yet a pivot is paired at once, with no
-// coboundary built (its unreduced column is already reduced).  Otherwise its
-// coboundary is regenerated from the distance matrix (implicit matrix
-// reduction) into a binary heap ordered oldest-first, so the heap top is the
-// column's low; Z/2 addition pushes the other column's entries, and equal
-// entries cancel in pairs when the low is taken.
+// Paper, "Reduction Matrix vs. Oblivious Matrix Reduction" (both techniques,
+// Algorithm 2 for the oblivious one) and "Core System Optimizations"
+// (two-layer pair store).  Columns arrive in coboundary order together with
+// their lows (oldest cofacets), computed on the GPU.  A column whose low is
+// not yet a pivot is paired at once, with no coboundary built (its
+// unreduced column is already reduced: the emergent shortcut).  Otherwise
+// its coboundary is regenerated from the distance matrix (implicit matrix
+// reduction) as a stream of keys, oldest first; a column is a 4-ary min-heap
+// over the fronts of the streams it has summed, so the heap top is its low;
+// Z/2 addition adds the other column's streams, and equal entries cancel in
+// pairs when the low is taken.
 #include "residual.h"
 
 #include <immintrin.h>
@@ -565,8 +567,15 @@ struct Ctx {
 };
 
 // ---------------------------------------------------------------------------
-// A small persistent worker pool for the speculative phase.
+// A small persistent worker pool, shared by every caller in the process.
 // ---------------------------------------------------------------------------
+// A job is a function that claims its work items dynamically (an atomic
+// counter) and returns once none is left, so any number of threads may run
+// it at once, and a thread that joins after the last item was claimed just
+// returns.  Several callers (the serving slots, the exact phase of one
+// dimension next to the speculative phase of the next) may run jobs at the
+// same time: each idle worker joins the open job with the fewest threads, so
+// the workers are shared out instead of going to whoever came first.
 class Pool {
 public:
     static Pool &get()
@@ -575,30 +584,32 @@ public:
         return pool;
     }
     int size() const { return (int)workers_.size() + 1; }
-    // Runs fn(tid) on every worker and on the calling thread (tid 0), and
-    // returns when all have finished.  One caller at a time uses the
-    // workers; a concurrent caller runs fn(0) alone on its own thread.
+    // Runs fn(tid) on the calling thread (tid 0) and on the workers that
+    // join, and returns when every thread that entered fn has left it.
     void run(const std::function<void(int)> &fn)
     {
-        std::unique_lock<std::mutex> owner(run_mu_, std::try_to_lock);
-        if (workers_.empty() || !owner.owns_lock()) {
+        if (workers_.empty()) {
             fn(0);
             return;
         }
+        Job job;
+        job.fn = &fn;
         {
-            std::unique_lock<std::mutex> lk(mu_);
-            job_ = &fn;
-            pending_ = (int)workers_.size();
-            ++epoch_;
+            std::lock_guard<std::mutex> lk(mu_);
+            open_.push_back(&job);
         }
         cv_.notify_all();
         fn(0);
         std::unique_lock<std::mutex> lk(mu_);
-        done_.wait(lk, [&] { return pending_ == 0; });
-        job_ = nullptr;
+        close_locked(&job);
+        done_.wait(lk, [&] { return job.active == 0; });
     }
 
 private:
+    struct Job {
+        const std::function<void(int)> *fn = nullptr;
+        int active = 0;  // threads inside fn, the caller excluded
+    };
     Pool()
     {
         unsigned hw = std::thread::hardware_concurrency();
@@ -612,40 +623,45 @@ private:
     ~Pool()
     {
         {
-            std::unique_lock<std::mutex> lk(mu_);
+            std::lock_guard<std::mutex> lk(mu_);
             stop_ = true;
-            ++epoch_;
         }
         cv_.notify_all();
         for (auto &w : workers_)
             w.join();
     }
+    // A job whose items are all claimed takes no new threads.
+    void close_locked(Job *j)
+    {
+        auto it = std::find(open_.begin(), open_.end(), j);
+        if (it != open_.end())
+            open_.erase(it);
+    }
     void loop(int tid)
     {
-        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
         while (true) {
-            const std::function<void(int)> *job;
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [&] { return stop_ || epoch_ != seen; });
-                if (stop_)
-                    return;
-                seen = epoch_;
-                job = job_;
-            }
-            (*job)(tid);
-            std::unique_lock<std::mutex> lk(mu_);
-            if (--pending_ == 0)
-                done_.notify_one();
+            cv_.wait(lk, [&] { return stop_ || !open_.empty(); });
+            if (stop_)
+                return;
+            Job *j = open_[0];
+            for (Job *o : open_)
+                if (o->active < j->active)
+                    j = o;
+            ++j->active;
+            lk.unlock();
+            (*j->fn)(tid);
+            lk.lock();
+            // fn returned: every item is claimed, so nobody else should join
+            close_locked(j);
+            if (--j->active == 0)
+                done_.notify_all();
         }
     }
     std::vector<std::thread> workers_;
-    std::mutex run_mu_;
     std::mutex mu_;
     std::condition_variable cv_, done_;
-    const std::function<void(int)> *job_ = nullptr;
-    int pending_ = 0;
-    uint64_t epoch_ = 0;
+    std::vector<Job *> open_;
     bool stop_ = false;
 };
 
@@ -844,7 +860,8 @@ private:
             R.tau.push_back(lo.cidx);
             R.birth.push_back(d);
             R.death.push_back(lo.diam);
-            reduced.push_back(spec_adds[j] ? std::move(state[j]) : nullptr);
+            // oblivious: nothing is kept, a later column adds D_k instead
+            reduced.push_back(spec_adds[j] && !P.oblivious ? std::move(state[j]) : nullptr);
             state[j].reset();
             auto it = whead.find(lo.cidx);
             if (it == whead.end())

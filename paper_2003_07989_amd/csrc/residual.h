@@ -42,6 +42,15 @@ struct ResidualProblem {
     // at most this many additions per column in the speculative phase
     // (0: no limit); a column cut off there resumes in the exact phase
     int64_t spec_budget = 0;
+    // How a column adds a host pivot column k (paper, "Reduction Matrix vs.
+    // Oblivious Matrix Reduction").  false: k's reduced column R_k, kept from
+    // k's own reduction as the streams of the coboundaries it summed (the
+    // reduction-matrix technique: V_k's coboundaries, duplicates cancelling).
+    // true: only k's unreduced coboundary D_k, with nothing kept after a
+    // column is final (oblivious reduction, Algorithm 2).  The paper's lemma
+    // on oblivious reduction makes the pairs and classes identical; the
+    // oblivious form needs less memory and may need more additions.
+    bool oblivious = false;
 };
 
 struct ResidualResult {
@@ -54,9 +63,10 @@ struct ResidualResult {
     int64_t lookups_hash = 0, lookups_apparent = 0;
 };
 
-// Oblivious column reduction (paper, Algorithm 2) of every column, in order,
-// with the two-layer pivot store: the pivots found here in a hash map first,
-// then the apparent pairs.
+// Column reduction (paper, Algorithm 1, with the additions chosen by
+// ResidualProblem::oblivious) of every column, in order, with the two-layer
+// pivot store: the pivots found here in a hash map first, then the apparent
+// pairs.
 void residual_reduce(const ResidualProblem &P, ResidualResult &R);
 
 // The same reduction in two steps.  residual_speculate runs the parallel

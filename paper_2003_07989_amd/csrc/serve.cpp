@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/rpp.h"
+#include "host_common.h"
 #include "pipeline.h"
 
 namespace rpp {
@@ -132,16 +133,25 @@ struct rpp_server {
         const size_t m = r.dist.size();
         hipStream_t s = streams[k];
         if (m * sizeof(float) > dev_in_cap[k]) {  // capacity is in bytes
-            if (dev_in[k])
+            const size_t old = dev_in_cap[k];
+            if (dev_in[k]) {
+                (void)hipStreamSynchronize(s);
                 (void)hipFree(dev_in[k]);
+            }
             dev_in[k] = nullptr;
             dev_in_cap[k] = 0;
-            if (hipMalloc(&dev_in[k], m * sizeof(float)) != hipSuccess) {
-                r.rc = RPP_E_NOMEM;
-                r.err = "hipMalloc of the request input failed";
-                return;
+            size_t b = rpp::grow_capacity(old, m * sizeof(float));
+            if (hipMalloc(&dev_in[k], b) != hipSuccess) {
+                b = rpp::grow_capacity(0, m * sizeof(float));
+                dev_in[k] = nullptr;
+                if (hipMalloc(&dev_in[k], b) != hipSuccess) {
+                    dev_in[k] = nullptr;
+                    r.rc = RPP_E_NOMEM;
+                    r.err = "hipMalloc of the request input failed";
+                    return;
+                }
             }
-            dev_in_cap[k] = m * sizeof(float);
+            dev_in_cap[k] = b;
         }
         if (m && hipMemcpyAsync(dev_in[k], r.dist.data(), m * sizeof(float),
                                 hipMemcpyHostToDevice, s) != hipSuccess) {

@@ -91,7 +91,10 @@ int main(int argc, char **argv)
     N = atoi(argv[2]);
     const int maxdim = atoi(argv[3]);
     const float thr = (float)atof(argv[4]);
+    // mode & 3: schedule (0 plain, 1 speculative budget, 2 overlapped);
+    // mode & 4: oblivious additions
     const int mode = atoi(argv[5]);
+    const int sched = mode & 3;
     const int n = N;
     const size_t m = (size_t)n * (n - 1) / 2;
     std::vector<float> dc(m);
@@ -252,9 +255,10 @@ int main(int argc, char **argv)
         P.col_low = low.data();
         P.col_low_diam = lowd.data();
         P.napp = napp;
-        P.spec_budget = mode >= 1 ? 2 : 0;
+        P.spec_budget = sched >= 1 ? 2 : 0;
+        P.oblivious = (mode & 4) != 0;
         ResidualResult R;
-        if (mode == 2) {
+        if (sched == 2) {
             std::unordered_set<uint64_t> ph(prev_host.begin(), prev_host.end());
             std::vector<uint8_t> drop(cid.size(), 0);
             for (size_t j = 0; j < cid.size(); ++j)
@@ -272,13 +276,14 @@ int main(int argc, char **argv)
                    (unsigned long long)R.tau[i]);
         for (uint64_t e : R.ess_sigma)
             printf("E %d %llu\n", p, (unsigned long long)e);
+        printf("A %d %lld\n", p, (long long)R.additions);
         // next clearing set: apparent pivots always; host pivots unless the
         // overlapped schedule drops them instead
         clear.clear();
         for (size_t i = 0; i < cc.size(); ++i)
             if (app_tau[i] != ~0ull)
                 clear.insert(app_tau[i]);
-        if (mode != 2)
+        if (sched != 2)
             for (uint64_t t : R.tau)
                 clear.insert(t);
         prev_host = R.tau;

@@ -103,3 +103,19 @@ def test_workspace_bound_grows_with_size():
     b = rpp.workspace_bytes(400, 2)
     assert 0 < a < b
     assert rpp.workspace_bytes(0, 1) == 0
+
+
+def test_flag_constants_match_the_header():
+    """Every RPP_* flag and limit the header defines has the same value in
+    the binding, and the flags are distinct bits."""
+    src = open(os.path.join(ROOT, "include", "rpp.h")).read()
+    defs = dict(re.findall(r"#define\s+(RPP_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", src))
+    assert "RPP_OBLIVIOUS_REDUCTION" in defs and "RPP_WANT_PAIRS" in defs
+    flags = []
+    for name, val in defs.items():
+        v = int(val, 0)
+        assert getattr(B, name) == v, name
+        if name != "RPP_MAX_DIM":
+            flags.append(v)
+    assert all(f and (f & (f - 1)) == 0 for f in flags)
+    assert len(set(flags)) == len(flags)

@@ -239,6 +239,28 @@ def test_torus400_sorted_pair_store(rpp):
     assert_bars_equal(got.bars, exp, "torus400 sorted store")
 
 
+@pytest.mark.parametrize("case", CASES[1::3], ids=[c[0] for c in CASES[1::3]])
+def test_oblivious_reduction_matches_oracle(rpp, case):
+    """Adding a host pivot's unreduced coboundary (oblivious reduction)
+    instead of its reduced column gives the same bars and pairs (the
+    paper's lemma on oblivious reduction)."""
+    name, d, n, maxdim, thr = case
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_OBLIVIOUS_REDUCTION)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+    f = rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    a = rpp.barcodes(d, maxdim, thr, flags=f)
+    b = rpp.barcodes(d, maxdim, thr, flags=f | rpp.RPP_OBLIVIOUS_REDUCTION)
+    for p in range(1, maxdim + 1):
+        assert set(zip(*map(list, a.pairs[p]))) == set(zip(*map(list, b.pairs[p])))
+
+
+def test_torus400_oblivious_reduction(rpp):
+    head, exp = _golden("torus400")
+    d = w.WORKLOADS["torus400"]["build"]()
+    got = rpp.barcodes(d, 2, flags=rpp.RPP_OBLIVIOUS_REDUCTION)
+    assert_bars_equal(got.bars, exp, "torus400 oblivious")
+
+
 SPARSE_CASES = [c for c in CASES if not math.isinf(c[4])] + CASES[:8]
 
 
@@ -295,6 +317,23 @@ def test_sphere4096_matches_stored_oracle(rpp):
     got = rpp.barcodes(d, cfg["maxdim"], cfg["threshold"])
     assert_bars_equal(got.bars, exp, "sphere4096")
     for p in range(3):
+        assert got.stats[p]["n_simplices"] == head["dims"][p]["simplices"]
+        assert got.stats[p]["n_apparent"] + got.stats[p]["n_host_pairs"] == head["dims"][p]["pairs"]
+
+
+def test_sphere4096_dim3_matches_stored_oracle(rpp):
+    """The same sphere with dimension 3 (2.1e8 tetrahedra under the
+    threshold, cofacet indices beyond 2^32): against the oracle's stored
+    barcodes and per-dimension simplex and pair counts."""
+    import hashlib
+    head, exp = _golden("sphere4096d3")
+    cfg = w.WORKLOADS["sphere4096d3"]
+    d = cfg["build"]()
+    assert hashlib.sha256(d.tobytes()).hexdigest() == head["sha256"], "input generator drifted"
+    print("case sphere4096d3", flush=True)
+    got = rpp.barcodes(d, cfg["maxdim"], cfg["threshold"])
+    assert_bars_equal(got.bars, exp, "sphere4096d3")
+    for p in range(4):
         assert got.stats[p]["n_simplices"] == head["dims"][p]["simplices"]
         assert got.stats[p]["n_apparent"] + got.stats[p]["n_host_pairs"] == head["dims"][p]["pairs"]
 

@@ -2,7 +2,10 @@
 driver that builds the GPU stages' hand-off by brute force: every schedule
 -- plain, with a speculative budget, and the overlapped one that drops the
 previous dimension's host pivots instead of clearing them -- gives the
-oracle's persistence pairs and essential classes exactly."""
+oracle's persistence pairs and essential classes exactly, with either way of
+adding a host pivot column: its reduced column (reduction-matrix technique)
+or its unreduced coboundary (oblivious reduction, the paper's lemma on
+oblivious reduction)."""
 import os
 import subprocess
 import tempfile
@@ -27,7 +30,7 @@ def driver():
     return out
 
 
-def _run(driver, d, n, maxdim, thr, mode):
+def _run(driver, d, n, maxdim, thr, mode, with_additions=False):
     with tempfile.NamedTemporaryFile(suffix=".f32", delete=False) as f:
         np.ascontiguousarray(d, dtype=np.float32).tofile(f)
         path = f.name
@@ -38,12 +41,17 @@ def _run(driver, d, n, maxdim, thr, mode):
         os.unlink(path)
     pairs = {p: set() for p in range(1, maxdim + 1)}
     ess = {p: set() for p in range(1, maxdim + 1)}
+    adds = {}
     for line in r.stdout.splitlines():
         t = line.split()
         if t[0] == "P":
             pairs[int(t[1])].add((int(t[2]), int(t[3])))
-        else:
+        elif t[0] == "E":
             ess[int(t[1])].add(int(t[2]))
+        else:
+            adds[int(t[1])] = int(t[2])
+    if with_additions:
+        return pairs, ess, adds
     return pairs, ess
 
 
@@ -67,7 +75,8 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,build,n,maxdim,thr", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("mode", [0, 1, 2], ids=["plain", "budget", "overlap"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 4, 6],
+                         ids=["plain", "budget", "overlap", "oblivious", "overlap-oblivious"])
 def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
     d = build()
     if np.isinf(thr):
@@ -77,3 +86,16 @@ def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
     for p in range(1, maxdim + 1):
         assert got_p[p] == exp_p[p], (name, mode, p)
         assert got_e[p] == exp_e[p], (name, mode, p)
+
+
+def test_oblivious_additions_differ_where_host_pivots_are_reduced(driver):
+    """The two ways of adding a host pivot column differ in work, not in the
+    result: on an input whose host pivot columns needed additions of their
+    own, the oblivious form (D_k) makes more additions than adding the kept
+    reduced columns (R_k), and the pairs are the same."""
+    d = w.random_permutation_metric(40, 3)
+    thr = oracle.enclosing_radius(d, 40)
+    rm_p, rm_e, rm_a = _run(driver, d, 40, 2, thr, 0, with_additions=True)
+    ob_p, ob_e, ob_a = _run(driver, d, 40, 2, thr, 4, with_additions=True)
+    assert rm_p == ob_p and rm_e == ob_e
+    assert sum(ob_a.values()) > sum(rm_a.values()), (ob_a, rm_a)
