@@ -644,10 +644,11 @@ def main():
     kname = max(cand, key=lambda k: cand[k][0])
     kms, kbytes = cand[kname]
     achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+    g = st.get("apparent_group", 8)
     if kname == "apparent":
-        g = st.get("apparent_group", 8)
-        kfull = "k_apparent_sparse<%d>" % top if g == 0 else "k_apparent<%d,%d>" % (top, g)
-    elif st.get("apparent_group", 8) == 0:
+        kfull = ("k_apparent_sparse<%d,%d>" % (top, -g) if g < 0
+                 else "k_apparent<%d,%d>" % (top, g))
+    elif g < 0:
         kfull = "k_ext<%d>" % top  # sparse enumeration (count + scatter passes)
     else:
         kfull = "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top)

@@ -122,10 +122,9 @@ typedef struct {
     float ms_apparent;      /* device time: apparent-pair kernel */
     float ms_partition;     /* device time: partition */
     float ms_sort;          /* device time: key sorts and clearing bitmap */
-    int32_t apparent_group; /* lanes that test one column in the dense apparent
-                               kernel; 0 when the sparse kernel ran (a wave
-                               per 64 columns, candidates from neighbour
-                               bitsets) */
+    int32_t apparent_group; /* lanes that test one column in the apparent
+                               kernel; negative when it was the sparse kernel
+                               (candidates from neighbour bitsets) */
 } rpp_dim_stats;
 
 typedef struct {

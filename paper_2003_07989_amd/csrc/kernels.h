@@ -142,21 +142,27 @@ struct ExtArgs {
     const float *pre_diam;           // (p-1)-simplices <= thr, cidx order
     const uint64_t *pre_cidx;
     int64_t npre;
-    const uint64_t *clear_sorted;    // cleared p-simplices, sorted cidx (may be null)
-    int64_t nclear;
 };
-// Pass 1: per prefix, the number of extensions and of non-cleared ones.
-void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, uint32_t *cnt_kept, hipStream_t s);
-// Pass 2: write all extensions (when all_cidx is not null) and the kept
-// ones at the given offsets, in cidx order.
-void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, const uint64_t *off_kept,
-                        float *all_diam, uint64_t *all_cidx, float *kept_diam,
-                        uint64_t *kept_cidx, hipStream_t s);
+// Pass 1: per prefix, the number of extensions.
+void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s);
+// Pass 2: write every extension at the given offsets, in cidx order.
+void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
+                        uint64_t *all_cidx, hipStream_t s);
+// Clearing filter: the entries of `all` (cidx order) that are not in the
+// sorted array `clear`, kept in order.  Count pass per COMPACT_TILE tile,
+// then the scatter at the scanned tile offsets.
+void launch_clear_count(const uint64_t *all_cidx, int64_t nall, const uint64_t *clear,
+                        int64_t nclear, uint32_t *tile_counts, hipStream_t s);
+void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64_t nall,
+                          const uint64_t *clear, int64_t nclear, const uint64_t *tile_offsets,
+                          float *kept_diam, uint64_t *kept_cidx, hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
-// neighbours of the column's vertices, scanned 64 at a time from the top.
+// neighbours of the column's vertices, scanned from the top, `group` words
+// per step by as many lanes (4, 8 or 16; anything else means 8).
+int sparse_group(int group);
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                             const float *dsq, int n, int p, const uint64_t *bits, int words,
-                            const uint64_t *binom, uint64_t *tau_out,
+                            const uint64_t *binom, int group, uint64_t *tau_out,
                             unsigned long long *scan_count, hipStream_t s);
 void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
                         const float *dsq, int n, int p, const uint64_t *bits, int words,

@@ -966,30 +966,14 @@ void launch_nbr_bits(const float *dsq, int n, float thr, uint64_t *bits, int wor
                        thr, bits, words);
 }
 
-__device__ __forceinline__ bool sorted_contains(const uint64_t *__restrict__ a, int64_t len,
-                                                uint64_t key)
-{
-    int64_t lo = 0, hi = len;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo < len && a[lo] == key;
-}
-
 // One wave per prefix, one lane per 64-vertex word of candidates v_0 < v_1.
+// Every extension is within the threshold; clearing is a separate pass
+// (k_clear_filter), so this kernel does no lookups.
 template <int P, bool WRITE>
 __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ cnt_all,
-                                             uint32_t *__restrict__ cnt_kept,
                                              const uint64_t *__restrict__ off_all,
-                                             const uint64_t *__restrict__ off_kept,
                                              float *__restrict__ all_diam,
-                                             uint64_t *__restrict__ all_cidx,
-                                             float *__restrict__ kept_diam,
-                                             uint64_t *__restrict__ kept_cidx)
+                                             uint64_t *__restrict__ all_cidx)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t pre = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1005,9 +989,8 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
     for (int i = 0; i < P; ++i)
         shifted += B(u[i], P + 1 - i);
     const int limit = u[P - 1];
-    uint64_t run_all = WRITE ? off_all ? off_all[pre] : 0 : 0;
-    uint64_t run_kept = WRITE ? off_kept[pre] : 0;
-    uint32_t tot_all = 0, tot_kept = 0;
+    uint64_t run = WRITE ? off_all[pre] : 0;
+    uint32_t tot = 0;
     for (int wb = 0; wb * 64 < limit; wb += WAVE) {
         const int word = wb + lane;
         uint64_t m = 0;
@@ -1021,48 +1004,25 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
                 m &= (1ull << hi) - 1;
         }
         const uint32_t na = (uint32_t)__popcll(m);
-        uint32_t nk = 0;
-        if (a.clear_sorted) {
-            for (uint64_t r = m; r; r &= r - 1) {
-                const int v0 = word * 64 + __ffsll((unsigned long long)r) - 1;
-                nk += !sorted_contains(a.clear_sorted, a.nclear, shifted + (uint64_t)v0);
-            }
-        } else {
-            nk = na;
-        }
         if (WRITE) {
-            const uint32_t ia = wave_inclusive_scan(na) - na;
-            const uint32_t ik = wave_inclusive_scan(nk) - nk;
-            uint64_t pa = run_all + ia, pk = run_kept + ik;
+            uint64_t pa = run + (wave_inclusive_scan(na) - na);
             for (uint64_t r = m; r; r &= r - 1) {
                 const int v0 = word * 64 + __ffsll((unsigned long long)r) - 1;
                 float d = pd;
 #pragma unroll
                 for (int i = 0; i < P; ++i)
                     d = fmaxf(d, dsq_at(a.dsq, a.n, u[i], v0));
-                const uint64_t c = shifted + (uint64_t)v0;
-                if (all_cidx) {
-                    all_diam[pa] = d;
-                    all_cidx[pa] = c;
-                    ++pa;
-                }
-                if (!a.clear_sorted || !sorted_contains(a.clear_sorted, a.nclear, c)) {
-                    kept_diam[pk] = d;
-                    kept_cidx[pk] = c;
-                    ++pk;
-                }
+                all_diam[pa] = d;
+                all_cidx[pa] = shifted + (uint64_t)v0;
+                ++pa;
             }
         }
-        const uint32_t sa = wave_sum(na), sk = wave_sum(nk);
-        run_all += sa;
-        run_kept += sk;
-        tot_all += sa;
-        tot_kept += sk;
+        const uint32_t sa = wave_sum(na);
+        run += sa;
+        tot += sa;
     }
-    if (!WRITE && lane == 0) {
-        cnt_all[pre] = tot_all;
-        cnt_kept[pre] = tot_kept;
-    }
+    if (!WRITE && lane == 0)
+        cnt_all[pre] = tot;
 }
 
 #define RPP_EXT_LAUNCH(WR, ...)                                                                  \
@@ -1072,53 +1032,178 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
     default: hipLaunchKernelGGL((k_ext<4, WR>), g, b, 0, s, a, __VA_ARGS__); break;              \
     }
 
-void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, uint32_t *cnt_kept, hipStream_t s)
+void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s)
 {
     if (a.npre <= 0)
         return;
     dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
-    RPP_EXT_LAUNCH(false, cnt_all, cnt_kept, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr)
+    RPP_EXT_LAUNCH(false, cnt_all, nullptr, nullptr, nullptr)
 }
 
-void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, const uint64_t *off_kept,
-                        float *all_diam, uint64_t *all_cidx, float *kept_diam,
-                        uint64_t *kept_cidx, hipStream_t s)
+void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
+                        uint64_t *all_cidx, hipStream_t s)
 {
     if (a.npre <= 0)
         return;
     dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
-    RPP_EXT_LAUNCH(true, nullptr, nullptr, off_all, off_kept, all_diam, all_cidx, kept_diam,
-                   kept_cidx)
+    RPP_EXT_LAUNCH(true, nullptr, off_all, all_diam, all_cidx)
 }
 
-// Sparse apparent test.  A wave owns 64 columns: each lane loads and
-// decodes one, then the wave takes them one at a time (diameter and
-// vertices by shuffles).  For a column, lane l holds word (top - l) of the
-// AND of sigma's neighbour bitsets -- the common neighbours, sigma's own
-// vertices excluded; a wave prefix sum of the popcounts ranks the
-// candidates from the highest vertex down, and they are written to LDS in
-// that order and tested 64 at a time, one per lane.  The ballot's lowest
-// lane is the highest candidate whose cofacet keeps the diameter: the
-// oldest cofacet when sigma's diameter is its own.  Only candidates above
-// the first hit are examined.
-constexpr int SP_CAP = 128;  // candidates staged per pass, per wave
+// Clearing filter of the sparse path.  `all` lists every p-simplex within
+// the threshold in cidx order and `clear` the cleared ones, sorted (a
+// subset).  A tile of COMPACT_TILE entries finds its slice of `clear` with
+// two binary searches and stages it in LDS; each entry then looks itself up
+// in the slice.  Because `clear` is a subset of `all`, a slice is never
+// longer than its tile; the global search only guards that assumption.  The
+// kept entries are written stably, as in the partition pass.
+constexpr int CLEAR_LDS = (int)COMPACT_TILE;
 
-template <int P>
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *__restrict__ a, int64_t lo,
+                                                   int64_t hi, uint64_t key)
+{
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(CT) void k_clear_filter(
+    const float *__restrict__ all_diam, const uint64_t *__restrict__ all_cidx, int64_t nall,
+    const uint64_t *__restrict__ clear, int64_t nclear, uint32_t *__restrict__ tile_counts,
+    const uint64_t *__restrict__ tile_offsets, float *__restrict__ kept_diam,
+    uint64_t *__restrict__ kept_cidx)
+{
+    __shared__ uint64_t sl[CLEAR_LDS];
+    __shared__ int64_t range[2];
+    __shared__ uint32_t wsum[CT / WAVE + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
+    const int64_t end = base + COMPACT_TILE < nall ? base + COMPACT_TILE : nall;
+    if (threadIdx.x == 0)
+        range[0] = lower_bound_u64(clear, 0, nclear, all_cidx[base]);
+    if (threadIdx.x == WAVE)
+        range[1] = lower_bound_u64(clear, 0, nclear, all_cidx[end - 1] + 1);
+    __syncthreads();
+    const int64_t lo = range[0], len = range[1] - range[0];
+    const bool in_lds = len <= CLEAR_LDS;
+    if (in_lds)
+        for (int64_t k = threadIdx.x; k < len; k += CT)
+            sl[k] = clear[lo + k];
+    __syncthreads();
+    uint64_t run = WRITE ? tile_offsets[blockIdx.x] : 0;
+    uint32_t cnt = 0;
+    for (int k = 0; k < CI; ++k) {
+        const int64_t i = base + (int64_t)k * CT + threadIdx.x;
+        const bool valid = i < end;
+        const uint64_t c = valid ? all_cidx[i] : 0;
+        bool keep = valid;
+        if (valid && len > 0) {
+            int64_t j;
+            bool hit;
+            if (in_lds) {
+                int a0 = 0, a1 = (int)len;
+                while (a0 < a1) {
+                    const int mid = (a0 + a1) >> 1;
+                    if (sl[mid] < c)
+                        a0 = mid + 1;
+                    else
+                        a1 = mid;
+                }
+                hit = a0 < len && sl[a0] == c;
+            } else {
+                j = lower_bound_u64(clear, lo, lo + len, c);
+                hit = j < lo + len && clear[j] == c;
+            }
+            keep = !hit;
+        }
+        if (!WRITE) {
+            cnt += keep ? 1u : 0u;
+            continue;
+        }
+        const uint64_t mk = __ballot(keep);
+        if (lane == 0)
+            wsum[wave] = (uint32_t)__popcll(mk);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < CT / WAVE; ++w) {
+            const uint32_t x = wsum[w];
+            pre += w < wave ? x : 0u;
+            tot += x;
+        }
+        if (keep) {
+            const uint64_t pos = run + pre + (uint32_t)__popcll(mk & lanemask_lt());
+            kept_diam[pos] = all_diam[i];
+            kept_cidx[pos] = c;
+        }
+        run += tot;
+        __syncthreads();
+    }
+    if (!WRITE) {
+        cnt = block_sum<CT>(cnt, wsum);
+        if (threadIdx.x == 0)
+            tile_counts[blockIdx.x] = cnt;
+    }
+}
+
+void launch_clear_count(const uint64_t *all_cidx, int64_t nall, const uint64_t *clear,
+                        int64_t nclear, uint32_t *tile_counts, hipStream_t s)
+{
+    const int64_t tiles = compact_tiles(nall);
+    if (tiles == 0)
+        return;
+    hipLaunchKernelGGL(k_clear_filter<false>, dim3((unsigned)tiles), dim3(CT), 0, s, nullptr,
+                       all_cidx, nall, clear, nclear, tile_counts, nullptr, nullptr, nullptr);
+}
+
+void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64_t nall,
+                          const uint64_t *clear, int64_t nclear, const uint64_t *tile_offsets,
+                          float *kept_diam, uint64_t *kept_cidx, hipStream_t s)
+{
+    const int64_t tiles = compact_tiles(nall);
+    if (tiles == 0)
+        return;
+    hipLaunchKernelGGL(k_clear_filter<true>, dim3((unsigned)tiles), dim3(CT), 0, s, all_diam,
+                       all_cidx, nall, clear, nclear, nullptr, tile_offsets, kept_diam,
+                       kept_cidx);
+}
+
+// Sparse apparent test.  The candidates for sigma's oldest cofacet are the
+// common neighbours of its vertices: the AND of their neighbour bitsets,
+// which leaves out sigma's own vertices.  Layout as in the dense kernel: a
+// wave owns CPR x rounds columns, every lane decodes one, and each round G
+// lanes take one column.  The group scans G words per step from the top
+// (lane g: word top - g); each lane walks its word's candidates downward
+// and stops at its first hit (every d(v_i, x) <= d).  The group's hit is
+// that of its first lane with one: the lanes before it hold higher words
+// and had no candidate that passed.  A column usually ends in its first
+// step, so it reads G words of each of its vertices' bitsets instead of
+// whole rows.
+template <int P, int G>
 __global__ __launch_bounds__(256) void k_apparent_sparse(
     const float *__restrict__ col_diam, const uint64_t *__restrict__ col_cidx, int64_t ncols,
     const float *__restrict__ dsq, int n, const uint64_t *__restrict__ bits, int words,
     const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
-    unsigned long long *__restrict__ scan_count)
+    unsigned long long *__restrict__ scan_count, int rounds)
 {
-    __shared__ int cand_all[256 / WAVE][SP_CAP];
+    constexpr int CPR = WAVE / G;  // columns per round
     const int lane = threadIdx.x & (WAVE - 1);
-    int *cand = cand_all[threadIdx.x / WAVE];
-    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * WAVE;
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int own = CPR * rounds;  // columns owned by a wave (rounds <= G)
+    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * own;
     if (base >= ncols)
         return;  // whole waves leave together
     const Binom B{binom, n + 1};
     const int64_t mycol = base + lane;
-    const bool myvalid = mycol < ncols;
+    const bool myvalid = lane < own && mycol < ncols;
     float myd = 0.0f;
     int myv[P + 1];
 #pragma unroll
@@ -1129,14 +1214,15 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         decode<P>(B, col_cidx[mycol], n, myv);
     }
     uint64_t mytau = NONE;
-    long long examined = 0;
-    const int ncol_wave = (int)((ncols - base) < WAVE ? (ncols - base) : WAVE);
-    for (int r = 0; r < ncol_wave; ++r) {
-        const float d = __shfl(myd, r, WAVE);
+    unsigned long long examined = 0;  // this lane's share of the candidates visited
+    for (int r = 0; r < rounds; ++r) {
+        const int src = r * CPR + grp;
+        const float d = __shfl(myd, src, WAVE);
         int v[P + 1];
 #pragma unroll
         for (int i = 0; i <= P; ++i)
-            v[i] = __shfl(myv[i], r, WAVE);
+            v[i] = __shfl(myv[i], src, WAVE);
+        const bool valid = base + src < ncols;  // uniform in the group
         const float *row[P + 1];
 #pragma unroll
         for (int i = 0; i <= P; ++i)
@@ -1145,79 +1231,65 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
 #pragma unroll
         for (int a = 0; a <= P; ++a)
 #pragma unroll
-            for (int b2 = a + 1; b2 <= P; ++b2)
-                dv[a][b2] = row[a][v[b2]];
-        int w = -1;
+            for (int b = a + 1; b <= P; ++b)
+                dv[a][b] = valid ? row[a][v[b]] : 0.0f;
+        int x = -1;  // this lane's hit in the current step
+        int hit = -1;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = words - 1; top >= 0; top -= G) {
+                const int word = top - g;
+                uint64_t m = 0;
+                if (word >= 0) {
+                    m = ~0ull;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        m &= bits[(int64_t)v[i] * words + word];
+                }
+                unsigned tested = 0;
+                for (uint64_t mm = m; mm;) {
+                    const int b = 63 - __clzll((long long)mm);
+                    const int c = word * 64 + b;
+                    bool ok = true;
+                    float t[P + 1];
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        t[i] = row[i][c];
+                        ok = ok && (t[i] <= d);
+                    }
+                    ++tested;
+                    if (ok) {
+                        x = c;
+#pragma unroll
+                        for (int i = 0; i <= P; ++i)
+                            e[i] = t[i];
+                        break;
+                    }
+                    mm &= ~(1ull << b);
+                }
+                const uint64_t hm = __ballot(x >= 0) & gmask;
+                const int hl = hm ? __ffsll((unsigned long long)hm) - 1 - gbase : G;
+                // candidates visited from the top: every one of the lanes
+                // before the hit lane, the hit lane's down to its hit
+                if (scan_count)
+                    examined += g < hl ? (unsigned)__popcll(m) : (g == hl ? tested : 0u);
+                if (hm) {
+                    hit = gbase + hl;
+                    break;
+                }
+            }
+        }
+        // w and d(v_i, w) from the lane that hit (every lane joins the shuffle)
+        const int w = __shfl(x, hit >= 0 ? hit : lane, WAVE);
         float ew[P + 1];
 #pragma unroll
         for (int i = 0; i <= P; ++i)
-            ew[i] = 0.0f;
-        // candidates examined, from the highest down to the hit (uniform in
-        // the wave): earlier chunks in full, the hit's chunk up to the hit
-        long long seen = 0;
-        for (int top = words - 1; top >= 0 && w < 0; top -= WAVE) {
-            const int word = top - lane;
-            uint64_t m = 0;
-            if (word >= 0) {
-                m = ~0ull;
-#pragma unroll
-                for (int i = 0; i <= P; ++i)
-                    m &= bits[(int64_t)v[i] * words + word];
-            }
-            const int c = __popcll(m);
-            const int inc = wave_inclusive_scan(c);
-            const int pre = inc - c;  // rank of this lane's highest candidate
-            const int total = __shfl(inc, WAVE - 1, WAVE);
-            for (int s0 = 0; s0 < total && w < 0; s0 += SP_CAP) {
-                if (c > 0 && pre < s0 + SP_CAP && pre + c > s0) {
-                    uint64_t mm = m;
-                    int k = pre;
-                    while (mm && k < s0 + SP_CAP) {
-                        const int bpos = 63 - __clzll((long long)mm);
-                        if (k >= s0)
-                            cand[k - s0] = word * 64 + bpos;
-                        ++k;
-                        mm &= ~(1ull << bpos);
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                const int lim = (total - s0) < SP_CAP ? (total - s0) : SP_CAP;
-                for (int b0 = 0; b0 < lim && w < 0; b0 += WAVE) {
-                    const int slot = b0 + lane;
-                    bool ok = false;
-                    int x = 0;
-                    float e[P + 1];
-#pragma unroll
-                    for (int i = 0; i <= P; ++i)
-                        e[i] = 0.0f;
-                    if (slot < lim) {
-                        x = cand[slot];
-                        ok = true;
-#pragma unroll
-                        for (int i = 0; i <= P; ++i) {
-                            e[i] = row[i][x];
-                            ok = ok && (e[i] <= d);
-                        }
-                    }
-                    const uint64_t bal = __ballot(ok);
-                    if (bal) {
-                        const int hl = __ffsll((unsigned long long)bal) - 1;
-                        w = __shfl(x, hl, WAVE);
-#pragma unroll
-                        for (int i = 0; i <= P; ++i)
-                            ew[i] = __shfl(e[i], hl, WAVE);
-                        seen += s0 + b0 + hl + 1;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (w < 0)
-                seen += total;  // the whole chunk was examined without a hit
-        }
+            ew[i] = __shfl(e[i], hit >= 0 ? hit : lane, WAVE);
         uint64_t tau = NONE;
-        if (w >= 0) {
+        if (hit >= 0) {
             bool apparent = true;
 #pragma unroll
             for (int j = 0; j <= P; ++j) {
@@ -1230,9 +1302,9 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
                             continue;
                         fd = fmaxf(fd, ew[a]);
 #pragma unroll
-                        for (int b2 = a + 1; b2 <= P; ++b2)
-                            if (b2 != j)
-                                fd = fmaxf(fd, dv[a][b2]);
+                        for (int b = a + 1; b <= P; ++b)
+                            if (b != j)
+                                fd = fmaxf(fd, dv[a][b]);
                     }
                     if (fd == d)
                         apparent = false;
@@ -1241,12 +1313,17 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
             if (apparent)
                 tau = cofacet_index<P>(B, v, w);
         }
-        examined += seen;
-        if (lane == r)
-            mytau = tau;
+        // the owner of column base + r*CPR + k is lane r*CPR + k; group k's
+        // first lane holds its tau
+        const uint64_t t = shfl_u64(tau, (lane % CPR) * G);
+        if (lane / CPR == r)
+            mytau = t;
     }
-    if (scan_count && lane == 0)
-        atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], (unsigned long long)examined);
+    if (scan_count) {
+        const unsigned long long tot = wave_sum(examined);
+        if (lane == 0)
+            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], tot);
+    }
     if (myvalid)
         tau_out[mycol] = mytau;
 }
@@ -1300,20 +1377,55 @@ __global__ __launch_bounds__(256) void k_lows_sparse(
     }
 }
 
+template <int P, int G>
+static void launch_apparent_sparse_pg(const float *cd, const uint64_t *cc, int64_t ncols,
+                                      const float *dsq, int n, const uint64_t *bits, int words,
+                                      const uint64_t *binom, uint64_t *tau,
+                                      unsigned long long *sc, hipStream_t s)
+{
+    // rounds per wave as in the dense kernel: as many as G allows while the
+    // grid keeps ~4 waves per SIMD
+    constexpr int cpr = WAVE / G;
+    int rounds = 1;
+    while (rounds < G && ncols / ((int64_t)cpr * rounds * 2) >= 4096)
+        rounds *= 2;
+    const int64_t waves = (ncols + (int64_t)cpr * rounds - 1) / ((int64_t)cpr * rounds);
+    dim3 g((unsigned)((waves * WAVE + 255) / 256)), b(256);
+    hipLaunchKernelGGL((k_apparent_sparse<P, G>), g, b, 0, s, cd, cc, ncols, dsq, n, bits, words,
+                       binom, tau, sc, rounds);
+}
+
+template <int P>
+static void launch_apparent_sparse_p(const float *cd, const uint64_t *cc, int64_t ncols,
+                                     const float *dsq, int n, const uint64_t *bits, int words,
+                                     const uint64_t *binom, int group, uint64_t *tau,
+                                     unsigned long long *sc, hipStream_t s)
+{
+    switch (group) {
+    case 4: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    case 16: launch_apparent_sparse_pg<P, 16>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    default: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    }
+}
+
+int sparse_group(int group)
+{
+    return (group == 4 || group == 16) ? group : 8;
+}
+
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                             const float *dsq, int n, int p, const uint64_t *bits, int words,
-                            const uint64_t *binom, uint64_t *tau_out,
+                            const uint64_t *binom, int group, uint64_t *tau_out,
                             unsigned long long *scan_count, hipStream_t s)
 {
     if (ncols <= 0)
         return;
-    const int64_t threads = (ncols + WAVE - 1) / WAVE * WAVE;  // one wave per 64 columns
-    dim3 g((unsigned)((threads + 255) / 256)), b(256);
+    group = sparse_group(group);
     switch (p) {
-    case 1: hipLaunchKernelGGL(k_apparent_sparse<1>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
-    case 2: hipLaunchKernelGGL(k_apparent_sparse<2>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
-    case 3: hipLaunchKernelGGL(k_apparent_sparse<3>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
-    default: hipLaunchKernelGGL(k_apparent_sparse<4>, g, b, 0, s, col_diam, col_cidx, ncols, dsq, n, bits, words, binom, tau_out, scan_count); break;
+    case 1: launch_apparent_sparse_p<1>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
+    case 2: launch_apparent_sparse_p<2>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
+    case 3: launch_apparent_sparse_p<3>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
+    default: launch_apparent_sparse_p<4>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
     }
 }
 

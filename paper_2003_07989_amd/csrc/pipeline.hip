@@ -70,6 +70,7 @@ struct Workspace {
     DevBuf mst, deaths, dedges, ufs;
     DevBuf tcount, toff, scan, tcount2, toff2;
     DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
+    DevBuf xd, xc;                   // sparse path: all simplices <= thr, top dim
     DevBuf bits;                     // sparse path: neighbour bitsets
     DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
     DevBuf cdiam, ccidx, tau;
@@ -119,7 +120,7 @@ size_t workspace_allocated(void *wp)
     const DevBuf *bufs[] = {&w.dsq, &w.rowmax, &w.scal, &w.binom, &w.ekey, &w.eval, &w.ekey2,
                             &w.eval2, &w.mst, &w.deaths, &w.dedges, &w.ufs, &w.tcount, &w.toff,
                             &w.scan, &w.tcount2, &w.toff2, &w.skd[0], &w.skd[1], &w.skc[0],
-                            &w.skc[1], &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
+                            &w.skc[1], &w.xd, &w.xc, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
                             &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
                             &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
                             &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt};
@@ -182,42 +183,49 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
 }
 
 // Sparse enumeration of the p-simplices (p >= 2) from the (p-1)-simplices in
-// ws.skd/skc[cur]: kept columns into ws.cdiam/ccidx, and, when want_all, all
-// p-simplices <= threshold into ws.skd/skc[1-cur] for the next dimension.
-static int enumerate_sparse(Workspace &ws, ExtArgs ea, bool want_all, int cur, hipStream_t s,
+// ws.skd/skc[cur]: every p-simplex <= threshold, in cidx order, into
+// ws.skd/skc[1-cur] when want_all (the next dimension's prefixes), else into
+// ws.xd/xc; then the clearing filter writes the kept columns, still in cidx
+// order, into ws.cdiam/ccidx.
+static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *clear,
+                            int64_t nclear, bool want_all, int cur, hipStream_t s,
                             int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm)
 {
     const int64_t np = ea.npre;
     ALLOC_TRY(ws.tcount, (size_t)(np + 1) * 4);
-    ALLOC_TRY(ws.tcount2, (size_t)(np + 1) * 4);
     ALLOC_TRY(ws.toff, (size_t)(np + 2) * 8);
-    ALLOC_TRY(ws.toff2, (size_t)(np + 2) * 8);
     ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(np) * 8);
     if (tm)
         tm->start();
-    launch_ext_count(ea, ws.tcount2.as<uint32_t>(), ws.tcount.as<uint32_t>(), s);
+    launch_ext_count(ea, ws.tcount.as<uint32_t>(), s);
     launch_exclusive_scan(ws.tcount.as<uint32_t>(), np, ws.toff.as<uint64_t>(),
-                          ws.scan.as<uint64_t>(), s);
-    launch_exclusive_scan(ws.tcount2.as<uint32_t>(), np, ws.toff2.as<uint64_t>(),
                           ws.scan.as<uint64_t>(), s);
     uint64_t *h = ws.h_small.as<uint64_t>();
     HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + np, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h + 1, ws.toff2.as<uint64_t>() + np, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *kept = np ? (int64_t)h[0] : 0;
-    *all = np ? (int64_t)h[1] : 0;
+    const int64_t nall = np ? (int64_t)h[0] : 0;
+    *all = nall;
+    DevBuf &bd = want_all ? ws.skd[1 - cur] : ws.xd;
+    DevBuf &bc = want_all ? ws.skc[1 - cur] : ws.xc;
+    ALLOC_TRY(bd, (size_t)(nall + 1) * 4);
+    ALLOC_TRY(bc, (size_t)(nall + 1) * 8);
+    launch_ext_scatter(ea, ws.toff.as<uint64_t>(), bd.as<float>(), bc.as<uint64_t>(), s);
+    // clearing filter, all -> kept
+    const int64_t tiles = compact_tiles(nall);
+    ALLOC_TRY(ws.tcount2, (size_t)(tiles + 1) * 4);
+    ALLOC_TRY(ws.toff2, (size_t)(tiles + 2) * 8);
+    ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(std::max(np, tiles)) * 8);
+    launch_clear_count(bc.as<uint64_t>(), nall, clear, nclear, ws.tcount2.as<uint32_t>(), s);
+    launch_exclusive_scan(ws.tcount2.as<uint32_t>(), tiles, ws.toff2.as<uint64_t>(),
+                          ws.scan.as<uint64_t>(), s);
+    HIP_TRY(hipMemcpyAsync(h, ws.toff2.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *kept = tiles ? (int64_t)h[0] : 0;
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
-    float *ad = nullptr;
-    uint64_t *ac = nullptr;
-    if (want_all) {
-        ALLOC_TRY(ws.skd[1 - cur], (size_t)(*all + 1) * 4);
-        ALLOC_TRY(ws.skc[1 - cur], (size_t)(*all + 1) * 8);
-        ad = ws.skd[1 - cur].as<float>();
-        ac = ws.skc[1 - cur].as<uint64_t>();
-    }
-    launch_ext_scatter(ea, ws.toff2.as<uint64_t>(), ws.toff.as<uint64_t>(), ad, ac,
-                       ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), s);
+    launch_clear_scatter(bd.as<float>(), bc.as<uint64_t>(), nall, clear, nclear,
+                         ws.toff2.as<uint64_t>(), ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(),
+                         s);
     if (tm)
         tm->stop();
     return RPP_OK;
@@ -254,7 +262,7 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     if (words > 0)
         launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                                ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
-                               ws.binom.as<uint64_t>(), ws.tau.as<uint64_t>(), sc, s);
+                               ws.binom.as<uint64_t>(), group, ws.tau.as<uint64_t>(), sc, s);
     else
         launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                         ws.dsq.as<float>(), n, p, ws.binom.as<uint64_t>(), group,
@@ -613,9 +621,10 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         } else {
             ExtArgs xa{ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
                        ws.binom.as<uint64_t>(), ws.skd[cur].as<float>(),
-                       ws.skc[cur].as<uint64_t>(), nskel, clear_sorted, nclear_sorted};
+                       ws.skc[cur].as<uint64_t>(), nskel};
             int64_t nall = 0;
-            rc = enumerate_sparse(ws, xa, p < maxdim, cur, s, &ncols, &nall, err, &t_enum);
+            rc = enumerate_sparse(ws, xa, clear_sorted, nclear_sorted, p < maxdim, cur, s,
+                                  &ncols, &nall, err, &t_enum);
             ncand = nall;
             nclr = (uint64_t)(nall - ncols);
             if (p < maxdim) {
@@ -741,7 +750,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.n_cleared = (int64_t)nclr;
         D.st.n_simplices = ncand - (int64_t)nthr;
         D.st.n_kept = ncols;
-        D.st.apparent_group = sparse ? 0 : group;  // 0: the sparse kernel
+        // negative: the sparse kernel, with that many lanes per column
+        D.st.apparent_group = sparse ? -sparse_group(group) : group;
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
 
