@@ -16,11 +16,13 @@
 #include <immintrin.h>
 
 #include <algorithm>
+#include <cstring>
 #include <atomic>
 #include <type_traits>
 #include <condition_variable>
 #include <functional>
 #include <memory>
+#include <new>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -93,47 +95,273 @@ template <class K> void select_smallest(K *a, size_t m, size_t c)
     std::sort(a + lo, a + hi);
 }
 
+// AVX-512 (F, VL, BW, VBMI2), checked once at load; the vector routines
+// below are chosen at run time.
+static bool cpu_has_avx512()
+{
+    return __builtin_cpu_supports("avx512f") && __builtin_cpu_supports("avx512vl") &&
+           __builtin_cpu_supports("avx512bw") && __builtin_cpu_supports("avx512vbmi2");
+}
+static const bool HAVE_AVX512 = cpu_has_avx512();
+
+// Index of the smallest of a[0..m) (distinct keys below 2^64 - 1): eight
+// running minima with their indices, then a reduction.
+__attribute__((target("avx512f"))) static size_t argmin_u64_avx512(const uint64_t *a, size_t m)
+{
+    const __m512i ones = _mm512_set1_epi64(-1);
+    __m512i best = ones, bidx = _mm512_setzero_si512();
+    __m512i idx = _mm512_set_epi64(7, 6, 5, 4, 3, 2, 1, 0);
+    const __m512i step = _mm512_set1_epi64(8);
+    size_t i = 0;
+    for (; i + 8 <= m; i += 8) {
+        const __m512i v = _mm512_loadu_si512(a + i);
+        const __mmask8 lt = _mm512_cmplt_epu64_mask(v, best);
+        best = _mm512_mask_mov_epi64(best, lt, v);
+        bidx = _mm512_mask_mov_epi64(bidx, lt, idx);
+        idx = _mm512_add_epi64(idx, step);
+    }
+    if (i < m) {
+        const __mmask8 lm = (__mmask8)((1u << (m - i)) - 1u);
+        const __m512i v = _mm512_mask_loadu_epi64(ones, lm, a + i);
+        const __mmask8 lt = _mm512_mask_cmplt_epu64_mask(lm, v, best);
+        best = _mm512_mask_mov_epi64(best, lt, v);
+        bidx = _mm512_mask_mov_epi64(bidx, lt, idx);
+    }
+    const uint64_t mn = _mm512_reduce_min_epu64(best);
+    const __mmask8 at = _mm512_cmpeq_epu64_mask(best, _mm512_set1_epi64((long long)mn));
+    alignas(64) uint64_t ix[8];
+    _mm512_store_si512(ix, bidx);
+    return (size_t)ix[__builtin_ctz((unsigned)at)];
+}
+
+// Splits a[0..m) (u64 keys) into the keys <= y, moved to the front in
+// order of appearance, and the others behind them; returns the count of the
+// first group.  Eight keys per step: each group is compressed in registers
+// and stored whole -- the low group in place (its write position never
+// passes the read position, so only consumed slots are overwritten), the
+// high group into tmp (m + 8 slots), copied back at the end.
+__attribute__((target("avx512f"))) static size_t partition_le_u64_avx512(uint64_t *a, size_t m,
+                                                                         uint64_t y,
+                                                                         uint64_t *tmp)
+{
+    const __m512i vy = _mm512_set1_epi64((long long)y);
+    size_t nl = 0, ng = 0, i = 0;
+    for (; i + 8 <= m; i += 8) {
+        const __m512i v = _mm512_loadu_si512(a + i);
+        const __mmask8 le = _mm512_cmple_epu64_mask(v, vy);
+        _mm512_storeu_si512(a + nl, _mm512_maskz_compress_epi64(le, v));
+        _mm512_storeu_si512(tmp + ng, _mm512_maskz_compress_epi64((__mmask8)~le, v));
+        const size_t k = (size_t)__builtin_popcount((unsigned)le);
+        nl += k;
+        ng += 8 - k;
+    }
+    for (; i < m; ++i) {
+        const uint64_t x = a[i];
+        if (x <= y)
+            a[nl++] = x;
+        else
+            tmp[ng++] = x;
+    }
+    memcpy(a + nl, tmp, ng * sizeof(uint64_t));
+    return nl;
+}
+
+// select_smallest for u64 keys with the vector partition: the pivot is the
+// sample key nearest the target rank among 15 spread over the range, so a
+// pass usually lands close to c and few passes follow.
+static void select_smallest_u64_avx512(uint64_t *a, size_t m, size_t c)
+{
+    thread_local std::vector<uint64_t> tmp;
+    if (tmp.size() < m + 8)
+        tmp.resize(m + 8);
+    size_t lo = 0, hi = m;
+    while (hi - lo > 48) {
+        const size_t len = hi - lo;
+        uint64_t smp[15];
+        for (int k = 0; k < 15; ++k)
+            smp[k] = a[lo + (len * (2 * k + 1)) / 30];
+        std::sort(smp, smp + 15);
+        size_t q = ((c - lo) * 15) / len;
+        q = q > 14 ? 14 : q;
+        const uint64_t y = smp[q];
+        size_t j = lo + partition_le_u64_avx512(a + lo, len, y, tmp.data());
+        if (j == hi)  // y is the largest key of the range: set it apart
+            j = lo + partition_le_u64_avx512(a + lo, len, y - 1, tmp.data());
+        if (c < j)
+            hi = j;
+        else if (c > j)
+            lo = j;
+        else
+            return;
+    }
+    std::sort(a + lo, a + hi);
+}
+
+// Index of the smallest of a[0..m), m >= 1.
+template <class K> static inline size_t argmin_keys(const K *a, size_t m)
+{
+    if (std::is_same<K, uint64_t>::value && HAVE_AVX512)
+        return argmin_u64_avx512(reinterpret_cast<const uint64_t *>(a), m);
+    size_t b = 0;
+    K best = a[0];
+    for (size_t i = 1; i < m; ++i) {
+        const K x = a[i];
+        const bool lt = x < best;
+        best = lt ? x : best;
+        b = lt ? i : b;
+    }
+    return b;
+}
+
+// Stream storage.  Streams are bump-allocated from blocks that a reduction
+// hands back to a process-wide pool when it ends, so a warm process neither
+// calls malloc per stream nor writes to fresh pages: the first touch of a
+// fresh page costs more than computing the coboundary written to it.
+class BlockPool {
+public:
+    static constexpr size_t BLOCK = (size_t)4 << 20;     // bytes
+    static constexpr size_t KEEP = (size_t)1 << 30;      // pooled bytes kept at most
+    static BlockPool &get()
+    {
+        static BlockPool pool;
+        return pool;
+    }
+    char *take()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!free_.empty()) {
+                char *b = free_.back();
+                free_.pop_back();
+                return b;
+            }
+        }
+        return static_cast<char *>(::operator new(BLOCK, std::align_val_t(64)));
+    }
+    void give(char *b)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if ((free_.size() + 1) * BLOCK <= KEEP) {
+                free_.push_back(b);
+                return;
+            }
+        }
+        ::operator delete(b, std::align_val_t(64));
+    }
+
+private:
+    BlockPool() = default;
+    ~BlockPool()
+    {
+        for (char *b : free_)
+            ::operator delete(b, std::align_val_t(64));
+    }
+    std::mutex mu_;
+    std::vector<char *> free_;
+};
+
+// Blocks of a reduction that are in use; returned to the pool together.
+struct BlockSink {
+    std::mutex mu;
+    std::vector<std::pair<char *, size_t>> blocks;  // size BLOCK: pooled
+    ~BlockSink()
+    {
+        for (auto &b : blocks) {
+            if (b.second == BlockPool::BLOCK)
+                BlockPool::get().give(b.first);
+            else
+                ::operator delete(b.first, std::align_val_t(64));
+        }
+    }
+};
+
+// A bump allocator for one thread; its blocks go to the sink when it ends
+// (the streams written into them live as long as the reduction).
+class Arena {
+public:
+    explicit Arena(BlockSink *sink) : sink_(sink) {}
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    ~Arena()
+    {
+        if (mine_.empty())
+            return;
+        std::lock_guard<std::mutex> lk(sink_->mu);
+        sink_->blocks.insert(sink_->blocks.end(), mine_.begin(), mine_.end());
+    }
+    // Room for `count` keys; commit() takes what was used of it.
+    template <class K> K *reserve(size_t count)
+    {
+        const size_t bytes = (count * sizeof(K) + 63) & ~(size_t)63;
+        if (used_ + bytes > cap_) {
+            if (bytes > BlockPool::BLOCK) {
+                char *b = static_cast<char *>(::operator new(bytes, std::align_val_t(64)));
+                mine_.push_back({b, bytes});
+                cur_ = b;
+                cap_ = bytes;
+            } else {
+                cur_ = BlockPool::get().take();
+                mine_.push_back({cur_, BlockPool::BLOCK});
+                cap_ = BlockPool::BLOCK;
+            }
+            used_ = 0;
+        }
+        return reinterpret_cast<K *>(cur_ + used_);
+    }
+    template <class K> void commit(size_t count)
+    {
+        used_ += (count * sizeof(K) + 63) & ~(size_t)63;
+    }
+
+private:
+    BlockSink *sink_;
+    std::vector<std::pair<char *, size_t>> mine_;
+    char *cur_ = nullptr;
+    size_t used_ = 0, cap_ = 0;
+};
+
 // One added coboundary, consumed oldest-first.  Only a sorted prefix is
 // kept: the oldest `chunk` remaining keys are selected (linear on average)
 // and sorted; when they run out the next, twice as large, chunk is
 // selected.  A column's low usually lies a few dozen entries into each
 // stream, so most keys are never ordered, and pops read memory in order.
-// Allocator whose construct() default-initialises: resizing a stream's
-// storage before the coboundary is written into it does not zero it.
-template <class T> struct NoInit : std::allocator<T> {
-    template <class U> struct rebind {
-        using other = NoInit<U>;
-    };
-    NoInit() = default;
-    template <class U> NoInit(const NoInit<U> &) noexcept {}
-    template <class U> void construct(U *p) noexcept { ::new ((void *)p) U; }
-    template <class U, class... A> void construct(U *p, A &&...a)
-    {
-        ::new ((void *)p) U(std::forward<A>(a)...);
-    }
-};
-template <class K> using KeyVec = std::vector<K, NoInit<K>>;
-
 template <class K> struct Stream {
-    KeyVec<K> e;
-    uint32_t pos = 0, sorted = 0, chunk = 32;
-    bool empty() const { return pos >= e.size(); }
+    static constexpr int SINGLES = 8;  // keys taken one at a time before chunks
+    K *e = nullptr;  // arena storage
+    uint32_t len = 0, pos = 0, sorted = 0, chunk = 32;
+    int singles = 0;
+    bool empty() const { return pos >= len; }
     K front() const { return e[pos]; }
     void prepare()
     {
         pos = sorted = 0;
+        singles = 0;
         chunk = 32;
         refill();
     }
     void refill()
     {
-        const size_t rem = e.size() - pos;
+        const size_t rem = len - pos;
         if (rem == 0)
             return;
+        if (singles < SINGLES && rem > 16) {
+            // the next key alone, by a scan for the minimum: most streams
+            // are consumed only a few keys deep
+            const size_t j = pos + argmin_keys(e + pos, rem);
+            std::swap(e[pos], e[j]);
+            sorted = pos + 1;
+            ++singles;
+            return;
+        }
         const size_t c = std::min<size_t>(rem, chunk);
-        if (c < rem)
-            select_smallest(e.data() + pos, rem, c);
-        std::sort(e.begin() + pos, e.begin() + pos + c);
+        if (c < rem) {
+            if (std::is_same<K, uint64_t>::value && HAVE_AVX512)
+                select_smallest_u64_avx512(reinterpret_cast<uint64_t *>(e + pos), rem, c);
+            else
+                select_smallest(e + pos, rem, c);
+        }
+        std::sort(e + pos, e + pos + c);
         sorted = pos + (uint32_t)c;
         chunk = chunk < (1u << 30) ? chunk * 2 : chunk;
     }
@@ -150,41 +378,38 @@ template <class K> struct Stream {
 // ever ordered, which is what finding the low needs.
 template <class K> class Column {
 public:
-    // Storage for the next coboundary: fill it, then commit().
-    KeyVec<K> &next_stream()
+    // Adds the coboundary in e[0..len) (arena storage) as a new stream.
+    void push_stream(K *e, size_t len)
     {
-        if (nstreams == streams.size())
-            streams.emplace_back();
-        KeyVec<K> &v = streams[nstreams].e;
-        v.clear();
-        return v;
-    }
-    void commit()
-    {
-        Stream<K> &st = streams[nstreams];
-        if (st.e.empty())
+        if (len == 0)
             return;
+        streams.emplace_back();
+        Stream<K> &st = streams.back();
+        st.e = e;
+        st.len = (uint32_t)len;
         st.prepare();
-        top_push(st.front(), (uint32_t)nstreams);
-        ++nstreams;
+        top_push(st.front(), (uint32_t)(streams.size() - 1));
     }
     // Add another column's current contents: its streams hold exactly its
-    // Z/2 sum (cancelled pairs were removed together).
-    void add(const Column &o)
+    // Z/2 sum (cancelled pairs were removed together).  The remaining keys
+    // are copied, since both columns reorder their streams as they go.
+    void add(const Column &o, Arena &arena)
     {
-        for (size_t k = 0; k < o.nstreams; ++k) {
-            const Stream<K> &src = o.streams[k];
+        for (const Stream<K> &src : o.streams) {
             if (src.empty())
                 continue;
-            if (nstreams == streams.size())
-                streams.emplace_back();
-            Stream<K> &dst = streams[nstreams];
-            dst.e.assign(src.e.begin() + src.pos, src.e.end());
+            const size_t rem = src.len - src.pos;
+            K *e = arena.reserve<K>(rem);
+            memcpy(e, src.e + src.pos, rem * sizeof(K));
+            arena.commit<K>(rem);
+            streams.emplace_back();
+            Stream<K> &dst = streams.back();
+            dst.e = e;
+            dst.len = (uint32_t)rem;
             dst.pos = 0;
             dst.sorted = src.sorted - src.pos;
             dst.chunk = src.chunk;
-            top_push(dst.front(), (uint32_t)nstreams);
-            ++nstreams;
+            top_push(dst.front(), (uint32_t)(streams.size() - 1));
         }
     }
     // Low of the sum over Z/2: keys present in an even number of streams
@@ -275,7 +500,6 @@ private:
         sift_down(0);
     }
     std::vector<Stream<K>> streams;
-    size_t nstreams = 0;
     std::vector<K> hk;
     std::vector<uint32_t> hs;
 };
@@ -283,14 +507,6 @@ private:
 // ---------------------------------------------------------------------------
 // AVX-512 variants (chosen at run time when the CPU has F, VL, BW and VBMI2)
 // ---------------------------------------------------------------------------
-static bool cpu_has_avx512()
-{
-    static const bool ok = __builtin_cpu_supports("avx512f") &&
-                           __builtin_cpu_supports("avx512vl") &&
-                           __builtin_cpu_supports("avx512bw") &&
-                           __builtin_cpu_supports("avx512vbmi2");
-    return ok;
-}
 
 // Dense coboundary with 32-bit cofacet indices (u64 keys): 16 candidate
 // vertices per step -- row maxima, the threshold test, the packed keys --
@@ -347,7 +563,8 @@ cob_dense_u64_avx512(const float *const *rows, int nv, const int *v, uint64_t si
 struct Ctx {
     const ResidualProblem &P;
     int n, p;
-    explicit Ctx(const ResidualProblem &pp) : P(pp), n(pp.n), p(pp.p) {}
+    mutable Arena arena;  // this thread's stream storage
+    Ctx(const ResidualProblem &pp, BlockSink *sink) : P(pp), n(pp.n), p(pp.p), arena(sink) {}
 
     uint64_t C(int v, int k) const { return P.binom[(int64_t)k * (n + 1) + v]; }
     float D(int a, int b) const { return P.dsq[(int64_t)a * n + b]; }
@@ -395,62 +612,91 @@ struct Ctx {
     // Adds sigma's coboundary to col as a new stream.
     template <class K> void add_coboundary(Column<K> &col, uint64_t sigma, float d) const
     {
-        coboundary(sigma, d, col.next_stream());
-        col.commit();
+        K *e;
+        const size_t len = coboundary<K>(sigma, d, e);
+        col.push_stream(e, len);
     }
 
     // Every cofacet of sigma with diameter <= threshold, appended to out as
     // packed keys.
-    template <class K> void coboundary(uint64_t sigma, float d, KeyVec<K> &out) const
+    // Writes sigma's coboundary into this thread's arena; returns its length.
+    template <class K> size_t coboundary(uint64_t sigma, float d, K *&out) const
     {
         int v[8];
         decode(sigma, p, v);
         if (P.bits) {
-            // common neighbours only: every new edge is within the threshold;
-            // count them first so the stream is sized exactly
+            // common neighbours only: every new edge is within the threshold.
+            // w runs upward; with sigma's vertices ascending u_0 < ... < u_p
+            // and k of them below w, cidx(sigma + {w}) = base[k] + C(w, k+1),
+            // where base[k] = sum_{i<k} C(u_i, i+1) + sum_{i>=k} C(u_i, i+2).
+            const int nv = p + 1;
+            int u[8];
+            for (int i = 0; i < nv; ++i)
+                u[i] = v[p - i];
+            uint64_t base[9];
+            for (int k = 0; k <= nv; ++k) {
+                uint64_t b = 0;
+                for (int i = 0; i < nv; ++i)
+                    b += i < k ? C(u[i], i + 1) : C(u[i], i + 2);
+                base[k] = b;
+            }
+            const float *rows[8];
+            for (int i = 0; i < nv; ++i)
+                rows[i] = P.dsq + (int64_t)v[i] * n;
+            const uint64_t *brow[8];  // C(., k+1) for each gap k
+            for (int k = 0; k <= nv; ++k)
+                brow[k] = P.binom + (int64_t)(k + 1) * (n + 1);
+            const uint64_t *bv[8];
+            for (int i = 0; i < nv; ++i)
+                bv[i] = P.bits + (int64_t)v[i] * P.words;
+            // count first so the stream is sized exactly
             size_t cnt = 0;
-            for (int k = 0; k < P.words; ++k) {
-                uint64_t m = ~0ull;
-                for (int i = 0; i <= p; ++i)
-                    m &= P.bits[(int64_t)v[i] * P.words + k];
+            for (int wd = 0; wd < P.words; ++wd) {
+                uint64_t m = bv[0][wd];
+                for (int i = 1; i < nv; ++i)
+                    m &= bv[i][wd];
                 cnt += (size_t)__builtin_popcountll(m);
             }
-            out.resize(cnt);
-            K *o = out.data();
-            for (int k = 0; k < P.words; ++k) {
-                uint64_t m = ~0ull;
-                for (int i = 0; i <= p; ++i)
-                    m &= P.bits[(int64_t)v[i] * P.words + k];
+            out = arena.reserve<K>(cnt);
+            arena.commit<K>(cnt);
+            K *o = out;
+            int k = 0;  // vertices of sigma below w
+            for (int wd = 0; wd < P.words; ++wd) {
+                uint64_t m = bv[0][wd];
+                for (int i = 1; i < nv; ++i)
+                    m &= bv[i][wd];
                 for (; m; m &= m - 1) {
-                    const int w = k * 64 + __builtin_ctzll(m);
+                    const int w = wd * 64 + __builtin_ctzll(m);
+                    while (k < nv && u[k] < w)
+                        ++k;
                     float nd = d;
-                    for (int i = 0; i <= p; ++i) {
-                        const float e = D(v[i], w);
+                    for (int i = 0; i < nv; ++i) {
+                        const float e = rows[i][w];
                         nd = e > nd ? e : nd;
                     }
-                    *o++ = pack<K>(nd, insert_index(v, w));
+                    *o++ = pack<K>(nd, base[k] + brow[k][w]);
                 }
             }
-            return;
+            return cnt;
         }
         const float *rows[8];
         for (int i = 0; i <= p; ++i)
             rows[i] = P.dsq + (int64_t)v[i] * n;
-        out.resize((size_t)n + 16);
+        out = arena.reserve<K>((size_t)n + 16);  // 16 slots of slack for vector stores
         size_t cnt;
         if (std::is_same<K, uint64_t>::value && cpu_has_avx512()) {
             cnt = cob_dense_u64_avx512(rows, p + 1, v, sigma, d, P.thr, P.binom, n,
-                                       reinterpret_cast<uint64_t *>(out.data()));
-            out.resize(cnt);
-            return;
+                                       reinterpret_cast<uint64_t *>(out));
+        } else {
+            switch (p) {
+            case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out); break;
+            case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out); break;
+            case 3: cnt = cob_dense<K, 4>(rows, v, sigma, d, out); break;
+            default: cnt = cob_dense<K, 0>(rows, v, sigma, d, out); break;
+            }
         }
-        switch (p) {
-        case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out.data()); break;
-        case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out.data()); break;
-        case 3: cnt = cob_dense<K, 4>(rows, v, sigma, d, out.data()); break;
-        default: cnt = cob_dense<K, 0>(rows, v, sigma, d, out.data()); break;
-        }
-        out.resize(cnt);
+        arena.commit<K>(cnt);
+        return cnt;
     }
 
     // Dense coboundary: cidx of sigma + {w} = above + C(w, j+1) + below,
@@ -733,7 +979,7 @@ private:
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
         const int64_t budget = P.spec_budget;
         auto phase_a = [&](int) {
-            Ctx X(P);
+            Ctx X(P, &sink);
             int64_t looks = 0;
             while (true) {
                 const int64_t j0 = next.fetch_add(chunk);
@@ -894,7 +1140,7 @@ private:
                     ++lh;
                     const int64_t k = f->second;
                     if (reduced[k])
-                        col->add(*reduced[k]);
+                        col->add(*reduced[k], Xc.arena);
                     else
                         Xc.add_coboundary(*col, R.sigma[k], R.birth[k]);
                 } else {
@@ -916,7 +1162,7 @@ private:
             look_app_b += la;
         };
 
-        Ctx X(P);
+        Ctx X(P, &sink);
         int64_t frontier = 0;
         std::vector<int64_t> round;
         while (frontier < ncols) {
@@ -932,7 +1178,7 @@ private:
             } else {
                 std::atomic<int64_t> nx{0};
                 pool.run([&](int) {
-                    Ctx Xw(P);
+                    Ctx Xw(P, &sink);
                     for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size(); i = nx.fetch_add(1))
                         advance(Xw, round[i]);
                 });
@@ -947,6 +1193,7 @@ private:
         R.lookups_apparent += look_app_b.load();
     }
 
+    BlockSink sink;  // stream storage of every column below; freed last
     const ResidualProblem P;
     const int64_t ncols;
     std::vector<Entry> spec_low;
