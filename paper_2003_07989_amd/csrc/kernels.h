@@ -158,7 +158,7 @@ void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64
                           float *kept_diam, uint64_t *kept_cidx, hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
 // neighbours of the column's vertices, scanned from the top, `group` words
-// per step by as many lanes (4, 8 or 16; anything else means 8).
+// per step by as many lanes (4, 8 or 16; anything else means 4).
 int sparse_group(int group);
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                             const float *dsq, int n, int p, const uint64_t *bits, int words,

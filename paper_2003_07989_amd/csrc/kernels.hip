@@ -1402,15 +1402,15 @@ static void launch_apparent_sparse_p(const float *cd, const uint64_t *cc, int64_
                                      unsigned long long *sc, hipStream_t s)
 {
     switch (group) {
-    case 4: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
     case 16: launch_apparent_sparse_pg<P, 16>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
-    default: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    case 8: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    default: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
     }
 }
 
 int sparse_group(int group)
 {
-    return (group == 4 || group == 16) ? group : 8;
+    return (group == 8 || group == 16) ? group : 4;
 }
 
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -299,6 +300,9 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
 // to the exact phase (which then drops it, if the previous dimension's host
 // pivots clear it).
 constexpr int64_t SPEC_BUDGET = 16;
+// Additions a column may make in the exact phase while the previous
+// dimension's host pivots (the columns to drop) are still unknown.
+constexpr int64_t OPEN_CAP = 64;
 
 static int default_group(int p)
 {
@@ -525,6 +529,10 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         ResidualResult RR;
         std::thread th;
         bool failed = false;
+        bool collected = false;     // results moved into the output
+        std::mutex mu;              // guards done
+        std::condition_variable cv;
+        bool done = false;          // exact phase over (RR final)
         float ms_spec = 0.0f, ms_exact = 0.0f;
         double t_exact_start = 0.0, t_exact_end = 0.0;  // ms since the call began
         int64_t napp = 0;
@@ -550,6 +558,9 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     const bool want_pairs_all = (a.flags & RPP_WANT_PAIRS) != 0;
     auto finish_dim = [&](int q) -> int {
         HostDim &H = hd[(size_t)q];
+        if (H.collected)
+            return RPP_OK;
+        H.collected = true;
         if (H.th.joinable())
             H.th.join();
         if (H.failed) {
@@ -691,6 +702,12 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                         ws.lowc.as<uint64_t>(), ws.lowd.as<float>(), s);
         // device -> host handoff (the set of this dimension's parity)
         const int hb = p & 1;
+        // dimension p-2 used these host buffers: its exact phase must be over
+        if (p >= 3) {
+            int rc2 = finish_dim(p - 2);
+            if (rc2)
+                return rc2;
+        }
         ALLOC_TRY(ws.h_na_key[hb], (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_na_cidx[hb], (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_low[hb], (size_t)(nna + 1) * 8);
@@ -794,41 +811,69 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                 fprintf(stderr, "rpp trace: dim %d hand-off at %.3f ms, speculative done at %.3f ms\n",
                         p, since(a0), since(a1));
         }
-        // the previous dimension's exact phase must be done: its pivots are
-        // this dimension's dropped columns
-        if (p > 1) {
-            int rc2 = finish_dim(p - 1);
-            if (rc2)
-                return rc2;
-            const std::vector<uint64_t> &prev = hd[p - 1].RR.tau;
-            H.drop.assign((size_t)nna, 0);
-            if (!prev.empty() && nna) {
-                std::vector<uint64_t> sp(prev);
-                std::sort(sp.begin(), sp.end());
-                const uint64_t *cc = H.P.col_cidx;
-                for (int64_t j = 0; j < nna; ++j)
-                    if (std::binary_search(sp.begin(), sp.end(), cc[j])) {
-                        H.drop[(size_t)j] = 1;
-                        ++H.ndrop;
+        // The exact phase starts at once.  The previous dimension's host
+        // pivots -- this dimension's dropped columns -- are still being found
+        // on its own thread; the gate waits for them when they are needed.
+        HostDim *prevp = p > 1 ? &hd[(size_t)p - 1] : nullptr;
+        H.th = std::thread([&H, prevp, &since] {
+            struct PrevGate final : DropGate {
+                HostDim &prev, &cur;
+                bool have = false;
+                PrevGate(HostDim &pr, HostDim &c) : prev(pr), cur(c) {}
+                bool ready() override
+                {
+                    std::lock_guard<std::mutex> lk(prev.mu);
+                    return prev.done;
+                }
+                const uint8_t *wait() override
+                {
+                    if (!have) {
+                        {
+                            std::unique_lock<std::mutex> lk(prev.mu);
+                            prev.cv.wait(lk, [&] { return prev.done; });
+                        }
+                        have = true;
+                        const std::vector<uint64_t> &tau = prev.RR.tau;
+                        const int64_t m = cur.P.ncols;
+                        if (!prev.failed && !tau.empty() && m) {
+                            cur.drop.assign((size_t)m, 0);
+                            std::vector<uint64_t> sp(tau);
+                            std::sort(sp.begin(), sp.end());
+                            for (int64_t j = 0; j < m; ++j)
+                                if (std::binary_search(sp.begin(), sp.end(), cur.P.col_cidx[j])) {
+                                    cur.drop[(size_t)j] = 1;
+                                    ++cur.ndrop;
+                                }
+                        }
                     }
-            }
-        }
-        H.th = std::thread([&H, &since] {
+                    return cur.drop.empty() ? nullptr : cur.drop.data();
+                }
+            };
             auto b0 = std::chrono::steady_clock::now();
             H.t_exact_start = since(b0);
             try {
-                H.spec->finish(H.drop.empty() ? nullptr : H.drop.data(), H.RR);
-            } catch (const std::bad_alloc &) {
+                if (prevp) {
+                    PrevGate gate(*prevp, H);
+                    H.spec->finish_gated(gate, OPEN_CAP, H.RR);
+                } else {
+                    H.spec->finish(nullptr, H.RR);
+                }
+            } catch (const std::exception &) {
                 H.failed = true;
             }
             H.spec.reset();
             const auto b1 = std::chrono::steady_clock::now();
             H.ms_exact = std::chrono::duration<float, std::milli>(b1 - b0).count();
             H.t_exact_end = since(b1);
+            {
+                std::lock_guard<std::mutex> lk(H.mu);
+                H.done = true;
+            }
+            H.cv.notify_all();
         });
     }
-    if (maxdim >= 1) {
-        int rc2 = finish_dim(maxdim);
+    for (int q = 1; q <= maxdim; ++q) {
+        int rc2 = finish_dim(q);
         if (rc2)
             return rc2;
     }

@@ -14,6 +14,10 @@
 #include "residual.h"
 
 #include <immintrin.h>
+#include <sched.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <cstring>
@@ -23,6 +27,7 @@
 #include <functional>
 #include <memory>
 #include <new>
+#include <stdexcept>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -856,13 +861,46 @@ private:
         const std::function<void(int)> *fn = nullptr;
         int active = 0;  // threads inside fn, the caller excluded
     };
+    // Threads: the CPUs this process may use (affinity mask, and the
+    // cgroup CPU quota when one is set), less one for the thread that
+    // enqueues GPU work while the pool is busy, at most 16.
+    static int usable_cpus()
+    {
+        int n = (int)std::thread::hardware_concurrency();
+        cpu_set_t set;
+        if (sched_getaffinity(0, sizeof(set), &set) == 0)
+            n = std::min(n > 0 ? n : CPU_COUNT(&set), CPU_COUNT(&set));
+        if (FILE *f = fopen("/sys/fs/cgroup/cpu.max", "r")) {
+            char quota[32] = {0};
+            long period = 0;
+            if (fscanf(f, "%31s %ld", quota, &period) == 2 && strcmp(quota, "max") != 0 &&
+                period > 0) {
+                const long q = atol(quota);
+                if (q > 0)
+                    n = std::min(n, (int)std::max(1L, q / period));
+            }
+            fclose(f);
+        } else if (FILE *fq = fopen("/sys/fs/cgroup/cpu/cpu.cfs_quota_us", "r")) {
+            long q = -1, period = 0;
+            if (fscanf(fq, "%ld", &q) != 1)
+                q = -1;
+            fclose(fq);
+            if (FILE *fp = fopen("/sys/fs/cgroup/cpu/cpu.cfs_period_us", "r")) {
+                if (fscanf(fp, "%ld", &period) != 1)
+                    period = 0;
+                fclose(fp);
+            }
+            if (q > 0 && period > 0)
+                n = std::min(n, (int)std::max(1L, q / period));
+        }
+        return std::max(1, n);
+    }
     Pool()
     {
-        unsigned hw = std::thread::hardware_concurrency();
-        int n = (int)(hw ? hw : 1);
+        int n = std::min(usable_cpus() - 1, 16);
         if (const char *e = getenv("RPP_HOST_THREADS"))
             n = atoi(e);
-        n = std::max(1, std::min(n, 16));
+        n = std::max(1, std::min(n, 64));
         for (int t = 1; t < n; ++t)
             workers_.emplace_back([this, t] { loop(t); });
     }
@@ -947,8 +985,19 @@ public:
     }
     void finish(const uint8_t *drop, ResidualResult &R) override
     {
+        struct Known final : DropGate {
+            const uint8_t *d;
+            bool ready() override { return true; }
+            const uint8_t *wait() override { return d; }
+        } gate;
+        gate.d = drop;
         R.lookups_apparent = looks_a;
-        phase_b(drop, R);
+        phase_b(gate, 0, R);
+    }
+    void finish_gated(DropGate &gate, int64_t cap, ResidualResult &R) override
+    {
+        R.lookups_apparent = looks_a;
+        phase_b(gate, cap, R);
     }
 
 private:
@@ -1034,7 +1083,7 @@ private:
         looks_a = look_app.load();
     }
 
-    void phase_b(const uint8_t *drop, ResidualResult &R)
+    void phase_b(DropGate &gate, int64_t cap, ResidualResult &R)
     {
         // ---- phase B ----------------------------------------------------------
         // Columns become final in column order (the frontier).  A column is
@@ -1051,13 +1100,17 @@ private:
         // step (R_j += R_k) instead of replaying k's reduction from the original
         // column.  The copied entries are a subset of what the replay would
         // regenerate, so this is never more work.
+        //
+        // Columns that clearing removes (pivots of the previous dimension, not
+        // known when the speculative phase ran) take no part: no pair, no
+        // class.  Until the gate says which they are, every column is reduced
+        // as usual (a dropped one would end at zero), zero columns wait to be
+        // classified, and a column past `cap` additions parks until then.
         Pool &pool = Pool::get();
-        // columns that clearing removes (pivots of the previous dimension, not
-        // known when the speculative phase ran) take no part: no pair, no class
-        if (drop)
-            for (int64_t j = 0; j < ncols; ++j)
-                if (drop[j])
-                    spec_nz[j] = 0;
+        const uint8_t *drop = nullptr;
+        bool known = false;
+        std::vector<uint8_t> parked(ncols, 0);
+        std::vector<int64_t> parked_list, zero_open;
         std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
         pivots.reserve((size_t)ncols * 2 + 16);
         std::vector<std::unique_ptr<Column<K>>> reduced;  // by index in R.sigma
@@ -1087,17 +1140,25 @@ private:
             }
         }
 
+        auto essential = [&](int64_t j) {
+            R.additions += spec_adds[j];
+            R.ess_sigma.push_back(P.col_cidx[j]);
+            R.ess_birth.push_back(diam_of_key(j));
+        };
         auto finalize = [&](int64_t j) {
             if (drop && drop[j])
                 return;
             const uint64_t sigma = P.col_cidx[j];
             const float d = diam_of_key(j);
-            R.additions += spec_adds[j];
             if (!spec_nz[j]) {
-                R.ess_sigma.push_back(sigma);
-                R.ess_birth.push_back(d);
+                if (known)
+                    essential(j);
+                else
+                    zero_open.push_back(j);  // an essential class unless dropped
                 return;
             }
+            // nonzero: not a dropped column, whatever the gate will say
+            R.additions += spec_adds[j];
             const Entry lo = spec_low[j];
             if (spec_adds[j] == 0)
                 ++R.emergent;
@@ -1120,10 +1181,38 @@ private:
             whead.erase(it);
         };
 
+        // The dropped columns are known: drop them, classify the open zero
+        // columns, and resume the parked ones.
+        auto learn = [&]() {
+            drop = gate.wait();
+            known = true;
+            if (drop)
+                for (int64_t j = 0; j < ncols; ++j)
+                    if (drop[j])
+                        spec_nz[j] = 0;  // never woken, never finalized
+            for (int64_t j : zero_open)
+                if (!(drop && drop[j]))
+                    essential(j);
+            zero_open.clear();
+            for (int64_t j : parked_list) {
+                parked[j] = 0;
+                if (!(drop && drop[j])) {
+                    pending[j] = 1;
+                    work.push_back(j);
+                }
+            }
+            parked_list.clear();
+        };
+        if (gate.ready())
+            learn();
+
         // Advance column j from a low that is a final pivot (read-only use of
         // the pivot store and the finished columns; safe to run concurrently).
         std::atomic<int64_t> look_hash{0}, look_app_b{0};
+        bool open = !known;  // read by advance(); set before each round
         auto advance = [&](Ctx &Xc, int64_t j) {
+            if (drop && drop[j])
+                return;  // dropped after it was queued
             std::unique_ptr<Column<K>> &col = state[j];
             if (!col) {
                 col.reset(new Column<K>());
@@ -1133,6 +1222,10 @@ private:
             int64_t adds = 0, lh = 0, la = 0;
             bool nz = true;
             while (true) {
+                if (open && cap > 0 && spec_adds[j] + adds >= cap) {
+                    parked[j] = 1;  // resumes once the dropped columns are known
+                    break;
+                }
                 // the owner of the low: a final host column, else an
                 // apparent column, else the column stops here
                 auto f = pivots.find(lo.cidx);
@@ -1166,10 +1259,20 @@ private:
         int64_t frontier = 0;
         std::vector<int64_t> round;
         while (frontier < ncols) {
-            while (frontier < ncols && !pending[frontier])
+            if (!known && gate.ready())
+                learn();
+            while (frontier < ncols && !pending[frontier] && !parked[frontier])
                 finalize(frontier++);
             if (frontier == ncols)
                 break;
+            if (work.empty()) {
+                // the frontier waits on a parked column: only the gate helps
+                if (known)
+                    throw std::logic_error("residual reduction: frontier stalled");
+                learn();
+                continue;
+            }
+            open = !known;
             round.swap(work);
             work.clear();
             if (round.size() == 1 || !P.parallel) {
@@ -1185,10 +1288,14 @@ private:
             }
             for (int64_t j : round) {
                 pending[j] = 0;
-                if (spec_nz[j])
+                if (parked[j])
+                    parked_list.push_back(j);
+                else if (spec_nz[j] && !(drop && drop[j]))
                     wait_on(j);
             }
         }
+        if (!known)
+            learn();  // classifies the zero columns still open
         R.lookups_hash += look_hash.load();
         R.lookups_apparent += look_app_b.load();
     }

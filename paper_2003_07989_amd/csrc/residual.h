@@ -75,10 +75,26 @@ void residual_reduce(const ResidualProblem &P, ResidualResult &R);
 // exact reduction, skipping every column j with drop[j] != 0 (columns the
 // clearing lemma removes, which would reduce to zero: no pair, no essential
 // class).  The problem's arrays must stay valid until finish() returns.
+// When the dropped columns of finish() become known.  ready() must not
+// block; wait() blocks until they are known and returns them (drop[j] != 0:
+// column j is dropped; nullptr: none is).
+struct DropGate {
+    virtual ~DropGate() = default;
+    virtual bool ready() = 0;
+    virtual const uint8_t *wait() = 0;
+};
 class ResidualSpec {
 public:
     virtual ~ResidualSpec() = default;
     virtual void finish(const uint8_t *drop, ResidualResult &R) = 0;
+    // The same, started before the dropped columns are known.  A column
+    // whose fate is open is still reduced -- a dropped column reduces to
+    // zero (the clearing lemma), so a column that ends nonzero is not
+    // dropped and its pair is final, and a zero column waits for the gate to
+    // tell an essential class from a dropped column -- but one that needs
+    // more than `cap` additions before the gate opens waits for it, so that
+    // little work is spent on columns that turn out to be dropped.
+    virtual void finish_gated(DropGate &gate, int64_t cap, ResidualResult &R) = 0;
 };
 std::unique_ptr<ResidualSpec> residual_speculate(const ResidualProblem &P);
 

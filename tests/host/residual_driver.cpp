@@ -91,7 +91,10 @@ int main(int argc, char **argv)
     N = atoi(argv[2]);
     const int maxdim = atoi(argv[3]);
     const float thr = (float)atof(argv[4]);
-    // mode & 3: schedule (0 plain, 1 speculative budget, 2 overlapped);
+    // mode & 3: schedule (0 plain, 1 speculative budget, 2 overlapped,
+    // 3 overlapped with the dropped columns known late: columns park past
+    // 2 additions, or with mode & 8 never, so dropped columns end at zero
+    // before the gate opens);
     // mode & 4: oblivious additions
     const int mode = atoi(argv[5]);
     const int sched = mode & 3;
@@ -258,12 +261,26 @@ int main(int argc, char **argv)
         P.spec_budget = sched >= 1 ? 2 : 0;
         P.oblivious = (mode & 4) != 0;
         ResidualResult R;
-        if (sched == 2) {
+        if (sched >= 2) {
             std::unordered_set<uint64_t> ph(prev_host.begin(), prev_host.end());
             std::vector<uint8_t> drop(cid.size(), 0);
             for (size_t j = 0; j < cid.size(); ++j)
                 drop[j] = ph.count(cid[j]) ? 1 : 0;
-            residual_speculate(P)->finish(drop.data(), R);
+            if (sched == 2) {
+                residual_speculate(P)->finish(drop.data(), R);
+            } else {
+                // the dropped columns become known only after a few polls:
+                // the reduction runs open, parks columns past 2 additions,
+                // and classifies its zero columns late
+                struct Late final : DropGate {
+                    const uint8_t *d;
+                    int polls = 0;
+                    bool ready() override { return ++polls > 5; }
+                    const uint8_t *wait() override { return d; }
+                } gate;
+                gate.d = drop.data();
+                residual_speculate(P)->finish_gated(gate, (mode & 8) ? 1000000 : 2, R);
+            }
         } else {
             residual_reduce(P, R);
         }
@@ -283,7 +300,7 @@ int main(int argc, char **argv)
         for (size_t i = 0; i < cc.size(); ++i)
             if (app_tau[i] != ~0ull)
                 clear.insert(app_tau[i]);
-        if (sched != 2)
+        if (sched < 2)
             for (uint64_t t : R.tau)
                 clear.insert(t);
         prev_host = R.tau;

@@ -1,7 +1,8 @@
 """Host residual reduction (csrc/residual.cpp) on the CPU, through a test
 driver that builds the GPU stages' hand-off by brute force: every schedule
--- plain, with a speculative budget, and the overlapped one that drops the
-previous dimension's host pivots instead of clearing them -- gives the
+-- plain, with a speculative budget, the overlapped one that drops the
+previous dimension's host pivots instead of clearing them, and the same with
+those pivots known only after the reduction has started -- gives the
 oracle's persistence pairs and essential classes exactly, with either way of
 adding a host pivot column: its reduced column (reduction-matrix technique)
 or its unreduced coboundary (oblivious reduction, the paper's lemma on
@@ -75,8 +76,9 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,build,n,maxdim,thr", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("mode", [0, 1, 2, 4, 6],
-                         ids=["plain", "budget", "overlap", "oblivious", "overlap-oblivious"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 11, 4, 6, 7],
+                         ids=["plain", "budget", "overlap", "late-drops", "late-drops-nocap",
+                              "oblivious", "overlap-oblivious", "late-drops-oblivious"])
 def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
     d = build()
     if np.isinf(thr):
