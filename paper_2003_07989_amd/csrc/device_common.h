@@ -130,6 +130,19 @@ __device__ __forceinline__ uint32_t diam_bits(float d)
     return __float_as_uint(d + 0.0f);
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin, and each XCD
+// has its own L2.  Renumbering block b of nb so that every XCD gets one
+// contiguous range of the logical grid keeps neighbouring tiles -- which
+// read the same distance rows -- in one L2.  A bijection on [0, nb): XCD x
+// gets q + 1 blocks when x < r, q otherwise (nb = 8q + r).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    constexpr uint32_t X = 8;
+    const uint32_t q = nb / X, r = nb % X;
+    const uint32_t x = b % X, i = b / X;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const int lane = threadIdx.x & (WAVE - 1);

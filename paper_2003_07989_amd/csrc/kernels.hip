@@ -385,7 +385,8 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
     tile_counts += (int64_t)blockIdx.y * gridDim.x;
     stats += 2 * blockIdx.y;
     const Binom B{a.binom, a.n + 1};
-    const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t base = (uint64_t)tile * COMPACT_TILE;
     uint32_t keep = 0, nthr = 0, nclr = 0;
 #pragma unroll 4
     for (int k = 0; k < CI; ++k) {
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
     uint32_t st = block_sum<CT>(nthr, sh);
     uint32_t sc = block_sum<CT>(nclr, sh);
     if (threadIdx.x == 0) {
-        tile_counts[blockIdx.x] = sk;
+        tile_counts[tile] = sk;
         if (st)
             atomicAdd(&stats[0], (unsigned long long)st);
         if (sc)
@@ -423,8 +424,9 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
     out_cidx += (int64_t)blockIdx.y * a.out_stride;
     const Binom B{a.binom, a.n + 1};
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const uint64_t base = (uint64_t)blockIdx.x * COMPACT_TILE;
-    uint64_t running = tile_offsets[blockIdx.x];
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t base = (uint64_t)tile * COMPACT_TILE;
+    uint64_t running = tile_offsets[tile];
     for (int k = 0; k < CI; ++k) {
         uint64_t c = base + (uint64_t)k * CT + threadIdx.x;
         float d = 0.0f;
@@ -535,7 +537,8 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
     const int gbase = lane - g;
     const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
     const int own = CPR * rounds;  // columns owned by a wave (rounds <= G)
-    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * own;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = ((blk * blockDim.x + threadIdx.x) / WAVE) * own;
     {
         const int64_t cl = blockIdx.y;
         ncols = batch_count(bt, cl, ncols);
@@ -976,7 +979,8 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
                                              uint64_t *__restrict__ all_cidx)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t pre = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t pre = (blk * blockDim.x + threadIdx.x) / WAVE;
     if (pre >= a.npre)
         return;
     const Binom B{a.binom, a.n + 1};
@@ -1198,7 +1202,8 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
     const int gbase = lane - g;
     const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
     const int own = CPR * rounds;  // columns owned by a wave (rounds <= G)
-    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * own;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = ((blk * blockDim.x + threadIdx.x) / WAVE) * own;
     if (base >= ncols)
         return;  // whole waves leave together
     const Binom B{binom, n + 1};
