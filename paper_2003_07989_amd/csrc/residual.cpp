@@ -338,36 +338,44 @@ template <class K> struct Stream {
     int singles = 0;
     bool empty() const { return pos >= len; }
     K front() const { return e[pos]; }
-    void prepare()
+    // hot: order a first chunk now, while the keys are in cache, instead of
+    // taking single keys later (each later scan reads the whole stream again)
+    void prepare(bool hot, uint32_t ordered)
     {
-        pos = sorted = 0;
-        singles = 0;
+        pos = 0;
+        singles = hot ? SINGLES : 0;
         chunk = 32;
-        refill();
+        sorted = ordered;  // an ordered prefix: nothing to do for it
+        // a deep consumer with a short ordered prefix gets its first chunk
+        // now, while the keys are in cache
+        if (ordered == 0 || (hot && ordered < 32 && ordered < len))
+            extend(ordered);
     }
-    void refill()
+    void refill() { extend(pos); }
+    // Orders keys from `at` (= sorted): the next one alone, or a chunk.
+    void extend(size_t at)
     {
-        const size_t rem = len - pos;
+        const size_t rem = len - at;
         if (rem == 0)
             return;
         if (singles < SINGLES && rem > 16) {
             // the next key alone, by a scan for the minimum: most streams
             // are consumed only a few keys deep
-            const size_t j = pos + argmin_keys(e + pos, rem);
-            std::swap(e[pos], e[j]);
-            sorted = pos + 1;
+            const size_t j = at + argmin_keys(e + at, rem);
+            std::swap(e[at], e[j]);
+            sorted = (uint32_t)at + 1;
             ++singles;
             return;
         }
         const size_t c = std::min<size_t>(rem, chunk);
         if (c < rem) {
             if (std::is_same<K, uint64_t>::value && HAVE_AVX512)
-                select_smallest_u64_avx512(reinterpret_cast<uint64_t *>(e + pos), rem, c);
+                select_smallest_u64_avx512(reinterpret_cast<uint64_t *>(e + at), rem, c);
             else
-                select_smallest(e + pos, rem, c);
+                select_smallest(e + at, rem, c);
         }
-        std::sort(e + pos, e + pos + c);
-        sorted = pos + (uint32_t)c;
+        std::sort(e + at, e + at + c);
+        sorted = (uint32_t)(at + c);
         chunk = chunk < (1u << 30) ? chunk * 2 : chunk;
     }
     void pop()
@@ -377,14 +385,33 @@ template <class K> struct Stream {
     }
 };
 
+// Whether new streams should be ordered up front (a dimension whose columns
+// cancel deeply) or one key at a time (most streams are consumed only a few
+// keys deep).  Decided by the share of this reduction's streams consumed
+// past the single-key phase; before 64 streams are seen, by the dimension
+// (edges' coboundaries cancel deeply, higher ones rarely).
+struct DepthPolicy {
+    std::atomic<uint64_t> streams{0}, deep{0};
+    bool prior = false;
+    bool hot() const
+    {
+        const uint64_t s = streams.load(std::memory_order_relaxed);
+        if (s < 64)
+            return prior;
+        return deep.load(std::memory_order_relaxed) * 4 > s;
+    }
+};
+
 // Working column = Z/2 sum of several coboundaries.  Each added coboundary
 // is its own stream; a min-heap over the streams' current fronts yields the
 // sum's entries oldest-first.  Only the entries that reach the front are
 // ever ordered, which is what finding the low needs.
 template <class K> class Column {
 public:
-    // Adds the coboundary in e[0..len) (arena storage) as a new stream.
-    void push_stream(K *e, size_t len)
+    DepthPolicy *policy = nullptr;  // shared by the columns of one reduction
+    // Adds the coboundary in e[0..len) (arena storage) as a new stream; its
+    // first `ties` keys are already in ascending order.
+    void push_stream(K *e, size_t len, size_t ties)
     {
         if (len == 0)
             return;
@@ -392,7 +419,9 @@ public:
         Stream<K> &st = streams.back();
         st.e = e;
         st.len = (uint32_t)len;
-        st.prepare();
+        st.prepare(policy && policy->hot(), (uint32_t)ties);
+        if (policy)
+            policy->streams.fetch_add(1, std::memory_order_relaxed);
         top_push(st.front(), (uint32_t)(streams.size() - 1));
     }
     // Add another column's current contents: its streams hold exactly its
@@ -492,6 +521,8 @@ private:
     {
         Stream<K> &st = streams[hs[0]];
         st.pop();
+        if (st.pos == Stream<K>::SINGLES && policy)
+            policy->deep.fetch_add(1, std::memory_order_relaxed);
         if (!st.empty()) {
             hk[0] = st.front();
         } else {
@@ -513,31 +544,55 @@ private:
 // AVX-512 variants (chosen at run time when the CPU has F, VL, BW and VBMI2)
 // ---------------------------------------------------------------------------
 
+// Bit reversal of a byte (lane order of an 8-lane mask).
+static const struct RevTable {
+    uint8_t t[256];
+    RevTable()
+    {
+        for (int x = 0; x < 256; ++x) {
+            int r = 0;
+            for (int b = 0; b < 8; ++b)
+                r |= ((x >> b) & 1) << (7 - b);
+            t[x] = (uint8_t)r;
+        }
+    }
+} REV8;
+
 // Dense coboundary with 32-bit cofacet indices (u64 keys): 16 candidate
 // vertices per step -- row maxima, the threshold test, the packed keys --
-// and a compress of the cofacets that pass (out needs 16 slots of slack).  Same set of keys as the
-// scalar loop; the order within a stream does not matter.
+// and register compresses of the cofacets that pass (the memory form of
+// compress is slow on some cores).  The vertices w run downward (each gap
+// between sigma's vertices from its top, the gaps from the top), so the
+// cofacets whose diameter is d itself -- sigma's own -- come out in
+// ascending key order (for a fixed diameter the key falls as w rises);
+// they go to out[0..ties), the others (larger diameters, unordered) to gt
+// and then behind them.  out and gt need 16 slots of slack.
 __attribute__((target("avx512f,avx512vl,avx512bw,avx512vbmi2"))) static size_t
 cob_dense_u64_avx512(const float *const *rows, int nv, const int *v, uint64_t sigma, float d,
-                     float thr, const uint64_t *binom, int n, uint64_t *out)
+                     float thr, const uint64_t *binom, int n, uint64_t *out, uint64_t *gt,
+                     size_t *ties)
 {
-    size_t cnt = 0;
+    size_t neq = 0, ngt = 0;
     uint64_t above = 0, below = sigma;
     int hi = n;
     const __m512 vd = _mm512_set1_ps(d), vthr = _mm512_set1_ps(thr);
     const __m512i vM = _mm512_set1_epi64((long long)0xffffffffull);
+    const __m512i rev = _mm512_set_epi64(0, 1, 2, 3, 4, 5, 6, 7);
     for (int idx = 0; idx <= nv; ++idx) {
         const int lo = idx < nv ? v[idx] : -1;
         const int j = nv - idx;  // vertices of sigma below w
         const uint64_t *Cj = binom + (int64_t)(j + 1) * (n + 1);
         const __m512i vbase = _mm512_set1_epi64((long long)(above + below));
-        for (int w0 = lo + 1; w0 < hi; w0 += 16) {
-            const int rem = hi - w0;
-            const __mmask16 lm = rem >= 16 ? (__mmask16)0xffff : (__mmask16)((1u << rem) - 1u);
+        for (int top = hi - 1; top > lo; top -= 16) {
+            const int w0 = top - 15 > lo + 1 ? top - 15 : lo + 1;  // lowest w of the step
+            const int cnt = top - w0 + 1;
+            const __mmask16 lm = cnt >= 16 ? (__mmask16)0xffff : (__mmask16)((1u << cnt) - 1u);
             __m512 mx = _mm512_maskz_loadu_ps(lm, rows[0] + w0);
             for (int i = 1; i < nv; ++i)
                 mx = _mm512_max_ps(mx, _mm512_maskz_loadu_ps(lm, rows[i] + w0));
-            const __mmask16 ok = _mm512_mask_cmp_ps_mask(lm, mx, vthr, _CMP_LE_OQ);
+            const __mmask16 in = _mm512_mask_cmp_ps_mask(lm, mx, vthr, _CMP_LE_OQ);
+            const __mmask16 eq = _mm512_mask_cmp_ps_mask(in, mx, vd, _CMP_LE_OQ);
+            const __mmask16 up = in & (__mmask16)~eq;
             const __m512i ndb = _mm512_castps_si512(_mm512_max_ps(mx, vd));
             const __m512i c0 =
                 _mm512_add_epi64(vbase, _mm512_maskz_loadu_epi64((__mmask8)lm, Cj + w0));
@@ -547,13 +602,20 @@ cob_dense_u64_avx512(const float *const *rows, int nv, const int *v, uint64_t si
             const __m512i d1 = _mm512_cvtepu32_epi64(_mm512_extracti64x4_epi64(ndb, 1));
             const __m512i k0 = _mm512_or_si512(_mm512_slli_epi64(d0, 32), _mm512_sub_epi64(vM, c0));
             const __m512i k1 = _mm512_or_si512(_mm512_slli_epi64(d1, 32), _mm512_sub_epi64(vM, c1));
-            // compress in registers, then full stores (the memory form of
-            // compress is slow on some cores); out has 16 slots of slack
-            const __mmask8 ok0 = (__mmask8)ok, ok1 = (__mmask8)(ok >> 8);
-            _mm512_storeu_si512(out + cnt, _mm512_maskz_compress_epi64(ok0, k0));
-            cnt += (size_t)__builtin_popcount(ok0);
-            _mm512_storeu_si512(out + cnt, _mm512_maskz_compress_epi64(ok1, k1));
-            cnt += (size_t)__builtin_popcount(ok1);
+            // ties in descending w: upper half first, each half lane-reversed
+            const __mmask8 e1 = (__mmask8)REV8.t[(uint8_t)(eq >> 8)];
+            const __mmask8 e0 = (__mmask8)REV8.t[(uint8_t)eq];
+            _mm512_storeu_si512(out + neq,
+                                _mm512_maskz_compress_epi64(e1, _mm512_permutexvar_epi64(rev, k1)));
+            neq += (size_t)__builtin_popcount((unsigned)e1);
+            _mm512_storeu_si512(out + neq,
+                                _mm512_maskz_compress_epi64(e0, _mm512_permutexvar_epi64(rev, k0)));
+            neq += (size_t)__builtin_popcount((unsigned)e0);
+            const __mmask8 u0 = (__mmask8)up, u1 = (__mmask8)(up >> 8);
+            _mm512_storeu_si512(gt + ngt, _mm512_maskz_compress_epi64(u0, k0));
+            ngt += (size_t)__builtin_popcount((unsigned)u0);
+            _mm512_storeu_si512(gt + ngt, _mm512_maskz_compress_epi64(u1, k1));
+            ngt += (size_t)__builtin_popcount((unsigned)u1);
         }
         if (idx < nv) {
             const int r = nv - 1 - idx;  // rank of v[idx] from the bottom
@@ -562,7 +624,9 @@ cob_dense_u64_avx512(const float *const *rows, int nv, const int *v, uint64_t si
         }
         hi = lo;
     }
-    return cnt;
+    memcpy(out + neq, gt, ngt * sizeof(uint64_t));
+    *ties = neq;
+    return neq + ngt;
 }
 
 struct Ctx {
@@ -618,14 +682,28 @@ struct Ctx {
     template <class K> void add_coboundary(Column<K> &col, uint64_t sigma, float d) const
     {
         K *e;
-        const size_t len = coboundary<K>(sigma, d, e);
-        col.push_stream(e, len);
+        size_t ties = 0;
+        const size_t len = coboundary<K>(sigma, d, e, ties);
+        col.push_stream(e, len, ties);
     }
 
     // Every cofacet of sigma with diameter <= threshold, appended to out as
     // packed keys.
+    // Scratch for the cofacets above sigma's diameter (reordered behind the
+    // ties), n + 16 keys.
+    template <class K> K *gt_scratch() const
+    {
+        thread_local std::vector<u128> buf;
+        const size_t need = ((size_t)n + 16) * sizeof(K) / sizeof(u128) + 1;
+        if (buf.size() < need)
+            buf.resize(need);
+        return reinterpret_cast<K *>(buf.data());
+    }
+
     // Writes sigma's coboundary into this thread's arena; returns its length.
-    template <class K> size_t coboundary(uint64_t sigma, float d, K *&out) const
+    // The first `ties` keys are the cofacets of sigma's own diameter, in
+    // ascending order; the rest are larger and unordered.
+    template <class K> size_t coboundary(uint64_t sigma, float d, K *&out, size_t &ties) const
     {
         int v[8];
         decode(sigma, p, v);
@@ -664,40 +742,52 @@ struct Ctx {
             }
             out = arena.reserve<K>(cnt);
             arena.commit<K>(cnt);
-            K *o = out;
-            int k = 0;  // vertices of sigma below w
-            for (int wd = 0; wd < P.words; ++wd) {
+            K *gt = gt_scratch<K>();
+            size_t neq = 0, ngt = 0;
+            int k = nv;  // vertices of sigma below w; w runs downward
+            for (int wd = P.words - 1; wd >= 0; --wd) {
                 uint64_t m = bv[0][wd];
                 for (int i = 1; i < nv; ++i)
                     m &= bv[i][wd];
-                for (; m; m &= m - 1) {
-                    const int w = wd * 64 + __builtin_ctzll(m);
-                    while (k < nv && u[k] < w)
-                        ++k;
+                while (m) {
+                    const int b = 63 - __builtin_clzll(m);
+                    m &= ~(1ull << b);
+                    const int w = wd * 64 + b;
+                    while (k > 0 && u[k - 1] > w)
+                        --k;
                     float nd = d;
                     for (int i = 0; i < nv; ++i) {
                         const float e = rows[i][w];
                         nd = e > nd ? e : nd;
                     }
-                    *o++ = pack<K>(nd, base[k] + brow[k][w]);
+                    const K key = pack<K>(nd, base[k] + brow[k][w]);
+                    out[neq] = key;
+                    gt[ngt] = key;
+                    const bool tie = !(nd > d);
+                    neq += tie ? 1 : 0;
+                    ngt += tie ? 0 : 1;
                 }
             }
+            memcpy(out + neq, gt, ngt * sizeof(K));
+            ties = neq;
             return cnt;
         }
         const float *rows[8];
         for (int i = 0; i <= p; ++i)
             rows[i] = P.dsq + (int64_t)v[i] * n;
         out = arena.reserve<K>((size_t)n + 16);  // 16 slots of slack for vector stores
+        K *gt = gt_scratch<K>();
         size_t cnt;
-        if (std::is_same<K, uint64_t>::value && cpu_has_avx512()) {
+        if (std::is_same<K, uint64_t>::value && HAVE_AVX512) {
             cnt = cob_dense_u64_avx512(rows, p + 1, v, sigma, d, P.thr, P.binom, n,
-                                       reinterpret_cast<uint64_t *>(out));
+                                       reinterpret_cast<uint64_t *>(out),
+                                       reinterpret_cast<uint64_t *>(gt), &ties);
         } else {
             switch (p) {
-            case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out); break;
-            case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out); break;
-            case 3: cnt = cob_dense<K, 4>(rows, v, sigma, d, out); break;
-            default: cnt = cob_dense<K, 0>(rows, v, sigma, d, out); break;
+            case 1: cnt = cob_dense<K, 2>(rows, v, sigma, d, out, gt, ties); break;
+            case 2: cnt = cob_dense<K, 3>(rows, v, sigma, d, out, gt, ties); break;
+            case 3: cnt = cob_dense<K, 4>(rows, v, sigma, d, out, gt, ties); break;
+            default: cnt = cob_dense<K, 0>(rows, v, sigma, d, out, gt, ties); break;
             }
         }
         arena.commit<K>(cnt);
@@ -708,13 +798,16 @@ struct Ctx {
     // where the vertices of sigma above w move up one rank.  Between two
     // consecutive vertices of sigma, j, above and below are constant, so w
     // runs over each gap in a tight loop that writes every cofacet and
-    // advances the output only for those within the threshold.
+    // advances an output only for those within the threshold: w runs
+    // downward, so the cofacets of sigma's own diameter reach out[0..ties)
+    // in ascending key order; the others go to gt, then behind them.
     template <class K, int NV>
-    size_t cob_dense(const float *const *rows, const int *v, uint64_t sigma, float d, K *out) const
+    size_t cob_dense(const float *const *rows, const int *v, uint64_t sigma, float d, K *out,
+                     K *gt, size_t &ties) const
     {
         const int nv = NV ? NV : p + 1;
         const float thr = P.thr;
-        size_t cnt = 0;
+        size_t neq = 0, ngt = 0;
         uint64_t above = 0, below = sigma;
         int hi = n;
         for (int idx = 0; idx <= nv; ++idx) {
@@ -729,8 +822,11 @@ struct Ctx {
                     mx = e > mx ? e : mx;
                 }
                 const float nd = mx > d ? mx : d;
-                out[cnt] = pack<K>(nd, base + Cj[w]);
-                cnt += (mx <= thr) ? 1 : 0;
+                const K key = pack<K>(nd, base + Cj[w]);
+                out[neq] = key;
+                gt[ngt] = key;
+                neq += (mx <= d) ? 1 : 0;
+                ngt += (mx > d && mx <= thr) ? 1 : 0;
             }
             if (idx < nv) {
                 const int r = nv - 1 - idx;  // rank of v[idx] from the bottom
@@ -739,7 +835,9 @@ struct Ctx {
             }
             hi = lo;
         }
-        return cnt;
+        memcpy(out + neq, gt, ngt * sizeof(K));
+        ties = neq;
+        return neq + ngt;
     }
 
     // Implicit second layer: if row tau (diameter dt) is the pivot of an
@@ -981,6 +1079,7 @@ public:
         : P(p), ncols(p.ncols), spec_low(p.ncols), spec_nz(p.ncols, 0), spec_adds(p.ncols, 0),
           spec_cut(p.ncols, 0), state(p.ncols)
     {
+        policy.prior = p.p == 1;
         phase_a();
     }
     void finish(const uint8_t *drop, ResidualResult &R) override
@@ -1047,6 +1146,7 @@ private:
                         continue;
                     }
                     std::unique_ptr<Column<K>> col(new Column<K>());
+                    col->policy = &policy;
                     X.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
                     bool nz;
                     int64_t adds = 0;
@@ -1216,6 +1316,7 @@ private:
             std::unique_ptr<Column<K>> &col = state[j];
             if (!col) {
                 col.reset(new Column<K>());
+                col->policy = &policy;
                 Xc.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
             }
             Entry lo = spec_low[j];
@@ -1301,6 +1402,7 @@ private:
     }
 
     BlockSink sink;  // stream storage of every column below; freed last
+    DepthPolicy policy;
     const ResidualProblem P;
     const int64_t ncols;
     std::vector<Entry> spec_low;
