@@ -39,15 +39,18 @@ __device__ __forceinline__ int top_vertex(const Binom &B, uint64_t c, int k, int
     if (k == 1)
         return (int)c;
     if (k <= 4) {
-        const double cd = (double)c;
-        double g;
+        // Guess from C(x, k) ~ x^k / k!, in single precision with the
+        // hardware square root, log2 and exp2: a guess a few units off only
+        // costs a step of the exact correction below.
+        const float cf = (float)c;
+        float g;
         if (k == 2)
-            g = 0.5 * (1.0 + sqrt(1.0 + 8.0 * cd));
+            g = 0.5f * (1.0f + __builtin_sqrtf(1.0f + 8.0f * cf));
         else if (k == 3)
-            g = cbrt(6.0 * cd) + 1.0;
+            g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(6.0f * cf) * (1.0f / 3.0f)) + 1.0f;
         else
-            g = sqrt(sqrt(24.0 * cd)) + 1.5;
-        int x = (int)fmin(g, (double)(hi - 1));
+            g = __builtin_sqrtf(__builtin_sqrtf(24.0f * cf)) + 1.5f;
+        int x = (int)fminf(g, (float)(hi - 1));
         x = x < k - 1 ? k - 1 : x;
         while (x > k - 1 && B(x, k) > c)
             --x;
@@ -84,7 +87,7 @@ __device__ __forceinline__ void decode(const Binom &B, uint64_t c, int n, int (&
 // Edge (a > b) from its index c = C(a,2) + b, without the table.
 __device__ __forceinline__ void decode_edge(uint64_t c, int &a, int &b)
 {
-    int x = (int)floor((1.0 + sqrt(1.0 + 8.0 * (double)c)) * 0.5);
+    int x = (int)(0.5f * (1.0f + __builtin_sqrtf(1.0f + 8.0f * (float)c)));
     while ((uint64_t)x * (x - 1) / 2 > c)
         --x;
     while ((uint64_t)(x + 1) * x / 2 <= c)
