@@ -301,8 +301,14 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
 // pivots clear it).
 constexpr int64_t SPEC_BUDGET = 16;
 // Additions a column may make in the exact phase while the previous
-// dimension's host pivots (the columns to drop) are still unknown.
+// dimension's host pivots (the columns to drop) are still unknown
+// (RPP_OPEN_CAP overrides it).
 constexpr int64_t OPEN_CAP = 64;
+static int64_t open_cap()
+{
+    const char *e = getenv("RPP_OPEN_CAP");
+    return e ? std::max<int64_t>(1, atoll(e)) : OPEN_CAP;
+}
 
 static int default_group(int p)
 {
@@ -815,7 +821,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         // pivots -- this dimension's dropped columns -- are still being found
         // on its own thread; the gate waits for them when they are needed.
         HostDim *prevp = p > 1 ? &hd[(size_t)p - 1] : nullptr;
-        H.th = std::thread([&H, prevp, &since] {
+        const int64_t cap = open_cap();
+        H.th = std::thread([&H, prevp, cap, &since] {
             struct PrevGate final : DropGate {
                 HostDim &prev, &cur;
                 bool have = false;
@@ -854,7 +861,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             try {
                 if (prevp) {
                     PrevGate gate(*prevp, H);
-                    H.spec->finish_gated(gate, OPEN_CAP, H.RR);
+                    H.spec->finish_gated(gate, cap, H.RR);
                 } else {
                     H.spec->finish(nullptr, H.RR);
                 }
