@@ -1419,7 +1419,9 @@ std::unique_ptr<ResidualSpec> residual_speculate(const ResidualProblem &P)
 {
     // largest cofacet index + 1 = C(n, p+2)
     const uint64_t ncof = P.binom[(int64_t)(P.p + 2) * (P.n + 1) + P.n];
-    if (ncof <= (1ull << 32))
+    // RPP_WIDE_KEYS=1 takes the 128-bit keys even where 64 suffice (tests)
+    static const bool wide = getenv("RPP_WIDE_KEYS") && atoi(getenv("RPP_WIDE_KEYS")) != 0;
+    if (ncof <= (1ull << 32) && !wide)
         return std::unique_ptr<ResidualSpec>(new SpecImpl<uint64_t>(P));
     return std::unique_ptr<ResidualSpec>(new SpecImpl<u128>(P));
 }

@@ -91,6 +91,7 @@ int main(int argc, char **argv)
     N = atoi(argv[2]);
     const int maxdim = atoi(argv[3]);
     const float thr = (float)atof(argv[4]);
+    // mode & 16: cofacets through neighbour bitsets (the sparse path);
     // mode & 3: schedule (0 plain, 1 speculative budget, 2 overlapped,
     // 3 overlapped with the dropped columns known late: columns park past
     // 2 additions, or with mode & 8 never, so dropped columns end at zero
@@ -258,6 +259,18 @@ int main(int argc, char **argv)
         P.col_low = low.data();
         P.col_low_diam = lowd.data();
         P.napp = napp;
+        // mode & 16: cofacets from neighbour bitsets (the sparse path)
+        std::vector<uint64_t> bits;
+        if (mode & 16) {
+            const int words = (n + 63) / 64;
+            bits.assign((size_t)n * words, 0);
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b)
+                    if (a != b && D(a, b) <= thr)
+                        bits[(size_t)a * words + b / 64] |= 1ull << (b % 64);
+            P.bits = bits.data();
+            P.words = words;
+        }
         P.spec_budget = sched >= 1 ? 2 : 0;
         P.oblivious = (mode & 4) != 0;
         ResidualResult R;

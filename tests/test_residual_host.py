@@ -31,13 +31,14 @@ def driver():
     return out
 
 
-def _run(driver, d, n, maxdim, thr, mode, with_additions=False):
+def _run(driver, d, n, maxdim, thr, mode, with_additions=False, env=None):
     with tempfile.NamedTemporaryFile(suffix=".f32", delete=False) as f:
         np.ascontiguousarray(d, dtype=np.float32).tofile(f)
         path = f.name
     try:
         r = subprocess.run([driver, path, str(n), str(maxdim), repr(float(thr)), str(mode)],
-                           check=True, capture_output=True, text=True)
+                           check=True, capture_output=True, text=True,
+                           env=dict(os.environ, **(env or {})))
     finally:
         os.unlink(path)
     pairs = {p: set() for p in range(1, maxdim + 1)}
@@ -76,9 +77,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,build,n,maxdim,thr", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 11, 4, 6, 7],
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 11, 4, 6, 7, 16, 19],
                          ids=["plain", "budget", "overlap", "late-drops", "late-drops-nocap",
-                              "oblivious", "overlap-oblivious", "late-drops-oblivious"])
+                              "oblivious", "overlap-oblivious", "late-drops-oblivious",
+                              "bitsets", "bitsets-late-drops"])
 def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
     d = build()
     if np.isinf(thr):
@@ -101,3 +103,19 @@ def test_oblivious_additions_differ_where_host_pivots_are_reduced(driver):
     ob_p, ob_e, ob_a = _run(driver, d, 40, 2, thr, 4, with_additions=True)
     assert rm_p == ob_p and rm_e == ob_e
     assert sum(ob_a.values()) > sum(rm_a.values()), (ob_a, rm_a)
+
+
+@pytest.mark.parametrize("mode", [0, 3, 16, 19], ids=["plain", "late-drops", "bitsets",
+                                                      "bitsets-late-drops"])
+def test_wide_keys_match_oracle(driver, mode):
+    """The 128-bit key path (cofacet indices past 2^32, as on the 4096-point
+    sphere), forced on small inputs: the same pairs and classes."""
+    for name, build, n, maxdim, thr in CASES:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        got_p, got_e = _run(driver, d, n, maxdim, thr, mode, env={"RPP_WIDE_KEYS": "1"})
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, p)
+            assert got_e[p] == exp_e[p], (name, mode, p)
