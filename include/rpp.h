@@ -94,6 +94,12 @@ enum {
  * are identical (the paper's lemma on oblivious reduction); the oblivious
  * form uses less host memory and may need many more additions. */
 #define RPP_OBLIVIOUS_REDUCTION 0x100u
+/* The paper's stage order: sort every kept column by (diameter desc, cidx
+ * asc) before the apparent-pair test, instead of sorting only the
+ * non-apparent columns after it (the default; apparent-ness does not depend
+ * on column order, so the results are identical).  Kept for comparison; the
+ * sort then runs over every column (stats.ms_sort includes it). */
+#define RPP_SORT_FIRST 0x200u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:

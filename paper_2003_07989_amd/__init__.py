@@ -11,7 +11,7 @@ and fails loudly if ``librpp.so`` has not been built.
 from ._binding import (NO_EDGE, RPP_BATCH_AUTOTUNE, RPP_BATCH_NO_GRAPH, RPP_FORCE_DENSE,
                        RPP_FORCE_SPARSE, RPP_MAX_DIM,
                        RPP_NO_ENCLOSING_RADIUS, RPP_OBLIVIOUS_REDUCTION,
-                       RPP_SORTED_PAIR_STORE,
+                       RPP_SORT_FIRST, RPP_SORTED_PAIR_STORE,
                        RPP_WANT_CRITICAL_EDGES, RPP_WANT_PAIRS, Barcodes,
                        PointCloudBarcodes, RppError, Server, apparent_count, apparent_pairs,
                        backward_points, barcodes,
@@ -20,7 +20,8 @@ from ._binding import (NO_EDGE, RPP_BATCH_AUTOTUNE, RPP_BATCH_NO_GRAPH, RPP_FORC
                        point_cloud_barcodes, strerror, version, workspace_bytes)
 
 __all__ = ["NO_EDGE", "RPP_BATCH_AUTOTUNE", "RPP_BATCH_NO_GRAPH", "RPP_FORCE_DENSE", "RPP_FORCE_SPARSE", "RPP_MAX_DIM",
-           "RPP_NO_ENCLOSING_RADIUS", "RPP_OBLIVIOUS_REDUCTION", "RPP_SORTED_PAIR_STORE", "RPP_WANT_CRITICAL_EDGES",
+           "RPP_NO_ENCLOSING_RADIUS", "RPP_OBLIVIOUS_REDUCTION", "RPP_SORT_FIRST",
+           "RPP_SORTED_PAIR_STORE", "RPP_WANT_CRITICAL_EDGES",
            "RPP_WANT_PAIRS", "Barcodes", "PointCloudBarcodes", "RppError", "Server",
            "apparent_count", "apparent_pairs",
            "backward_points", "barcodes", "barcodes_batch", "barcodes_device", "barcodes_host", "load",

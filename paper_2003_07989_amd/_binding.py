@@ -29,6 +29,7 @@ RPP_WANT_CRITICAL_EDGES = 0x20
 RPP_BATCH_NO_GRAPH = 0x40
 RPP_BATCH_AUTOTUNE = 0x80
 RPP_OBLIVIOUS_REDUCTION = 0x100
+RPP_SORT_FIRST = 0x200
 NO_EDGE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",

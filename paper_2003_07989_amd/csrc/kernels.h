@@ -109,6 +109,7 @@ void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
                               uint64_t *app_sigma, uint64_t *na_key, uint64_t *na_cidx,
                               hipStream_t s, Batch bt = Batch(), int nbatch = 1);
 // key[i] = ~bits(diam[i]) (descending-diameter radix key).
+void launch_diam_from_keys(const uint64_t *keys, int64_t count, float *diam, hipStream_t s);
 void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s,
                       Batch bt = Batch(), int nbatch = 1);
 

@@ -840,6 +840,24 @@ __global__ void k_desc_keys(const float *__restrict__ diam, int64_t count,
         keys[cl * bt.stride + i] = (uint64_t)(~diam_bits(diam[cl * bt.stride + i]));
 }
 
+// Diameters back from the keys of launch_desc_keys (the low 32 bits hold
+// the complemented bit pattern).
+__global__ void k_diam_from_keys(const uint64_t *__restrict__ keys, int64_t count,
+                                 float *__restrict__ diam)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        diam[i] = __uint_as_float(~(uint32_t)keys[i]);
+}
+
+void launch_diam_from_keys(const uint64_t *keys, int64_t count, float *diam, hipStream_t s)
+{
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(k_diam_from_keys, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       keys, count, diam);
+}
+
 void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s, Batch bt,
                       int nbatch)
 {

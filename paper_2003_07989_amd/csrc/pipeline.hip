@@ -237,7 +237,8 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
 static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, int group,
                                   hipStream_t s, int64_t *napp, std::string &err,
                                   GpuTimer *t_app = nullptr, GpuTimer *t_part = nullptr,
-                                  int64_t *scanned = nullptr, int words = 0)
+                                  int64_t *scanned = nullptr, int words = 0,
+                                  GpuTimer *t_pre = nullptr)
 {
     const int64_t tiles = compact_tiles(ncols);
     ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
@@ -257,6 +258,27 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
         ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
         sc = ws.scancnt.as<unsigned long long>();
         HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+    }
+    if (t_pre) {
+        // The paper's order: every kept column sorted by (diameter desc,
+        // cidx asc) before the apparent test, so the partition leaves the
+        // non-apparent columns in coboundary order.  The columns are in cidx
+        // order, so a stable sort on the complemented diameter suffices.
+        t_pre->start();
+        ALLOC_TRY(ws.rscratch, (size_t)radix_scratch_words(ncols) * 8);
+        launch_desc_keys(ws.cdiam.as<float>(), ncols, ws.nkey.as<uint64_t>(), s);
+        if (ncols)
+            HIP_TRY(hipMemcpyAsync(ws.nval.p, ws.ccidx.p, (size_t)ncols * 8,
+                                   hipMemcpyDeviceToDevice, s));
+        const int w = radix_sort_pairs(ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(),
+                                       ws.nkey2.as<uint64_t>(), ws.nval2.as<uint64_t>(), ncols,
+                                       32, ws.rscratch.as<uint64_t>(), s);
+        const DevBuf &k = w ? ws.nkey2 : ws.nkey;
+        const DevBuf &v = w ? ws.nval2 : ws.nval;
+        launch_diam_from_keys(k.as<uint64_t>(), ncols, ws.cdiam.as<float>(), s);
+        if (ncols)
+            HIP_TRY(hipMemcpyAsync(ws.ccidx.p, v.p, (size_t)ncols * 8, hipMemcpyDeviceToDevice, s));
+        t_pre->stop();
     }
     if (t_app)
         t_app->start();
@@ -658,8 +680,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             if (rc)
                 return rc;
         }
+        const bool sort_first = (a.flags & RPP_SORT_FIRST) != 0;
+        GpuTimer t_pre(s);
         rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
-                                    a.count_scans ? &scanned : nullptr, sparse ? words : 0);
+                                    a.count_scans ? &scanned : nullptr, sparse ? words : 0,
+                                    sort_first ? &t_pre : nullptr);
         if (rc)
             return rc;
         t_sort.start();
@@ -680,9 +705,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         const bool want_pairs = (a.flags & RPP_WANT_PAIRS) != 0;
         ALLOC_TRY(ws.rscratch,
                   (size_t)radix_scratch_words(sorted_store ? std::max(napp, nna) : nna) * 8);
-        int wn = radix_sort_pairs(ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(),
-                                  ws.nkey2.as<uint64_t>(), ws.nval2.as<uint64_t>(), nna, 32,
-                                  ws.rscratch.as<uint64_t>(), s);
+        // (already in coboundary order when every column was sorted first)
+        int wn = sort_first ? 0
+                            : radix_sort_pairs(ws.nkey.as<uint64_t>(), ws.nval.as<uint64_t>(),
+                                               ws.nkey2.as<uint64_t>(), ws.nval2.as<uint64_t>(),
+                                               nna, 32, ws.rscratch.as<uint64_t>(), s);
         const uint64_t *d_nk = wn ? ws.nkey2.as<uint64_t>() : ws.nkey.as<uint64_t>();
         const uint64_t *d_nv = wn ? ws.nval2.as<uint64_t>() : ws.nval.as<uint64_t>();
         const uint64_t *d_at = ws.akey.as<uint64_t>();
@@ -766,7 +793,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.ms_enumerate = t_enum.ms();
         D.st.ms_apparent = t_app.ms();
         D.st.ms_partition = t_part.ms();
-        D.st.ms_sort = t_sort.ms();
+        D.st.ms_sort = t_sort.ms() + (sort_first ? t_pre.ms() : 0.0f);
         D.st.n_scanned = scanned;
         D.st.n_candidates = ncand;
         D.st.n_thresholded = (int64_t)nthr;

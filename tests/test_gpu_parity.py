@@ -261,6 +261,31 @@ def test_torus400_oblivious_reduction(rpp):
     assert_bars_equal(got.bars, exp, "torus400 oblivious")
 
 
+@pytest.mark.parametrize("case", CASES[2::3], ids=[c[0] for c in CASES[2::3]])
+def test_sort_first_order_matches_oracle(rpp, case):
+    """The paper's stage order (every kept column sorted before the
+    apparent test) gives the same bars and pairs as sorting only the
+    non-apparent columns after it."""
+    name, d, n, maxdim, thr = case
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_SORT_FIRST)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+    f = rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    a = rpp.barcodes(d, maxdim, thr, flags=f)
+    b = rpp.barcodes(d, maxdim, thr, flags=f | rpp.RPP_SORT_FIRST)
+    for p in range(1, maxdim + 1):
+        assert set(zip(*map(list, a.pairs[p]))) == set(zip(*map(list, b.pairs[p])))
+        assert a.stats[p]["n_apparent"] == b.stats[p]["n_apparent"]
+
+
+def test_torus400_sort_first(rpp):
+    head, exp = _golden("torus400")
+    d = w.WORKLOADS["torus400"]["build"]()
+    got = rpp.barcodes(d, 2, flags=rpp.RPP_SORT_FIRST)
+    assert_bars_equal(got.bars, exp, "torus400 sort first")
+    got = rpp.barcodes(d, 2, flags=rpp.RPP_SORT_FIRST | rpp.RPP_FORCE_SPARSE)
+    assert_bars_equal(got.bars, exp, "torus400 sort first, sparse path")
+
+
 SPARSE_CASES = [c for c in CASES if not math.isinf(c[4])] + CASES[:8]
 
 
