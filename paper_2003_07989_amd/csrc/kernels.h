@@ -110,6 +110,18 @@ void launch_partition_scatter(const uint64_t *tau, const float *col_diam,
                               hipStream_t s, Batch bt = Batch(), int nbatch = 1);
 // key[i] = ~bits(diam[i]) (descending-diameter radix key).
 void launch_diam_from_keys(const uint64_t *keys, int64_t count, float *diam, hipStream_t s);
+// Rank-coded diameters (host reduction of the sparse path): flags of the
+// edges (sorted by diameter descending) that start a new length; after an
+// exclusive scan of the flags (excl, m + 1 entries), the n x n matrix of
+// ranks as floats (`above` beyond the threshold, 0 on the diagonal) and the
+// table vals[rank] of the distinct lengths, ascending.
+void launch_rank_flags(const uint64_t *keys, int64_t m, uint32_t *flags, hipStream_t s);
+void launch_rank_matrix(const uint64_t *keys, const uint64_t *cidx, const uint32_t *flags,
+                        const uint64_t *excl, int64_t m, int n, float above, float *rk,
+                        float *vals, hipStream_t s);
+// Recodes column keys (~bits(diameter)) and low diameters as ranks.
+void launch_recode_ranks(uint64_t *keys, float *lowd, int64_t m, const float *vals, int64_t R,
+                         hipStream_t s);
 void launch_desc_keys(const float *diam, int64_t count, uint64_t *keys, hipStream_t s,
                       Batch bt = Batch(), int nbatch = 1);
 

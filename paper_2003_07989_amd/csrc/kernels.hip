@@ -840,6 +840,108 @@ __global__ void k_desc_keys(const float *__restrict__ diam, int64_t count,
         keys[cl * bt.stride + i] = (uint64_t)(~diam_bits(diam[cl * bt.stride + i]));
 }
 
+// ===========================================================================
+// Rank-coded diameters for the host reduction: the rank of each edge length
+// among the distinct lengths within the threshold, ascending.
+// ===========================================================================
+// flags[i] = 1 where sorted edge i (diameter descending) starts a new length
+__global__ void k_rank_flags(const uint64_t *__restrict__ keys, int64_t m,
+                             uint32_t *__restrict__ flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m)
+        flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// n x n matrix of ranks (as floats): `above` everywhere, 0 on the diagonal
+__global__ void k_rank_fill(float *__restrict__ rk, int n, float above)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)n * n)
+        rk[i] = (i / n == i % n) ? 0.0f : above;
+}
+
+// Edge i of the sorted list gets rank R - (excl[i] + flags[i]), R = excl[m]
+// distinct lengths; vals[rank] = its length.
+__global__ void k_rank_scatter(const uint64_t *__restrict__ keys,
+                               const uint64_t *__restrict__ cidx,
+                               const uint32_t *__restrict__ flags,
+                               const uint64_t *__restrict__ excl, int64_t m, int n,
+                               float *__restrict__ rk, float *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m)
+        return;
+    const uint64_t R = excl[m];
+    const uint64_t r = R - (excl[i] + flags[i]);
+    int a, b;
+    decode_edge(cidx[i], a, b);
+    const float rf = (float)r;
+    rk[(int64_t)a * n + b] = rf;
+    rk[(int64_t)b * n + a] = rf;
+    if (flags[i])
+        vals[r] = __uint_as_float(~(uint32_t)keys[i]);
+}
+
+void launch_rank_flags(const uint64_t *keys, int64_t m, uint32_t *flags, hipStream_t s)
+{
+    if (m <= 0)
+        return;
+    hipLaunchKernelGGL(k_rank_flags, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, keys, m,
+                       flags);
+}
+
+void launch_rank_matrix(const uint64_t *keys, const uint64_t *cidx, const uint32_t *flags,
+                        const uint64_t *excl, int64_t m, int n, float above, float *rk,
+                        float *vals, hipStream_t s)
+{
+    const int64_t nn = (int64_t)n * n;
+    hipLaunchKernelGGL(k_rank_fill, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, rk, n,
+                       above);
+    if (m > 0)
+        hipLaunchKernelGGL(k_rank_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           keys, cidx, flags, excl, m, n, rk, vals);
+}
+
+// Rank of a length within the threshold: its index in vals (ascending,
+// distinct, R entries); larger values are left alone.
+__device__ __forceinline__ float rank_of(float x, const float *__restrict__ vals, int64_t R)
+{
+    if (!(x <= vals[R - 1]))
+        return x;
+    int64_t lo = 0, hi = R - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (vals[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (float)lo;
+}
+
+// Column keys (~bits(diameter) in the low 32 bits) and low diameters
+// recoded as ranks.
+__global__ void k_recode_ranks(uint64_t *__restrict__ keys, float *__restrict__ lowd, int64_t m,
+                               const float *__restrict__ vals, int64_t R)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m)
+        return;
+    const float d = __uint_as_float(~(uint32_t)keys[i]);
+    keys[i] = (uint64_t)(~diam_bits(rank_of(d, vals, R)));
+    lowd[i] = rank_of(lowd[i], vals, R);
+}
+
+void launch_recode_ranks(uint64_t *keys, float *lowd, int64_t m, const float *vals, int64_t R,
+                         hipStream_t s)
+{
+    if (m <= 0 || R <= 0)
+        return;
+    hipLaunchKernelGGL(k_recode_ranks, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, keys,
+                       lowd, m, vals, R);
+}
+
 // Diameters back from the keys of launch_desc_keys (the low 32 bits hold
 // the complemented bit pattern).
 __global__ void k_diam_from_keys(const uint64_t *__restrict__ keys, int64_t count,

@@ -72,6 +72,7 @@ struct Workspace {
     DevBuf tcount, toff, scan, tcount2, toff2;
     DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
     DevBuf xd, xc;                   // sparse path: all simplices <= thr, top dim
+    DevBuf rflags, rexcl, rmat, rvals;  // sparse path: rank-coded diameters
     DevBuf bits;                     // sparse path: neighbour bitsets
     DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
     DevBuf cdiam, ccidx, tau;
@@ -121,7 +122,7 @@ size_t workspace_allocated(void *wp)
     const DevBuf *bufs[] = {&w.dsq, &w.rowmax, &w.scal, &w.binom, &w.ekey, &w.eval, &w.ekey2,
                             &w.eval2, &w.mst, &w.deaths, &w.dedges, &w.ufs, &w.tcount, &w.toff,
                             &w.scan, &w.tcount2, &w.toff2, &w.skd[0], &w.skd[1], &w.skc[0],
-                            &w.skc[1], &w.xd, &w.xc, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
+                            &w.skc[1], &w.xd, &w.xc, &w.rflags, &w.rexcl, &w.rmat, &w.rvals, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
                             &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
                             &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
                             &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt};
@@ -141,6 +142,7 @@ size_t workspace_bytes(int n, int maxdim)
     uint64_t maxbits = binom_sat(n, std::min(maxdim + 1, n) + 1);
     size_t b = 0;
     b += (size_t)n * n * 4 + (size_t)n * 4 * 4;
+    b += (size_t)n * n * 4;                 // rank-coded distances (sparse path)
     b += (size_t)E * 8 * 4;                 // edge keys / values, double buffered
     b += (size_t)maxc * (4 + 8 + 8);        // kept columns + tau
     b += (size_t)maxc * 8 * 4 * 2;          // partition outputs, double buffered
@@ -446,6 +448,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
 
     // ---------------- a2: H0 ---------------------------------------------
     int64_t nedges = 0;
+    const uint64_t *h0_keys = nullptr, *h0_cidx = nullptr;  // edges <= thr, diameter desc
     {
         EnumArgs ea{a.dcond_dev, n, 1, thr, ws.binom.as<uint64_t>(), nullptr, E};
         uint64_t nthr = 0, nclr = 0;
@@ -469,6 +472,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                                      32, ws.rscratch.as<uint64_t>(), s);
         const uint64_t *sk = where ? ws.ekey2.as<uint64_t>() : ws.ekey.as<uint64_t>();
         const uint64_t *sv = where ? ws.eval2.as<uint64_t>() : ws.eval.as<uint64_t>();
+        h0_keys = sk;
+        h0_cidx = sv;
         launch_fill_u32(ws.mst.as<uint32_t>(), (int64_t)(E / 32 + 1), 0u, s);
         int *counters = ws.scal.as<int>() + 8;
         launch_kruskal(sk, sv, nedges, n, ws.mst.as<uint32_t>(), ws.deaths.as<float>(),
@@ -545,6 +550,55 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                                hipMemcpyDeviceToHost, s));
     }
 
+    // Rank-coded diameters for the host reduction (sparse path): where a
+    // dimension's cofacet indices pass 2^32, the host keys hold the rank of
+    // the diameter among the distinct edge lengths under the threshold
+    // instead of its bit pattern, and fit 64 bits instead of 128.  The host
+    // then sees every distance as its rank: a matrix of ranks replaces its
+    // copy of the distances, and column and low diameters are recoded.
+    bool ranks = false;
+    int64_t nranks = 0;
+    std::vector<float> rank_vals;
+    if (sparse && nedges > 0 && nedges < (1 << 24)) {
+        // (RPP_RANK_CODING=1 takes this path whenever it can: tests)
+        const char *force = getenv("RPP_RANK_CODING");
+        bool wide = force && atoi(force) != 0;
+        for (int q = 1; q <= maxdim; ++q)
+            wide = wide || binom_sat(n, q + 2) > (1ull << 32);
+        if (wide) {
+            ALLOC_TRY(ws.rflags, (size_t)(nedges + 1) * 4);
+            ALLOC_TRY(ws.rexcl, (size_t)(nedges + 2) * 8);
+            ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(nedges) * 8);
+            launch_rank_flags(h0_keys, nedges, ws.rflags.as<uint32_t>(), s);
+            launch_exclusive_scan(ws.rflags.as<uint32_t>(), nedges, ws.rexcl.as<uint64_t>(),
+                                  ws.scan.as<uint64_t>(), s);
+            uint64_t *hs = ws.h_small.as<uint64_t>();
+            HIP_TRY(hipMemcpyAsync(hs, ws.rexcl.as<uint64_t>() + nedges, 8,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            nranks = (int64_t)hs[0];
+            ALLOC_TRY(ws.rmat, (size_t)n * n * 4);
+            ALLOC_TRY(ws.rvals, (size_t)(nranks + 1) * 4);
+            launch_rank_matrix(h0_keys, h0_cidx, ws.rflags.as<uint32_t>(),
+                               ws.rexcl.as<uint64_t>(), nedges, n, (float)nranks,
+                               ws.rmat.as<float>(), ws.rvals.as<float>(), s);
+            HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.rmat.p, (size_t)n * n * 4,
+                                   hipMemcpyDeviceToHost, s));
+            rank_vals.resize((size_t)nranks);
+            HIP_TRY(hipMemcpyAsync(rank_vals.data(), ws.rvals.p, (size_t)nranks * 4,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ranks = true;
+        }
+    }
+    int rank_bits = 0;
+    while (ranks && ((uint64_t)1 << rank_bits) <= (uint64_t)nranks)
+        ++rank_bits;
+    // a diameter seen by the host reduction, back as a length
+    auto length_of = [&](float x) -> float {
+        return (ranks && x < (float)nranks) ? rank_vals[(size_t)x] : x;
+    };
+
     // ---------------- dimensions 1..maxdim --------------------------------
     // Host reduction of each dimension: the speculative phase, then the
     // exact phase on a host thread that overlaps the next dimension's GPU
@@ -607,15 +661,15 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                     (long long)H.ndrop);
         for (size_t i = 0; i < RR.sigma.size(); ++i)
             if (RR.death[i] > RR.birth[i]) {
-                Dq.birth.push_back(RR.birth[i]);
-                Dq.death.push_back(RR.death[i]);
+                Dq.birth.push_back(length_of(RR.birth[i]));
+                Dq.death.push_back(length_of(RR.death[i]));
                 Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
                                                       RR.sigma[i], q));
                 Dq.death_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
                                                       RR.tau[i], q + 1));
             }
         for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
-            Dq.birth.push_back(RR.ess_birth[i]);
+            Dq.birth.push_back(length_of(RR.ess_birth[i]));
             Dq.death.push_back(INFINITY);
             Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
                                                   RR.ess_sigma[i], q));
@@ -745,6 +799,9 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         ALLOC_TRY(ws.h_na_cidx[hb], (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_low[hb], (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.h_lowd[hb], (size_t)(nna + 1) * 4);
+        if (ranks)
+            launch_recode_ranks(const_cast<uint64_t *>(d_nk), ws.lowd.as<float>(), nna,
+                                ws.rvals.as<float>(), nranks, s);
         if (nna) {
             HIP_TRY(hipMemcpyAsync(ws.h_na_key[hb].p, d_nk, (size_t)nna * 8,
                                    hipMemcpyDeviceToHost, s));
@@ -826,6 +883,10 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         H.P.app_tau = sorted_store ? ws.h_app_tau[hb].as<uint64_t>() : nullptr;
         H.P.app_sigma = sorted_store ? ws.h_app_sigma[hb].as<uint64_t>() : nullptr;
         H.P.spec_budget = SPEC_BUDGET;
+        if (ranks) {
+            H.P.rank_bits = rank_bits;
+            H.P.thr = (float)(nranks - 1);
+        }
         H.P.oblivious = (a.flags & RPP_OBLIVIOUS_REDUCTION) != 0;
         H.napp = napp;
         H.app_tau = ws.h_app_tau[hb].as<uint64_t>();

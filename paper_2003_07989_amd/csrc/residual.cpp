@@ -56,14 +56,34 @@ template <> struct KeyFmt<u128> {
     static constexpr int S = 64;
     static constexpr uint64_t M = ~0ull;
 };
-template <class K> inline K pack(float d, uint64_t c)
+// How a key is laid out: the diameter above an index field of `shift`
+// bits holding (mask - cidx).  By default the diameter is its float bit
+// pattern and the field is 32 or 64 bits wide (KeyFmt).  With rank-coded
+// diameters (integer ranks held as floats) the rank itself is stored and
+// the field is only as wide as the largest cofacet index needs, so 64-bit
+// keys cover indices past 2^32.
+struct KeyCodec {
+    int shift = 32;
+    uint64_t mask = 0xffffffffull;
+    bool rank = false;
+};
+template <class K> inline KeyCodec default_codec()
 {
-    return ((K)__builtin_bit_cast(uint32_t, d) << KeyFmt<K>::S) | (K)(KeyFmt<K>::M - c);
+    KeyCodec kc;
+    kc.shift = KeyFmt<K>::S;
+    kc.mask = KeyFmt<K>::M;
+    return kc;
 }
-template <class K> inline Entry unpack(K k)
+template <class K> inline K pack_key(const KeyCodec &kc, float d, uint64_t c)
 {
-    return Entry{__builtin_bit_cast(float, (uint32_t)(k >> KeyFmt<K>::S)),
-                 KeyFmt<K>::M - (uint64_t)(k & (K)KeyFmt<K>::M)};
+    const uint32_t hi = kc.rank ? (uint32_t)d : __builtin_bit_cast(uint32_t, d);
+    return ((K)hi << kc.shift) | (K)(kc.mask - c);
+}
+template <class K> inline Entry unpack_key(const KeyCodec &kc, K k)
+{
+    const uint32_t hi = (uint32_t)(k >> kc.shift);
+    return Entry{kc.rank ? (float)hi : __builtin_bit_cast(float, hi),
+                 kc.mask - (uint64_t)(k & (K)kc.mask)};
 }
 
 // Moves the c smallest of a[0..m) (distinct keys) to a[0..c), unordered:
@@ -409,6 +429,7 @@ struct DepthPolicy {
 template <class K> class Column {
 public:
     DepthPolicy *policy = nullptr;  // shared by the columns of one reduction
+    const KeyCodec *codec = nullptr;  // key layout of that reduction
     // Adds the coboundary in e[0..len) (arena storage) as a new stream; its
     // first `ties` keys are already in ascending order.
     void push_stream(K *e, size_t len, size_t ties)
@@ -460,7 +481,7 @@ public:
             for (size_t j = 1; j < e4; ++j)
                 dup |= hk[j] == e;
             if (!dup) {
-                out = unpack<K>(e);
+                out = unpack_key<K>(*codec, e);
                 return true;
             }
             advance_root();  // the other copy becomes the root
@@ -633,7 +654,11 @@ struct Ctx {
     const ResidualProblem &P;
     int n, p;
     mutable Arena arena;  // this thread's stream storage
-    Ctx(const ResidualProblem &pp, BlockSink *sink) : P(pp), n(pp.n), p(pp.p), arena(sink) {}
+    KeyCodec kc;          // key layout
+    Ctx(const ResidualProblem &pp, BlockSink *sink, const KeyCodec &codec)
+        : P(pp), n(pp.n), p(pp.p), arena(sink), kc(codec)
+    {
+    }
 
     uint64_t C(int v, int k) const { return P.binom[(int64_t)k * (n + 1) + v]; }
     float D(int a, int b) const { return P.dsq[(int64_t)a * n + b]; }
@@ -760,7 +785,7 @@ struct Ctx {
                         const float e = rows[i][w];
                         nd = e > nd ? e : nd;
                     }
-                    const K key = pack<K>(nd, base[k] + brow[k][w]);
+                    const K key = pack_key<K>(kc, nd, base[k] + brow[k][w]);
                     out[neq] = key;
                     gt[ngt] = key;
                     const bool tie = !(nd > d);
@@ -778,7 +803,7 @@ struct Ctx {
         out = arena.reserve<K>((size_t)n + 16);  // 16 slots of slack for vector stores
         K *gt = gt_scratch<K>();
         size_t cnt;
-        if (std::is_same<K, uint64_t>::value && HAVE_AVX512) {
+        if (std::is_same<K, uint64_t>::value && HAVE_AVX512 && !kc.rank && kc.shift == 32) {
             cnt = cob_dense_u64_avx512(rows, p + 1, v, sigma, d, P.thr, P.binom, n,
                                        reinterpret_cast<uint64_t *>(out),
                                        reinterpret_cast<uint64_t *>(gt), &ties);
@@ -822,7 +847,7 @@ struct Ctx {
                     mx = e > mx ? e : mx;
                 }
                 const float nd = mx > d ? mx : d;
-                const K key = pack<K>(nd, base + Cj[w]);
+                const K key = pack_key<K>(kc, nd, base + Cj[w]);
                 out[neq] = key;
                 gt[ngt] = key;
                 neq += (mx <= d) ? 1 : 0;
@@ -1075,8 +1100,8 @@ namespace {
 // constructor runs phase A, finish() phase B.
 template <class K> class SpecImpl final : public ResidualSpec {
 public:
-    explicit SpecImpl(const ResidualProblem &p)
-        : P(p), ncols(p.ncols), spec_low(p.ncols), spec_nz(p.ncols, 0), spec_adds(p.ncols, 0),
+    SpecImpl(const ResidualProblem &p, const KeyCodec &kc)
+        : codec(kc), P(p), ncols(p.ncols), spec_low(p.ncols), spec_nz(p.ncols, 0), spec_adds(p.ncols, 0),
           spec_cut(p.ncols, 0), state(p.ncols)
     {
         policy.prior = p.p == 1;
@@ -1127,7 +1152,7 @@ private:
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
         const int64_t budget = P.spec_budget;
         auto phase_a = [&](int) {
-            Ctx X(P, &sink);
+            Ctx X(P, &sink, codec);
             int64_t looks = 0;
             while (true) {
                 const int64_t j0 = next.fetch_add(chunk);
@@ -1147,6 +1172,7 @@ private:
                     }
                     std::unique_ptr<Column<K>> col(new Column<K>());
                     col->policy = &policy;
+                    col->codec = &codec;
                     X.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
                     bool nz;
                     int64_t adds = 0;
@@ -1317,6 +1343,7 @@ private:
             if (!col) {
                 col.reset(new Column<K>());
                 col->policy = &policy;
+                col->codec = &codec;
                 Xc.add_coboundary(*col, P.col_cidx[j], diam_of_key(j));
             }
             Entry lo = spec_low[j];
@@ -1356,7 +1383,7 @@ private:
             look_app_b += la;
         };
 
-        Ctx X(P, &sink);
+        Ctx X(P, &sink, codec);
         int64_t frontier = 0;
         std::vector<int64_t> round;
         while (frontier < ncols) {
@@ -1382,7 +1409,7 @@ private:
             } else {
                 std::atomic<int64_t> nx{0};
                 pool.run([&](int) {
-                    Ctx Xw(P, &sink);
+                    Ctx Xw(P, &sink, codec);
                     for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size(); i = nx.fetch_add(1))
                         advance(Xw, round[i]);
                 });
@@ -1403,6 +1430,7 @@ private:
 
     BlockSink sink;  // stream storage of every column below; freed last
     DepthPolicy policy;
+    const KeyCodec codec;
     const ResidualProblem P;
     const int64_t ncols;
     std::vector<Entry> spec_low;
@@ -1419,11 +1447,25 @@ std::unique_ptr<ResidualSpec> residual_speculate(const ResidualProblem &P)
 {
     // largest cofacet index + 1 = C(n, p+2)
     const uint64_t ncof = P.binom[(int64_t)(P.p + 2) * (P.n + 1) + P.n];
-    // RPP_WIDE_KEYS=1 takes the 128-bit keys even where 64 suffice (tests)
-    static const bool wide = getenv("RPP_WIDE_KEYS") && atoi(getenv("RPP_WIDE_KEYS")) != 0;
-    if (ncof <= (1ull << 32) && !wide)
-        return std::unique_ptr<ResidualSpec>(new SpecImpl<uint64_t>(P));
-    return std::unique_ptr<ResidualSpec>(new SpecImpl<u128>(P));
+    // tests: RPP_WIDE_KEYS=1 takes the 128-bit keys even where 64 suffice,
+    // RPP_RANK_KEYS=1 the rank-coded ones whenever diameters are ranks
+    const char *wide_env = getenv("RPP_WIDE_KEYS"), *rank_env = getenv("RPP_RANK_KEYS");
+    const bool wide = wide_env && atoi(wide_env) != 0;
+    const bool rank_keys = rank_env && atoi(rank_env) != 0;
+    if (ncof <= (1ull << 32) && !wide && !(rank_keys && P.rank_bits > 0))
+        return std::unique_ptr<ResidualSpec>(
+            new SpecImpl<uint64_t>(P, default_codec<uint64_t>()));
+    int cbits = 0;  // bits of the largest cofacet index, ncof - 1
+    while (cbits < 64 && ((ncof - 1) >> cbits) != 0)
+        ++cbits;
+    if (P.rank_bits > 0 && P.rank_bits <= 24 && P.rank_bits + cbits <= 64 && !wide) {
+        KeyCodec kc;
+        kc.rank = true;
+        kc.shift = cbits;
+        kc.mask = cbits == 64 ? ~0ull : (1ull << cbits) - 1;
+        return std::unique_ptr<ResidualSpec>(new SpecImpl<uint64_t>(P, kc));
+    }
+    return std::unique_ptr<ResidualSpec>(new SpecImpl<u128>(P, default_codec<u128>()));
 }
 
 void residual_reduce(const ResidualProblem &P, ResidualResult &R)

@@ -51,6 +51,12 @@ struct ResidualProblem {
     // on oblivious reduction makes the pairs and classes identical; the
     // oblivious form needs less memory and may need more additions.
     bool oblivious = false;
+    // > 0: every diameter in this problem -- dsq, col_key, col_low_diam,
+    // thr -- is an integer rank below 2^rank_bits (<= 24) held as a float
+    // (ranks of the distinct edge lengths, ascending), so keys can pack the
+    // rank and the cofacet index into 64 bits where the diameter's bit
+    // pattern and the index would need 128.  The results carry ranks too.
+    int rank_bits = 0;
 };
 
 struct ResidualResult {

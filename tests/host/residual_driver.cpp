@@ -90,7 +90,8 @@ int main(int argc, char **argv)
         return 2;
     N = atoi(argv[2]);
     const int maxdim = atoi(argv[3]);
-    const float thr = (float)atof(argv[4]);
+    float thr = (float)atof(argv[4]);
+    // mode & 32: rank-coded diameters (below);
     // mode & 16: cofacets through neighbour bitsets (the sparse path);
     // mode & 3: schedule (0 plain, 1 speculative budget, 2 overlapped,
     // 3 overlapped with the dropped columns known late: columns park past
@@ -110,6 +111,34 @@ int main(int argc, char **argv)
     for (int i = 1; i < n; ++i)
         for (int j = 0; j < i; ++j)
             Dsq[(size_t)i * n + j] = Dsq[(size_t)j * n + i] = dc[(size_t)i * (i - 1) / 2 + j];
+    // Rank-coded diameters: every distance within the threshold becomes the
+    // rank of its length among the distinct ones (as a float), larger ones a
+    // rank above them all, and the threshold the top rank.  Every
+    // comparison keeps its outcome, so pairs and classes must not change.
+    int rank_bits = 0;
+    if (mode & 32) {
+        std::vector<float> vals;
+        for (int i = 1; i < n; ++i)
+            for (int j = 0; j < i; ++j)
+                if (Dsq[(size_t)i * n + j] <= thr)
+                    vals.push_back(Dsq[(size_t)i * n + j]);
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        const float above = (float)vals.size();
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                float &x = Dsq[(size_t)i * n + j];
+                if (i == j)
+                    x = 0.0f;
+                else if (x <= thr)
+                    x = (float)(std::lower_bound(vals.begin(), vals.end(), x) - vals.begin());
+                else
+                    x = above;
+            }
+        thr = vals.empty() ? 0.0f : (float)(vals.size() - 1);
+        while ((1u << rank_bits) <= vals.size())
+            ++rank_bits;
+    }
     const int K = maxdim + 2;
     B.assign((size_t)(K + 1) * (n + 1), 0);
     for (int k = 0; k <= K; ++k)
@@ -259,6 +288,7 @@ int main(int argc, char **argv)
         P.col_low = low.data();
         P.col_low_diam = lowd.data();
         P.napp = napp;
+        P.rank_bits = rank_bits;
         // mode & 16: cofacets from neighbour bitsets (the sparse path)
         std::vector<uint64_t> bits;
         if (mode & 16) {

@@ -309,6 +309,25 @@ def test_sparse_path_matches_oracle(rpp, case):
         assert st["n_simplices"] == oracle.count_simplices(d, n, p, thr)
 
 
+@pytest.mark.parametrize("case", SPARSE_CASES[::2], ids=["rk_" + c[0] for c in SPARSE_CASES[::2]])
+def test_rank_coded_host_keys_match_oracle(rpp, case, monkeypatch):
+    """Sparse path with the host reduction on rank-coded diameters and
+    64-bit rank keys (taken by default only where cofacet indices pass
+    2^32, forced here on small inputs): the oracle's bars and pairs."""
+    name, d, n, maxdim, thr = case
+    monkeypatch.setenv("RPP_RANK_CODING", "1")
+    monkeypatch.setenv("RPP_RANK_KEYS", "1")
+    got = rpp.barcodes(d, maxdim, thr, flags=rpp.RPP_FORCE_SPARSE)
+    assert_bars_equal(got.bars, _oracle_bars(d, n, maxdim, thr), name)
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    g = rpp.barcodes(d, maxdim, thr, flags=f | rpp.RPP_WANT_CRITICAL_EDGES)
+    red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+    for p in range(1, maxdim + 1):
+        gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+        es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+        assert gs == es, (name, p)
+
+
 def test_sparse_and_dense_paths_agree_on_maxdim3(rpp):
     d = w.condensed_from_points(w.noisy_torus_points(60, 77))
     thr = float(np.quantile(d, 0.2))

@@ -119,3 +119,22 @@ def test_wide_keys_match_oracle(driver, mode):
         for p in range(1, maxdim + 1):
             assert got_p[p] == exp_p[p], (name, mode, p)
             assert got_e[p] == exp_e[p], (name, mode, p)
+
+
+@pytest.mark.parametrize("mode", [32, 35, 48, 51], ids=["ranks", "ranks-late-drops",
+                                                      "ranks-bitsets",
+                                                      "ranks-bitsets-late-drops"])
+def test_rank_coded_keys_match_oracle(driver, mode):
+    """Diameters replaced by the ranks of the distinct edge lengths, and
+    keys that pack the rank above a cofacet-index field only as wide as the
+    largest index (the layout that gives 64-bit keys where indices pass
+    2^32): the same pairs and classes."""
+    for name, build, n, maxdim, thr in CASES:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        got_p, got_e = _run(driver, d, n, maxdim, thr, mode, env={"RPP_RANK_KEYS": "1"})
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, p)
+            assert got_e[p] == exp_e[p], (name, mode, p)
