@@ -30,7 +30,6 @@
 #include <stdexcept>
 #include <mutex>
 #include <thread>
-#include <unordered_map>
 
 namespace rpp {
 
@@ -420,6 +419,100 @@ struct DepthPolicy {
             return prior;
         return deep.load(std::memory_order_relaxed) * 4 > s;
     }
+};
+
+// Hash map from cofacet indices (never ~0) to column positions: open
+// addressing with linear probing over a power-of-two table, backward-shift
+// deletion.  One flat array instead of a node per entry (the exact phase
+// inserts a pivot for every nonzero column: 787k on the dimension-3
+// sphere).
+class FlatMap {
+public:
+    explicit FlatMap(size_t expected)
+    {
+        size_t c = 16;
+        while (c < 2 * expected + 16)
+            c *= 2;
+        keys_.assign(c, EMPTY);
+        vals_.resize(c);
+        mask_ = c - 1;
+    }
+    // The value of key k, or nullptr.
+    int64_t *find(uint64_t k)
+    {
+        for (size_t i = home(k);; i = (i + 1) & mask_) {
+            if (keys_[i] == k)
+                return &vals_[i];
+            if (keys_[i] == EMPTY)
+                return nullptr;
+        }
+    }
+    // Inserts (k, v) unless k is present; the value slot and whether it was
+    // inserted.
+    std::pair<int64_t *, bool> emplace(uint64_t k, int64_t v)
+    {
+        if (2 * (size_ + 1) > keys_.size())
+            grow();
+        for (size_t i = home(k);; i = (i + 1) & mask_) {
+            if (keys_[i] == k)
+                return {&vals_[i], false};
+            if (keys_[i] == EMPTY) {
+                keys_[i] = k;
+                vals_[i] = v;
+                ++size_;
+                return {&vals_[i], true};
+            }
+        }
+    }
+    void erase(uint64_t k)
+    {
+        size_t i = home(k);
+        while (keys_[i] != k) {
+            if (keys_[i] == EMPTY)
+                return;
+            i = (i + 1) & mask_;
+        }
+        // shift back the entries of the cluster that may fill the hole
+        for (size_t j = (i + 1) & mask_; keys_[j] != EMPTY; j = (j + 1) & mask_) {
+            const size_t h = home(keys_[j]);
+            if (((j - h) & mask_) >= ((j - i) & mask_)) {
+                keys_[i] = keys_[j];
+                vals_[i] = vals_[j];
+                i = j;
+            }
+        }
+        keys_[i] = EMPTY;
+        --size_;
+    }
+
+private:
+    static constexpr uint64_t EMPTY = ~0ull;
+    size_t home(uint64_t k) const
+    {
+        k ^= k >> 33;  // a 64-bit mixer (the MurmurHash3 finaliser)
+        k *= 0xff51afd7ed558ccdull;
+        k ^= k >> 33;
+        k *= 0xc4ceb9fe1a85ec53ull;
+        k ^= k >> 33;
+        return (size_t)k & mask_;
+    }
+    void grow()
+    {
+        std::vector<uint64_t> ok;
+        std::vector<int64_t> ov;
+        ok.swap(keys_);
+        ov.swap(vals_);
+        keys_.assign(ok.size() * 2, EMPTY);
+        vals_.resize(ok.size() * 2);
+        mask_ = keys_.size() - 1;
+        size_ = 0;
+        for (size_t i = 0; i < ok.size(); ++i)
+            if (ok[i] != EMPTY)
+                emplace(ok[i], ov[i]);
+    }
+    std::vector<uint64_t> keys_;
+    std::vector<int64_t> vals_;
+    size_t mask_ = 0, size_ = 0;
 };
 
 // Working column = Z/2 sum of several coboundaries.  Each added coboundary
@@ -1237,20 +1330,18 @@ private:
         bool known = false;
         std::vector<uint8_t> parked(ncols, 0);
         std::vector<int64_t> parked_list, zero_open;
-        std::unordered_map<uint64_t, int64_t> pivots;  // tau -> index in R.sigma
-        pivots.reserve((size_t)ncols * 2 + 16);
+        FlatMap pivots((size_t)ncols);  // tau -> index in R.sigma
         std::vector<std::unique_ptr<Column<K>>> reduced;  // by index in R.sigma
         reduced.reserve((size_t)ncols);
-        std::unordered_map<uint64_t, int64_t> whead;  // low -> last waiting column
-        whead.reserve((size_t)ncols * 2 + 16);
+        FlatMap whead((size_t)ncols);  // low -> last waiting column
         std::vector<int64_t> wnext(ncols, -1);
         std::vector<uint8_t> pending(ncols, 0);
         std::vector<int64_t> work;
         auto wait_on = [&](int64_t j) {
             auto r = whead.emplace(spec_low[j].cidx, j);
             if (!r.second) {
-                wnext[j] = r.first->second;
-                r.first->second = j;
+                wnext[j] = *r.first;
+                *r.first = j;
             } else {
                 wnext[j] = -1;
             }
@@ -1296,15 +1387,15 @@ private:
             // oblivious: nothing is kept, a later column adds D_k instead
             reduced.push_back(spec_adds[j] && !P.oblivious ? std::move(state[j]) : nullptr);
             state[j].reset();
-            auto it = whead.find(lo.cidx);
-            if (it == whead.end())
+            const int64_t *it = whead.find(lo.cidx);
+            if (!it)
                 return;
-            for (int64_t k = it->second; k >= 0; k = wnext[k])
+            for (int64_t k = *it; k >= 0; k = wnext[k])
                 if (k != j && spec_nz[k] && spec_low[k].cidx == lo.cidx && !pending[k]) {
                     pending[k] = 1;
                     work.push_back(k);
                 }
-            whead.erase(it);
+            whead.erase(lo.cidx);
         };
 
         // The dropped columns are known: drop them, classify the open zero
@@ -1356,10 +1447,10 @@ private:
                 }
                 // the owner of the low: a final host column, else an
                 // apparent column, else the column stops here
-                auto f = pivots.find(lo.cidx);
-                if (f != pivots.end()) {
+                const int64_t *f = pivots.find(lo.cidx);
+                if (f) {
                     ++lh;
-                    const int64_t k = f->second;
+                    const int64_t k = *f;
                     if (reduced[k])
                         col->add(*reduced[k], Xc.arena);
                     else
