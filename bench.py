@@ -46,6 +46,16 @@ def algorithmic_bytes_apparent(st: dict, p: int) -> float:
     return st["n_kept"] * 20.0 + 4.0 * (p + 1) * st["n_scanned"]
 
 
+def apparent_kernel_name(p, g):
+    """The apparent kernel a dimension ran, from its apparent_group stat:
+    negative for the sparse kernel, 100 K + G for the two-phase kernel."""
+    if g < 0:
+        return "k_apparent_sparse<%d,%d>" % (p, -g)
+    if g >= 100:
+        return "k_apparent2<%d,%d,%d>" % (p, g // 100, g % 100)
+    return "k_apparent<%d,%d>" % (p, g)
+
+
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary committed under profiles/, scaled by a copy kernel
@@ -531,8 +541,8 @@ def bench_perm(args, n0, kind="perm"):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("%s%d" % (kind, n0),
-                                                 "k_apparent<1,%d>" % st["apparent_group"]),
-                     "kernel": "k_apparent<1,%d>" % st["apparent_group"], "dim": 1,
+                                                 apparent_kernel_name(1, st["apparent_group"])),
+                     "kernel": apparent_kernel_name(1, st["apparent_group"]), "dim": 1,
                      "ms": round(kms, 4), "bytes": kbytes},
     }
     if not args.no_cpu_baseline and kind == "perm":
@@ -650,8 +660,7 @@ def main():
     achieved = kbytes / (kms / 1e3) / 1e9 if kms > 0 else 0.0
     g = st.get("apparent_group", 8)
     if kname == "apparent":
-        kfull = ("k_apparent_sparse<%d,%d>" % (top, -g) if g < 0
-                 else "k_apparent<%d,%d>" % (top, g))
+        kfull = apparent_kernel_name(top, g)
     elif g < 0:
         kfull = "k_ext<%d>" % top  # sparse enumeration (count + scatter passes)
     else:

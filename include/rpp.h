@@ -130,7 +130,10 @@ typedef struct {
     float ms_sort;          /* device time: key sorts and clearing bitmap */
     int32_t apparent_group; /* lanes that test one column in the apparent
                                kernel; negative when it was the sparse kernel
-                               (candidates from neighbour bitsets) */
+                               (candidates from neighbour bitsets); 100 K + G
+                               for the two-phase dense kernel (each lane alone
+                               on the top K candidates of its column, then G
+                               lanes per column still open) */
 } rpp_dim_stats;
 
 typedef struct {

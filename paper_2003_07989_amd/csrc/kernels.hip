@@ -335,7 +335,6 @@ __device__ __forceinline__ float dc_at(const float *__restrict__ dcond, int a, i
     return dcond[(int64_t)a * (a - 1) / 2 + b];
 }
 
-// 0 = kept, 1 = removed by the threshold, 2 = removed by clearing.
 // Per-cloud view of the enumeration arguments (batched launches).
 __device__ __forceinline__ EnumArgs enum_view(EnumArgs a)
 {
@@ -350,25 +349,94 @@ __device__ __forceinline__ EnumArgs enum_view(EnumArgs a)
     return a;
 }
 
-template <int P>
-__device__ __forceinline__ int enum_eval(const EnumArgs &a, const Binom &B, uint64_t c,
-                                         float &diam)
-{
-    float d;
-    if (P == 1) {
-        d = a.dcond[c];
-    } else {
-        int v[P + 1];
-        decode<P>(B, c, a.n, v);
-        d = 0.0f;
+// A lane's walk through consecutive candidates.  A wave owns a contiguous
+// run of CI * 64 candidates of its workgroup's tile and steps through it 64
+// at a time, lane i at candidate run + 64 k + i, so reads and writes stay
+// coalesced; instead of decoding every candidate, a lane moves its vertex
+// tuple forward by 64: within the current row (v_0 .. v_{P-1} fixed) the
+// last vertex just grows, across up to four row ends the next-to-last vertex
+// carries, and only a longer jump decodes afresh.  The walk itself is
+// register arithmetic, so a chunk of steps computes all its condensed
+// offsets first and then issues every load of the chunk at once.
+template <int P> struct EnumWalk {
+    static constexpr int NPAIR = (P + 1) * P / 2;
+    int v[P + 1];
+    // to candidate c_new = current + delta (c_new < number of candidates)
+    __device__ __forceinline__ void advance(const Binom &B, uint64_t c_new, int delta, int n)
+    {
+        const int x = v[P] + delta;
+        if (x < v[P - 1]) {
+            v[P] = x;
+            return;
+        }
+        int y = v[P - 1] + 1;  // next row: v_P runs over [0, y)
+        int e = x - v[P - 1];  // position in it
+        const int lim = P >= 2 ? v[P >= 2 ? P - 2 : 0] : n;
+        for (int it = 0; it < 3 && e >= y && y + 1 < lim; ++it) {
+            e -= y;  // past that row too
+            ++y;
+        }
+        if (y < lim && e < y) {
+            v[P - 1] = y;
+            v[P] = e;
+        } else {
+            decode<P>(B, c_new, n, v);
+        }
+    }
+    // condensed offsets a (a - 1) / 2 + b of every pair a > b of the simplex
+    // (n <= 65535 keeps them below 2^31)
+    __device__ __forceinline__ void offsets(uint32_t (&o)[NPAIR]) const
+    {
+        int q = 0;
 #pragma unroll
-        for (int i = 0; i < P; ++i)
+        for (int i = 0; i < P; ++i) {
+            const uint32_t r = (uint32_t)v[i] * (uint32_t)(v[i] - 1) / 2u;
 #pragma unroll
             for (int j = i + 1; j <= P; ++j)
-                d = fmaxf(d, dc_at(a.dcond, v[i], v[j]));
+                o[q++] = r + (uint32_t)v[j];
+        }
     }
-    d = d + 0.0f;
-    diam = d;
+};
+
+// Steps per chunk of the walk: all loads of a chunk are in flight together.
+template <int P> struct EnumChunk {
+    static constexpr int S = P <= 2 ? 8 : P == 3 ? 4 : 2;
+};
+
+// Diameters of the candidates c0 + 64 (k0 + s), s < S, of a lane's walk
+// (valid where the candidate exists), advancing the walk past them.
+template <int P, int S>
+__device__ __forceinline__ void enum_chunk(EnumWalk<P> &wk, const Binom &B, const EnumArgs &a,
+                                           uint64_t c, int k0, float (&d)[S])
+{
+    constexpr int NP = EnumWalk<P>::NPAIR;
+    uint32_t o[S][NP];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint64_t cs = c + (uint64_t)s * WAVE;
+        if (cs < a.ncand) {
+            wk.offsets(o[s]);
+            if (k0 + s + 1 < CI && cs + WAVE < a.ncand)
+                wk.advance(B, cs + WAVE, WAVE, a.n);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                o[s][q] = 0;  // a harmless load; the candidate is ignored
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        float x = 0.0f;
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+            x = fmaxf(x, a.dcond[o[s][q]]);
+        d[s] = x + 0.0f;  // -0 -> +0
+    }
+}
+
+// 0 = kept, 1 = removed by the threshold, 2 = removed by clearing.
+__device__ __forceinline__ int enum_filter(const EnumArgs &a, uint64_t c, float d)
+{
     if (!(d <= a.thr))
         return 1;
     if (a.clear && ((a.clear[c >> 5] >> (c & 31)) & 1u))
@@ -385,18 +453,35 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
     tile_counts += (int64_t)blockIdx.y * gridDim.x;
     stats += 2 * blockIdx.y;
     const Binom B{a.binom, a.n + 1};
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
-    const uint64_t base = (uint64_t)tile * COMPACT_TILE;
+    uint64_t c = (uint64_t)tile * COMPACT_TILE + (uint64_t)wave * (CI * WAVE) + lane;
     uint32_t keep = 0, nthr = 0, nclr = 0;
-#pragma unroll 4
-    for (int k = 0; k < CI; ++k) {
-        uint64_t c = base + (uint64_t)k * CT + threadIdx.x;
-        if (c < a.ncand) {
-            float d;
-            int r = enum_eval<P>(a, B, c, d);
+    if (P == 1) {
+        for (int k = 0; k < CI && c < a.ncand; ++k, c += WAVE) {
+            const int r = enum_filter(a, c, a.dcond[c] + 0.0f);
             keep += (r == 0);
             nthr += (r == 1);
             nclr += (r == 2);
+        }
+    } else if (c < a.ncand) {
+        constexpr int S = EnumChunk<P>::S;
+        EnumWalk<P> wk;
+        decode<P>(B, c, a.n, wk.v);
+        for (int k0 = 0; k0 < CI; k0 += S) {
+            float d[S];
+            enum_chunk<P, S>(wk, B, a, c, k0, d);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const uint64_t cs = c + (uint64_t)s * WAVE;
+                if (cs < a.ncand) {
+                    const int r = enum_filter(a, cs, d[s]);
+                    keep += (r == 0);
+                    nthr += (r == 1);
+                    nclr += (r == 2);
+                }
+            }
+            c += (uint64_t)S * WAVE;
         }
     }
     uint32_t sk = block_sum<CT>(keep, sh);
@@ -425,30 +510,55 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
     const Binom B{a.binom, a.n + 1};
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
-    const uint64_t base = (uint64_t)tile * COMPACT_TILE;
-    uint64_t running = tile_offsets[tile];
-    for (int k = 0; k < CI; ++k) {
-        uint64_t c = base + (uint64_t)k * CT + threadIdx.x;
-        float d = 0.0f;
-        bool keep = (c < a.ncand) && enum_eval<P>(a, B, c, d) == 0;
-        uint64_t m = __ballot(keep);
-        if (lane == 0)
-            wsum[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t pre = 0, tot = 0;
+    const uint64_t c0 = (uint64_t)tile * COMPACT_TILE + (uint64_t)wave * (CI * WAVE) + lane;
+    // sweep 1: every candidate once; keep flags as bits, diameters in registers
+    float dk[CI];
+    uint32_t bits = 0;
+    uint32_t total = 0;  // kept by the wave
+    if (P == 1) {
 #pragma unroll
-        for (int w = 0; w < CT / WAVE; ++w) {
-            uint32_t x = wsum[w];
-            pre += (w < wave) ? x : 0;
-            tot += x;
+        for (int k = 0; k < CI; ++k) {
+            const uint64_t c = c0 + (uint64_t)k * WAVE;
+            dk[k] = c < a.ncand ? a.dcond[c] + 0.0f : 0.0f;
         }
+    } else if (c0 < a.ncand) {
+        constexpr int S = EnumChunk<P>::S;
+        EnumWalk<P> wk;
+        decode<P>(B, c0, a.n, wk.v);
+#pragma unroll
+        for (int k0 = 0; k0 < CI; k0 += S) {
+            float d[S];
+            enum_chunk<P, S>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                dk[k0 + s] = d[s];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+        const uint64_t c = c0 + (uint64_t)k * WAVE;
+        const bool keep = c < a.ncand && enum_filter(a, c, dk[k]) == 0;
+        bits |= (keep ? 1u : 0u) << k;
+        total += (uint32_t)__popcll(__ballot(keep));
+    }
+    if (lane == 0)
+        wsum[wave] = total;
+    __syncthreads();
+    uint64_t running = tile_offsets[tile];
+#pragma unroll
+    for (int w = 0; w < CT / WAVE; ++w)
+        running += (w < wave) ? wsum[w] : 0;
+    // sweep 2: the kept candidates in cidx order, coalesced per step
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+        const bool keep = (bits >> k) & 1u;
+        const uint64_t m = __ballot(keep);
         if (keep) {
-            uint64_t pos = running + pre + (uint32_t)__popcll(m & lanemask_lt());
-            out_diam[pos] = d;
-            out_cidx[pos] = c;
+            const uint64_t pos = running + (uint32_t)__popcll(m & lanemask_lt());
+            out_diam[pos] = dk[k];
+            out_cidx[pos] = c0 + (uint64_t)k * WAVE;
         }
-        running += tot;
-        __syncthreads();
+        running += (uint32_t)__popcll(m);
     }
 }
 
@@ -657,12 +767,261 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
         tau_out[mycol] = mytau;
 }
 
+// Two-phase form for short scans.  Most columns find their oldest cofacet
+// among the first few candidates (on a dense torus 85% within 4), but a
+// wave of k_apparent runs until its deepest group is done.  Here every lane
+// first tests the top K candidates of its own column with all loads in
+// flight at once; the columns still open after them are numbered within the
+// wave (ballot + popcount) and scanned G lanes per column from candidate
+// n-1-K down, as in k_apparent.  A wave owns 64 consecutive columns.
+__device__ __forceinline__ int select_set_bit(uint64_t m, int t)
+{
+    // lane index of the t-th set bit of m (t < popcount(m))
+    int pos = 0;
+#pragma unroll
+    for (int half = 32; half >= 1; half >>= 1) {
+        const uint64_t low = m & ((1ull << half) - 1);
+        const int c = __popcll(low);
+        const bool up = t >= c;
+        t -= up ? c : 0;
+        m = up ? (m >> half) : low;
+        pos += up ? half : 0;
+    }
+    return pos;
+}
+
+template <int P, int K, int G>
+__global__ __launch_bounds__(256) void k_apparent2(const float *__restrict__ col_diam,
+                                                   const uint64_t *__restrict__ col_cidx,
+                                                   int64_t ncols, const float *__restrict__ dsq,
+                                                   int n, const uint64_t *__restrict__ binom,
+                                                   uint64_t *__restrict__ tau_out,
+                                                   unsigned long long *__restrict__ scan_count)
+{
+    constexpr int CPR = WAVE / G;  // open columns per round of phase 2
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = ((blk * blockDim.x + threadIdx.x) / WAVE) * WAVE;
+    if (base >= ncols)
+        return;  // whole waves leave together
+    const Binom B{binom, n + 1};
+    const int64_t mycol = base + lane;
+    const bool myvalid = mycol < ncols;
+    float myd = 0.0f;
+    int myv[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        decode<P>(B, col_cidx[mycol], n, myv);
+    }
+
+    // ---- phase 1: candidates n-1 .. n-K of the lane's own column ----
+    float dv[P + 1][P + 1];  // distances among sigma's vertices
+    float ew[P + 1];         // d(v_i, w) at the hit
+    int w = -1;
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        ew[i] = 0.0f;
+    if (myvalid) {
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)myv[i] * n;
+        float e[K][P + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = n - 1 - k >= 0 ? n - 1 - k : 0;  // in bounds; n-1-k < 0 never hits
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                e[k][i] = row[i][u];
+        }
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= P; ++b)
+                dv[a][b] = row[a][myv[b]];
+        // the largest passing u wins: k runs down so k = 0 is applied last
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int u = n - 1 - k;
+            bool ok = u >= 0;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                ok = ok && (u != myv[i]) && (e[k][i] <= myd);
+            if (ok) {
+                w = u;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    ew[i] = e[k][i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= P; ++b)
+                dv[a][b] = 0.0f;
+    }
+    // open: no hit among the K and candidates below them remain
+    const bool open = myvalid && w < 0 && n - 1 - K >= 0;
+    const uint64_t omask = __ballot(open);
+
+    // ---- phase 2: open columns, G lanes each ----
+    const int nopen = __popcll(omask);
+    uint64_t tau2 = NONE;  // this lane's tau when its column was open
+    int w2 = -1;           // and its hit (scan count)
+    for (int r = 0; r * CPR < nopen; ++r) {
+        const int t = r * CPR + grp;
+        const bool valid = t < nopen;  // uniform in the group
+        const int src = valid ? select_set_bit(omask, t) : lane;
+        const float d = __shfl(myd, src, WAVE);
+        int v[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            v[i] = __shfl(myv[i], src, WAVE);
+        float dvv[P + 1][P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= P; ++b)
+                dvv[a][b] = __shfl(dv[a][b], src, WAVE);
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)v[i] * n;
+        int ww = -1, hit = 0;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = n - 1 - K; top >= 0; top -= G) {
+                const int u = top - g;
+                bool ok = u >= 0;
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        e[i] = row[i][u];
+                        ok = ok && (u != v[i]) && (e[i] <= d);
+                    }
+                }
+                const uint64_t m = __ballot(ok) & gmask;
+                if (m) {
+                    hit = __ffsll((unsigned long long)m) - 1;  // lane of the largest u
+                    ww = top - (hit - gbase);
+                    break;
+                }
+            }
+        }
+        float eh[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            eh[i] = __shfl(e[i], ww >= 0 ? hit : lane, WAVE);
+        uint64_t tau = NONE;
+        if (ww >= 0) {
+            bool apparent = true;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                if (v[j] > ww && apparent) {
+                    float fd = 0.0f;
+#pragma unroll
+                    for (int a = 0; a <= P; ++a) {
+                        if (a == j)
+                            continue;
+                        fd = fmaxf(fd, eh[a]);
+#pragma unroll
+                        for (int b = a + 1; b <= P; ++b)
+                            if (b != j)
+                                fd = fmaxf(fd, dvv[a][b]);
+                    }
+                    if (fd == d)
+                        apparent = false;
+                }
+            }
+            if (apparent)
+                tau = cofacet_index<P>(B, v, ww);
+        }
+        // the owner of open column t is the t-th set lane of omask; group
+        // (t mod CPR)'s first lane holds its tau
+        const int mine = open ? __popcll(omask & ((1ull << lane) - 1)) : -1;
+        const int from = mine >= 0 ? (mine % CPR) * G : lane;
+        const uint64_t tt = shfl_u64(tau, from);
+        const int wt = __shfl(ww, from, WAVE);
+        if (mine >= 0 && mine / CPR == r) {
+            tau2 = tt;
+            w2 = wt;
+        }
+    }
+
+    if (!myvalid)
+        return;
+    uint64_t mytau = NONE;
+    if (open) {
+        mytau = tau2;
+        w = w2;
+    } else if (w >= 0) {
+        bool apparent = true;
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            if (myv[j] > w && apparent) {
+                // facet sigma - {v_j} + {w}
+                float fd = 0.0f;
+#pragma unroll
+                for (int a = 0; a <= P; ++a) {
+                    if (a == j)
+                        continue;
+                    fd = fmaxf(fd, ew[a]);
+#pragma unroll
+                    for (int b = a + 1; b <= P; ++b)
+                        if (b != j)
+                            fd = fmaxf(fd, dv[a][b]);
+                }
+                if (fd == myd)
+                    apparent = false;
+            }
+        }
+        if (apparent)
+            mytau = cofacet_index<P>(B, myv, w);
+    }
+    if (scan_count) {
+        // candidates w not in sigma, visited from n-1 down to w*
+        long long sc = n - P - 1;
+        if (w >= 0) {
+            sc = (n - 1) - w + 1;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                sc -= (myv[i] > w);
+        }
+        atomicAdd(&scan_count[(blockIdx.x * 4 + lane) & (SCAN_COUNTERS - 1)],
+                  (unsigned long long)sc);
+    }
+    tau_out[mycol] = mytau;
+}
+
 template <int P>
 static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
                               const float *dsq, int n, const uint64_t *binom, int group,
                               uint64_t *tau, unsigned long long *sc, hipStream_t s,
                               Batch bt = Batch(), int nbatch = 1)
 {
+    if (group >= 100 && nbatch <= 1 && bt.count == nullptr && bt.stride == 0) {
+        // two-phase kernel: group = 100 K + G (K candidates alone, then G
+        // lanes per open column)
+        const int64_t waves = (ncols + WAVE - 1) / WAVE;
+        dim3 g((unsigned)((waves * WAVE + 255) / 256)), b(256);
+        switch (group) {
+        case 416: hipLaunchKernelGGL((k_apparent2<P, 4, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+        case 808: hipLaunchKernelGGL((k_apparent2<P, 8, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+        default: hipLaunchKernelGGL((k_apparent2<P, 4, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+        }
+        return;
+    }
     if (group != 1 && group != 4 && group != 16 && group != 32 && group != 64)
         group = 8;  // the instantiated group sizes; 8 is the default
     // Rounds per wave (each round covers 64/group columns): as many as the

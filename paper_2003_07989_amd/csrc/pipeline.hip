@@ -157,6 +157,12 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
                            uint64_t *nthr, uint64_t *nclr, std::string &err,
                            GpuTimer *tm = nullptr)
 {
+    if (ea.p >= 2 && ea.n > 65535) {
+        // the enumeration walks address the condensed matrix with 32-bit
+        // offsets (and C(n, 3) candidates would not fit in any case)
+        err = "dense enumeration of p >= 2 needs n <= 65535";
+        return RPP_E_RANGE;
+    }
     const int64_t tiles = compact_tiles((int64_t)ea.ncand);
     ALLOC_TRY(ws.tcount, (size_t)(tiles + 1) * 4);
     ALLOC_TRY(ws.toff, (size_t)(tiles + 2) * 8);
@@ -334,19 +340,24 @@ static int64_t open_cap()
     return e ? std::max<int64_t>(1, atoll(e)) : OPEN_CAP;
 }
 
+// 100 K + G selects the two-phase kernel (K candidates per lane alone,
+// then G lanes per column still open): for short mean scans.
+constexpr int TWO_PHASE = 408;
+
 static int default_group(int p)
 {
-    return p == 1 ? 16 : 4;
+    return p == 1 ? 16 : TWO_PHASE;
 }
 
 // Lanes per column for the dense apparent kernel, from the mean scan length
 // s of the oldest-cofacet search: a step tests `group` candidates, so the
 // group should cover about one mean scan.  Large inputs measure s on a
 // probe of 16384 columns; small ones use the per-dimension default (edges
-// of point clouds scan ~10-15 candidates, higher simplices ~4).
+// of point clouds scan ~10-15 candidates, higher simplices ~4, where most
+// columns stop within 4 and the two-phase kernel takes them).
 static int group_for_scan(double sbar)
 {
-    return sbar <= 6 ? 4 : sbar <= 12 ? 8 : sbar <= 40 ? 16 : sbar <= 96 ? 32 : 64;
+    return sbar <= 6 ? TWO_PHASE : sbar <= 12 ? 8 : sbar <= 40 ? 16 : sbar <= 96 ? 32 : 64;
 }
 
 static int choose_group(Workspace &ws, int64_t ncols, int n, int p, hipStream_t s, int *group,
@@ -1046,9 +1057,14 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     // lanes per column from the mean scan length (random edge orders scan
     // hundreds of candidates per column, point clouds a few)
     int group = 8;
-    rc = choose_group(ws, ncols, n, p, s, &group, err);
-    if (rc)
-        return rc;
+    const char *ge = getenv("RPP_APPARENT_GROUP");  // tests: a fixed kernel form
+    if (ge && atoi(ge) > 0) {
+        group = atoi(ge);
+    } else {
+        rc = choose_group(ws, ncols, n, p, s, &group, err);
+        if (rc)
+            return rc;
+    }
     int64_t scanned = 0;
     rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
                                 count_scans ? &scanned : nullptr);

@@ -137,6 +137,48 @@ def test_apparent_kernel_matches_definition(rpp, p, case):
     assert set(zip(s.tolist(), t.tolist())) == set(zip(es.tolist(), et.tolist()))
 
 
+TWO_PHASE_CASES = [
+    # (name, n, p): shallow scans (torus, square), ties (integer metric),
+    # deep scans (random orders), and n at or below the K candidates
+    ("torus60", 60, 2), ("square50", 50, 3), ("int40", 40, 3), ("int45", 45, 2),
+    ("perm80", 80, 1), ("perm30", 30, 2), ("tiny3", 3, 1), ("tiny4", 4, 2),
+    ("tiny5", 5, 1), ("tiny9", 9, 3),
+]
+
+
+def _two_phase_metric(name, n):
+    if name.startswith("torus"):
+        return w.condensed_from_points(w.noisy_torus_points(n, 5))
+    if name.startswith("square") or name.startswith("tiny"):
+        return w.condensed_from_points(w.uniform_square_points(n, 31 + n))
+    if name.startswith("int"):
+        return w.random_integer_metric(n, 611 + n, 3)
+    return w.random_permutation_metric(n, 12 + n)
+
+
+@pytest.mark.parametrize("group", [408, 416, 808])
+@pytest.mark.parametrize("case", TWO_PHASE_CASES, ids=[c[0] for c in TWO_PHASE_CASES])
+def test_two_phase_apparent_kernel_matches_oracle(rpp, monkeypatch, group, case):
+    """The two-phase apparent kernel (each lane alone on the top K
+    candidates of its column, then G lanes per column still open): pairs
+    equal the oracle's, with and without a threshold, over several waves and
+    a ragged last one, and the scan tally equals the single-phase kernel's."""
+    name, n, p = case
+    d = _two_phase_metric(name, n)
+    for thr in (math.inf, float(np.quantile(d, 0.7))):
+        monkeypatch.setenv("RPP_APPARENT_GROUP", str(group))
+        s, t, ncols = rpp.apparent_pairs(d, p, thr)
+        es, et = oracle.apparent_pairs(d, n, p, thr)
+        assert ncols == oracle.count_simplices(d, n, p, thr)
+        assert set(zip(s.tolist(), t.tolist())) == set(zip(es.tolist(), et.tolist())), thr
+    monkeypatch.setenv("RPP_COUNT_SCANS", "1")
+    _, _, st2 = rpp.apparent_count(d, p)
+    monkeypatch.setenv("RPP_APPARENT_GROUP", "8")
+    _, _, st1 = rpp.apparent_count(d, p)
+    assert st2["apparent_group"] == group and st1["apparent_group"] == 8
+    assert st2["n_scanned"] == st1["n_scanned"]
+
+
 @pytest.mark.parametrize("n,p", [(60, 1), (60, 2), (30, 3), (400, 1), (100, 2)])
 def test_theorem1_upper_bound_all_equal_on_gpu(rpp, n, p):
     s, _, ncols = rpp.apparent_pairs(w.all_equal_metric(n), p)
@@ -159,7 +201,7 @@ def test_theorem1_lower_bound_on_gpu(rpp, p):
 def test_group_sizes_agree(rpp, monkeypatch):
     d = w.condensed_from_points(w.noisy_torus_points(80, 5))
     ref = None
-    for g in (1, 4, 8, 16, 32, 64):
+    for g in (1, 4, 8, 16, 32, 64, 408, 416, 808):
         monkeypatch.setenv("RPP_APPARENT_GROUP", str(g))
         r = rpp.barcodes(d, 2, flags=rpp.RPP_WANT_PAIRS)
         key = [set(zip(a.tolist(), b.tolist())) for a, b in r.pairs[1:]]
