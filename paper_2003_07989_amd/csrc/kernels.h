@@ -74,7 +74,8 @@ struct EnumArgs {
     int64_t out_stride = 0;
     int nbatch = 1;
 };
-// Pass 1: kept count per tile; stats[0] += thresholded, stats[1] += cleared.
+// Pass 1: kept count per tile; stats[0] += thresholded, stats[1] += cleared
+// (per cloud), unless stats is null.
 void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts,
                        unsigned long long *stats, hipStream_t s);
 // Pass 2: write kept simplices (diameter, cidx) in increasing cidx order.

@@ -450,8 +450,10 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
 {
     __shared__ uint32_t sh[CT / WAVE + 1];
     const EnumArgs a = enum_view(a0);
+    const bool count_stats = stats != nullptr;
     tile_counts += (int64_t)blockIdx.y * gridDim.x;
-    stats += 2 * blockIdx.y;
+    if (count_stats)
+        stats += 2 * blockIdx.y;
     const Binom B{a.binom, a.n + 1};
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -468,6 +470,7 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
         constexpr int S = EnumChunk<P>::S;
         EnumWalk<P> wk;
         decode<P>(B, c, a.n, wk.v);
+#pragma unroll
         for (int k0 = 0; k0 < CI; k0 += S) {
             float d[S];
             enum_chunk<P, S>(wk, B, a, c, k0, d);
@@ -485,10 +488,14 @@ __global__ __launch_bounds__(CT) void k_enum_count(EnumArgs a0, uint32_t *__rest
         }
     }
     uint32_t sk = block_sum<CT>(keep, sh);
+    if (threadIdx.x == 0)
+        tile_counts[tile] = sk;
+    if (!count_stats)
+        return;  // the caller derives both counts (one counter for every
+                 // block is a long queue of atomics on one address)
     uint32_t st = block_sum<CT>(nthr, sh);
     uint32_t sc = block_sum<CT>(nclr, sh);
     if (threadIdx.x == 0) {
-        tile_counts[tile] = sk;
         if (st)
             atomicAdd(&stats[0], (unsigned long long)st);
         if (sc)
@@ -833,32 +840,41 @@ __global__ __launch_bounds__(256) void k_apparent2(const float *__restrict__ col
 #pragma unroll
         for (int i = 0; i <= P; ++i)
             row[i] = dsq + (int64_t)myv[i] * n;
-        float e[K][P + 1];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int u = n - 1 - k >= 0 ? n - 1 - k : 0;  // in bounds; n-1-k < 0 never hits
-#pragma unroll
-            for (int i = 0; i <= P; ++i)
-                e[k][i] = row[i][u];
-        }
 #pragma unroll
         for (int a = 0; a <= P; ++a)
 #pragma unroll
             for (int b = a + 1; b <= P; ++b)
                 dv[a][b] = row[a][myv[b]];
-        // the largest passing u wins: k runs down so k = 0 is applied last
+        // batches of up to 8 candidates, every load of a batch in flight
+        constexpr int KB = K < 8 ? K : 8;
 #pragma unroll
-        for (int k = K - 1; k >= 0; --k) {
-            const int u = n - 1 - k;
-            bool ok = u >= 0;
+        for (int k0 = 0; k0 < K; k0 += KB) {
+            if (w < 0) {
+                float e[KB][P + 1];
 #pragma unroll
-            for (int i = 0; i <= P; ++i)
-                ok = ok && (u != myv[i]) && (e[k][i] <= myd);
-            if (ok) {
-                w = u;
+                for (int k = 0; k < KB; ++k) {
+                    const int u = n - 1 - k0 - k;
+                    const int uc = u >= 0 ? u : 0;  // in bounds; u < 0 never hits
 #pragma unroll
-                for (int i = 0; i <= P; ++i)
-                    ew[i] = e[k][i];
+                    for (int i = 0; i <= P; ++i)
+                        e[k][i] = row[i][uc];
+                }
+                // the largest passing u wins: k runs down so the smallest
+                // k is applied last
+#pragma unroll
+                for (int k = KB - 1; k >= 0; --k) {
+                    const int u = n - 1 - k0 - k;
+                    bool ok = u >= 0;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        ok = ok && (u != myv[i]) && (e[k][i] <= myd);
+                    if (ok) {
+                        w = u;
+#pragma unroll
+                        for (int i = 0; i <= P; ++i)
+                            ew[i] = e[k][i];
+                    }
+                }
             }
         }
     } else {
@@ -1018,6 +1034,8 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
         switch (group) {
         case 416: hipLaunchKernelGGL((k_apparent2<P, 4, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
         case 808: hipLaunchKernelGGL((k_apparent2<P, 8, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+        case 1608: hipLaunchKernelGGL((k_apparent2<P, 16, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+        case 1616: hipLaunchKernelGGL((k_apparent2<P, 16, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
         default: hipLaunchKernelGGL((k_apparent2<P, 4, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
         }
         return;

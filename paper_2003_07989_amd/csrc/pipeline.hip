@@ -153,9 +153,13 @@ size_t workspace_bytes(int n, int maxdim)
 
 // Stable compaction of the p-simplices (dense enumeration) into ws.cdiam /
 // ws.ccidx; returns the kept count through *kept and the counters.
+// ncleared: the number of set bits of ea.clear, all of them candidates
+// within the threshold (pivots of earlier pairs), when the caller knows it:
+// the thresholded count is then the remainder and the kernel counts
+// nothing; -1: the kernel counts both.
 static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int64_t *kept,
                            uint64_t *nthr, uint64_t *nclr, std::string &err,
-                           GpuTimer *tm = nullptr)
+                           GpuTimer *tm = nullptr, int64_t ncleared = -1)
 {
     if (ea.p >= 2 && ea.n > 65535) {
         // the enumeration walks address the condensed matrix with 32-bit
@@ -172,7 +176,7 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     HIP_TRY(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
     if (tm)
         tm->start();
-    launch_enum_count(ea, ws.tcount.as<uint32_t>(), stats, s);
+    launch_enum_count(ea, ws.tcount.as<uint32_t>(), ncleared >= 0 ? nullptr : stats, s);
     launch_exclusive_scan(ws.tcount.as<uint32_t>(), tiles, ws.toff.as<uint64_t>(),
                           ws.scan.as<uint64_t>(), s);
     uint64_t *h = ws.h_small.as<uint64_t>();
@@ -182,6 +186,10 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     *kept = tiles ? (int64_t)h[0] : 0;
     *nthr = h[1];
     *nclr = h[2];
+    if (ncleared >= 0) {
+        *nclr = (uint64_t)ncleared;
+        *nthr = ea.ncand - (uint64_t)*kept - (uint64_t)ncleared;
+    }
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
     launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
@@ -459,11 +467,12 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
 
     // ---------------- a2: H0 ---------------------------------------------
     int64_t nedges = 0;
+    int64_t mst_edges = 0;  // spanning-forest edges: the p = 1 clearing set
     const uint64_t *h0_keys = nullptr, *h0_cidx = nullptr;  // edges <= thr, diameter desc
     {
         EnumArgs ea{a.dcond_dev, n, 1, thr, ws.binom.as<uint64_t>(), nullptr, E};
         uint64_t nthr = 0, nclr = 0;
-        int rc = enumerate_dense(ws, ea, s, &nedges, &nthr, &nclr, err);
+        int rc = enumerate_dense(ws, ea, s, &nedges, &nthr, &nclr, err, nullptr, 0);
         if (rc)
             return rc;
         ALLOC_TRY(ws.ekey, (size_t)(nedges + 1) * 8);
@@ -492,6 +501,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         int hc[2];
         HIP_TRY(hipMemcpyAsync(hc, counters, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        mst_edges = hc[1];
         DimOut &d0 = out.dims[0];
         d0.death.resize(hc[0]);
         d0.death_edge.resize(hc[0]);
@@ -708,6 +718,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     // later dimensions a bitmap (dense) or a sorted cidx array (sparse) of
     // the previous dimension's apparent pivots
     const uint32_t *clear_bits = ws.mst.as<uint32_t>();
+    int64_t clear_count = mst_edges;  // set bits of clear_bits
     int64_t nclear_sorted = 0;
     const uint64_t *clear_sorted = nullptr;
     for (int p = 1; p <= maxdim; ++p) {
@@ -720,7 +731,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         if (!sparse || p == 1) {
             const uint64_t nc = binom_sat(n, p + 1);
             EnumArgs ea{a.dcond_dev, n, p, thr, ws.binom.as<uint64_t>(), clear_bits, nc};
-            rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
+            rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum, clear_count);
             ncand = (int64_t)nc;
         } else {
             ExtArgs xa{ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
@@ -838,6 +849,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             if (!sparse) {
                 std::swap(ws.clear, ws.next);
                 clear_bits = ws.clear.as<uint32_t>();
+                clear_count = napp;
             } else {
                 ALLOC_TRY(ws.clr, (size_t)(napp + 1) * 8);
                 ALLOC_TRY(ws.clr2, (size_t)(napp + 1) * 8);
@@ -1051,7 +1063,7 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     const uint64_t ncand = binom_sat(n, p + 1);
     EnumArgs ea{dcond_dev, n, p, threshold, ws.binom.as<uint64_t>(), nullptr, ncand};
     uint64_t nthr = 0, nclr = 0;
-    int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum);
+    int rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum, 0);
     if (rc)
         return rc;
     // lanes per column from the mean scan length (random edge orders scan
