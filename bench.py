@@ -48,9 +48,12 @@ def algorithmic_bytes_apparent(st: dict, p: int) -> float:
 
 def apparent_kernel_name(p, g):
     """The apparent kernel a dimension ran, from its apparent_group stat:
-    negative for the sparse kernel, 100 K + G for the two-phase kernel."""
+    negative for the sparse kernel, 100 K + G for the two-phase kernel,
+    10000 + 100 K + G for its workgroup-pooled form."""
     if g < 0:
         return "k_apparent_sparse<%d,%d>" % (p, -g)
+    if g >= 10000:
+        return "k_apparent2b<%d,%d,%d>" % (p, (g - 10000) // 100, g % 100)
     if g >= 100:
         return "k_apparent2<%d,%d,%d>" % (p, g // 100, g % 100)
     return "k_apparent<%d,%d>" % (p, g)

@@ -133,7 +133,9 @@ typedef struct {
                                (candidates from neighbour bitsets); 100 K + G
                                for the two-phase dense kernel (each lane alone
                                on the top K candidates of its column, then G
-                               lanes per column still open) */
+                               lanes per column still open), 10000 + 100 K + G
+                               for its form that pools the open columns of a
+                               workgroup */
 } rpp_dim_stats;
 
 typedef struct {

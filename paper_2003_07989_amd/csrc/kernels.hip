@@ -1020,6 +1020,249 @@ __global__ __launch_bounds__(256) void k_apparent2(const float *__restrict__ col
     tau_out[mycol] = mytau;
 }
 
+// The same two phases with the open columns of a whole workgroup pooled:
+// phase 1 leaves about 15% of the 256 columns open, which a wave alone
+// would scan in ceil(open/8) rounds; queued in LDS they are shared by the
+// four waves (fewer, fuller rounds), and a group reads its column straight
+// from the queue instead of selecting and shuffling it from the owner lane.
+// The workgroup owns 256 consecutive columns.
+template <int P, int K, int G>
+__global__ __launch_bounds__(256) void k_apparent2b(const float *__restrict__ col_diam,
+                                                    const uint64_t *__restrict__ col_cidx,
+                                                    int64_t ncols, const float *__restrict__ dsq,
+                                                    int n, const uint64_t *__restrict__ binom,
+                                                    uint64_t *__restrict__ tau_out,
+                                                    unsigned long long *__restrict__ scan_count)
+{
+    constexpr int NT = 256, NW = NT / WAVE;
+    constexpr int CPR = WAVE / G;  // open columns per wave per round
+    constexpr int NPAIR = (P + 1) * P / 2;
+    __shared__ int q_col[NT];             // thread (column) of each open slot
+    __shared__ float q_d[NT];
+    __shared__ int q_v[P + 1][NT];
+    __shared__ float q_dv[NPAIR > 0 ? NPAIR : 1][NT];
+    __shared__ int q_wave[NW + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = blk * NT;  // the workgroup's first column
+    const Binom B{binom, n + 1};
+    const int64_t mycol = base + threadIdx.x;
+    const bool myvalid = mycol < ncols;
+    float myd = 0.0f;
+    int myv[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        decode<P>(B, col_cidx[mycol], n, myv);
+    }
+
+    // ---- phase 1: candidates n-1 .. n-K of the thread's own column ----
+    float dv[NPAIR > 0 ? NPAIR : 1];  // distances among sigma's vertices
+    float ew[P + 1];                  // d(v_i, w) at the hit
+    int w = -1;
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        ew[i] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NPAIR; ++q)
+        dv[q] = 0.0f;
+    if (myvalid) {
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)myv[i] * n;
+        {
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+#pragma unroll
+                for (int b = a + 1; b <= P; ++b)
+                    dv[q++] = row[a][myv[b]];
+        }
+        float e[K][P + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = n - 1 - k;
+            const int uc = u >= 0 ? u : 0;  // in bounds; u < 0 never hits
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                e[k][i] = row[i][uc];
+        }
+        // the largest passing u wins: k runs down so k = 0 is applied last
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int u = n - 1 - k;
+            bool ok = u >= 0;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                ok = ok && (u != myv[i]) && (e[k][i] <= myd);
+            if (ok) {
+                w = u;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    ew[i] = e[k][i];
+            }
+        }
+    }
+    // open: no hit among the K and candidates below them remain
+    const bool open = myvalid && w < 0 && n - 1 - K >= 0;
+
+    // ---- queue the open columns in LDS, in thread order ----
+    const uint64_t omask = __ballot(open);
+    if (lane == 0)
+        q_wave[wave] = __popcll(omask);
+    __syncthreads();
+    int woff = 0, nopen = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) {
+        const int c = q_wave[x];
+        woff += x < wave ? c : 0;
+        nopen += c;
+    }
+    if (open) {
+        const int t = woff + __popcll(omask & lanemask_lt());
+        q_col[t] = threadIdx.x;
+        q_d[t] = myd;
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            q_v[i][t] = myv[i];
+#pragma unroll
+        for (int q = 0; q < NPAIR; ++q)
+            q_dv[q][t] = dv[q];
+    }
+    __syncthreads();
+
+    // ---- resolved columns: facet test and tau ----
+    if (myvalid && !open) {
+        uint64_t mytau = NONE;
+        if (w >= 0) {
+            bool apparent = true;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                if (myv[j] > w && apparent) {
+                    // facet sigma - {v_j} + {w}
+                    float fd = 0.0f;
+                    int q = 0;
+#pragma unroll
+                    for (int a = 0; a <= P; ++a) {
+                        if (a != j)
+                            fd = fmaxf(fd, ew[a]);
+#pragma unroll
+                        for (int b = a + 1; b <= P; ++b, ++q)
+                            if (a != j && b != j)
+                                fd = fmaxf(fd, dv[q]);
+                    }
+                    if (fd == myd)
+                        apparent = false;
+                }
+            }
+            if (apparent)
+                mytau = cofacet_index<P>(B, myv, w);
+        }
+        tau_out[mycol] = mytau;
+        if (scan_count) {
+            // candidates w not in sigma, visited from n-1 down to w*
+            long long sc = n - P - 1;
+            if (w >= 0) {
+                sc = (n - 1) - w + 1;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    sc -= (myv[i] > w);
+            }
+            atomicAdd(&scan_count[(blockIdx.x * 4 + lane) & (SCAN_COUNTERS - 1)],
+                      (unsigned long long)sc);
+        }
+    }
+
+    // ---- phase 2: the queue, G lanes per column, every wave taking turns ----
+    for (int r0 = 0; r0 < nopen; r0 += NW * CPR) {
+        const int t = r0 + wave * CPR + grp;
+        const bool valid = t < nopen;  // uniform in the group
+        const int tq = valid ? t : 0;
+        const float d = q_d[tq];
+        int v[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            v[i] = q_v[i][tq];
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsq + (int64_t)v[i] * n;
+        int ww = -1, hit = 0;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = n - 1 - K; top >= 0; top -= G) {
+                const int u = top - g;
+                bool ok = u >= 0;
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        e[i] = row[i][u];
+                        ok = ok && (u != v[i]) && (e[i] <= d);
+                    }
+                }
+                const uint64_t m = __ballot(ok) & gmask;
+                if (m) {
+                    hit = __ffsll((unsigned long long)m) - 1;  // lane of the largest u
+                    ww = top - (hit - gbase);
+                    break;
+                }
+            }
+        }
+        float eh[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            eh[i] = __shfl(e[i], ww >= 0 ? hit : lane, WAVE);
+        if (valid && g == 0) {
+            uint64_t tau = NONE;
+            if (ww >= 0) {
+                bool apparent = true;
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    if (v[j] > ww && apparent) {
+                        float fd = 0.0f;
+                        int q = 0;
+#pragma unroll
+                        for (int a = 0; a <= P; ++a) {
+                            if (a != j)
+                                fd = fmaxf(fd, eh[a]);
+#pragma unroll
+                            for (int b = a + 1; b <= P; ++b, ++q)
+                                if (a != j && b != j)
+                                    fd = fmaxf(fd, q_dv[q][tq]);
+                        }
+                        if (fd == d)
+                            apparent = false;
+                    }
+                }
+                if (apparent)
+                    tau = cofacet_index<P>(B, v, ww);
+            }
+            tau_out[base + q_col[tq]] = tau;
+            if (scan_count) {
+                long long sc = n - P - 1;
+                if (ww >= 0) {
+                    sc = (n - 1) - ww + 1;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        sc -= (v[i] > ww);
+                }
+                atomicAdd(&scan_count[(blockIdx.x * 4 + lane) & (SCAN_COUNTERS - 1)],
+                          (unsigned long long)sc);
+            }
+        }
+    }
+}
+
 template <int P>
 static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
                               const float *dsq, int n, const uint64_t *binom, int group,
@@ -1028,9 +1271,18 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
 {
     if (group >= 100 && nbatch <= 1 && bt.count == nullptr && bt.stride == 0) {
         // two-phase kernel: group = 100 K + G (K candidates alone, then G
-        // lanes per open column)
+        // lanes per open column); 10000 + that: open columns pooled per
+        // workgroup
         const int64_t waves = (ncols + WAVE - 1) / WAVE;
         dim3 g((unsigned)((waves * WAVE + 255) / 256)), b(256);
+        if (group >= 10000) {
+            dim3 gb((unsigned)((ncols + 255) / 256));
+            switch (group - 10000) {
+            case 416: hipLaunchKernelGGL((k_apparent2b<P, 4, 16>), gb, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+            default: hipLaunchKernelGGL((k_apparent2b<P, 4, 8>), gb, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
+            }
+            return;
+        }
         switch (group) {
         case 416: hipLaunchKernelGGL((k_apparent2<P, 4, 16>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;
         case 808: hipLaunchKernelGGL((k_apparent2<P, 8, 8>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc); break;

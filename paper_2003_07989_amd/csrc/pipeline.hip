@@ -349,8 +349,9 @@ static int64_t open_cap()
 }
 
 // 100 K + G selects the two-phase kernel (K candidates per lane alone,
-// then G lanes per column still open): for short mean scans.
-constexpr int TWO_PHASE = 408;
+// then G lanes per column still open), 10000 + that its form with the open
+// columns pooled per workgroup: for short mean scans.
+constexpr int TWO_PHASE = 10408;
 
 static int default_group(int p)
 {
