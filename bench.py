@@ -59,12 +59,25 @@ def apparent_kernel_name(p, g):
     return "k_apparent<%d,%d>" % (p, g)
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "device_common.h")
+
+
+def kernel_sources_sha256() -> str:
+    """SHA-256 over the device kernels' sources, in KERNEL_SOURCES order:
+    the profiles' counters hold for the code with this hash only."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_07989_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary committed under profiles/, scaled by a copy kernel
     of known size; None when there is none or the kernel source changed
     since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "counters_%s.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -74,9 +87,8 @@ def measured_traffic(workload: str, kernel: str):
             continue
         k, v = line.split(":", 1)
         kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2003_07989_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("kernels_hip_sha256") != sha or kv.get("kernel", "").replace(" ", "") != kernel.replace(" ", ""):
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256() or \
+            kv.get("kernel", "").replace(" ", "") != kernel.replace(" ", ""):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
