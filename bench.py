@@ -49,9 +49,15 @@ def algorithmic_bytes_apparent(st: dict, p: int) -> float:
 def apparent_kernel_name(p, g):
     """The apparent kernel a dimension ran, from its apparent_group stat:
     negative for the sparse kernel, 100 K + G for the two-phase kernel,
-    10000 + 100 K + G for its workgroup-pooled form."""
+    10000 + 100 K + G for its workgroup-pooled form, 20000 + 100 NB + G
+    for the pooled form with vector reads of its first NB blocks of four
+    candidates (NB = 0 meaning 2)."""
     if g < 0:
         return "k_apparent_sparse<%d,%d>" % (p, -g)
+    if g >= 20000:
+        nb = (g - 20000) // 100
+        return "k_apparent2v<%d,%d,%d>" % (p, 16 if g % 100 == 16 and nb in (0, 2) else 8,
+                                            nb if nb in (3, 4) else 2)
     if g >= 10000:
         return "k_apparent2b<%d,%d,%d>" % (p, (g - 10000) // 100, g % 100)
     if g >= 100:

@@ -135,7 +135,9 @@ typedef struct {
                                on the top K candidates of its column, then G
                                lanes per column still open), 10000 + 100 K + G
                                for its form that pools the open columns of a
-                               workgroup */
+                               workgroup, 20000 + 100 NB + G for the pooled
+                               form reading its first NB blocks of 4
+                               candidates as 16-byte vectors (NB = 0: 2) */
 } rpp_dim_stats;
 
 typedef struct {

@@ -93,6 +93,17 @@ constexpr int SCAN_COUNTERS = 1024;
 void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                      const float *dsq, int n, int p, const uint64_t *binom, int group,
                      uint64_t *tau_out, unsigned long long *scan_count, hipStream_t s);
+// Row-padded copy of the n x n matrix: out[r * pitch + c] = dsq[r * n + c]
+// for c < n, pitch a multiple of 4 (16-byte aligned rows), 0 in the pad.
+void launch_pad_rows(const float *dsq, int n, int pitch, float *out, hipStream_t s);
+// The two-phase apparent test with vector reads of the first candidates
+// over the row-padded matrix (group = 20000 + 100 NB + G: NB aligned blocks
+// of 4 candidates, NB in {2, 3, 4}, 0 meaning 2; G = 16 only with 2 blocks,
+// else 8); the same output as launch_apparent.
+void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                         const float *dsqp, int pitch, int n, int p, const uint64_t *binom,
+                         int group, uint64_t *tau_out, unsigned long long *scan_count,
+                         hipStream_t s);
 // Batched: cap = per-cloud capacity (grid size); dsq packed n*n per cloud.
 void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
                        const float *dsq, int n, int p, const uint64_t *binom, int group,

@@ -1263,6 +1263,316 @@ __global__ __launch_bounds__(256) void k_apparent2b(const float *__restrict__ co
     }
 }
 
+// Row-padded copy of the square matrix: pitch = n rounded up to a multiple
+// of 4, so every row starts 16-byte aligned (the pad entries are never read
+// as candidates).
+__global__ void k_pad_rows(const float *__restrict__ dsq, int n, int pitch,
+                           float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * pitch)
+        return;
+    const int r = (int)(i / pitch), c = (int)(i - (int64_t)r * pitch);
+    out[i] = c < n ? dsq[(int64_t)r * n + c] : 0.0f;
+}
+
+void launch_pad_rows(const float *dsq, int n, int pitch, float *out, hipStream_t s)
+{
+    const int64_t total = (int64_t)n * pitch;
+    if (total <= 0)
+        return;
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, dsq, n,
+                       pitch, out);
+}
+
+// The pooled two-phase kernel with vector reads in phase 1.  A lane's first
+// candidates lie in one row segment per vertex of sigma, but read one by
+// one each load instruction touches a different cache line for every lane
+// of the wave.  With 16-byte aligned rows a lane reads the aligned block of
+// four that holds candidate n-1 and the NB-1 blocks below it as 16-byte
+// loads, one per block and vertex, testing candidates n-1 down to
+// a-4(NB-1) (a = (n-1) rounded down to a multiple of 4).  Phase 2 goes on
+// below them.
+template <int P, int G, int NB>
+__global__ __launch_bounds__(256) void k_apparent2v(const float *__restrict__ col_diam,
+                                                    const uint64_t *__restrict__ col_cidx,
+                                                    int64_t ncols, const float *__restrict__ dsqp,
+                                                    int pitch, int n,
+                                                    const uint64_t *__restrict__ binom,
+                                                    uint64_t *__restrict__ tau_out,
+                                                    unsigned long long *__restrict__ scan_count)
+{
+    constexpr int NT = 256, NW = NT / WAVE;
+    constexpr int CPR = WAVE / G;  // open columns per wave per round
+    constexpr int NPAIR = (P + 1) * P / 2;
+    __shared__ int q_col[NT];             // thread (column) of each open slot
+    __shared__ float q_d[NT];
+    __shared__ int q_v[P + 1][NT];
+    __shared__ float q_dv[NPAIR > 0 ? NPAIR : 1][NT];
+    __shared__ int q_wave[NW + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = blk * NT;  // the workgroup's first column
+    const Binom B{binom, n + 1};
+    const int64_t mycol = base + threadIdx.x;
+    const bool myvalid = mycol < ncols;
+    const int a4 = (n - 1) & ~3;  // aligned block holding candidate n-1
+    float myd = 0.0f;
+    int myv[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        decode<P>(B, col_cidx[mycol], n, myv);
+    }
+
+    // ---- phase 1: candidates n-1 .. max(a4-4, 0) of the thread's column ----
+    float dv[NPAIR > 0 ? NPAIR : 1];
+    float ew[P + 1];
+    int w = -1;
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        ew[i] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NPAIR; ++q)
+        dv[q] = 0.0f;
+    if (myvalid) {
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsqp + (int64_t)myv[i] * pitch;
+        {
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+#pragma unroll
+                for (int b = a + 1; b <= P; ++b)
+                    dv[q++] = row[a][myv[b]];
+        }
+        constexpr int NC = 4 * NB;
+        const int lo = a4 - 4 * (NB - 1);  // lowest candidate of the blocks
+        float e[P + 1][NC];  // e[i][c]: d(v_i, lo + c)
+#pragma unroll
+        for (int i = 0; i <= P; ++i) {
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) {
+                const int at = lo + 4 * bk;
+                const float4 x = at >= 0 ? *reinterpret_cast<const float4 *>(row[i] + at)
+                                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                e[i][4 * bk + 0] = x.x;
+                e[i][4 * bk + 1] = x.y;
+                e[i][4 * bk + 2] = x.z;
+                e[i][4 * bk + 3] = x.w;
+            }
+        }
+        // ascending u, so the largest passing u is applied last
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int u = lo + c;
+            bool ok = u >= 0 && u <= n - 1;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                ok = ok && (u != myv[i]) && (e[i][c] <= myd);
+            if (ok) {
+                w = u;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    ew[i] = e[i][c];
+            }
+        }
+    }
+    // open: no hit and candidates below the blocks remain
+    const int below = a4 - 4 * (NB - 1) - 1;  // highest candidate of phase 2
+    const bool open = myvalid && w < 0 && below >= 0;
+
+    // ---- queue the open columns in LDS, in thread order ----
+    const uint64_t omask = __ballot(open);
+    if (lane == 0)
+        q_wave[wave] = __popcll(omask);
+    __syncthreads();
+    int woff = 0, nopen = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) {
+        const int c = q_wave[x];
+        woff += x < wave ? c : 0;
+        nopen += c;
+    }
+    if (open) {
+        const int t = woff + __popcll(omask & lanemask_lt());
+        q_col[t] = threadIdx.x;
+        q_d[t] = myd;
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            q_v[i][t] = myv[i];
+#pragma unroll
+        for (int q = 0; q < NPAIR; ++q)
+            q_dv[q][t] = dv[q];
+    }
+    __syncthreads();
+
+    // ---- resolved columns: facet test and tau ----
+    if (myvalid && !open) {
+        uint64_t mytau = NONE;
+        if (w >= 0) {
+            bool apparent = true;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                if (myv[j] > w && apparent) {
+                    // facet sigma - {v_j} + {w}
+                    float fd = 0.0f;
+                    int q = 0;
+#pragma unroll
+                    for (int a = 0; a <= P; ++a) {
+                        if (a != j)
+                            fd = fmaxf(fd, ew[a]);
+#pragma unroll
+                        for (int b = a + 1; b <= P; ++b, ++q)
+                            if (a != j && b != j)
+                                fd = fmaxf(fd, dv[q]);
+                    }
+                    if (fd == myd)
+                        apparent = false;
+                }
+            }
+            if (apparent)
+                mytau = cofacet_index<P>(B, myv, w);
+        }
+        tau_out[mycol] = mytau;
+        if (scan_count) {
+            // candidates w not in sigma, visited from n-1 down to w*
+            long long sc = n - P - 1;
+            if (w >= 0) {
+                sc = (n - 1) - w + 1;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    sc -= (myv[i] > w);
+            }
+            atomicAdd(&scan_count[(blockIdx.x * 4 + lane) & (SCAN_COUNTERS - 1)],
+                      (unsigned long long)sc);
+        }
+    }
+
+    // ---- phase 2: the queue, G lanes per column, every wave taking turns ----
+    for (int r0 = 0; r0 < nopen; r0 += NW * CPR) {
+        const int t = r0 + wave * CPR + grp;
+        const bool valid = t < nopen;  // uniform in the group
+        const int tq = valid ? t : 0;
+        const float d = q_d[tq];
+        int v[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            v[i] = q_v[i][tq];
+        const float *row[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            row[i] = dsqp + (int64_t)v[i] * pitch;
+        int ww = -1, hit = 0;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = below; top >= 0; top -= G) {
+                const int u = top - g;
+                bool ok = u >= 0;
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        e[i] = row[i][u];
+                        ok = ok && (u != v[i]) && (e[i] <= d);
+                    }
+                }
+                const uint64_t m = __ballot(ok) & gmask;
+                if (m) {
+                    hit = __ffsll((unsigned long long)m) - 1;  // lane of the largest u
+                    ww = top - (hit - gbase);
+                    break;
+                }
+            }
+        }
+        float eh[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            eh[i] = __shfl(e[i], ww >= 0 ? hit : lane, WAVE);
+        if (valid && g == 0) {
+            uint64_t tau = NONE;
+            if (ww >= 0) {
+                bool apparent = true;
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    if (v[j] > ww && apparent) {
+                        float fd = 0.0f;
+                        int q = 0;
+#pragma unroll
+                        for (int a = 0; a <= P; ++a) {
+                            if (a != j)
+                                fd = fmaxf(fd, eh[a]);
+#pragma unroll
+                            for (int b = a + 1; b <= P; ++b, ++q)
+                                if (a != j && b != j)
+                                    fd = fmaxf(fd, q_dv[q][tq]);
+                        }
+                        if (fd == d)
+                            apparent = false;
+                    }
+                }
+                if (apparent)
+                    tau = cofacet_index<P>(B, v, ww);
+            }
+            tau_out[base + q_col[tq]] = tau;
+            if (scan_count) {
+                long long sc = n - P - 1;
+                if (ww >= 0) {
+                    sc = (n - 1) - ww + 1;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        sc -= (v[i] > ww);
+                }
+                atomicAdd(&scan_count[(blockIdx.x * 4 + lane) & (SCAN_COUNTERS - 1)],
+                          (unsigned long long)sc);
+            }
+        }
+    }
+}
+
+void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
+                         const float *dsqp, int pitch, int n, int p, const uint64_t *binom,
+                         int group, uint64_t *tau_out, unsigned long long *scan_count,
+                         hipStream_t s)
+{
+    if (ncols <= 0)
+        return;
+    dim3 g((unsigned)((ncols + 255) / 256)), b(256);
+    // group = 20000 + 100 NB + G (NB = 0 means 2)
+    const int nb = (group - 20000) / 100;
+    const bool g16 = group % 100 == 16;
+#define RPP_LAUNCH_VEC(PP)                                                                        \
+    if (nb == 3)                                                                                  \
+        hipLaunchKernelGGL((k_apparent2v<PP, 8, 3>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
+                           pitch, n, binom, tau_out, scan_count);                                 \
+    else if (nb == 4)                                                                             \
+        hipLaunchKernelGGL((k_apparent2v<PP, 8, 4>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
+                           pitch, n, binom, tau_out, scan_count);                                 \
+    else if (g16)                                                                                 \
+        hipLaunchKernelGGL((k_apparent2v<PP, 16, 2>), g, b, 0, s, col_diam, col_cidx, ncols,      \
+                           dsqp, pitch, n, binom, tau_out, scan_count);                           \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_apparent2v<PP, 8, 2>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
+                           pitch, n, binom, tau_out, scan_count);
+    switch (p) {
+    case 1: RPP_LAUNCH_VEC(1) break;
+    case 2: RPP_LAUNCH_VEC(2) break;
+    case 3: RPP_LAUNCH_VEC(3) break;
+    default: RPP_LAUNCH_VEC(4) break;
+    }
+#undef RPP_LAUNCH_VEC
+}
+
 template <int P>
 static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
                               const float *dsq, int n, const uint64_t *binom, int group,

@@ -82,6 +82,8 @@ struct Workspace {
     DevBuf lowc, lowd;               // lows of the non-apparent columns
     DevBuf gedges, gvals;            // backward: gradient terms
     DevBuf rscratch, scancnt;
+    DevBuf dsqp;                     // row-padded square matrix (vector apparent kernel)
+    bool dsqp_ready = false;         // dsqp holds this call's matrix
     // host hand-off of one dimension; two sets, since the reduction of
     // dimension p still reads its set while dimension p+1 fills the other
     HostBuf h_app_tau[2], h_app_sigma[2], h_na_key[2], h_na_cidx[2], h_low[2], h_lowd[2];
@@ -125,7 +127,7 @@ size_t workspace_allocated(void *wp)
                             &w.skc[1], &w.xd, &w.xc, &w.rflags, &w.rexcl, &w.rmat, &w.rvals, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
                             &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
                             &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
-                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt};
+                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt, &w.dsqp};
     for (const DevBuf *b : bufs)
         t += b->cap;
     return t;
@@ -142,7 +144,8 @@ size_t workspace_bytes(int n, int maxdim)
     uint64_t maxbits = binom_sat(n, std::min(maxdim + 1, n) + 1);
     size_t b = 0;
     b += (size_t)n * n * 4 + (size_t)n * 4 * 4;
-    b += (size_t)n * n * 4;                 // rank-coded distances (sparse path)
+    b += (size_t)n * (n + 3) * 4;           // rank-coded distances (sparse path) or the
+                                            // row-padded matrix (dense path)
     b += (size_t)E * 8 * 4;                 // edge keys / values, double buffered
     b += (size_t)maxc * (4 + 8 + 8);        // kept columns + tau
     b += (size_t)maxc * 8 * 4 * 2;          // partition outputs, double buffered
@@ -302,7 +305,17 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
         launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                                ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
                                ws.binom.as<uint64_t>(), group, ws.tau.as<uint64_t>(), sc, s);
-    else
+    else if (group >= 20000) {
+        const int pitch = (n + 3) & ~3;
+        if (!ws.dsqp_ready) {
+            ALLOC_TRY(ws.dsqp, (size_t)n * pitch * 4);
+            launch_pad_rows(ws.dsq.as<float>(), n, pitch, ws.dsqp.as<float>(), s);
+            ws.dsqp_ready = true;
+        }
+        launch_apparent_vec(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
+                            ws.dsqp.as<float>(), pitch, n, p, ws.binom.as<uint64_t>(), group,
+                            ws.tau.as<uint64_t>(), sc, s);
+    } else
         launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                         ws.dsq.as<float>(), n, p, ws.binom.as<uint64_t>(), group,
                         ws.tau.as<uint64_t>(), sc, s);
@@ -350,8 +363,10 @@ static int64_t open_cap()
 
 // 100 K + G selects the two-phase kernel (K candidates per lane alone,
 // then G lanes per column still open), 10000 + that its form with the open
-// columns pooled per workgroup: for short mean scans.
-constexpr int TWO_PHASE = 10408;
+// columns pooled per workgroup, 20000 + 100 NB + G the pooled form reading
+// its first NB blocks of four candidates as 16-byte vectors (from a
+// row-padded copy of the matrix): for short mean scans.
+constexpr int TWO_PHASE = 20008;
 
 static int default_group(int p)
 {
@@ -425,6 +440,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     float *radius = ws.scal.as<float>() + 1;
     HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
     launch_stage(a.dcond_dev, n, ws.dsq.as<float>(), ws.rowmax.as<float>(), bad, s);
+    ws.dsqp_ready = false;
     launch_min(ws.rowmax.as<float>(), n, radius, s);
     uint32_t *hs = ws.h_small.as<uint32_t>();
     HIP_TRY(hipMemcpyAsync(hs, ws.scal.p, 8, hipMemcpyDeviceToHost, s));
@@ -1045,6 +1061,7 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     uint32_t *bad = ws.scal.as<uint32_t>();
     HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
     launch_stage(dcond_dev, n, ws.dsq.as<float>(), ws.rowmax.as<float>(), bad, s);
+    ws.dsqp_ready = false;
     uint32_t hb = 0;
     HIP_TRY(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -156,7 +156,8 @@ def _two_phase_metric(name, n):
     return w.random_permutation_metric(n, 12 + n)
 
 
-@pytest.mark.parametrize("group", [408, 416, 808, 1608, 1616, 10408, 10416])
+@pytest.mark.parametrize("group", [408, 416, 808, 1608, 1616, 10408, 10416, 20008, 20016,
+                                   20308, 20408])
 @pytest.mark.parametrize("case", TWO_PHASE_CASES, ids=[c[0] for c in TWO_PHASE_CASES])
 def test_two_phase_apparent_kernel_matches_oracle(rpp, monkeypatch, group, case):
     """The two-phase apparent kernel (each lane alone on the top K
@@ -201,7 +202,8 @@ def test_theorem1_lower_bound_on_gpu(rpp, p):
 def test_group_sizes_agree(rpp, monkeypatch):
     d = w.condensed_from_points(w.noisy_torus_points(80, 5))
     ref = None
-    for g in (1, 4, 8, 16, 32, 64, 408, 416, 808, 1608, 1616, 10408, 10416):
+    for g in (1, 4, 8, 16, 32, 64, 408, 416, 808, 1608, 1616, 10408, 10416, 20008, 20016,
+              20308, 20408):
         monkeypatch.setenv("RPP_APPARENT_GROUP", str(g))
         r = rpp.barcodes(d, 2, flags=rpp.RPP_WANT_PAIRS)
         key = [set(zip(a.tolist(), b.tolist())) for a, b in r.pairs[1:]]
