@@ -143,6 +143,9 @@ TWO_PHASE_CASES = [
     ("torus60", 60, 2), ("square50", 50, 3), ("int40", 40, 3), ("int45", 45, 2),
     ("perm80", 80, 1), ("perm30", 30, 2), ("tiny3", 3, 1), ("tiny4", 4, 2),
     ("tiny5", 5, 1), ("tiny9", 9, 3),
+    # n = 3 mod 4 (with the cases above, every residue of n mod 4: the
+    # vector form's aligned top block holds 4, 1, 2 or 3 real candidates)
+    ("torus63", 63, 2), ("perm43", 43, 2), ("tiny7", 7, 2),
 ]
 
 
