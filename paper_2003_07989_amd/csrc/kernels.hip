@@ -2917,44 +2917,95 @@ int radix_sort_pairs_b(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint6
 }
 
 // Small sorts in one launch: one workgroup sorts fewer than 8192 pairs by
-// the low `bits` (<= 51) bits of the key, stably -- a bitonic network in LDS
-// over (key bits << 13 | index), whose distinct values make it stable, then
+// the low `bits` (<= 51) bits of the key, stably -- a bitonic network over
+// (key bits << 13 | index), whose distinct values make it stable, then
 // whole keys and values gathered by index.  A radix sort of a few thousand
 // keys would spend its time in ~20 launches.
 constexpr int SS_N = 8192;
 constexpr int SS_T = 1024;
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, mask, WAVE);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), mask, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Thread t holds elements t + SS_T r, r < R, in registers.  Partners closer
+// than 64 (j < 64) sit in the same wave at lane t ^ j with the same r, so
+// those stages are register compare-exchanges across a shuffle; only the
+// wider stages go through LDS, one barrier each.
 __global__ __launch_bounds__(SS_T) void k_small_sort(const uint64_t *__restrict__ kin,
                                                      const uint64_t *__restrict__ vin,
                                                      uint64_t *__restrict__ kout,
                                                      uint64_t *__restrict__ vout, int count,
                                                      int bits)
 {
+    constexpr int RMAX = SS_N / SS_T;
     __shared__ uint64_t a[SS_N];
     int m = 2;
     while (m < count)
         m <<= 1;
+    const int t = threadIdx.x;
+    const int R = m >= SS_T ? m / SS_T : 1;  // elements per thread
+    const bool act = t < m;
     const uint64_t mask = (1ull << bits) - 1;
     // padding sorts last: a real composite is below ~0 (index <= 8190)
-    for (int i = threadIdx.x; i < m; i += SS_T)
-        a[i] = i < count ? (((kin[i] & mask) << 13) | (uint64_t)i) : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= m; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < m; i += SS_T) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = a[i], y = a[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        a[i] = y;
-                        a[l] = x;
+    uint64_t x[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        const int i = t + SS_T * r;
+        x[r] = (r < R && act && i < count) ? (((kin[i] & mask) << 13) | (uint64_t)i) : ~0ull;
+    }
+    for (int k = 2; k <= m; k <<= 1) {
+        int j = k >> 1;
+        if (j >= WAVE) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r)
+                if (r < R && act)
+                    a[t + SS_T * r] = x[r];
+            __syncthreads();
+            for (; j >= WAVE; j >>= 1) {
+#pragma unroll
+                for (int r = 0; r < RMAX; ++r) {
+                    const int i = t + SS_T * r;
+                    const int l = i ^ j;
+                    if (r < R && act && l > i) {
+                        const uint64_t p = a[i], q = a[l];
+                        const bool up = (i & k) == 0;
+                        if ((p > q) == up) {
+                            a[i] = q;
+                            a[l] = p;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r)
+                if (r < R && act)
+                    x[r] = a[t + SS_T * r];
+            __syncthreads();  // every read done before the next stores
         }
-    for (int i = threadIdx.x; i < count; i += SS_T) {
+        for (; j > 0; j >>= 1) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                const int i = t + SS_T * r;
+                const uint64_t y = shfl_xor_u64(x[r], j);  // element i ^ j
+                const bool up = (i & k) == 0, lower = (i & j) == 0;
+                const bool keep_min = lower == up;
+                const uint64_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
+                if (r < R && act)
+                    x[r] = keep_min ? lo : hi;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+        if (r < R && act)
+            a[t + SS_T * r] = x[r];
+    __syncthreads();
+    for (int i = t; i < count; i += SS_T) {
         const int src = (int)(a[i] & 0x1fffull);
         kout[i] = kin[src];
         vout[i] = vin[src];
