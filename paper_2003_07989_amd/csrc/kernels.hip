@@ -2935,42 +2935,43 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask)
 // than 64 (j < 64) sit in the same wave at lane t ^ j with the same r, so
 // those stages are register compare-exchanges across a shuffle; only the
 // wider stages go through LDS, one barrier each.
+// R = elements per thread = max(1, m / SS_T), m = count rounded up to a
+// power of two.
+template <int R>
 __global__ __launch_bounds__(SS_T) void k_small_sort(const uint64_t *__restrict__ kin,
                                                      const uint64_t *__restrict__ vin,
                                                      uint64_t *__restrict__ kout,
                                                      uint64_t *__restrict__ vout, int count,
                                                      int bits)
 {
-    constexpr int RMAX = SS_N / SS_T;
     __shared__ uint64_t a[SS_N];
     int m = 2;
     while (m < count)
         m <<= 1;
     const int t = threadIdx.x;
-    const int R = m >= SS_T ? m / SS_T : 1;  // elements per thread
     const bool act = t < m;
     const uint64_t mask = (1ull << bits) - 1;
     // padding sorts last: a real composite is below ~0 (index <= 8190)
-    uint64_t x[RMAX];
+    uint64_t x[R];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int i = t + SS_T * r;
-        x[r] = (r < R && act && i < count) ? (((kin[i] & mask) << 13) | (uint64_t)i) : ~0ull;
+        x[r] = (act && i < count) ? (((kin[i] & mask) << 13) | (uint64_t)i) : ~0ull;
     }
     for (int k = 2; k <= m; k <<= 1) {
         int j = k >> 1;
         if (j >= WAVE) {
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r)
-                if (r < R && act)
+            for (int r = 0; r < R; ++r)
+                if (act)
                     a[t + SS_T * r] = x[r];
             __syncthreads();
             for (; j >= WAVE; j >>= 1) {
 #pragma unroll
-                for (int r = 0; r < RMAX; ++r) {
+                for (int r = 0; r < R; ++r) {
                     const int i = t + SS_T * r;
                     const int l = i ^ j;
-                    if (r < R && act && l > i) {
+                    if (act && l > i) {
                         const uint64_t p = a[i], q = a[l];
                         const bool up = (i & k) == 0;
                         if ((p > q) == up) {
@@ -2982,27 +2983,27 @@ __global__ __launch_bounds__(SS_T) void k_small_sort(const uint64_t *__restrict_
                 __syncthreads();
             }
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r)
-                if (r < R && act)
+            for (int r = 0; r < R; ++r)
+                if (act)
                     x[r] = a[t + SS_T * r];
             __syncthreads();  // every read done before the next stores
         }
         for (; j > 0; j >>= 1) {
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int i = t + SS_T * r;
                 const uint64_t y = shfl_xor_u64(x[r], j);  // element i ^ j
                 const bool up = (i & k) == 0, lower = (i & j) == 0;
                 const bool keep_min = lower == up;
                 const uint64_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
-                if (r < R && act)
+                if (act)
                     x[r] = keep_min ? lo : hi;
             }
         }
     }
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-        if (r < R && act)
+    for (int r = 0; r < R; ++r)
+        if (act)
             a[t + SS_T * r] = x[r];
     __syncthreads();
     for (int i = t; i < count; i += SS_T) {
@@ -3018,8 +3019,16 @@ int radix_sort_pairs(uint64_t *keys, uint64_t *vals, uint64_t *keys_alt, uint64_
     if (count <= 1 || bits <= 0)
         return 0;
     if (count < SS_N && bits <= 51) {
-        hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt,
-                           (int)count, bits);
+        int m = 2;
+        while (m < count)
+            m <<= 1;
+        const int r = m >= SS_T ? (int)(m / SS_T) : 1;
+        switch (r) {
+        case 1: hipLaunchKernelGGL(k_small_sort<1>, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt, (int)count, bits); break;
+        case 2: hipLaunchKernelGGL(k_small_sort<2>, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt, (int)count, bits); break;
+        case 4: hipLaunchKernelGGL(k_small_sort<4>, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt, (int)count, bits); break;
+        default: hipLaunchKernelGGL(k_small_sort<8>, dim3(1), dim3(SS_T), 0, s, keys, vals, keys_alt, vals_alt, (int)count, bits); break;
+        }
         return 1;
     }
     return radix_sort_pairs_b(keys, vals, keys_alt, vals_alt, count, bits, scratch, s, Batch(), 1);
