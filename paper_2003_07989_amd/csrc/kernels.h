@@ -79,8 +79,10 @@ struct EnumArgs {
 void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts,
                        unsigned long long *stats, hipStream_t s);
 // Pass 2: write kept simplices (diameter, cidx) in increasing cidx order.
+// out_vtx (p = 2 or 3, n <= 65536, or null): each kept simplex's vertices
+// v_0 > ... > v_p packed 16 bits each, v_i at bit 16 i.
 void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float *out_diam,
-                         uint64_t *out_cidx, hipStream_t s);
+                         uint64_t *out_cidx, hipStream_t s, uint64_t *out_vtx = nullptr);
 
 // ---- a5: apparent-pair test -----------------------------------------------
 // tau_out[i] = cidx of the apparent partner of column i, or ~0 when the
@@ -100,10 +102,12 @@ void launch_pad_rows(const float *dsq, int n, int pitch, float *out, hipStream_t
 // over the row-padded matrix (group = 20000 + 100 NB + G: NB aligned blocks
 // of 4 candidates, NB in {2, 3, 4}, 0 meaning 2; G = 16 only with 2 blocks,
 // else 8); the same output as launch_apparent.
+// col_vtx (or null): the columns' packed vertex tuples, as launch_enum_scatter
+// writes them, read instead of decoding col_cidx.
 void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                          const float *dsqp, int pitch, int n, int p, const uint64_t *binom,
                          int group, uint64_t *tau_out, unsigned long long *scan_count,
-                         hipStream_t s);
+                         hipStream_t s, const uint64_t *col_vtx = nullptr);
 // Batched: cap = per-cloud capacity (grid size); dsq packed n*n per cloud.
 void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
                        const float *dsq, int n, int p, const uint64_t *binom, int group,

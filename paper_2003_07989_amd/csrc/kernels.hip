@@ -405,9 +405,10 @@ template <int P> struct EnumChunk {
 
 // Diameters of the candidates c0 + 64 (k0 + s), s < S, of a lane's walk
 // (valid where the candidate exists), advancing the walk past them.
-template <int P, int S>
+template <int P, int S, bool VTX = false>
 __device__ __forceinline__ void enum_chunk(EnumWalk<P> &wk, const Binom &B, const EnumArgs &a,
-                                           uint64_t c, int k0, float (&d)[S])
+                                           uint64_t c, int k0, float (&d)[S],
+                                           uint64_t *vtx = nullptr)
 {
     constexpr int NP = EnumWalk<P>::NPAIR;
     uint32_t o[S][NP];
@@ -416,6 +417,13 @@ __device__ __forceinline__ void enum_chunk(EnumWalk<P> &wk, const Binom &B, cons
         const uint64_t cs = c + (uint64_t)s * WAVE;
         if (cs < a.ncand) {
             wk.offsets(o[s]);
+            if (VTX) {
+                uint64_t x = 0;
+#pragma unroll
+                for (int i = 0; i <= P; ++i)
+                    x |= (uint64_t)(uint32_t)wk.v[i] << (16 * i);
+                vtx[s] = x;  // vtx: an array of S, indexed by constants
+            }
             if (k0 + s + 1 < CI && cs + WAVE < a.ncand)
                 wk.advance(B, cs + WAVE, WAVE, a.n);
         } else {
@@ -507,7 +515,8 @@ template <int P>
 __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
                                                      const uint64_t *__restrict__ tile_offsets,
                                                      float *__restrict__ out_diam,
-                                                     uint64_t *__restrict__ out_cidx)
+                                                     uint64_t *__restrict__ out_cidx,
+                                                     uint64_t *__restrict__ out_vtx)
 {
     __shared__ uint32_t wsum[CT / WAVE];
     const EnumArgs a = enum_view(a0);
@@ -518,8 +527,11 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     const uint64_t c0 = (uint64_t)tile * COMPACT_TILE + (uint64_t)wave * (CI * WAVE) + lane;
-    // sweep 1: every candidate once; keep flags as bits, diameters in registers
+    // sweep 1: every candidate once; keep flags as bits, diameters (and the
+    // packed vertex tuples, when asked for) in registers
     float dk[CI];
+    uint64_t vk[P <= 3 ? CI : 1];
+    const bool want_vtx = P >= 2 && P <= 3 && out_vtx != nullptr;
     uint32_t bits = 0;
     uint32_t total = 0;  // kept by the wave
     if (P == 1) {
@@ -535,7 +547,15 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
 #pragma unroll
         for (int k0 = 0; k0 < CI; k0 += S) {
             float d[S];
-            enum_chunk<P, S>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d);
+            if (P <= 3 && want_vtx) {
+                uint64_t x[S];
+                enum_chunk<P, S, true>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d, x);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    vk[P <= 3 ? k0 + s : 0] = x[s];
+            } else {
+                enum_chunk<P, S>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d);
+            }
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 dk[k0 + s] = d[s];
@@ -564,6 +584,8 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
             const uint64_t pos = running + (uint32_t)__popcll(m & lanemask_lt());
             out_diam[pos] = dk[k];
             out_cidx[pos] = c0 + (uint64_t)k * WAVE;
+            if (P <= 3 && want_vtx)
+                out_vtx[pos] = vk[P <= 3 ? k : 0];
         }
         running += (uint32_t)__popcll(m);
     }
@@ -593,17 +615,17 @@ void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts, unsigned long l
 }
 
 void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float *out_diam,
-                         uint64_t *out_cidx, hipStream_t s)
+                         uint64_t *out_cidx, hipStream_t s, uint64_t *out_vtx)
 {
     int64_t tiles = compact_tiles((int64_t)a.ncand);
     if (tiles == 0)
         return;
     dim3 g((unsigned)tiles, a.nbatch > 0 ? a.nbatch : 1), b(CT);
     switch (a.p) {
-    case 1: hipLaunchKernelGGL(k_enum_scatter<1>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
-    case 2: hipLaunchKernelGGL(k_enum_scatter<2>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
-    case 3: hipLaunchKernelGGL(k_enum_scatter<3>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
-    default: hipLaunchKernelGGL(k_enum_scatter<4>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx); break;
+    case 1: hipLaunchKernelGGL(k_enum_scatter<1>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx, nullptr); break;
+    case 2: hipLaunchKernelGGL(k_enum_scatter<2>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx, out_vtx); break;
+    case 3: hipLaunchKernelGGL(k_enum_scatter<3>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx, out_vtx); break;
+    default: hipLaunchKernelGGL(k_enum_scatter<4>, g, b, 0, s, a, tile_offsets, out_diam, out_cidx, nullptr); break;
     }
 }
 
@@ -1300,7 +1322,8 @@ __global__ __launch_bounds__(256) void k_apparent2v(const float *__restrict__ co
                                                     int pitch, int n,
                                                     const uint64_t *__restrict__ binom,
                                                     uint64_t *__restrict__ tau_out,
-                                                    unsigned long long *__restrict__ scan_count)
+                                                    unsigned long long *__restrict__ scan_count,
+                                                    const uint64_t *__restrict__ col_vtx)
 {
     constexpr int NT = 256, NW = NT / WAVE;
     constexpr int CPR = WAVE / G;  // open columns per wave per round
@@ -1328,7 +1351,15 @@ __global__ __launch_bounds__(256) void k_apparent2v(const float *__restrict__ co
         myv[i] = 0;
     if (myvalid) {
         myd = col_diam[mycol];
-        decode<P>(B, col_cidx[mycol], n, myv);
+        if (P <= 3 && col_vtx) {
+            // the vertex tuple as the enumeration packed it: no decode
+            const uint64_t x = col_vtx[mycol];
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                myv[i] = (int)((x >> (16 * i)) & 0xffffu);
+        } else {
+            decode<P>(B, col_cidx[mycol], n, myv);
+        }
     }
 
     // ---- phase 1: candidates n-1 .. max(a4-4, 0) of the thread's column ----
@@ -1543,7 +1574,7 @@ __global__ __launch_bounds__(256) void k_apparent2v(const float *__restrict__ co
 void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                          const float *dsqp, int pitch, int n, int p, const uint64_t *binom,
                          int group, uint64_t *tau_out, unsigned long long *scan_count,
-                         hipStream_t s)
+                         hipStream_t s, const uint64_t *col_vtx)
 {
     if (ncols <= 0)
         return;
@@ -1554,16 +1585,16 @@ void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_
 #define RPP_LAUNCH_VEC(PP)                                                                        \
     if (nb == 3)                                                                                  \
         hipLaunchKernelGGL((k_apparent2v<PP, 8, 3>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
-                           pitch, n, binom, tau_out, scan_count);                                 \
+                           pitch, n, binom, tau_out, scan_count, col_vtx);                        \
     else if (nb == 4)                                                                             \
         hipLaunchKernelGGL((k_apparent2v<PP, 8, 4>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
-                           pitch, n, binom, tau_out, scan_count);                                 \
+                           pitch, n, binom, tau_out, scan_count, col_vtx);                        \
     else if (g16)                                                                                 \
         hipLaunchKernelGGL((k_apparent2v<PP, 16, 2>), g, b, 0, s, col_diam, col_cidx, ncols,      \
-                           dsqp, pitch, n, binom, tau_out, scan_count);                           \
+                           dsqp, pitch, n, binom, tau_out, scan_count, col_vtx);                  \
     else                                                                                          \
         hipLaunchKernelGGL((k_apparent2v<PP, 8, 2>), g, b, 0, s, col_diam, col_cidx, ncols, dsqp, \
-                           pitch, n, binom, tau_out, scan_count);
+                           pitch, n, binom, tau_out, scan_count, col_vtx);
     switch (p) {
     case 1: RPP_LAUNCH_VEC(1) break;
     case 2: RPP_LAUNCH_VEC(2) break;

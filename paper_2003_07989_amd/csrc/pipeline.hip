@@ -84,6 +84,8 @@ struct Workspace {
     DevBuf rscratch, scancnt;
     DevBuf dsqp;                     // row-padded square matrix (vector apparent kernel)
     bool dsqp_ready = false;         // dsqp holds this call's matrix
+    DevBuf cvtx;                     // packed vertex tuples of the kept columns
+    bool cvtx_ok = false;            // cvtx matches cdiam / ccidx
     // host hand-off of one dimension; two sets, since the reduction of
     // dimension p still reads its set while dimension p+1 fills the other
     HostBuf h_app_tau[2], h_app_sigma[2], h_na_key[2], h_na_cidx[2], h_low[2], h_lowd[2];
@@ -127,7 +129,8 @@ size_t workspace_allocated(void *wp)
                             &w.skc[1], &w.xd, &w.xc, &w.rflags, &w.rexcl, &w.rmat, &w.rvals, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
                             &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
                             &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
-                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt, &w.dsqp};
+                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt, &w.dsqp,
+                            &w.cvtx};
     for (const DevBuf *b : bufs)
         t += b->cap;
     return t;
@@ -195,8 +198,13 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     }
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+    // the vertex tuples too, which the two-phase apparent kernel reads
+    // instead of decoding every column (the walk has them at hand)
+    ws.cvtx_ok = (ea.p == 2 || ea.p == 3) && ea.n <= 65536;
+    if (ws.cvtx_ok)
+        ALLOC_TRY(ws.cvtx, (size_t)(*kept + 1) * 8);
     launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
-                        ws.ccidx.as<uint64_t>(), s);
+                        ws.ccidx.as<uint64_t>(), s, ws.cvtx_ok ? ws.cvtx.as<uint64_t>() : nullptr);
     if (tm)
         tm->stop();
     return RPP_OK;
@@ -211,6 +219,7 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
                             int64_t nclear, bool want_all, int cur, hipStream_t s,
                             int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm)
 {
+    ws.cvtx_ok = false;  // no vertex tuples on this path
     const int64_t np = ea.npre;
     ALLOC_TRY(ws.tcount, (size_t)(np + 1) * 4);
     ALLOC_TRY(ws.toff, (size_t)(np + 2) * 8);
@@ -279,6 +288,7 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
         HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
     }
     if (t_pre) {
+        ws.cvtx_ok = false;  // the columns are reordered below; cvtx is not
         // The paper's order: every kept column sorted by (diameter desc,
         // cidx asc) before the apparent test, so the partition leaves the
         // non-apparent columns in coboundary order.  The columns are in cidx
@@ -314,7 +324,8 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
         }
         launch_apparent_vec(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                             ws.dsqp.as<float>(), pitch, n, p, ws.binom.as<uint64_t>(), group,
-                            ws.tau.as<uint64_t>(), sc, s);
+                            ws.tau.as<uint64_t>(), sc, s,
+                            ws.cvtx_ok ? ws.cvtx.as<uint64_t>() : nullptr);
     } else
         launch_apparent(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
                         ws.dsq.as<float>(), n, p, ws.binom.as<uint64_t>(), group,
