@@ -150,7 +150,7 @@ size_t workspace_bytes(int n, int maxdim)
     b += (size_t)n * (n + 3) * 4;           // rank-coded distances (sparse path) or the
                                             // row-padded matrix (dense path)
     b += (size_t)E * 8 * 4;                 // edge keys / values, double buffered
-    b += (size_t)maxc * (4 + 8 + 8);        // kept columns + tau
+    b += (size_t)maxc * (4 + 8 + 8 + 8);    // kept columns, their vertex tuples, tau
     b += (size_t)maxc * 8 * 4 * 2;          // partition outputs, double buffered
     b += (size_t)(maxc / 32 + 1) * 4 * 2 + (size_t)(maxbits / 32 + 1) * 4;
     b += (size_t)radix_scratch_words((int64_t)maxc) * 8 * 2;
@@ -180,33 +180,55 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     ALLOC_TRY(ws.h_small, 256);
     unsigned long long *stats = ws.scal.as<unsigned long long>() + 2;
     HIP_TRY(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
+    // the vertex tuples too, which the two-phase apparent kernel reads
+    // instead of decoding every column (the walk has them at hand)
+    ws.cvtx_ok = (ea.p == 2 || ea.p == 3) && ea.n <= 65536;
+    // Outputs sized for every candidate when that takes at most 1 GiB: the
+    // count, scan and scatter passes then run back to back and the kept
+    // count is read once, after them; larger inputs read it between the
+    // passes and size the outputs exactly.
+    const size_t per = 4 + 8 + (ws.cvtx_ok ? 8 : 0);
+    const bool upfront = (ea.ncand + 1) * per <= ((size_t)1 << 30);
+    if (upfront) {
+        ALLOC_TRY(ws.cdiam, (size_t)(ea.ncand + 1) * 4);
+        ALLOC_TRY(ws.ccidx, (size_t)(ea.ncand + 1) * 8);
+        if (ws.cvtx_ok)
+            ALLOC_TRY(ws.cvtx, (size_t)(ea.ncand + 1) * 8);
+    }
+    uint64_t *h = ws.h_small.as<uint64_t>();
+    auto read_counts = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h + 1, stats, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *kept = tiles ? (int64_t)h[0] : 0;
+        *nthr = h[1];
+        *nclr = h[2];
+        if (ncleared >= 0) {
+            *nclr = (uint64_t)ncleared;
+            *nthr = ea.ncand - (uint64_t)*kept - (uint64_t)ncleared;
+        }
+        return RPP_OK;
+    };
     if (tm)
         tm->start();
     launch_enum_count(ea, ws.tcount.as<uint32_t>(), ncleared >= 0 ? nullptr : stats, s);
     launch_exclusive_scan(ws.tcount.as<uint32_t>(), tiles, ws.toff.as<uint64_t>(),
                           ws.scan.as<uint64_t>(), s);
-    uint64_t *h = ws.h_small.as<uint64_t>();
-    HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h + 1, stats, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    *kept = tiles ? (int64_t)h[0] : 0;
-    *nthr = h[1];
-    *nclr = h[2];
-    if (ncleared >= 0) {
-        *nclr = (uint64_t)ncleared;
-        *nthr = ea.ncand - (uint64_t)*kept - (uint64_t)ncleared;
+    if (!upfront) {
+        int rc = read_counts();
+        if (rc)
+            return rc;
+        ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
+        ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+        if (ws.cvtx_ok)
+            ALLOC_TRY(ws.cvtx, (size_t)(*kept + 1) * 8);
     }
-    ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
-    ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
-    // the vertex tuples too, which the two-phase apparent kernel reads
-    // instead of decoding every column (the walk has them at hand)
-    ws.cvtx_ok = (ea.p == 2 || ea.p == 3) && ea.n <= 65536;
-    if (ws.cvtx_ok)
-        ALLOC_TRY(ws.cvtx, (size_t)(*kept + 1) * 8);
     launch_enum_scatter(ea, ws.toff.as<uint64_t>(), ws.cdiam.as<float>(),
                         ws.ccidx.as<uint64_t>(), s, ws.cvtx_ok ? ws.cvtx.as<uint64_t>() : nullptr);
     if (tm)
         tm->stop();
+    if (upfront)
+        return read_counts();
     return RPP_OK;
 }
 
