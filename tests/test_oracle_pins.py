@@ -91,6 +91,27 @@ def test_bars_match_brute_force_betti_numbers(case):
     brute.check_bars_against_betti(dc, n, maxdim, bars, thr)
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_zero_distance_bars_match_brute_force_betti_numbers(case):
+    """Coincident points and explicit -0.0 / +0.0 entries: the bars still
+    give beta_p(Rips_t) at every scale, no bar has zero length, and every
+    reported value is written as +0.0, never -0.0."""
+    n = 6 + case % 3
+    if case % 2 == 0:
+        dc = w.signed_zero_metric(n, seed=300 + case, vmax=3)
+        assert np.any(np.signbit(dc) & (dc == 0))
+    else:
+        dc = w.condensed_from_points(w.duplicate_points_cloud(n, 310 + case, 2))
+    assert np.any(dc == 0)
+    thr = np.inf if case < 4 else 1.5
+    maxdim = 2 if n > 6 else 3
+    bars = oracle.barcodes(dc, n, maxdim, thr)
+    brute.check_bars_against_betti(dc, n, maxdim, bars, thr)
+    for b, d in bars:
+        assert np.all(d > b)
+        assert not np.any(np.signbit(b)) and not np.any(np.signbit(d))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_pair_count_identity(seed):
     """n_p = P_p + E_p + P_{p-1}; full Rips: P_p = C(n-1, p+1), E_p = 0 for
@@ -131,6 +152,31 @@ def test_clearing_lemma():
     red = oracle.reduce(dc, n, 2)
     for p in (1, 2):
         assert np.all(np.isin(red[p - 1]["tau"], red[p]["zero_sigma"]))
+
+
+def test_enclosing_radius_closed_forms():
+    """R = min_x max_y d(x, y) on inputs where it is known in closed form,
+    chosen so that the usual slips (the global maximum, the smallest entry,
+    the maximum of the row minima) give other values:
+      - the unit square's corners: every corner's farthest point is the
+        opposite corner, R = fl32(sqrt 2);
+      - the cycle-graph metric on C_n: every vertex's farthest vertex is
+        floor(n/2) steps away, R = floor(n/2);
+      - the points 0..k on a line: the middle point sees both ends,
+        R = ceil(k/2), while the global maximum is k;
+      - one point: R = 0; two points: R = their distance."""
+    assert oracle.enclosing_radius(w.unit_square_example(), 4) == np.float32(math.sqrt(2.0))
+    for n in range(3, 14):
+        assert oracle.enclosing_radius(w.cycle_graph_metric(n), n) == n // 2, n
+    for k in range(1, 12):
+        assert oracle.enclosing_radius(w.collinear_integer_metric(k), k + 1) == (k + 1) // 2, k
+    assert oracle.enclosing_radius(np.zeros(0, np.float32), 1) == 0.0
+    assert oracle.enclosing_radius(np.array([2.5], np.float32), 2) == 2.5
+    # a star: the centre (vertex 0) is at distance 1 from every leaf, leaves
+    # are 2 apart; R = 1 although most rows have maximum 2
+    n = 7
+    star = np.array([1.0 if j == 0 else 2.0 for i in range(1, n) for j in range(i)], np.float32)
+    assert oracle.enclosing_radius(star, n) == 1.0
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -228,6 +274,32 @@ def test_clearing_mode_matches_plain_reduction(case):
         assert a == b
         if p > 0:
             assert clear[p]["n_cleared"] == len(plain[p - 1]["tau"])
+    _bars_equal(oracle.bars_from_pairs(plain), oracle.bars_from_pairs(clear))
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_clearing_mode_matches_plain_reduction_maxdim3(case):
+    """The clearing mode against the plain reduction through dimension 3,
+    where clearing removes columns in three dimensions (dimension 3's
+    cleared columns are the taus of dimension 2, themselves found on
+    columns that survived dimension 1's clearing)."""
+    n = 10 + case % 3
+    if case % 3 == 0:
+        dc = w.random_integer_metric(n, seed=420 + case, vmax=4)
+    elif case % 3 == 1:
+        dc = w.condensed_from_points(w.noisy_torus_points(n, seed=520 + case))
+    else:
+        dc = w.signed_zero_metric(n, seed=620 + case, vmax=4)
+    thr = np.inf if case < 3 else float(np.quantile(dc, 0.6))
+    plain = oracle.reduce(dc, n, 3, thr)
+    clear = oracle.reduce(dc, n, 3, thr, clearing=True)
+    for p in range(4):
+        a = set(zip(plain[p]["sigma"].tolist(), plain[p]["tau"].tolist()))
+        b = set(zip(clear[p]["sigma"].tolist(), clear[p]["tau"].tolist()))
+        assert a == b, p
+        if p > 0:
+            assert clear[p]["n_cleared"] == len(plain[p - 1]["tau"])
+    assert clear[3]["n_cleared"] > 0
     _bars_equal(oracle.bars_from_pairs(plain), oracle.bars_from_pairs(clear))
 
 

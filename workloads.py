@@ -41,6 +41,9 @@ __all__ = [
     "greedy_assignment_order",
     "greedy_assignment_metric",
     "random_integer_metric",
+    "duplicate_points_cloud",
+    "signed_zero_metric",
+    "collinear_integer_metric",
     "WORKLOADS",
 ]
 
@@ -89,7 +92,11 @@ _COS_C = [
 
 
 def det_sincos(x):
-    """(sin x, cos x) for float64 arrays with |x| < 1e6, error ~1e-16."""
+    """(sin x, cos x) for float64 arrays with |x| < 1e6, error ~1e-16.
+
+    Method: Cody-Waite argument reduction by pi/2 with a two-part constant
+    (x - k*hi - k*lo, exact for the small k used here), then the Taylor
+    polynomials of sin and cos on |r| <= pi/4 and the quadrant swap."""
     x = np.asarray(x, dtype=np.float64)
     k = np.floor(x / _PIO2_HI + 0.5)
     r = (x - k * _PIO2_HI) - k * _PIO2_LO          # |r| <= pi/4 (+tiny)
@@ -103,7 +110,11 @@ def det_sincos(x):
 
 
 def det_log(u):
-    """Natural logarithm of positive float64 arrays, error ~1e-16."""
+    """Natural logarithm of positive float64 arrays, error ~1e-16.
+
+    Method: u = m * 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+    s = (m - 1)/(m + 1), by its odd power series; e * ln 2 is added with a
+    two-part (Cody-Waite) constant."""
     u = np.asarray(u, dtype=np.float64)
     m, e = np.frexp(u)                      # u = m * 2^e, m in [0.5, 1)
     e = e.astype(np.float64)
@@ -119,7 +130,10 @@ def det_log(u):
 
 
 def det_exp(x):
-    """exp of float64 arrays with |x| < 700, error ~1e-15 relative."""
+    """exp of float64 arrays with |x| < 700, error ~1e-15 relative.
+
+    Method: x = k ln 2 + r with a two-part (Cody-Waite) ln 2, |r| <= ln2/2;
+    the Taylor polynomial of exp(r), scaled by 2^k."""
     x = np.asarray(x, dtype=np.float64)
     k = np.floor(x / (_LN2_HI + _LN2_LO) + 0.5)
     r = (x - k * _LN2_HI) - k * _LN2_LO     # |r| <= ln2/2
@@ -380,6 +394,43 @@ def random_integer_metric(n: int, seed: int, vmax: int = 4) -> np.ndarray:
     metric; the method only reads edge lengths)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(1, vmax + 1, size=n * (n - 1) // 2).astype(np.float32)
+
+
+def duplicate_points_cloud(n: int, seed: int, ndup: int) -> np.ndarray:
+    """n points i.i.d. uniform in [0,1]^2 of which ndup are exact copies of
+    earlier points (coincident points: zero distances off the diagonal),
+    the copies spread over the index range."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.random((n, 2))
+    for i in rng.choice(np.arange(1, n), size=min(ndup, n - 1), replace=False):
+        x[i] = x[int(rng.integers(0, i))]
+    return x
+
+
+def signed_zero_metric(n: int, seed: int, vmax: int = 3, zero_frac: float = 0.15) -> np.ndarray:
+    """Tie-heavy integer matrix (entries in [1, vmax]) in which about
+    zero_frac of the entries are zero, half of them written as -0.0 and half
+    as +0.0 (both are the distance 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = n * (n - 1) // 2
+    d = rng.integers(1, vmax + 1, size=m).astype(np.float32)
+    z = rng.random(m) < zero_frac
+    neg = rng.random(m) < 0.5
+    d[z & neg] = np.float32(-0.0)
+    d[z & ~neg] = np.float32(0.0)
+    return d
+
+
+def collinear_integer_metric(k: int) -> np.ndarray:
+    """The k+1 points 0, 1, ..., k on a line: d(i, j) = |i - j| (exact)."""
+    n = k + 1
+    out = np.empty(n * (n - 1) // 2, dtype=np.float32)
+    idx = 0
+    for i in range(1, n):
+        for j in range(i):
+            out[idx] = float(i - j)
+            idx += 1
+    return out
 
 
 def _dist(points_fn, *a, **k):
