@@ -445,6 +445,12 @@ WORKLOADS = {
                      build=lambda: _dist(noisy_torus_points, 400, 1002)),
     "sphere4096": dict(n=4096, maxdim=2, threshold=0.4,
                        build=lambda: _dist(noisy_sphere_points, 4096, 1003)),
+    # request 448 of the serving stream: 703 points of a 5-dimensional
+    # Gaussian mixture, dims 0-2, threshold at its enclosing radius (its
+    # C(703,3) = 57.7M triangle candidates take more than 1 GiB of outputs,
+    # so the dense enumeration counts them before sizing its outputs)
+    "mixture448": dict(n=703, maxdim=2, threshold=float("inf"), golden_threshold="radius",
+                       build=lambda: mixture_request(448)["dist"]),
     # the same cloud and threshold, one dimension higher (C(4096,5) ~ 9.5e15
     # cofacet indices)
     "sphere4096d3": dict(n=4096, maxdim=3, threshold=0.4,
