@@ -11,13 +11,18 @@ diameter up to the workload's threshold (all C(n, p+1) when the workload has
 no threshold; the library's own truncation at the enclosing radius is an
 optimisation and does not change the count).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload torus400]
-Other workloads (their own JSON lines): --workload sphere4096 (4096 points on
-the sphere, threshold 0.4), --workload circles64x512 (batched forward +
-backward), --workload serving512 (Poisson request stream, served vs batched
-vs plain), --workload perm20000 (dimension-1 apparent test over all edges of
-a random edge order on 20000 points), --workload greedy200 (the same test on
-the greedy deterministic distance assignment).
+Default (no --workload): the headline line is the 4096-point sphere at
+threshold 0.4, dims 0-2 (the largest single-GPU configuration), with the
+other four configurations measured in the same process under "configs":
+square32 (latency per barcode), torus400 (simplices/s), serving512
+(barcodes/s and p50/p99, served vs batched vs plain) and circles64x512
+(batched vs plain forward, backward, finite-difference check).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+--workload runs one workload on its own line: sphere4096, torus400, square32,
+circles64x512, serving512, perm20000 (dimension-1 apparent test over all
+edges of a random edge order on 20000 points), greedy200 (the same test on
+the greedy deterministic distance assignment), sphere4096d3, mixture448.
 """
 from __future__ import annotations
 
@@ -79,14 +84,13 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary committed under profiles/, scaled by a copy kernel
-    of known size; None when there is none or the kernel source changed
-    since the counters were taken."""
+def _counter_summary(workload: str, kernel: str) -> dict:
+    """The committed rocprofv3 counter summary of `kernel` on `workload`
+    (profiles/counters_<workload>.txt) as a dict, or {} when there is none,
+    it names another kernel, or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "counters_%s.txt" % workload)
     if not os.path.exists(path):
-        return None
+        return {}
     kv = {}
     for line in open(path):
         if line.startswith("#") or ":" not in line:
@@ -95,11 +99,87 @@ def measured_traffic(workload: str, kernel: str):
         kv[k.strip()] = v.strip()
     if kv.get("kernel_sources_sha256") != kernel_sources_sha256() or \
             kv.get("kernel", "").replace(" ", "") != kernel.replace(" ", ""):
-        return None
+        return {}
+    return kv
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary committed under profiles/, scaled by a copy kernel
+    of known size; None when there is none or the kernel source changed
+    since the counters were taken."""
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(_counter_summary(workload, kernel)["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measured_l2_hit(workload: str, kernel: str):
+    """L2 (TCC) hit rate of `kernel` from the same summary, or None."""
+    try:
+        return float(_counter_summary(workload, kernel)["l2_hit_rate"])
+    except (KeyError, ValueError):
+        return None
+
+
+def host_info() -> dict:
+    """Host cores this process may use, the machine's CPU count and model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "cpu_model": model}
+
+
+def host_threads() -> int:
+    """Threads for the oracle baselines: the cores this process may use,
+    at most 16 (the host share of one GPU on the MI355X boxes)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline_sphere(m: int = 2048) -> dict:
+    """The oracle on the host cores: one random subset of m of the 4096
+    sphere points per thread (each subset its own seeded draw), threshold
+    0.4, dims 0-2, clearing mode, one thread per subset, all subsets at
+    once; simplices/s = the subsets' p-simplices (p = 1, 2) over the wall
+    time.  Denser subsets cost more per simplex, so the full-size oracle is
+    slower per simplex than this sample."""
+    import threading
+    import numpy as np
+    import oracle
+    import workloads
+    oracle.build()
+    cores = host_threads()
+    pts = workloads.noisy_sphere_points(4096, 1003)
+    subsets = []
+    for k in range(cores):
+        rng = np.random.Generator(np.random.PCG64([1003, k]))
+        idx = np.sort(rng.choice(4096, size=m, replace=False))
+        subsets.append(workloads.condensed_from_points(pts[idx]))
+    counts = [0] * cores
+
+    def run(k):
+        red = oracle.reduce(subsets[k], m, 2, 0.4, threads=1, clearing=True)
+        counts[k] = red[1]["n_simplices"] + red[2]["n_simplices"]
+    ths = [threading.Thread(target=run, args=(k,)) for k in range(cores)]
+    t0 = time.perf_counter()
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    out = {"value": round(sum(counts) / el, 1), "unit": "simplices/s", "cores": cores,
+           "kind": "oracle", "seconds": round(el, 3),
+           "sample": "%d random subsets of %d of the 4096 sphere points (one per thread, run "
+                     "together), threshold 0.4, dims 0-2, oracle clearing mode; %d simplices "
+                     "in total" % (cores, m, sum(counts))}
+    out.update(host_info())
+    return out
 
 
 def cpu_baseline(name: str) -> dict:
@@ -107,6 +187,8 @@ def cpu_baseline(name: str) -> dict:
     import numpy as np
     import oracle
     import workloads
+    if name == "sphere4096":
+        return cpu_baseline_sphere()
     if name == "torus400":
         m = 300
         pts = workloads.noisy_torus_points(400, 1002)[:m]
@@ -130,8 +212,10 @@ def cpu_baseline(name: str) -> dict:
         if el > 5.0 or name != "square32":
             break
     simplices = sum(math.comb(m, p + 1) for p in range(1, maxdim + 1)) * reps
-    return {"value": simplices / el, "unit": "simplices/s", "cores": 1, "kind": "oracle",
-            "sample": sample, "seconds": round(el, 3)}
+    out = {"value": simplices / el, "unit": "simplices/s", "cores": 1, "kind": "oracle",
+           "sample": sample, "seconds": round(el, 3)}
+    out.update(host_info())
+    return out
 
 
 def _pct(x, q):
@@ -207,7 +291,7 @@ def bench_circles(args):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_clouds(dists, 512)
-    print(json.dumps(out))
+    return out
 
 
 def _edge_vertices(e):
@@ -291,7 +375,7 @@ def cpu_baseline_clouds(dists, n):
     import threading
     import oracle
     oracle.build()
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    cores = host_threads()
     sample = dists[:cores]
     t0 = time.perf_counter()
     ths = [threading.Thread(target=lambda d=d: oracle.barcodes(
@@ -434,7 +518,7 @@ def bench_serving(args):
         out["sweep"] = sweep
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_requests(rpp, reqs)
-    print(json.dumps(out))
+    return out
 
 
 def cpu_baseline_requests(rpp, reqs, n_max=256, k=32):
@@ -444,7 +528,7 @@ def cpu_baseline_requests(rpp, reqs, n_max=256, k=32):
     import threading
     import oracle
     oracle.build()
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    cores = host_threads()
     sample = [r for r in reqs if r["n"] <= n_max][:k]
     queue = list(range(len(sample)))
     lock = threading.Lock()
@@ -588,44 +672,17 @@ def cpu_baseline_perm(n0=500):
             "sample": "random order on %d points (all %d edges), dimension 1" % (n0, n0 * (n0 - 1) // 2)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="torus400")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sort-first", action="store_true",
-                    help="the paper's stage order: sort every kept column before the "
-                         "apparent test (default: sort only the non-apparent ones after it)")
-    ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--rates", default="0.8",
-                    help="serving: arrival rates as multiples of the plain capacity")
-    ap.add_argument("--fd-full", action="store_true",
-                    help="circles: finite-difference check of every coordinate")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the hot path runs on a single MI355X and this "
-              "build has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload.startswith("perm"):
-        return bench_perm(args, int(args.workload[4:]))
-    if args.workload.startswith("greedy"):
-        return bench_perm(args, int(args.workload[6:]), kind="greedy")
-    if args.workload == "copy1g":
-        return bench_copy(args)
-    if args.workload == "circles64x512":
-        return bench_circles(args)
-    if args.workload.startswith("serving"):
-        return bench_serving(args)
-
+def bench_cloud(args, name: str, cpu: bool = True) -> dict:
+    """One named point cloud (workloads.WORKLOADS): W warm-up calls, then K
+    timed calls of rpp_barcodes_device on the resident matrix; simplices/s
+    of whole-step time, the GPU stage times, and the roofline of the
+    dominant kernel of the top dimension."""
     import numpy as np
     import torch
     import paper_2003_07989_amd as rpp
     import workloads
 
-    cfg = workloads.WORKLOADS[args.workload]
+    cfg = workloads.WORKLOADS[name]
     n, maxdim, thr = cfg["n"], cfg["maxdim"], cfg["threshold"]
     d_host = cfg["build"]()
     torch.cuda.set_device(0)
@@ -683,13 +740,16 @@ def main():
     if kname == "apparent":
         kfull = apparent_kernel_name(top, g)
     elif g < 0:
-        kfull = "k_ext<%d>" % top  # sparse enumeration (count + scatter passes)
+        kfull = "k_ext<%d>+k_clear_filter" % top  # sparse enumeration and clearing
     else:
         kfull = "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top)
+    traffic = measured_traffic(name, kfull)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, kfull),
-            "kernel": kfull, "dim": top, "ms": round(kms, 4), "bytes": kbytes}
+            "traffic": traffic, "kernel": kfull, "dim": top, "ms": round(kms, 4),
+            "bytes": kbytes,
+            "measured_gbs": round(traffic / (kms / 1e3) / 1e9, 2) if traffic else None,
+            "l2_hit_rate": measured_l2_hit(name, kfull)}
 
     out = {
         "metric": "simplices/sec through apparent-pair+filtration",
@@ -704,7 +764,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "maxdim": maxdim,
+        "config": {"workload": name, "n": n, "maxdim": maxdim,
                    "stage_order": "sort-first" if args.sort_first else "sort-after",
                    "threshold": "inf" if math.isinf(thr) else thr,
                    "threshold_used": last.threshold_used,
@@ -717,9 +777,98 @@ def main():
         "n_scanned": {p: tally.stats[p]["n_scanned"] for p in range(1, maxdim + 1)},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload)
-    print(json.dumps(out))
+    if cpu and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(name)
+    return out
+
+
+def bench_latency(args, name: str = "square32") -> dict:
+    """Latency per barcode of a small cloud (launch-bound): the median and
+    mean over K x 10 calls of rpp_barcodes_device on the resident matrix."""
+    import numpy as np
+    import torch
+    import paper_2003_07989_amd as rpp
+    import workloads
+    cfg = workloads.WORKLOADS[name]
+    dist = torch.from_numpy(cfg["build"]()).cuda()
+    stream = torch.cuda.current_stream()
+    rpp.load()
+    for _ in range(args.warmup):
+        rpp.barcodes_device(dist, cfg["maxdim"], cfg["threshold"], stream=stream)
+    torch.cuda.synchronize()
+    lat, gpu = [], []
+    for _ in range(10 * args.steps):
+        t0 = time.perf_counter()
+        r = rpp.barcodes_device(dist, cfg["maxdim"], cfg["threshold"], stream=stream)
+        lat.append(time.perf_counter() - t0)
+        gpu.append(sum(s["ms_gpu"] for s in r.stats))
+    return {"metric": "latency per barcode (32 points, dims 0-1)", "value":
+            round(float(np.median(lat)) * 1e6, 1), "unit": "us", "higher_is_better": False,
+            "mean_us": round(float(np.mean(lat)) * 1e6, 1), "calls": len(lat),
+            "gpu_stage_ms_mean": round(float(np.mean(gpu)), 4),
+            "config": {"workload": name, "n": cfg["n"], "maxdim": cfg["maxdim"]},
+            "roofline": "launch-bound: 496 edges and 4960 triangle cofacets per call, far "
+                        "below any bandwidth roof"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=None,
+                    help="one workload on its own line (default: the sphere headline with "
+                         "every configuration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default run: the headline only, without the other configurations")
+    ap.add_argument("--sort-first", action="store_true",
+                    help="the paper's stage order: sort every kept column before the "
+                         "apparent test (default: sort only the non-apparent ones after it)")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rates", default="0.8",
+                    help="serving: arrival rates as multiples of the plain capacity")
+    ap.add_argument("--fd-full", action="store_true",
+                    help="circles: finite-difference check of every coordinate")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X and this "
+              "build has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    wl = args.workload
+    if wl is None:
+        out = bench_cloud(args, "sphere4096")
+        print("bench: sphere4096 headline done", file=sys.stderr, flush=True)
+        if not args.no_extras:
+            extras = {}
+            extras["square32"] = bench_latency(args)
+            print("bench: square32 done", file=sys.stderr, flush=True)
+            extras["torus400"] = bench_cloud(args, "torus400", cpu=False)
+            print("bench: torus400 done", file=sys.stderr, flush=True)
+            extras["serving512"] = bench_serving(args)
+            print("bench: serving512 done", file=sys.stderr, flush=True)
+            extras["circles64x512"] = bench_circles(args)
+            print("bench: circles64x512 done", file=sys.stderr, flush=True)
+            out["configs"] = extras
+        print(json.dumps(out))
+        return
+    if wl.startswith("perm"):
+        return bench_perm(args, int(wl[4:]))
+    if wl.startswith("greedy"):
+        return bench_perm(args, int(wl[6:]), kind="greedy")
+    if wl == "copy1g":
+        return bench_copy(args)
+    if wl == "circles64x512":
+        print(json.dumps(bench_circles(args)))
+        return
+    if wl.startswith("serving"):
+        print(json.dumps(bench_serving(args)))
+        return
+    if wl == "square32":
+        print(json.dumps(bench_latency(args)))
+        return
+    print(json.dumps(bench_cloud(args, wl)))
 
 
 if __name__ == "__main__":

@@ -39,7 +39,10 @@
  *
  * Errors.  Every function returning int returns RPP_OK (0) or a negative
  * RPP_E_* code; on error *out is left NULL and rpp_last_error() describes
- * the failure (thread-local text).
+ * the failure (thread-local text).  Test hook: the environment variable
+ * RPP_FAULT_INJECT=<stage>[:<n>] makes every call (or every call on n
+ * points) fail with RPP_E_DEVICE at that stage boundary, stage one of
+ * stage, h0, enumerate, apparent, host; nothing else changes.
  */
 #ifndef RPP_H
 #define RPP_H
@@ -60,6 +63,7 @@ enum {
     RPP_E_RANGE = -3,  /* C(n, maxdim+2) does not fit the index type, or n too large */
     RPP_E_NOMEM = -4,  /* host or device allocation failed, or workspace too small */
     RPP_E_DEVICE = -5, /* HIP runtime error */
+    RPP_E_CANCELLED = -6, /* serving request cancelled (rpp_server_cancel) */
 };
 
 /* flags for rpp_barcodes_device */
@@ -189,9 +193,25 @@ int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
 
 /* As rpp_barcodes, for a distance matrix already resident in device memory
  * (HBM).  Work is issued on hip_stream (a hipStream_t, NULL = null stream)
- * of the current device; the call returns after the result is complete.
- * workspace_dev / workspace_bytes: caller-provided device scratch, or
- * NULL / 0 to let the library use its own per-device cache.  flags: RPP_*. */
+ * of the current device; the call returns after the result is complete and
+ * every kernel it launched has finished.  flags: RPP_*.
+ *
+ * Device memory.  workspace_dev / workspace_bytes: caller-owned device
+ * memory (any alignment is accepted; 256-byte alignment is best) from which
+ * EVERY device buffer of the call is carved; the library allocates no device
+ * memory of its own for the call and keeps no pointer into the workspace
+ * after it returns.  The caller keeps ownership and must not touch the
+ * memory during the call.  A workspace of at least rpp_workspace_bytes(n,
+ * maxdim, threshold) never runs out.  A smaller one is used as far as it
+ * goes (a threshold usually leaves most of that bound unused): the call
+ * fails with RPP_E_NOMEM, *out left NULL, as soon as a buffer no longer fits,
+ * and up front, before any device work, when workspace_bytes is below what
+ * staging and H0 need for n points.  workspace_bytes > 0 with a NULL
+ * workspace_dev is RPP_E_INVAL.
+ * NULL / 0: the library uses its own grow-only per-device cache; the
+ * environment variable RPP_DEVICE_BUDGET_BYTES then caps the device bytes
+ * that cache may hold during the call (RPP_E_NOMEM when a buffer would pass
+ * it; up front, before any device work, when staging and H0 alone would). */
 int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
                         void *workspace_dev, size_t workspace_bytes, void *hip_stream,
                         uint32_t flags, rpp_result **out);
@@ -217,7 +237,10 @@ int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream,
                        rpp_result **outs);
 
 /* Upper bound of the device workspace that rpp_barcodes_device needs for a
- * matrix of n points, dimensions 0..maxdim (0 on invalid arguments). */
+ * matrix of n points, dimensions 0..maxdim, whatever the distances and the
+ * threshold (0 on invalid arguments): the sum over the call's device buffers
+ * of their largest possible size, every count taken at its combinatorial
+ * maximum C(n, p+1).  Also the footprint bound of the serving admission. */
 size_t rpp_workspace_bytes(int32_t n, int32_t maxdim, float threshold);
 
 /* Apparent pairs of dimension (p, p+1) over EVERY p-simplex with diameter
@@ -299,6 +322,11 @@ int rpp_server_submit(rpp_server *s, const float *dist, int32_t n, int32_t maxdi
  * error code if it failed.  Each ticket can be waited for once. */
 int rpp_server_wait(rpp_server *s, uint64_t ticket, rpp_result **out, double *latency_ms,
                     double *queue_ms);
+/* Cancel a request.  A queued request never runs; a running one stops at
+ * its next stage boundary (its GPU work so far completes).  Its
+ * rpp_server_wait then returns RPP_E_CANCELLED.  Returns RPP_OK, or
+ * RPP_E_INVAL for an unknown, already finished or already waited ticket. */
+int rpp_server_cancel(rpp_server *s, uint64_t ticket);
 int rpp_server_stats(rpp_server *s, rpp_server_info *st);
 /* Finishes the queued requests, then releases everything. */
 void rpp_server_destroy(rpp_server *s);

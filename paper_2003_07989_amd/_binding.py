@@ -33,7 +33,7 @@ RPP_SORT_FIRST = 0x200
 NO_EDGE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
-          -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE"}
+          -4: "RPP_E_NOMEM", -5: "RPP_E_DEVICE", -6: "RPP_E_CANCELLED"}
 
 
 class RppError(RuntimeError):
@@ -131,6 +131,8 @@ def load() -> ctypes.CDLL:
     lib.rpp_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(P(_Result)),
                                     P(ctypes.c_double), P(ctypes.c_double)]
     lib.rpp_server_wait.restype = ctypes.c_int
+    lib.rpp_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    lib.rpp_server_cancel.restype = ctypes.c_int
     lib.rpp_server_stats.argtypes = [ctypes.c_void_p, P(_ServerStats)]
     lib.rpp_server_stats.restype = ctypes.c_int
     lib.rpp_server_destroy.argtypes = [ctypes.c_void_p]
@@ -216,19 +218,28 @@ def _stream_handle(stream) -> int:
 
 
 def barcodes_device(dist: torch.Tensor, maxdim: int, threshold: float = math.inf,
-                    n: int = None, flags: int = 0, stream=None) -> Barcodes:
+                    n: int = None, flags: int = 0, stream=None,
+                    workspace: torch.Tensor = None) -> Barcodes:
     """rpp_barcodes_device on a contiguous float32 CUDA tensor holding the
-    condensed lower triangle."""
+    condensed lower triangle.  workspace: an optional contiguous CUDA tensor
+    (any dtype) whose memory the call uses for every device buffer."""
     if not (isinstance(dist, torch.Tensor) and dist.is_cuda and dist.dtype == torch.float32
             and dist.is_contiguous()):
         raise TypeError("dist must be a contiguous float32 CUDA tensor")
     if n is None:
         n = _n_from_len(dist.numel())
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda
+                and workspace.is_contiguous()):
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        ws_ptr = ctypes.c_void_p(workspace.data_ptr())
+        ws_bytes = workspace.numel() * workspace.element_size()
     lib = load()
     out = ctypes.POINTER(_Result)()
     rc = lib.rpp_barcodes_device(ctypes.c_void_p(dist.data_ptr() if dist.numel() else 0),
-                                 int(n), int(maxdim), ctypes.c_float(threshold), None, 0,
-                                 ctypes.c_void_p(_stream_handle(stream)), int(flags),
+                                 int(n), int(maxdim), ctypes.c_float(threshold), ws_ptr,
+                                 ws_bytes, ctypes.c_void_p(_stream_handle(stream)), int(flags),
                                  ctypes.byref(out))
     _check(rc)
     try:
@@ -466,6 +477,11 @@ class Server:
             return _collect(out), lat.value, q.value
         finally:
             self._lib.rpp_result_free(out)
+
+    def cancel(self, ticket: int):
+        """rpp_server_cancel: a queued request never runs, a running one
+        stops at its next stage boundary; its wait raises RPP_E_CANCELLED."""
+        _check(load().rpp_server_cancel(self._h, int(ticket)))
 
     def stats(self) -> dict:
         st = _ServerStats()

@@ -46,6 +46,39 @@ int check_args(int32_t n, int32_t maxdim, float threshold, rpp_result **out)
     return RPP_OK;
 }
 
+// RPP_DEVICE_BUDGET_BYTES: cap on the device bytes the library's own cache
+// may hold during a call (SIZE_MAX when unset).
+size_t device_budget()
+{
+    const char *e = getenv("RPP_DEVICE_BUDGET_BYTES");
+    if (!e || !*e)
+        return SIZE_MAX;
+    return (size_t)strtoull(e, nullptr, 10);
+}
+
+// Up-front device-memory check of a call on n points (before any device
+// work): a caller workspace below the floor, or a budget below the floor
+// plus `extra` bytes of the call's own (the host entry point's input copy).
+int check_device_memory(int32_t n, int32_t maxdim, const void *ws, size_t ws_bytes,
+                        size_t extra)
+{
+    if (!ws && ws_bytes)
+        return fail(RPP_E_INVAL, "workspace_bytes > 0 with a NULL workspace_dev");
+    const size_t floor = rpp::workspace_floor_bytes(n, maxdim);
+    if (ws && ws_bytes < floor)
+        return fail(RPP_E_NOMEM, "caller workspace of " + std::to_string(ws_bytes) +
+                                     " bytes is below the " + std::to_string(floor) +
+                                     " bytes that staging and H0 need for n = " +
+                                     std::to_string(n));
+    const size_t budget = device_budget();
+    if (!ws && budget != SIZE_MAX && floor + extra > budget)
+        return fail(RPP_E_NOMEM, "RPP_DEVICE_BUDGET_BYTES=" + std::to_string(budget) +
+                                     " is below the " + std::to_string(floor + extra) +
+                                     " device bytes that staging and H0 need for n = " +
+                                     std::to_string(n));
+    return RPP_OK;
+}
+
 template <typename T>
 T *dup(const std::vector<T> &v)
 {
@@ -138,21 +171,28 @@ void set_last_error(const std::string &msg)
 }
 }  // namespace rpp
 
-extern "C" {
+namespace {
 
-int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
-                        void *workspace_dev, size_t workspace_bytes, void *hip_stream,
-                        uint32_t flags, rpp_result **out)
+// rpp_barcodes_device with `held_elsewhere` device bytes of the caller's
+// counted against the budget (the host entry point's input copy).
+int barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
+                    void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                    uint32_t flags, rpp_result **out, size_t held_elsewhere)
 {
     int rc = check_args(n, maxdim, threshold, out);
     if (rc)
         return rc;
     if (n > 1 && !dist_dev)
         return fail(RPP_E_INVAL, "dist_dev is NULL");
-    (void)workspace_dev;
-    (void)workspace_bytes;
+    rc = check_device_memory(n, maxdim, workspace_dev, workspace_bytes, held_elsewhere);
+    if (rc)
+        return rc;
     try {
         rpp::RunArgs a;
+        a.arena = workspace_dev;
+        a.arena_bytes = workspace_dev ? workspace_bytes : 0;
+        const size_t budget = device_budget();
+        a.device_limit = budget == SIZE_MAX ? SIZE_MAX : budget - held_elsewhere;
         a.dcond_dev = dist_dev;
         a.n = n;
         a.maxdim = maxdim;
@@ -172,6 +212,18 @@ int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float 
     } catch (const std::bad_alloc &) {
         return fail(RPP_E_NOMEM, "host allocation failed");
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpp_barcodes_device(const float *dist_dev, int32_t n, int32_t maxdim, float threshold,
+                        void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                        uint32_t flags, rpp_result **out)
+{
+    return barcodes_device(dist_dev, n, maxdim, threshold, workspace_dev, workspace_bytes,
+                           hip_stream, flags, out, 0);
 }
 
 int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream, uint32_t flags,
@@ -259,6 +311,9 @@ int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
     for (size_t i = 0; i < m; ++i)
         if (!(dist[i] >= 0.0f) || isinf(dist[i]))
             return fail(RPP_E_DATA, "distance matrix holds a NaN, infinite or negative entry");
+    rc = check_device_memory(n, maxdim, nullptr, 0, m * sizeof(float));
+    if (rc)
+        return rc;
     float *d = nullptr;
     if (m) {
         hipError_t e = hipMalloc(&d, m * sizeof(float));
@@ -270,7 +325,7 @@ int rpp_barcodes(const float *dist, int32_t n, int32_t maxdim, float threshold,
             return fail(RPP_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
         }
     }
-    rc = rpp_barcodes_device(d, n, maxdim, threshold, nullptr, 0, nullptr, 0, out);
+    rc = barcodes_device(d, n, maxdim, threshold, nullptr, 0, nullptr, 0, out, m * sizeof(float));
     if (d)
         (void)hipFree(d);
     return rc;
@@ -411,6 +466,7 @@ const char *rpp_strerror(int code)
     case RPP_E_RANGE: return "problem size outside the supported index range";
     case RPP_E_NOMEM: return "out of memory";
     case RPP_E_DEVICE: return "HIP runtime error";
+    case RPP_E_CANCELLED: return "request cancelled";
     default: return "unknown error";
     }
 }

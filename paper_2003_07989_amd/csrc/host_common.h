@@ -30,39 +30,91 @@ inline size_t grow_capacity(size_t old, size_t bytes)
     return (b + 65535) & ~(size_t)65535;
 }
 
-// Owning device buffer; grows, never shrinks; movable, not copyable.
+// Where the device buffers of one workspace come from.
+//  - Own allocations (the default): hipMalloc, with 1.5x growth headroom;
+//    with a limit (a serving slot's reservation, RPP_DEVICE_BUDGET_BYTES)
+//    every allocation is exact-sized and the buffers together never hold
+//    more than the limit.
+//  - A caller-provided arena (rpp_barcodes_device's workspace argument):
+//    buffers are carved from it bottom-up and never freed; a buffer takes
+//    its planned maximum for the call (its hint) on first use when that
+//    still fits, so an arena of at least the sum of the hints never runs
+//    out, and otherwise exactly what is asked.
+struct DevPool {
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_top = 0;
+    size_t limit = SIZE_MAX;    // own allocations: most bytes held at once
+    size_t held = 0;            // own allocations: bytes held now
+    bool exhausted = false;     // the last failed request hit the arena end or the limit
+};
+
+// Device buffer; grows, never shrinks; movable, not copyable.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    size_t hint = 0;            // planned maximum (arena mode)
+    DevPool *pool = nullptr;    // allocation policy; null = plain hipMalloc
+    bool owned = true;          // false: carved from an arena, never freed here
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), cap(o.cap)
+    DevBuf(DevBuf &&o) noexcept
+        : p(o.p), cap(o.cap), hint(o.hint), pool(o.pool), owned(o.owned)
     {
         o.p = nullptr;
         o.cap = 0;
+        o.owned = true;
     }
     DevBuf &operator=(DevBuf &&o) noexcept
     {
         std::swap(p, o.p);
         std::swap(cap, o.cap);
+        std::swap(hint, o.hint);
+        std::swap(pool, o.pool);
+        std::swap(owned, o.owned);
         return *this;
     }
-    ~DevBuf()
+    ~DevBuf() { release(); }
+    // Free own memory (arena memory is simply forgotten).
+    void release()
     {
-        if (p)
+        if (p && owned) {
             (void)hipFree(p);
+            if (pool)
+                pool->held -= cap;
+        }
+        p = nullptr;
+        cap = 0;
+        owned = true;
     }
     bool ensure(size_t bytes)
     {
         if (bytes <= cap && p)
             return true;
-        const size_t cap0 = p ? cap : 0;
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        size_t b = grow_capacity(cap0, bytes);
+        if (pool && pool->arena) {
+            const size_t left = pool->arena_size - pool->arena_top;
+            size_t want = ((bytes > hint ? bytes : hint) + 255) & ~(size_t)255;
+            if (want > left)
+                want = (bytes + 255) & ~(size_t)255;
+            if (want > left) {
+                pool->exhausted = true;
+                return false;
+            }
+            release();
+            p = pool->arena + pool->arena_top;
+            pool->arena_top += want;
+            cap = want;
+            owned = false;
+            return true;
+        }
+        const size_t cap0 = (p && owned) ? cap : 0;
+        const bool limited = pool && pool->limit != SIZE_MAX;
+        size_t b = limited ? grow_capacity(0, bytes) : grow_capacity(cap0, bytes);
+        if (limited && pool->held - cap0 + b > pool->limit) {
+            pool->exhausted = true;
+            return false;
+        }
+        release();
         if (hipMalloc(&p, b) != hipSuccess) {
             // The headroom may not fit where the exact size does.
             const size_t e = grow_capacity(0, bytes);
@@ -74,6 +126,8 @@ struct DevBuf {
             b = e;
         }
         cap = b;
+        if (pool)
+            pool->held += b;
         return true;
     }
     template <typename T>
@@ -151,10 +205,28 @@ struct HostBuf {
 #define ALLOC_TRY(buf, bytes)                                                      \
     do {                                                                           \
         if (!(buf).ensure(bytes)) {                                                \
-            err = "allocation of " + std::to_string((size_t)(bytes)) + " bytes failed"; \
+            err = alloc_failure_text(buf, (size_t)(bytes));                        \
             return RPP_E_NOMEM;                                                    \
         }                                                                          \
     } while (0)
+
+inline std::string alloc_failure_text(const DevBuf &b, size_t bytes)
+{
+    if (b.pool && b.pool->arena)
+        return "caller workspace too small: " + std::to_string(bytes) + " more bytes needed with " +
+               std::to_string(b.pool->arena_size - b.pool->arena_top) + " of " +
+               std::to_string(b.pool->arena_size) + " left";
+    if (b.pool && b.pool->exhausted)
+        return "device memory limit of " + std::to_string(b.pool->limit) +
+               " bytes reached (allocation of " + std::to_string(bytes) + " bytes)";
+    return "allocation of " + std::to_string(bytes) + " bytes failed";
+}
+
+template <typename B>
+inline std::string alloc_failure_text(const B &, size_t bytes)
+{
+    return "allocation of " + std::to_string(bytes) + " bytes failed";
+}
 
 struct GpuTimer {
     hipEvent_t a = nullptr, b = nullptr;

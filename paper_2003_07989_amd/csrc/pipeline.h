@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -36,12 +37,27 @@ struct RunArgs {
     int apparent_group = 0;            // lanes per column, 0 = default
     bool count_scans = false;          // tally cofacet candidates per column
     void *workspace = nullptr;         // explicit workspace (workspace_new), or the device's
+    void *arena = nullptr;             // caller device memory for every device buffer, or null
+    size_t arena_bytes = 0;
+    size_t device_limit = SIZE_MAX;    // most device bytes the call's own buffers may hold
+    const std::atomic<bool> *cancel = nullptr;  // set: stop at the next stage boundary
 };
 
 // Device workspaces for concurrent callers (one per serving slot).
 void *workspace_new();
 void workspace_delete(void *w);
-size_t workspace_allocated(void *w);
+size_t workspace_allocated(void *w);   // device bytes the workspace holds
+void workspace_trim(void *w);          // free every device buffer of an idle workspace
+void workspace_set_limit(void *w, size_t limit);  // cap on the bytes it may hold
+
+// Device bytes every call on n points needs whatever its data (staging and
+// H0); a caller workspace or a device budget below it cannot work.
+size_t workspace_floor_bytes(int n, int maxdim);
+
+// RPP_FAULT_INJECT=<stage>[:<n>]: true when the call on n points should fail
+// at `stage` (tests of the error paths; stages: stage, h0, enumerate,
+// apparent, host).
+bool fault_injected(const char *stage, int n);
 
 // Returns an RPP_* code; on error `err` holds a message.
 int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);

@@ -65,6 +65,8 @@ uint64_t binom_sat(int n, int k)
 // device workspace: grow-only buffers cached per device
 // ---------------------------------------------------------------------------
 struct Workspace {
+    Workspace();
+    DevPool pool;                    // where the device buffers come from
     std::mutex mu;
     DevBuf dsq, rowmax, scal, binom;
     DevBuf ekey, eval, ekey2, eval2;  // edges for H0
@@ -95,6 +97,109 @@ struct Workspace {
     std::vector<uint64_t> binom_host;
 };
 
+// Every device buffer of a workspace, in one list (pool wiring, swaps,
+// accounting).
+static std::vector<DevBuf *> device_buffers(Workspace &w)
+{
+    return {&w.dsq,     &w.rowmax,  &w.scal,    &w.binom,  &w.ekey,   &w.eval,    &w.ekey2,
+            &w.eval2,   &w.mst,     &w.deaths,  &w.dedges, &w.ufs,    &w.tcount,  &w.toff,
+            &w.scan,    &w.tcount2, &w.toff2,   &w.skd[0], &w.skd[1], &w.skc[0],  &w.skc[1],
+            &w.xd,      &w.xc,      &w.rflags,  &w.rexcl,  &w.rmat,   &w.rvals,   &w.bits,
+            &w.clr,     &w.clr2,    &w.clrv,    &w.clrv2,  &w.cdiam,  &w.ccidx,   &w.tau,
+            &w.akey,    &w.aval,    &w.akey2,   &w.aval2,  &w.nkey,   &w.nval,    &w.nkey2,
+            &w.nval2,   &w.clear,   &w.next,    &w.hostpiv, &w.lowc,  &w.lowd,    &w.gedges,
+            &w.gvals,   &w.rscratch, &w.scancnt, &w.dsqp,  &w.cvtx};
+}
+
+Workspace::Workspace()
+{
+    for (DevBuf *b : device_buffers(*this))
+        b->pool = &pool;
+}
+
+// The largest size each device buffer can take in one call of run_pipeline
+// on n points and dimensions 0..maxdim, whatever the distances, the
+// threshold and the path (dense or sparse): every count is bounded by the
+// number of candidates, C(n, p+1) for a p-simplex.  Written into the
+// buffers' hints (arena plan); rpp_workspace_bytes is their sum.
+static void plan_limits(Workspace &w, int n, int maxdim)
+{
+    for (DevBuf *b : device_buffers(w))
+        b->hint = 0;
+    if (n < 2)
+        return;
+    const int m = std::max(1, maxdim);
+    const uint64_t E = binom_sat(n, 2);
+    // C(n, k) is not monotone in k (it falls past k = n/2): take maxima
+    auto cmax_k = [&](int k0, int k1) {
+        uint64_t c = 0;
+        for (int k = k0; k <= k1; ++k)
+            c = std::max(c, binom_sat(n, k));
+        return c;
+    };
+    const uint64_t cmax = cmax_k(2, m + 1);   // most p-simplices, p = 1..maxdim
+    const uint64_t cpre = cmax_k(2, m);       // p-simplices, p < maxdim (skeleton, prefixes)
+    const uint64_t cnext = cmax_k(3, m + 1);  // bitmap of the next dimension's clearing set
+    const uint64_t tiles = (uint64_t)compact_tiles((int64_t)cmax);
+    const uint64_t scan_n = std::max(std::max(tiles, cpre), E);
+    const int words = (n + 63) / 64;
+    const size_t pitch = (size_t)((n + 3) & ~3);
+    const size_t nn = (size_t)n;
+    w.dsq.hint = nn * nn * 4;
+    w.rowmax.hint = nn * 4;
+    w.scal.hint = 256;
+    w.binom.hint = (size_t)(maxdim + 3) * (nn + 1) * 8;
+    w.ekey.hint = w.eval.hint = w.ekey2.hint = w.eval2.hint = (E + 1) * 8;
+    w.mst.hint = (E / 32 + 2) * 4;
+    w.deaths.hint = nn * 4;
+    w.dedges.hint = nn * 8;
+    w.ufs.hint = 2 * nn * 4 + 64;
+    w.tcount.hint = (std::max(tiles, cpre) + 1) * 4;
+    w.toff.hint = (std::max(tiles, cpre) + 2) * 8;
+    w.scan.hint = (size_t)scan_scratch_words((int64_t)scan_n) * 8;
+    w.tcount2.hint = (tiles + 1) * 4;
+    w.toff2.hint = (tiles + 2) * 8;
+    w.cdiam.hint = (cmax + 1) * 4;
+    w.ccidx.hint = w.cvtx.hint = (cmax + 1) * 8;
+    w.tau.hint = w.akey.hint = w.aval.hint = w.akey2.hint = w.aval2.hint = (cmax + 1) * 8;
+    w.nkey.hint = w.nval.hint = w.nkey2.hint = w.nval2.hint = (cmax + 1) * 8;
+    w.lowc.hint = (cmax + 1) * 8;
+    w.lowd.hint = (cmax + 1) * 4;
+    w.rscratch.hint = (size_t)radix_scratch_words((int64_t)cmax) * 8;
+    w.scancnt.hint = (size_t)SCAN_COUNTERS * 8;
+    w.dsqp.hint = nn * pitch * 4;
+    w.next.hint = w.clear.hint = (cnext / 32 + 2) * 4;
+    if (maxdim >= 1) {  // sparse path
+        w.skd[0].hint = w.skd[1].hint = (cpre + 1) * 4;
+        w.skc[0].hint = w.skc[1].hint = (cpre + 1) * 8;
+        w.xd.hint = (cmax + 1) * 4;
+        w.xc.hint = (cmax + 1) * 8;
+        w.rflags.hint = (E + 1) * 4;
+        w.rexcl.hint = (E + 2) * 8;
+        w.rmat.hint = nn * nn * 4;
+        w.rvals.hint = (E + 1) * 4;
+        w.bits.hint = nn * (size_t)words * 8;
+        w.clr.hint = w.clr2.hint = w.clrv.hint = w.clrv2.hint = (cpre + 1) * 8;
+    }
+}
+
+// Device bytes every call on n points needs before its data are seen: the
+// square matrix and H0 (staging, edge enumeration, edge keys and sort,
+// union-find).
+size_t workspace_floor_bytes(int n, int maxdim)
+{
+    if (n < 2)
+        return 0;
+    const uint64_t E = binom_sat(n, 2);
+    const int64_t tiles = compact_tiles((int64_t)E);
+    size_t b = (size_t)n * n * 4 + (size_t)n * 4 + 256 + (size_t)(maxdim + 3) * (n + 1) * 8;
+    b += (size_t)(tiles + 1) * 4 + (size_t)(tiles + 2) * 8 + (size_t)scan_scratch_words(tiles) * 8;
+    b += (size_t)(E + 1) * (4 + 8) + (size_t)(E + 1) * 8 * 4;
+    b += (size_t)radix_scratch_words((int64_t)E) * 8 + (size_t)(E / 32 + 2) * 4;
+    b += (size_t)n * (4 + 8 + 8) + 64;
+    return b;
+}
+
 static std::mutex g_ws_mu;
 static std::map<int, Workspace *> g_ws;
 
@@ -123,38 +228,115 @@ size_t workspace_allocated(void *wp)
 {
     Workspace &w = *static_cast<Workspace *>(wp);
     size_t t = 0;
-    const DevBuf *bufs[] = {&w.dsq, &w.rowmax, &w.scal, &w.binom, &w.ekey, &w.eval, &w.ekey2,
-                            &w.eval2, &w.mst, &w.deaths, &w.dedges, &w.ufs, &w.tcount, &w.toff,
-                            &w.scan, &w.tcount2, &w.toff2, &w.skd[0], &w.skd[1], &w.skc[0],
-                            &w.skc[1], &w.xd, &w.xc, &w.rflags, &w.rexcl, &w.rmat, &w.rvals, &w.bits, &w.clr, &w.clr2, &w.clrv, &w.clrv2, &w.cdiam,
-                            &w.ccidx, &w.tau, &w.akey, &w.aval, &w.akey2, &w.aval2, &w.nkey,
-                            &w.nval, &w.nkey2, &w.nval2, &w.clear, &w.next, &w.hostpiv, &w.lowc,
-                            &w.lowd, &w.gedges, &w.gvals, &w.rscratch, &w.scancnt, &w.dsqp,
-                            &w.cvtx};
-    for (const DevBuf *b : bufs)
-        t += b->cap;
+    for (const DevBuf *b : device_buffers(w))
+        t += b->owned ? b->cap : 0;
     return t;
+}
+
+void workspace_trim(void *wp)
+{
+    Workspace &w = *static_cast<Workspace *>(wp);
+    std::lock_guard<std::mutex> lk(w.mu);
+    for (DevBuf *b : device_buffers(w))
+        b->release();
+    w.binom_n = w.binom_k = -1;
+    w.dsqp_ready = false;
+    w.cvtx_ok = false;
+}
+
+void workspace_set_limit(void *wp, size_t limit)
+{
+    Workspace &w = *static_cast<Workspace *>(wp);
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.pool.limit = limit;
 }
 
 size_t workspace_bytes(int n, int maxdim)
 {
     if (n < 2)
         return 4096;
-    uint64_t E = binom_sat(n, 2);
-    uint64_t maxc = E;
-    for (int p = 2; p <= maxdim; ++p)
-        maxc = std::max(maxc, binom_sat(n, p + 1));
-    uint64_t maxbits = binom_sat(n, std::min(maxdim + 1, n) + 1);
+    Workspace w;
+    plan_limits(w, n, maxdim);
     size_t b = 0;
-    b += (size_t)n * n * 4 + (size_t)n * 4 * 4;
-    b += (size_t)n * (n + 3) * 4;           // rank-coded distances (sparse path) or the
-                                            // row-padded matrix (dense path)
-    b += (size_t)E * 8 * 4;                 // edge keys / values, double buffered
-    b += (size_t)maxc * (4 + 8 + 8 + 8);    // kept columns, their vertex tuples, tau
-    b += (size_t)maxc * 8 * 4 * 2;          // partition outputs, double buffered
-    b += (size_t)(maxc / 32 + 1) * 4 * 2 + (size_t)(maxbits / 32 + 1) * 4;
-    b += (size_t)radix_scratch_words((int64_t)maxc) * 8 * 2;
+    for (const DevBuf *x : device_buffers(w))
+        if (x->hint)
+            b += grow_capacity(0, x->hint);  // each at most one 64 KiB round-up
     return b;
+}
+
+// For the length of one call, the workspace's device buffers come from a
+// caller-provided arena: its own buffers are set aside (and put back
+// afterwards), and each buffer's hint is its planned maximum for the call.
+struct ArenaScope {
+    Workspace &w;
+    std::vector<DevBuf> kept;
+    int binom_n, binom_k;
+    ArenaScope(Workspace &ws, void *base, size_t bytes, int n, int maxdim)
+        : w(ws), binom_n(ws.binom_n), binom_k(ws.binom_k)
+    {
+        for (DevBuf *b : device_buffers(w)) {
+            kept.push_back(std::move(*b));
+            b->pool = &w.pool;
+        }
+        w.pool.arena = static_cast<char *>(base);
+        w.pool.arena_size = bytes;
+        w.pool.arena_top = 0;
+        w.binom_n = w.binom_k = -1;
+        plan_limits(w, n, maxdim);
+    }
+    ~ArenaScope()
+    {
+        size_t i = 0;
+        for (DevBuf *b : device_buffers(w)) {
+            b->release();  // arena memory: forgotten, not freed
+            *b = std::move(kept[i++]);
+            b->hint = 0;
+        }
+        w.pool.arena = nullptr;
+        w.pool.arena_size = w.pool.arena_top = 0;
+        w.binom_n = binom_n;
+        w.binom_k = binom_k;
+        w.dsqp_ready = false;
+        w.cvtx_ok = false;
+    }
+};
+
+bool fault_injected(const char *stage, int n)
+{
+    const char *e = getenv("RPP_FAULT_INJECT");
+    if (!e || !*e)
+        return false;
+    const char *colon = strchr(e, ':');
+    const size_t len = colon ? (size_t)(colon - e) : strlen(e);
+    if (strlen(stage) != len || strncmp(e, stage, len) != 0)
+        return false;
+    return !colon || atoi(colon + 1) == n;
+}
+
+#define FAULT_POINT(stage)                                                         \
+    do {                                                                           \
+        if (fault_injected(stage, n)) {                                            \
+            err = std::string("fault injected at stage '") + stage + "' (RPP_FAULT_INJECT)"; \
+            return RPP_E_DEVICE;                                                   \
+        }                                                                          \
+    } while (0)
+
+#define CANCEL_POINT()                                                             \
+    do {                                                                           \
+        if (a.cancel && a.cancel->load(std::memory_order_relaxed)) {               \
+            err = "request cancelled";                                             \
+            return RPP_E_CANCELLED;                                                \
+        }                                                                          \
+    } while (0)
+
+// Largest output allocation (bytes) that the dense enumeration makes for every
+// candidate before counting them: 1 GiB, or RPP_ENUM_UPFRONT_MAX_BYTES (the
+// tests set 0 to run every input through the path that reads the kept count
+// back between the count and scatter passes).
+static size_t upfront_limit()
+{
+    const char *e = getenv("RPP_ENUM_UPFRONT_MAX_BYTES");
+    return e ? (size_t)strtoull(e, nullptr, 10) : ((size_t)1 << 30);
 }
 
 // Stable compaction of the p-simplices (dense enumeration) into ws.cdiam /
@@ -188,7 +370,7 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     // count is read once, after them; larger inputs read it between the
     // passes and size the outputs exactly.
     const size_t per = 4 + 8 + (ws.cvtx_ok ? 8 : 0);
-    const bool upfront = (ea.ncand + 1) * per <= ((size_t)1 << 30);
+    const bool upfront = (ea.ncand + 1) * per <= upfront_limit();
     if (upfront) {
         ALLOC_TRY(ws.cdiam, (size_t)(ea.ncand + 1) * 4);
         ALLOC_TRY(ws.ccidx, (size_t)(ea.ncand + 1) * 8);
@@ -459,6 +641,38 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     Workspace &ws = a.workspace ? *static_cast<Workspace *>(a.workspace)
                                 : workspace_for_current_device();
     std::lock_guard<std::mutex> lk(ws.mu);
+    // A caller-provided arena replaces the workspace's buffers for this
+    // call; a device limit caps the workspace's own buffers (an idle cache
+    // holding more is emptied first).  Either way the stream is drained
+    // before the call returns, on success or error, so no kernel still uses
+    // the memory afterwards.
+    struct Drain {
+        hipStream_t s;
+        ~Drain() { (void)hipStreamSynchronize(s); }
+    };
+    struct LimitScope {
+        Workspace &w;
+        size_t saved;
+        LimitScope(Workspace &ws_, size_t lim) : w(ws_), saved(ws_.pool.limit)
+        {
+            if (lim == SIZE_MAX)
+                return;
+            if (w.pool.held > lim) {
+                for (DevBuf *b : device_buffers(w))
+                    b->release();
+                w.binom_n = w.binom_k = -1;
+            }
+            w.pool.limit = lim;
+        }
+        ~LimitScope() { w.pool.limit = saved; }
+    };
+    LimitScope limit_scope(ws, a.arena ? SIZE_MAX : a.device_limit);
+    std::unique_ptr<ArenaScope> arena;
+    if (a.arena)
+        arena.reset(new ArenaScope(ws, a.arena, a.arena_bytes, n, maxdim));
+    Drain drain{s};
+    ws.pool.exhausted = false;
+    FAULT_POINT("stage");
 
     const uint64_t E = (uint64_t)n * (n - 1) / 2;
     ALLOC_TRY(ws.dsq, (size_t)n * n * 4);
@@ -516,6 +730,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     }
 
     // ---------------- a2: H0 ---------------------------------------------
+    FAULT_POINT("h0");
+    CANCEL_POINT();
     int64_t nedges = 0;
     int64_t mst_edges = 0;  // spanning-forest edges: the p = 1 clearing set
     const uint64_t *h0_keys = nullptr, *h0_cidx = nullptr;  // edges <= thr, diameter desc
@@ -778,6 +994,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         int64_t ncols = 0, ncand = 0;
         uint64_t nthr = 0, nclr = 0;
         int rc;
+        FAULT_POINT("enumerate");
+        CANCEL_POINT();
         if (!sparse || p == 1) {
             const uint64_t nc = binom_sat(n, p + 1);
             EnumArgs ea{a.dcond_dev, n, p, thr, ws.binom.as<uint64_t>(), clear_bits, nc};
@@ -808,6 +1026,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         }
         const bool sort_first = (a.flags & RPP_SORT_FIRST) != 0;
         GpuTimer t_pre(s);
+        FAULT_POINT("apparent");
         rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
                                     a.count_scans ? &scanned : nullptr, sparse ? words : 0,
                                     sort_first ? &t_pre : nullptr);
@@ -935,6 +1154,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
 
+        FAULT_POINT("host");
+        CANCEL_POINT();
         // a7: host residual reduction.  The speculative phase runs now; the
         // exact phase needs the previous dimension's host pivots (its
         // clearing set) and runs on a host thread while the next dimension's

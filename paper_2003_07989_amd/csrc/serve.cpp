@@ -4,17 +4,31 @@
 // device workspace, so the GPU stages of different requests overlap on the
 // device and their filtrations and clearing state stay resident in the
 // slot's HBM buffers until they finish.  A request is admitted as soon as a
-// slot is free and its footprint bound (rpp_workspace_bytes) fits the HBM
-// budget next to the requests in flight -- requests that arrive while
-// others run join immediately, without waiting for a batch to drain.  The
-// queue is scanned in arrival order and the first request that fits is
-// admitted.  Per request the server records the time spent queued and the
-// latency from submission to completion.
+// slot is free and its footprint fits the HBM budget -- requests that
+// arrive while others run join immediately, without waiting for a batch to
+// drain.  The queue is scanned in arrival order and the first request that
+// fits is admitted.
+//
+// Memory accounting.  A running slot holds a reservation: the device bytes
+// its workspace and input buffer may reach during the request, enforced by
+// the workspace's own limit.  An idle slot holds what its buffers retain from
+// earlier requests (grow-only buffers are what lets a warm server allocate
+// nothing).  A request fits when the reservations of the running slots, the
+// retained bytes of the idle ones and its own reservation stay within the
+// budget.  Its reservation is its footprint bound (rpp_workspace_bytes +
+// input) on top of what the slot already retains, or, if that does not fit,
+// the bound alone once the slot's buffers are freed; if even that does not
+// fit, the buffers of the other idle slots are freed too.  So the device
+// memory held by the slots never passes the budget, except for a request
+// whose bound alone exceeds it, which runs by itself, without a limit, when
+// nothing else is in flight.  Per request the server records the time spent
+// queued and the latency from submission to completion.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -51,6 +65,7 @@ struct Request {
     std::string err;
     rpp_result *result = nullptr;
     int slot = -1;
+    std::atomic<bool> cancel{false};
 };
 
 }  // namespace
@@ -71,7 +86,57 @@ struct rpp_server {
     std::vector<hipStream_t> streams;
     std::vector<float *> dev_in;
     std::vector<size_t> dev_in_cap;
+    std::vector<size_t> reserve;  // running slot: its reservation; idle: 0
     size_t peak_allocated = 0;
+
+    // Device bytes slot k retains (its workspace buffers and input buffer).
+    size_t retained(int k) { return rpp::workspace_allocated(workspaces[k]) + dev_in_cap[k]; }
+
+    // Bytes counted against the budget by every slot except k.
+    size_t committed_except(int k)
+    {
+        size_t t = 0;
+        for (int j = 0; j < (int)workspaces.size(); ++j)
+            if (j != k)
+                t += reserve[j] ? reserve[j] : retained(j);
+        return t;
+    }
+
+    void free_slot(int j)
+    {
+        rpp::workspace_trim(workspaces[j]);
+        if (dev_in[j]) {
+            (void)hipStreamSynchronize(streams[j]);
+            (void)hipFree(dev_in[j]);
+        }
+        dev_in[j] = nullptr;
+        dev_in_cap[j] = 0;
+    }
+
+    // Admission of r on idle slot k: 0 = does not fit now; otherwise the
+    // reservation (the slot's buffers trimmed first when `trim` comes back
+    // true, the other idle slots' when `trim_others` does).
+    size_t plan(const Request &r, int k, bool *trim, bool *trim_others)
+    {
+        *trim = *trim_others = false;
+        const size_t in_bytes = rpp::grow_capacity(0, r.dist.size() * sizeof(float));
+        const size_t others = committed_except(k);
+        const size_t keep = retained(k) + r.need;
+        if (others + keep <= budget)
+            return keep;
+        const size_t fresh = in_bytes + (r.need - r.dist.size() * sizeof(float));
+        *trim = true;
+        if (others + fresh <= budget)
+            return fresh;
+        size_t busy = 0;
+        for (int j = 0; j < (int)workspaces.size(); ++j)
+            if (j != k && reserve[j])
+                busy += reserve[j];
+        *trim_others = true;
+        if (busy + fresh <= budget || running == 0)
+            return fresh;
+        return 0;
+    }
 
     void slot_loop(int k)
     {
@@ -80,15 +145,37 @@ struct rpp_server {
             std::shared_ptr<Request> r;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                work_cv.wait(lk, [&] { return stop || admissible() != queue.end(); });
-                if (stop && queue.empty())
-                    return;
-                auto it = admissible();
-                if (it == queue.end())
+                bool trim = false, trim_others = false;
+                size_t res = 0;
+                auto pick = [&]() {
+                    for (auto it = queue.begin(); it != queue.end(); ++it)
+                        if ((res = plan(**it, k, &trim, &trim_others)) != 0)
+                            return it;
+                    return queue.end();
+                };
+                auto it = queue.end();
+                work_cv.wait(lk, [&] { return stop || (it = pick()) != queue.end(); });
+                if (it == queue.end()) {
+                    if (stop && queue.empty())
+                        return;
                     continue;
+                }
                 r = *it;
                 queue.erase(it);
-                in_flight += r->need;
+                if (trim_others)
+                    for (int j = 0; j < (int)workspaces.size(); ++j)
+                        if (j != k && !reserve[j])
+                            free_slot(j);
+                if (trim)
+                    free_slot(k);
+                const bool oversize = r->need > budget;
+                reserve[k] = res;
+                // the workspace's share: the reservation less the input buffer
+                const size_t in_bytes =
+                    std::max(dev_in_cap[k], rpp::grow_capacity(0, r->dist.size() * sizeof(float)));
+                rpp::workspace_set_limit(workspaces[k],
+                                         oversize ? SIZE_MAX : res - std::min(res, in_bytes));
+                in_flight += res;
                 peak_in_flight = std::max(peak_in_flight, in_flight);
                 ++running;
                 peak_running = std::max(peak_running, running);
@@ -99,57 +186,49 @@ struct rpp_server {
             execute(k, *r);
             {
                 std::lock_guard<std::mutex> lk(mu);
-                in_flight -= r->need;
+                peak_allocated = std::max(peak_allocated, allocated_locked());
+                in_flight -= reserve[k];
+                reserve[k] = 0;
                 --running;
                 ++completed;
                 r->finished = Clock::now();
                 r->done = true;
-                peak_allocated = std::max(peak_allocated, allocated_locked());
             }
             done_cv.notify_all();
             work_cv.notify_all();
         }
     }
 
-    // First queued request (arrival order) whose bound fits the budget.
-    std::deque<std::shared_ptr<Request>>::iterator admissible()
-    {
-        for (auto it = queue.begin(); it != queue.end(); ++it)
-            if (in_flight + (*it)->need <= budget || in_flight == 0)
-                return it;
-        return queue.end();
-    }
-
     size_t allocated_locked()
     {
         size_t t = 0;
         for (size_t k = 0; k < workspaces.size(); ++k)
-            t += rpp::workspace_allocated(workspaces[k]) + dev_in_cap[k];
+            t += retained((int)k);
         return t;
     }
 
     void execute(int k, Request &r)
     {
+        if (r.cancel.load()) {
+            r.rc = RPP_E_CANCELLED;
+            r.err = "request cancelled";
+            return;
+        }
         const size_t m = r.dist.size();
         hipStream_t s = streams[k];
         if (m * sizeof(float) > dev_in_cap[k]) {  // capacity is in bytes
-            const size_t old = dev_in_cap[k];
             if (dev_in[k]) {
                 (void)hipStreamSynchronize(s);
                 (void)hipFree(dev_in[k]);
             }
             dev_in[k] = nullptr;
             dev_in_cap[k] = 0;
-            size_t b = rpp::grow_capacity(old, m * sizeof(float));
+            const size_t b = rpp::grow_capacity(0, m * sizeof(float));
             if (hipMalloc(&dev_in[k], b) != hipSuccess) {
-                b = rpp::grow_capacity(0, m * sizeof(float));
                 dev_in[k] = nullptr;
-                if (hipMalloc(&dev_in[k], b) != hipSuccess) {
-                    dev_in[k] = nullptr;
-                    r.rc = RPP_E_NOMEM;
-                    r.err = "hipMalloc of the request input failed";
-                    return;
-                }
+                r.rc = RPP_E_NOMEM;
+                r.err = "hipMalloc of the request input failed";
+                return;
             }
             dev_in_cap[k] = b;
         }
@@ -167,6 +246,7 @@ struct rpp_server {
         a.flags = r.flags;
         a.stream = s;
         a.workspace = workspaces[k];
+        a.cancel = &r.cancel;
         rpp::RunOut ro;
         r.rc = rpp::run_pipeline(a, ro, r.err);
         if (r.rc == RPP_OK)
@@ -204,6 +284,7 @@ int rpp_server_create(int32_t slots, size_t hbm_budget_bytes, rpp_server **out)
         sv->workspaces.push_back(rpp::workspace_new());
         sv->dev_in.push_back(nullptr);
         sv->dev_in_cap.push_back(0);
+        sv->reserve.push_back(0);
     }
     for (int k = 0; k < slots; ++k)
         sv->slots.emplace_back([sv, k] { sv->slot_loop(k); });
@@ -271,6 +352,33 @@ int rpp_server_wait(rpp_server *sv, uint64_t ticket, rpp_result **out, double *l
     }
     *out = r->result;
     r->result = nullptr;
+    return RPP_OK;
+}
+
+int rpp_server_cancel(rpp_server *sv, uint64_t ticket)
+{
+    if (!sv)
+        return RPP_E_INVAL;
+    std::shared_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->tickets.find(ticket);
+        if (it == sv->tickets.end() || it->second->done)
+            return RPP_E_INVAL;
+        r = it->second;
+        r->cancel.store(true);
+        auto q = std::find(sv->queue.begin(), sv->queue.end(), r);
+        if (q != sv->queue.end()) {
+            // never admitted: finished here
+            sv->queue.erase(q);
+            r->rc = RPP_E_CANCELLED;
+            r->err = "request cancelled";
+            r->started = r->finished = Clock::now();
+            r->done = true;
+        }
+    }
+    sv->done_cv.notify_all();
+    sv->work_cv.notify_all();
     return RPP_OK;
 }
 

@@ -37,8 +37,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_strings():
     assert "gfx950" in rpp.version()
-    for code in (0, -1, -2, -3, -4, -5):
-        assert rpp.strerror(code)
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert rpp.strerror(code) != "unknown error"
     assert rpp.strerror(-99) == "unknown error"
 
 
@@ -119,3 +119,49 @@ def test_flag_constants_match_the_header():
             flags.append(v)
     assert all(f and (f & (f - 1)) == 0 for f in flags)
     assert len(set(flags)) == len(flags)
+
+
+def test_device_budget_refuses_before_device_work(monkeypatch):
+    """RPP_DEVICE_BUDGET_BYTES below what staging and H0 need for n points:
+    RPP_E_NOMEM before any HIP call (this machine has no GPU, so a call that
+    reached the device would fail with a HIP message instead)."""
+    d = np.ones(20 * 19 // 2, np.float32)
+    monkeypatch.setenv("RPP_DEVICE_BUDGET_BYTES", "1000")
+    assert _call(d, 20, 1, math.inf) == -4
+    assert b"RPP_DEVICE_BUDGET_BYTES" in rpp.load().rpp_last_error()
+    # a budget above the floor passes the up-front check (and then meets
+    # the missing device, which is not a budget failure)
+    monkeypatch.setenv("RPP_DEVICE_BUDGET_BYTES", str(1 << 40))
+    _call(d, 20, 1, math.inf)
+    assert b"RPP_DEVICE_BUDGET_BYTES" not in rpp.load().rpp_last_error()
+
+
+def _device_call(n, maxdim, ws_ptr, ws_bytes):
+    lib = rpp.load()
+    out = ctypes.POINTER(B._Result)()
+    # the distance pointer is never read: every case fails before device work
+    rc = lib.rpp_barcodes_device(ctypes.c_void_p(0x1000), n, maxdim, ctypes.c_float(math.inf),
+                                 ws_ptr, ws_bytes, None, 0, ctypes.byref(out))
+    assert not bool(out)
+    return rc
+
+
+def test_caller_workspace_checks_before_device_work():
+    """A workspace below the floor is RPP_E_NOMEM up front; a size without a
+    pointer is RPP_E_INVAL.  (The pointer is never dereferenced.)"""
+    assert _device_call(50, 2, ctypes.c_void_p(0x2000), 4096) == -4
+    assert b"caller workspace" in rpp.load().rpp_last_error()
+    assert _device_call(50, 2, None, 4096) == -1
+
+
+def test_workspace_bound_covers_every_buffer_at_its_maximum():
+    """The bound is at least the sum of the buffers every dense call on n
+    points holds at its combinatorial maximum: the square matrix, the edge
+    keys (four u64 arrays) and, for the top dimension's C(n, maxdim+1)
+    columns, diameters, indices, vertex tuples, tau and the eight u64
+    partition arrays."""
+    for n, maxdim in ((50, 1), (100, 2), (400, 2), (60, 3), (7, 4)):
+        E = math.comb(n, 2)
+        cmax = max(math.comb(n, k) for k in range(2, maxdim + 2))
+        need = n * n * 4 + 4 * 8 * E + cmax * (4 + 8 + 8 + 8 + 8 * 8)
+        assert rpp.workspace_bytes(n, maxdim) >= need, (n, maxdim)
