@@ -104,6 +104,9 @@ enum {
  * on column order, so the results are identical).  Kept for comparison; the
  * sort then runs over every column (stats.ms_sort includes it). */
 #define RPP_SORT_FIRST 0x200u
+/* rpp_barcodes_batch: group requests by their exact n instead of by shape
+ * bucket (n rounded up to a multiple of 64).  Kept for comparison. */
+#define RPP_BATCH_EXACT_SHAPES 0x400u
 
 /* Per-dimension counters (paper, tables of apparent pairs and of the
  * clearing / threshold accounting).  For p >= 1:
@@ -225,11 +228,21 @@ typedef struct {
     float threshold;
 } rpp_request;
 
-/* Barcodes of count clouds at once.  Requests with equal (n, maxdim) form a
- * shape group: each stage runs as one launch over the whole group, the GPU
- * stages of a dimension are captured once per shape as a hipGraph and
- * replayed, and the host reductions of the clouds run in parallel.  Results
- * are identical to rpp_barcodes_device on each cloud with the dense path.
+/* Barcodes of count clouds at once.  Requests with the same maxdim whose n
+ * round up to the same multiple of 64 form a shape bucket: each cloud is
+ * padded to that size with points at infinite distance (no simplex within
+ * the threshold contains one, so every cloud's bars and pairs are its own;
+ * the kernels read each cloud's own size from device memory), each stage
+ * runs as one launch over the whole bucket, the GPU stages of a dimension
+ * are captured once per bucket as a hipGraph and replayed for any mix of
+ * sizes in it, and the host reductions of the clouds run in parallel.
+ * Padding needs a finite threshold, so a request with threshold +INFINITY
+ * under RPP_NO_ENCLOSING_RADIUS groups by its exact n, as every request
+ * does under RPP_BATCH_EXACT_SHAPES.  A group of one cloud, or one whose
+ * clouds have more than 2^22 candidate simplices in the top dimension (the
+ * batch sizes its buffers by that count per cloud), runs cloud by cloud
+ * through the single-cloud pipeline of rpp_barcodes_device.  Bars and
+ * critical edges are identical to rpp_barcodes_device on each cloud.
  * outs: count pointers, each set to a library-allocated result (free each
  * with rpp_result_free); on error every out is NULL.  flags: RPP_* (pair
  * lists are not supported here). */

@@ -30,6 +30,7 @@ RPP_BATCH_NO_GRAPH = 0x40
 RPP_BATCH_AUTOTUNE = 0x80
 RPP_OBLIVIOUS_REDUCTION = 0x100
 RPP_SORT_FIRST = 0x200
+RPP_BATCH_EXACT_SHAPES = 0x400
 NO_EDGE = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERRORS = {0: "RPP_OK", -1: "RPP_E_INVAL", -2: "RPP_E_DATA", -3: "RPP_E_RANGE",
@@ -343,22 +344,25 @@ def pdist_device(points: torch.Tensor, out: torch.Tensor = None, stream=None) ->
 
 
 def backward_points(points: torch.Tensor, birth_edge, death_edge, grad_birth, grad_death,
-                    stream=None) -> torch.Tensor:
+                    stream=None, out=None) -> torch.Tensor:
     """rpp_backward: gradient w.r.t. (n, d) float32 CUDA coordinates of a
-    loss whose gradient w.r.t. each bar's (birth, death) is given."""
+    loss whose gradient w.r.t. each bar's (birth, death) is given; out: a
+    preallocated (n, d) float32 result."""
     pts = points.contiguous()
     n, d = pts.shape
     be = np.ascontiguousarray(birth_edge, dtype=np.uint64)
     de = np.ascontiguousarray(death_edge, dtype=np.uint64)
     gb = np.ascontiguousarray(grad_birth, dtype=np.float32)
     gd = np.ascontiguousarray(grad_death, dtype=np.float32)
-    out = torch.empty_like(pts)
+    if out is None:
+        out = torch.empty_like(pts)
     U64, F32 = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_float)
-    _check(load().rpp_backward(ctypes.c_void_p(pts.data_ptr()), int(n), int(d), int(be.size),
-                               be.ctypes.data_as(U64), de.ctypes.data_as(U64),
-                               gb.ctypes.data_as(F32), gd.ctypes.data_as(F32),
-                               ctypes.c_void_p(out.data_ptr()),
-                               ctypes.c_void_p(_stream_handle(stream))))
+    lib = load()
+    fn = lib.rpp_backward
+    _check(fn(ctypes.c_void_p(pts.data_ptr()), int(n), int(d), int(be.size),
+              be.ctypes.data_as(U64), de.ctypes.data_as(U64),
+              gb.ctypes.data_as(F32), gd.ctypes.data_as(F32),
+              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_handle(stream))))
     return out
 
 

@@ -155,6 +155,7 @@ struct BatchWs {
     std::mutex mu;
     int n = 0, maxdim = 0, nb = 0;
     DevBuf dcond, dsq, rowmax, bad, radius, thr_req, thr;
+    DevBuf nv;                             // each cloud's own number of points (bucket)
     DevBuf binom;
     DevBuf stats;                          // 2 u64 per cloud per stage
     DevBuf tcount, toff, scan;             // compaction
@@ -281,6 +282,7 @@ static int batch_alloc(BatchWs &W, std::string &err)
         nwords = std::max<int64_t>(nwords, (int64_t)binom_sat(n, p + 2) / 32 + 1);
     const size_t B = (size_t)nb;
     ALLOC_TRY(W.dcond, B * E * 4 + 4);
+    ALLOC_TRY(W.nv, B * 4);
     ALLOC_TRY(W.dsq, B * n * n * 4);
     ALLOC_TRY(W.rowmax, B * n * 4);
     ALLOC_TRY(W.bad, B * 4);
@@ -338,11 +340,13 @@ static void enqueue_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags
     if (p == 1) {
         hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(nb)), dim3(256), 0, s,
                            reinterpret_cast<uint64_t *>(W.bad.p), (int64_t)(nb + 1) / 2, 0ull);
+        // bucket padding: the edges of each cloud's padding vertices at +inf
+        launch_pad_dcond_b(W.dcond.as<float>(), n, nb, W.nv.as<int32_t>(), s);
         launch_stage_b(W.dcond.as<float>(), n, nb, W.dsq.as<float>(), W.rowmax.as<float>(),
-                       W.bad.as<uint32_t>(), s);
+                       W.bad.as<uint32_t>(), s, W.nv.as<int32_t>());
         launch_radius_b(W.rowmax.as<float>(), n, nb, W.thr_req.as<float>(),
                         (flags & RPP_NO_ENCLOSING_RADIUS) ? 1 : 0, W.radius.as<float>(),
-                        W.thr.as<float>(), s);
+                        W.thr.as<float>(), s, W.nv.as<int32_t>());
         // H0: edges <= thr per cloud, sorted, Kruskal (one workgroup each)
         unsigned long long *st0 = W.stats.as<unsigned long long>();
         hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(2 * nb)), dim3(256), 0, s,
@@ -357,7 +361,7 @@ static void enqueue_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags
                                 W.scan.as<uint64_t>(), s);
         launch_enum_scatter(ea, W.toff.as<uint64_t>(), W.cdiam.as<float>(), W.ccidx.as<uint64_t>(),
                             s);
-        Batch be{W.toff.as<uint64_t>() + t1, t1 + 1, E};
+        Batch be{W.toff.as<uint64_t>() + t1, t1 + 1, E, W.nv.as<int32_t>()};
         launch_desc_keys(W.cdiam.as<float>(), E, W.ekey.as<uint64_t>(), s, be, nb);
         hipLaunchKernelGGL(k_copy_u64, dim3(blocks_for((int64_t)nb * E)), dim3(256), 0, s,
                            W.ccidx.as<uint64_t>(), W.eval.as<uint64_t>(), (int64_t)nb * E);
@@ -386,7 +390,7 @@ static void enqueue_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags
     launch_exclusive_scan_b(W.tcount.as<uint32_t>(), D.tiles, nb, W.toff.as<uint64_t>(),
                             W.scan.as<uint64_t>(), s);
     launch_enum_scatter(ea, W.toff.as<uint64_t>(), W.cdiam.as<float>(), W.ccidx.as<uint64_t>(), s);
-    Batch bk{W.toff.as<uint64_t>() + D.tiles, D.tiles + 1, D.cap};  // kept per cloud
+    Batch bk{W.toff.as<uint64_t>() + D.tiles, D.tiles + 1, D.cap, W.nv.as<int32_t>()};  // kept per cloud
     launch_apparent_b(W.cdiam.as<float>(), W.ccidx.as<uint64_t>(), D.cap, W.dsq.as<float>(), n, p,
                       binom, group, W.tau.as<uint64_t>(), bk, nb, s);
     launch_partition_count(W.tau.as<uint64_t>(), D.cap, W.tcount2.as<uint32_t>(), s, bk, nb);
@@ -491,7 +495,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             RunArgs r;
             hipStream_t s = a.stream;
             r.dcond_dev = a.dist_dev[c];
-            r.n = n;
+            r.n = a.nv ? a.nv[c] : n;
             r.maxdim = maxdim;
             r.threshold = a.threshold[c];
             r.flags = a.flags | RPP_FORCE_DENSE;
@@ -518,11 +522,20 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
     HIP_TRY(hipEventRecord(W.ready, a.stream));
     HIP_TRY(hipStreamWaitEvent(s, W.ready, 0));
     const int64_t E = (int64_t)n * (n - 1) / 2;
-    // inputs: pack the clouds; requested thresholds
+    // each cloud's own size (bucket padding beyond it)
+    std::vector<int32_t> nvh((size_t)nb);
     for (int c = 0; c < nb; ++c)
-        HIP_TRY(hipMemcpyAsync(W.dcond.as<float>() + (size_t)c * E, a.dist_dev[c], (size_t)E * 4,
-                               hipMemcpyDeviceToDevice, s));
+        nvh[c] = a.nv ? a.nv[c] : n;
+    // inputs: pack the clouds (a cloud's condensed matrix is a prefix of its
+    // padded one); requested thresholds; sizes
+    for (int c = 0; c < nb; ++c) {
+        const int64_t Ec = (int64_t)nvh[c] * (nvh[c] - 1) / 2;
+        if (Ec > 0)
+            HIP_TRY(hipMemcpyAsync(W.dcond.as<float>() + (size_t)c * E, a.dist_dev[c],
+                                   (size_t)Ec * 4, hipMemcpyDeviceToDevice, s));
+    }
     HIP_TRY(hipMemcpyAsync(W.thr_req.p, a.threshold, (size_t)nb * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.nv.p, nvh.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s));
 
     // host copies for the reductions (pinned, kept with the batch workspace)
     if (maxdim >= 1 && !W.h_dsq.ensure((size_t)nb * n * n * 4)) {
@@ -601,17 +614,18 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
                                      dedges.begin() + (size_t)c * n + nd);
                 d0.birth.assign(nd, 0.0f);
                 d0.birth_edge.assign(nd, UINT64_MAX);
-                for (int i = 0; i < n - merges; ++i) {
+                const int nc = nvh[c];  // padding vertices are components of their own
+                for (int i = 0; i < nc - merges; ++i) {
                     d0.birth.push_back(0.0f);
                     d0.death.push_back(INFINITY);
                     d0.birth_edge.push_back(UINT64_MAX);
                     d0.death_edge.push_back(UINT64_MAX);
                 }
-                d0.st.n_candidates = n;
-                d0.st.n_simplices = n;
-                d0.st.n_kept = n;
+                d0.st.n_candidates = nc;
+                d0.st.n_simplices = nc;
+                d0.st.n_kept = nc;
                 d0.st.n_host_pairs = merges;
-                d0.st.n_essential = n - merges;
+                d0.st.n_essential = nc - merges;
                 d0.st.n_bars = (int64_t)d0.birth.size();
             }
         }
@@ -686,10 +700,12 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             }
             const int64_t kept = (int64_t)toff[(size_t)c * (D.tiles + 1) + D.tiles];
             const int64_t napp = (int64_t)toff2[(size_t)c * (D.tiles + 1) + D.tiles];
-            Dd.st.n_candidates = D.cap;
-            Dd.st.n_thresholded = (int64_t)st[2 * c];
+            // candidates with a padding vertex were all thresholded (+inf)
+            const int64_t own = (int64_t)binom_sat(nvh[c], p + 1);
+            Dd.st.n_candidates = own;
+            Dd.st.n_thresholded = (int64_t)st[2 * c] - (D.cap - own);
             Dd.st.n_cleared = (int64_t)st[2 * c + 1];
-            Dd.st.n_simplices = D.cap - (int64_t)st[2 * c];
+            Dd.st.n_simplices = own - Dd.st.n_thresholded;
             Dd.st.n_kept = kept;
             Dd.st.apparent_group = group;
             Dd.st.n_apparent = napp;

@@ -19,11 +19,21 @@
 
 namespace {
 
-thread_local std::string g_last_error;
+// The last error's text, per thread, in a fixed buffer: setting it never
+// allocates (the allocation-free entry point reports through it too).
+thread_local char g_last_error[512];
+
+void set_error_text(const char *msg, size_t len)
+{
+    if (len >= sizeof(g_last_error))
+        len = sizeof(g_last_error) - 1;
+    memcpy(g_last_error, msg, len);
+    g_last_error[len] = 0;
+}
 
 int fail(int code, const std::string &msg)
 {
-    g_last_error = msg;
+    set_error_text(msg.data(), msg.size());
     return code;
 }
 
@@ -167,7 +177,11 @@ int build_result_public(const RunOut &ro, int n, int maxdim, uint32_t flags, rpp
 }
 void set_last_error(const std::string &msg)
 {
-    g_last_error = msg;
+    set_error_text(msg.data(), msg.size());
+}
+void set_last_error_text(const char *msg)
+{
+    set_error_text(msg, strlen(msg));
 }
 }  // namespace rpp
 
@@ -244,10 +258,21 @@ int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream,
             return fail(RPP_E_INVAL, "dist_dev is NULL");
     }
     try {
-        // shape groups, in first-appearance order
+        // Shape groups, in first-appearance order.  A group is a shape
+        // bucket: n rounded up to a multiple of 64 (each cloud padded with
+        // vertices at infinite distance), with one maxdim.  Padding needs a
+        // finite threshold: a request with threshold +inf and
+        // RPP_NO_ENCLOSING_RADIUS, and any request with RPP_BATCH_EXACT_SHAPES,
+        // keeps its exact n.
+        const bool radius = !(flags & RPP_NO_ENCLOSING_RADIUS);
+        auto bucket_of = [&](const rpp_request &r) {
+            const bool pad = !(flags & RPP_BATCH_EXACT_SHAPES) && r.n >= 2 && r.maxdim >= 1 &&
+                             (radius || !isinf(r.threshold));
+            return pad ? (r.n + 63) / 64 * 64 : -r.n;  // negative: exact
+        };
         std::vector<std::pair<std::pair<int, int>, std::vector<int>>> groups;
         for (int32_t i = 0; i < count; ++i) {
-            std::pair<int, int> key{reqs[i].n, reqs[i].maxdim};
+            std::pair<int, int> key{bucket_of(reqs[i]), reqs[i].maxdim};
             auto it = std::find_if(groups.begin(), groups.end(),
                                    [&](const auto &g) { return g.first == key; });
             if (it == groups.end())
@@ -257,15 +282,41 @@ int rpp_barcodes_batch(int32_t count, const rpp_request *reqs, void *hip_stream,
         }
         std::vector<rpp::RunOut> all(count);
         for (auto &g : groups) {
+            // A group of one cloud, or of clouds whose top dimension has more
+            // than 2^22 candidate columns each (the batch sizes its buffers
+            // by that capacity per cloud, e.g. 17 GB at n = 1024, maxdim 2),
+            // runs cloud by cloud through the single-cloud pipeline.
+            const int nb_pts = std::abs(g.first.first);
+            if (g.second.size() == 1 || nb_pts < 2 || g.first.second < 1 ||
+                rpp::binom_sat(nb_pts, g.first.second + 1) > (1ull << 22)) {
+                for (int i : g.second) {
+                    rpp::RunArgs r;
+                    r.dcond_dev = reqs[i].dist_dev;
+                    r.n = reqs[i].n;
+                    r.maxdim = reqs[i].maxdim;
+                    r.threshold = reqs[i].threshold;
+                    r.flags = flags & ~(RPP_BATCH_NO_GRAPH | RPP_BATCH_AUTOTUNE |
+                                        RPP_BATCH_EXACT_SHAPES);
+                    r.stream = static_cast<hipStream_t>(hip_stream);
+                    std::string err;
+                    int rc = rpp::run_pipeline(r, all[i], err);
+                    if (rc)
+                        return fail(rc, err);
+                }
+                continue;
+            }
             std::vector<const float *> ptrs;
             std::vector<float> thr;
+            std::vector<int> nv;
             for (int i : g.second) {
                 ptrs.push_back(reqs[i].dist_dev);
                 thr.push_back(reqs[i].threshold);
+                nv.push_back(reqs[i].n);
             }
             rpp::BatchArgs a;
             a.count = (int)g.second.size();
-            a.n = g.first.first;
+            a.n = std::abs(g.first.first);
+            a.nv = nv.data();
             a.maxdim = g.first.second;
             a.dist_dev = ptrs.data();
             a.threshold = thr.data();
@@ -473,7 +524,7 @@ const char *rpp_strerror(int code)
 
 const char *rpp_last_error(void)
 {
-    return g_last_error.c_str();
+    return g_last_error;
 }
 
 const char *rpp_version(void)

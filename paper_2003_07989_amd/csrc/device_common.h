@@ -96,6 +96,31 @@ __device__ __forceinline__ void decode_edge(uint64_t c, int &a, int &b)
     b = (int)(c - (uint64_t)x * (x - 1) / 2);
 }
 
+// One gradient term of the backward pass: an edge e of length |x_a - x_b|
+// with dL/dlength = gval adds gval * (x_u[k] - x_o[k]) / |x_u - x_o| to
+// coordinate k of its endpoint u (o the other endpoint), accumulated in FP64.
+// Edges not touching u, the "no edge" index and zero-length edges add
+// nothing.
+__device__ __forceinline__ void edge_grad_add(double &acc, const float *__restrict__ pts, int d,
+                                              int u, int k, uint64_t e, float gval)
+{
+    if (e == NONE)
+        return;
+    int a, b;
+    decode_edge(e, a, b);
+    if (a != u && b != u)
+        return;
+    const int o = (a == u) ? b : a;
+    double len2 = 0.0;
+    for (int q = 0; q < d; ++q) {
+        const double df = (double)pts[(int64_t)u * d + q] - (double)pts[(int64_t)o * d + q];
+        len2 += df * df;
+    }
+    if (len2 > 0.0)
+        acc += (double)gval * ((double)pts[(int64_t)u * d + k] - (double)pts[(int64_t)o * d + k]) /
+               sqrt(len2);
+}
+
 // cidx of sigma + {w} where sigma = v[0] > ... > v[P] and w is not in sigma:
 // with j = #{i : v_i < w}, cidx = sum_{v_i < w} C(v_i, rank+1) + C(w, j+1)
 // + sum_{v_i > w} C(v_i, rank+2) (ranks counted from the bottom).

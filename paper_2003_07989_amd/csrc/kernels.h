@@ -16,15 +16,23 @@ namespace rpp {
 // c * stride elements in, and its element count is count[c * cstride] when
 // count is set (device memory), else the launch's own count.  The default
 // describes a single cloud.
+// A shape bucket packs clouds of different sizes at one padded size n:
+// nv (device memory, or null) holds each cloud's own number of points; its
+// vertices nv[c] .. n-1 are padding, at infinite distance from everything.
 struct Batch {
     const uint64_t *count = nullptr;
     int64_t cstride = 0;
     int64_t stride = 0;
+    const int32_t *nv = nullptr;
 };
 #ifdef __HIPCC__
 __device__ __forceinline__ int64_t batch_count(const Batch &b, int64_t c, int64_t fallback)
 {
     return b.count ? (int64_t)b.count[c * b.cstride] : fallback;
+}
+__device__ __forceinline__ int batch_nv(const Batch &b, int64_t c, int n)
+{
+    return b.nv ? b.nv[c] : n;
 }
 #endif
 
@@ -37,10 +45,17 @@ void launch_stage(const float *dcond, int n, float *dsq, float *rowmax, uint32_t
 void launch_min(const float *x, int n, float *out, hipStream_t s);
 // Batched staging of nb clouds of n points (inputs and outputs packed cloud
 // after cloud), and per-cloud radius / threshold used.
+// nv (device, or null): each cloud's own number of points in a shape bucket
+// of padded size n; entries of padding vertices must already hold +inf in
+// dcond (launch_pad_dcond_b) and are neither validated nor counted in the
+// row maxima or the radius.
 void launch_stage_b(const float *dcond, int n, int nb, float *dsq, float *rowmax, uint32_t *bad,
-                    hipStream_t s);
+                    hipStream_t s, const int32_t *nv = nullptr);
 void launch_radius_b(const float *rowmax, int n, int nb, const float *req, int no_radius,
-                     float *radius, float *thr, hipStream_t s);
+                     float *radius, float *thr, hipStream_t s, const int32_t *nv = nullptr);
+// Per cloud of a bucket: condensed entries nv(nv-1)/2 .. n(n-1)/2 - 1 (the
+// padding vertices' edges) set to +inf.
+void launch_pad_dcond_b(float *dcond, int n, int nb, const int32_t *nv, hipStream_t s);
 
 // ---- device-wide helpers --------------------------------------------------
 void launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
@@ -157,44 +172,66 @@ void launch_lows(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
 void launch_nbr_bits(const float *dsq, int n, float thr, uint64_t *bits, int words,
                      hipStream_t s);
 
+// Packed neighbour rows (sparse path).  nbd lists every vertex's neighbours'
+// distances (d <= thr, the vertex itself excluded), row after row, the
+// neighbours of a row in ascending order.  nbw[v*words + k] is a 16-byte
+// record (x, y: bitset word k of v's row, low and high halves; z: position
+// in nbd of v's first neighbour in that word; w: 0), read with one load, so
+// a neighbour u = 64k + b of v has d(v, u) = nbd[z + popcount(word &
+// (2^b - 1))].  The rows hold the 2E distances of the E edges under the
+// threshold: a few MB that stay in L2 where the square matrix (n^2 floats)
+// does not.
+void launch_nbr_degree(const uint64_t *bits, int n, int words, uint32_t *deg, hipStream_t s);
+// row_off: exclusive scan of the degrees (n + 1 entries); cap: entries nbd
+// holds (2E; writes past it are dropped)
+void launch_nbr_pack(const float *dsq, const uint64_t *bits, int n, int words,
+                     const uint64_t *row_off, uint4 *nbw, float *nbd, uint64_t cap,
+                     hipStream_t s);
+
 // p-simplices <= thr as one-vertex extensions of the (p-1)-simplices <= thr
 // (paper, enumeration of cofacets for sparse 1-skeletons): prefix
 // (v_p > ... > v_1) extends by every common neighbour v_0 < v_1.  Listing
 // prefixes in cidx order and v_0 upward yields the p-simplices in cidx order.
+// Distances come from the packed neighbour rows.
 struct ExtArgs {
-    const float *dsq;
     int n;
     int p;                           // dimension of the produced simplices, >= 2
-    const uint64_t *bits;
     int words;
+    const uint4 *nbw;                // packed neighbour rows
+    const float *nbd;
     const uint64_t *binom;
     const float *pre_diam;           // (p-1)-simplices <= thr, cidx order
     const uint64_t *pre_cidx;
-    int64_t npre;
+    int64_t npre_count;              // number of prefixes
 };
 // Pass 1: per prefix, the number of extensions.
 void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s);
-// Pass 2: write every extension at the given offsets, in cidx order.
+// Pass 2, with the clearing filter (the paper's clearing lemma) fused in:
+// every extension is written to all_diam/all_cidx at the scanned offsets
+// off_all (skipped when all_diam is null), and those not in `clear` -- the
+// sorted cidx of the previous dimension's pivot rows, a subset of the
+// extensions -- to kept_diam/kept_cidx, in cidx order.  A prefix's kept
+// entries start at off_all[prefix] minus the number of clear entries below
+// the prefix's first extension, which one wave-wide search of `clear`
+// finds; the kept total is (number of extensions) - nclear, and kept_cap
+// (that total) bounds the kept writes.  kept_vtx (may be null; used for
+// p <= 3 and n <= 65536): the kept columns' vertex tuples, 16 bits per
+// vertex from the largest.
 void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
-                        uint64_t *all_cidx, hipStream_t s);
-// Clearing filter: the entries of `all` (cidx order) that are not in the
-// sorted array `clear`, kept in order.  Count pass per COMPACT_TILE tile,
-// then the scatter at the scanned tile offsets.
-void launch_clear_count(const uint64_t *all_cidx, int64_t nall, const uint64_t *clear,
-                        int64_t nclear, uint32_t *tile_counts, hipStream_t s);
-void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64_t nall,
-                          const uint64_t *clear, int64_t nclear, const uint64_t *tile_offsets,
-                          float *kept_diam, uint64_t *kept_cidx, hipStream_t s);
+                        uint64_t *all_cidx, const uint64_t *clear, int64_t nclear,
+                        float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
+                        uint64_t *kept_vtx, hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
 // neighbours of the column's vertices, scanned from the top, `group` words
 // per step by as many lanes (4, 8 or 16; anything else means 4).
 int sparse_group(int group);
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
-                            const float *dsq, int n, int p, const uint64_t *bits, int words,
+                            int n, int p, int words, const uint4 *nbw, const float *nbd,
                             const uint64_t *binom, int group, uint64_t *tau_out,
-                            unsigned long long *scan_count, hipStream_t s);
+                            unsigned long long *scan_count, hipStream_t s,
+                            const uint64_t *col_vtx = nullptr);
 void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
-                        const float *dsq, int n, int p, const uint64_t *bits, int words,
+                        const uint4 *nbw, const float *nbd, int n, int p, int words,
                         const uint64_t *binom, uint64_t *low_out, float *low_diam_out,
                         hipStream_t s);
 

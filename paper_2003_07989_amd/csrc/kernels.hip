@@ -90,16 +90,20 @@ __device__ __forceinline__ T block_sum(T v, T *sh)
 __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dcond, int n,
                                                float *__restrict__ dsq,
                                                float *__restrict__ rowmax,
-                                               uint32_t *__restrict__ bad)
+                                               uint32_t *__restrict__ bad,
+                                               const int32_t *__restrict__ nvs)
 {
     __shared__ float sh[5];
     const int i = blockIdx.x;
+    int nv = n;  // the cloud's own points; the rest is bucket padding
     {   // batched launch: cloud blockIdx.y, arrays packed cloud after cloud
         const int64_t c = blockIdx.y;
         dcond += c * ((int64_t)n * (n - 1) / 2);
         dsq += c * (int64_t)n * n;
         rowmax += c * n;
         bad += c;
+        if (nvs)
+            nv = nvs[c];
     }
     float mx = 0.0f;
     uint32_t flag = 0;
@@ -112,11 +116,13 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dcond, 
             d = dcond[rowi + j];
         else
             d = dcond[(int64_t)j * (j - 1) / 2 + i];
-        if (!(d >= 0.0f) || isinf(d))
+        const bool real = i < nv && j < nv;
+        if (real && (!(d >= 0.0f) || isinf(d)))
             flag = 1;
         d = d + 0.0f;
         dsq[(int64_t)i * n + j] = d;
-        mx = fmaxf(mx, d);
+        if (j < nv)
+            mx = fmaxf(mx, d);
     }
     // block max
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -160,7 +166,8 @@ __global__ __launch_bounds__(1024) void k_min(const float *__restrict__ x, int n
 void launch_stage(const float *dcond, int n, float *dsq, float *rowmax, uint32_t *bad,
                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage, dim3(n), dim3(256), 0, s, dcond, n, dsq, rowmax, bad);
+    hipLaunchKernelGGL(k_stage, dim3(n), dim3(256), 0, s, dcond, n, dsq, rowmax, bad,
+                       (const int32_t *)nullptr);
 }
 
 void launch_min(const float *x, int n, float *out, hipStream_t s)
@@ -169,9 +176,30 @@ void launch_min(const float *x, int n, float *out, hipStream_t s)
 }
 
 void launch_stage_b(const float *dcond, int n, int nb, float *dsq, float *rowmax, uint32_t *bad,
-                    hipStream_t s)
+                    hipStream_t s, const int32_t *nv)
 {
-    hipLaunchKernelGGL(k_stage, dim3(n, nb), dim3(256), 0, s, dcond, n, dsq, rowmax, bad);
+    hipLaunchKernelGGL(k_stage, dim3(n, nb), dim3(256), 0, s, dcond, n, dsq, rowmax, bad, nv);
+}
+
+__global__ void k_pad_dcond(float *__restrict__ dcond, int n, const int32_t *__restrict__ nvs)
+{
+    const int64_t c = blockIdx.y;
+    const int64_t E = (int64_t)n * (n - 1) / 2;
+    const int64_t nv = nvs[c];
+    const int64_t t = nv * (nv - 1) / 2 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < E)
+        dcond[c * E + t] = INFINITY;
+}
+
+void launch_pad_dcond_b(float *dcond, int n, int nb, const int32_t *nv, hipStream_t s)
+{
+    // the largest padding region is that of the smallest cloud: bound it by
+    // the whole matrix (threads past a cloud's region exit)
+    const int64_t E = (int64_t)n * (n - 1) / 2;
+    if (E <= 0 || nb <= 0)
+        return;
+    hipLaunchKernelGGL(k_pad_dcond, dim3((unsigned)((E + 255) / 256), nb), dim3(256), 0, s, dcond,
+                       n, nv);
 }
 
 // Per cloud: radius = min over rows of the row maxima; the threshold used is
@@ -180,12 +208,14 @@ void launch_stage_b(const float *dcond, int n, int nb, float *dsq, float *rowmax
 __global__ __launch_bounds__(1024) void k_radius_b(const float *__restrict__ rowmax, int n,
                                                   const float *__restrict__ req, int no_radius,
                                                   float *__restrict__ radius,
-                                                  float *__restrict__ thr)
+                                                  float *__restrict__ thr,
+                                                  const int32_t *__restrict__ nvs)
 {
     __shared__ float sh[16];
     const int c = blockIdx.x;
+    const int nv = nvs ? nvs[c] : n;
     float m = INFINITY;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int i = threadIdx.x; i < nv; i += blockDim.x)
         m = fminf(m, rowmax[(int64_t)c * n + i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -204,10 +234,10 @@ __global__ __launch_bounds__(1024) void k_radius_b(const float *__restrict__ row
 }
 
 void launch_radius_b(const float *rowmax, int n, int nb, const float *req, int no_radius,
-                     float *radius, float *thr, hipStream_t s)
+                     float *radius, float *thr, hipStream_t s, const int32_t *nv)
 {
     hipLaunchKernelGGL(k_radius_b, dim3(nb), dim3(1024), 0, s, rowmax, n, req, no_radius, radius,
-                       thr);
+                       thr, nv);
 }
 
 // ===========================================================================
@@ -688,6 +718,9 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
     }
     if (base >= ncols)
         return;  // whole waves leave together
+    // the cloud's own points: candidates above are bucket padding (never a
+    // cofacet: infinitely far), so the scans start below them
+    const int nv = batch_nv(bt, blockIdx.y, n);
     const Binom B{binom, n + 1};
     const int64_t mycol = base + lane;
     const bool myvalid = lane < own && mycol < ncols;
@@ -727,7 +760,7 @@ __global__ __launch_bounds__(256) void k_apparent(const float *__restrict__ col_
         for (int i = 0; i <= P; ++i)
             e[i] = 0.0f;
         if (valid) {
-            for (int top = n - 1; top >= 0; top -= G) {
+            for (int top = nv - 1; top >= 0; top -= G) {
                 const int u = top - g;
                 bool ok = u >= 0;
                 if (ok) {
@@ -2059,64 +2092,241 @@ void launch_nbr_bits(const float *dsq, int n, float thr, uint64_t *bits, int wor
                        thr, bits, words);
 }
 
+// Degree of every vertex in the threshold graph: one wave per row.
+__global__ __launch_bounds__(256) void k_nbr_degree(const uint64_t *__restrict__ bits, int n,
+                                                   int words, uint32_t *__restrict__ deg)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (v >= n)
+        return;
+    uint32_t c = 0;
+    for (int k = lane; k < words; k += WAVE)
+        c += (uint32_t)__popcll(bits[v * words + k]);
+    c = wave_sum(c);
+    if (lane == 0)
+        deg[v] = c;
+}
+
+void launch_nbr_degree(const uint64_t *bits, int n, int words, uint32_t *deg, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_nbr_degree, dim3((unsigned)(((int64_t)n * WAVE + 255) / 256)), dim3(256),
+                       0, s, bits, n, words, deg);
+}
+
+// Packed rows: one wave per vertex, lane k on word k of a 64-word block; the
+// position of a word's first neighbour is the row offset plus an exclusive
+// scan of the words' popcounts.
+__global__ __launch_bounds__(256) void k_nbr_pack(const float *__restrict__ dsq,
+                                                 const uint64_t *__restrict__ bits, int n,
+                                                 int words, const uint64_t *__restrict__ row_off,
+                                                 uint4 *__restrict__ nbw,
+                                                 float *__restrict__ nbd, uint64_t cap)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (v >= n)
+        return;
+    uint64_t run = row_off[v];
+    const float *row = dsq + v * n;
+    for (int wb = 0; wb < words; wb += WAVE) {
+        const int k = wb + lane;
+        const uint64_t m = k < words ? bits[v * words + k] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(m);
+        const uint32_t inc = wave_inclusive_scan(c);
+        uint64_t pos = run + (inc - c);
+        if (k < words)
+            nbw[v * words + k] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), (uint32_t)pos, 0u);
+        for (uint64_t r = m; r && pos < cap; r &= r - 1)
+            nbd[pos++] = row[k * 64 + __ffsll((unsigned long long)r) - 1];
+        run += __shfl(inc, WAVE - 1, WAVE);
+    }
+}
+
+void launch_nbr_pack(const float *dsq, const uint64_t *bits, int n, int words,
+                     const uint64_t *row_off, uint4 *nbw, float *nbd, uint64_t cap,
+                     hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    hipLaunchKernelGGL(k_nbr_pack, dim3((unsigned)(((int64_t)n * WAVE + 255) / 256)), dim3(256),
+                       0, s, dsq, bits, n, words, row_off, nbw, nbd, cap);
+}
+
+// Word k of v's neighbour row as one 16-byte record: its bitset word and the
+// packed position of its first neighbour.
+__device__ __forceinline__ void nb_word(const uint4 *__restrict__ nbw, int64_t idx,
+                                        uint64_t &bits, uint32_t &pre)
+{
+    const uint4 x = nbw[idx];
+    bits = (uint64_t)x.x | ((uint64_t)x.y << 32);
+    pre = x.z;
+}
+
+// d(v, u) for a neighbour u = 64k + b of v, given v's bitset word k and the
+// packed position of its first neighbour in that word.
+__device__ __forceinline__ float nb_dist(const float *__restrict__ nbd, uint32_t pre,
+                                         uint64_t word_bits, int b)
+{
+    return nbd[pre + (uint32_t)__popcll(word_bits & ((1ull << b) - 1ull))];
+}
+
+// First index j of the sorted array a[0, m) with a[j] >= key (m if none),
+// found by the whole wave: each round probes 64 evenly spaced entries and
+// keeps the interval between the last probe below the key and the next, so
+// four rounds cover 2^24 entries.  Every lane returns the same value; call
+// with the whole wave.
+__device__ __forceinline__ int64_t wave_lower_bound(const uint64_t *__restrict__ a, int64_t m,
+                                                    uint64_t key)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    int64_t lo = 0, hi = m;  // a[j] < key for j < lo; a[hi] >= key or hi == m
+    while (hi - lo > WAVE) {
+        const int64_t step = (hi - lo + WAVE - 1) / WAVE;
+        const int64_t j = lo + (int64_t)lane * step;
+        const bool below = j < hi && a[j] < key;
+        const int c = __popcll(__ballot(below));  // the probes below key come first
+        if (c == 0) {
+            hi = lo;
+            break;
+        }
+        const int64_t nhi = lo + (int64_t)c * step;
+        lo = lo + (int64_t)(c - 1) * step + 1;
+        hi = nhi < hi ? nhi : hi;
+    }
+    const int64_t j = lo + lane;
+    const bool below = j < hi && a[j] < key;
+    return lo + __popcll(__ballot(below));
+}
+
 // One wave per prefix, one lane per 64-vertex word of candidates v_0 < v_1.
-// Every extension is within the threshold; clearing is a separate pass
-// (k_clear_filter), so this kernel does no lookups.
+// Count pass (WRITE = false): extensions per prefix.  Scatter pass: every
+// extension to all_* (when given) and the uncleared ones to kept_*.
 template <int P, bool WRITE>
 __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ cnt_all,
                                              const uint64_t *__restrict__ off_all,
                                              float *__restrict__ all_diam,
-                                             uint64_t *__restrict__ all_cidx)
+                                             uint64_t *__restrict__ all_cidx,
+                                             const uint64_t *__restrict__ clear, int64_t nclear,
+                                             float *__restrict__ kept_diam,
+                                             uint64_t *__restrict__ kept_cidx, uint64_t kept_cap,
+                                             uint64_t *__restrict__ kept_vtx)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t pre = (blk * blockDim.x + threadIdx.x) / WAVE;
-    if (pre >= a.npre)
-        return;
+    if (pre >= a.npre_count)
+        return;  // whole waves leave together
     const Binom B{a.binom, a.n + 1};
     int u[P];  // prefix vertices, decreasing; u[P-1] = v_1
     decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
-    const float pd = a.pre_diam[pre];
     // cidx of (u, v0) = sum_i C(u_i, P+1-i) + v0
     uint64_t shifted = 0;
 #pragma unroll
     for (int i = 0; i < P; ++i)
         shifted += B(u[i], P + 1 - i);
     const int limit = u[P - 1];
-    uint64_t run = WRITE ? off_all[pre] : 0;
-    uint32_t tot = 0;
+    if (!WRITE) {
+        uint32_t tot = 0;
+        for (int wb = 0; wb * 64 < limit; wb += WAVE) {
+            const int word = wb + lane;
+            uint64_t m = 0;
+            if (word * 64 < limit) {
+                m = ~0ull;
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    m &= (uint64_t)a.nbw[(int64_t)u[i] * a.words + word].x |
+                         ((uint64_t)a.nbw[(int64_t)u[i] * a.words + word].y << 32);
+                const int hi = limit - word * 64;  // keep bits below v_1
+                if (hi < 64)
+                    m &= (1ull << hi) - 1;
+            }
+            tot += wave_sum((uint32_t)__popcll(m));
+        }
+        if (lane == 0)
+            cnt_all[pre] = tot;
+        return;
+    }
+    const float pd = a.pre_diam[pre];
+    // the kept columns' vertex tuples, 16 bits per vertex from the largest
+    // (the form the apparent kernels read instead of decoding the column)
+    uint64_t vtx_hi = 0;
+    if (P <= 3) {
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            vtx_hi |= (uint64_t)(uint32_t)u[i] << (16 * i);
+    }
+    uint64_t run = off_all[pre];
+    // cleared entries below this prefix's first extension: the kept entries
+    // of the prefix start that many places before its extensions
+    int64_t cpos = nclear ? wave_lower_bound(clear, nclear, shifted) : 0;
+    uint64_t krun = run - (uint64_t)cpos;
     for (int wb = 0; wb * 64 < limit; wb += WAVE) {
         const int word = wb + lane;
-        uint64_t m = 0;
+        uint64_t m = 0, bw[P];
+        uint32_t pw[P];
         if (word * 64 < limit) {
             m = ~0ull;
 #pragma unroll
-            for (int i = 0; i < P; ++i)
-                m &= a.bits[(int64_t)u[i] * a.words + word];
-            const int hi = limit - word * 64;  // keep bits below v_1
+            for (int i = 0; i < P; ++i) {
+                nb_word(a.nbw, (int64_t)u[i] * a.words + word, bw[i], pw[i]);
+                m &= bw[i];
+            }
+            const int hi = limit - word * 64;
             if (hi < 64)
                 m &= (1ull << hi) - 1;
         }
-        const uint32_t na = (uint32_t)__popcll(m);
-        if (WRITE) {
-            uint64_t pa = run + (wave_inclusive_scan(na) - na);
-            for (uint64_t r = m; r; r &= r - 1) {
-                const int v0 = word * 64 + __ffsll((unsigned long long)r) - 1;
-                float d = pd;
+        // this block's cleared extensions, 64 clear entries per step: the
+        // ones below the block's end belong to it (the clear entries are
+        // sorted, a subset of the extensions, and none lies below the
+        // prefix's first extension past cpos)
+        const int blk_end = (wb + WAVE) * 64 < limit ? (wb + WAVE) * 64 : limit;
+        uint64_t cm = 0;
+        for (;;) {
+            const int64_t j = cpos + lane;
+            const uint64_t cv = j < nclear ? clear[j] : ~0ull;
+            const bool in = cv < shifted + (uint64_t)blk_end;
+            const uint64_t bm = __ballot(in);
+            const int c = __popcll(bm);
+            for (int k = 0; k < c; ++k) {
+                const uint64_t x = __shfl(cv, k, WAVE) - shifted;  // the cleared v0
+                if ((int)(x >> 6) == word)
+                    cm |= 1ull << (x & 63);
+            }
+            cpos += c;
+            if (c < WAVE)
+                break;
+        }
+        const uint64_t km = m & ~cm;
+        const uint32_t na = (uint32_t)__popcll(m), nk = (uint32_t)__popcll(km);
+        uint64_t pa = run + (wave_inclusive_scan(na) - na);
+        uint64_t pk = krun + (wave_inclusive_scan(nk) - nk);
+        for (uint64_t r = m; r; r &= r - 1) {
+            const int b = __ffsll((unsigned long long)r) - 1;
+            const int v0 = word * 64 + b;
+            float d = pd;
 #pragma unroll
-                for (int i = 0; i < P; ++i)
-                    d = fmaxf(d, dsq_at(a.dsq, a.n, u[i], v0));
+            for (int i = 0; i < P; ++i)
+                d = fmaxf(d, nb_dist(a.nbd, pw[i], bw[i], b));
+            const uint64_t c = shifted + (uint64_t)v0;
+            if (all_diam) {
                 all_diam[pa] = d;
-                all_cidx[pa] = shifted + (uint64_t)v0;
+                all_cidx[pa] = c;
                 ++pa;
             }
+            if (((km >> b) & 1ull) && pk < kept_cap) {  // (the cap only guards the subset property)
+                kept_diam[pk] = d;
+                kept_cidx[pk] = c;
+                if (P <= 3 && kept_vtx)
+                    kept_vtx[pk] = vtx_hi | ((uint64_t)(uint32_t)v0 << (16 * P));
+                ++pk;
+            }
         }
-        const uint32_t sa = wave_sum(na);
-        run += sa;
-        tot += sa;
+        run += wave_sum(na);
+        krun += wave_sum(nk);
     }
-    if (!WRITE && lane == 0)
-        cnt_all[pre] = tot;
 }
 
 #define RPP_EXT_LAUNCH(WR, ...)                                                                  \
@@ -2128,143 +2338,25 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
 
 void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s)
 {
-    if (a.npre <= 0)
+    if (a.npre_count <= 0)
         return;
-    dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
-    RPP_EXT_LAUNCH(false, cnt_all, nullptr, nullptr, nullptr)
+    dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
+    RPP_EXT_LAUNCH(false, cnt_all, nullptr, nullptr, nullptr, nullptr, (int64_t)0, nullptr,
+                   nullptr, (uint64_t)0, nullptr)
 }
 
 void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
-                        uint64_t *all_cidx, hipStream_t s)
+                        uint64_t *all_cidx, const uint64_t *clear, int64_t nclear,
+                        float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
+                        uint64_t *kept_vtx, hipStream_t s)
 {
-    if (a.npre <= 0)
+    if (a.npre_count <= 0)
         return;
-    dim3 g((unsigned)((a.npre * WAVE + 255) / 256)), b(256);
-    RPP_EXT_LAUNCH(true, nullptr, off_all, all_diam, all_cidx)
-}
-
-// Clearing filter of the sparse path.  `all` lists every p-simplex within
-// the threshold in cidx order and `clear` the cleared ones, sorted (a
-// subset).  A tile of COMPACT_TILE entries finds its slice of `clear` with
-// two binary searches and stages it in LDS; each entry then looks itself up
-// in the slice.  Because `clear` is a subset of `all`, a slice is never
-// longer than its tile; the global search only guards that assumption.  The
-// kept entries are written stably, as in the partition pass.
-constexpr int CLEAR_LDS = (int)COMPACT_TILE;
-
-__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *__restrict__ a, int64_t lo,
-                                                   int64_t hi, uint64_t key)
-{
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-template <bool WRITE>
-__global__ __launch_bounds__(CT) void k_clear_filter(
-    const float *__restrict__ all_diam, const uint64_t *__restrict__ all_cidx, int64_t nall,
-    const uint64_t *__restrict__ clear, int64_t nclear, uint32_t *__restrict__ tile_counts,
-    const uint64_t *__restrict__ tile_offsets, float *__restrict__ kept_diam,
-    uint64_t *__restrict__ kept_cidx)
-{
-    __shared__ uint64_t sl[CLEAR_LDS];
-    __shared__ int64_t range[2];
-    __shared__ uint32_t wsum[CT / WAVE + 1];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const int64_t base = (int64_t)blockIdx.x * COMPACT_TILE;
-    const int64_t end = base + COMPACT_TILE < nall ? base + COMPACT_TILE : nall;
-    if (threadIdx.x == 0)
-        range[0] = lower_bound_u64(clear, 0, nclear, all_cidx[base]);
-    if (threadIdx.x == WAVE)
-        range[1] = lower_bound_u64(clear, 0, nclear, all_cidx[end - 1] + 1);
-    __syncthreads();
-    const int64_t lo = range[0], len = range[1] - range[0];
-    const bool in_lds = len <= CLEAR_LDS;
-    if (in_lds)
-        for (int64_t k = threadIdx.x; k < len; k += CT)
-            sl[k] = clear[lo + k];
-    __syncthreads();
-    uint64_t run = WRITE ? tile_offsets[blockIdx.x] : 0;
-    uint32_t cnt = 0;
-    for (int k = 0; k < CI; ++k) {
-        const int64_t i = base + (int64_t)k * CT + threadIdx.x;
-        const bool valid = i < end;
-        const uint64_t c = valid ? all_cidx[i] : 0;
-        bool keep = valid;
-        if (valid && len > 0) {
-            int64_t j;
-            bool hit;
-            if (in_lds) {
-                int a0 = 0, a1 = (int)len;
-                while (a0 < a1) {
-                    const int mid = (a0 + a1) >> 1;
-                    if (sl[mid] < c)
-                        a0 = mid + 1;
-                    else
-                        a1 = mid;
-                }
-                hit = a0 < len && sl[a0] == c;
-            } else {
-                j = lower_bound_u64(clear, lo, lo + len, c);
-                hit = j < lo + len && clear[j] == c;
-            }
-            keep = !hit;
-        }
-        if (!WRITE) {
-            cnt += keep ? 1u : 0u;
-            continue;
-        }
-        const uint64_t mk = __ballot(keep);
-        if (lane == 0)
-            wsum[wave] = (uint32_t)__popcll(mk);
-        __syncthreads();
-        uint32_t pre = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < CT / WAVE; ++w) {
-            const uint32_t x = wsum[w];
-            pre += w < wave ? x : 0u;
-            tot += x;
-        }
-        if (keep) {
-            const uint64_t pos = run + pre + (uint32_t)__popcll(mk & lanemask_lt());
-            kept_diam[pos] = all_diam[i];
-            kept_cidx[pos] = c;
-        }
-        run += tot;
-        __syncthreads();
-    }
-    if (!WRITE) {
-        cnt = block_sum<CT>(cnt, wsum);
-        if (threadIdx.x == 0)
-            tile_counts[blockIdx.x] = cnt;
-    }
-}
-
-void launch_clear_count(const uint64_t *all_cidx, int64_t nall, const uint64_t *clear,
-                        int64_t nclear, uint32_t *tile_counts, hipStream_t s)
-{
-    const int64_t tiles = compact_tiles(nall);
-    if (tiles == 0)
-        return;
-    hipLaunchKernelGGL(k_clear_filter<false>, dim3((unsigned)tiles), dim3(CT), 0, s, nullptr,
-                       all_cidx, nall, clear, nclear, tile_counts, nullptr, nullptr, nullptr);
-}
-
-void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64_t nall,
-                          const uint64_t *clear, int64_t nclear, const uint64_t *tile_offsets,
-                          float *kept_diam, uint64_t *kept_cidx, hipStream_t s)
-{
-    const int64_t tiles = compact_tiles(nall);
-    if (tiles == 0)
-        return;
-    hipLaunchKernelGGL(k_clear_filter<true>, dim3((unsigned)tiles), dim3(CT), 0, s, all_diam,
-                       all_cidx, nall, clear, nclear, nullptr, tile_offsets, kept_diam,
-                       kept_cidx);
+    if (a.p > 3 || a.n > 65536)
+        kept_vtx = nullptr;
+    dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
+    RPP_EXT_LAUNCH(true, nullptr, off_all, all_diam, all_cidx, clear, nclear, kept_diam,
+                   kept_cidx, kept_cap, kept_vtx)
 }
 
 // Sparse apparent test.  The candidates for sigma's oldest cofacet are the
@@ -2281,9 +2373,10 @@ void launch_clear_scatter(const float *all_diam, const uint64_t *all_cidx, int64
 template <int P, int G>
 __global__ __launch_bounds__(256) void k_apparent_sparse(
     const float *__restrict__ col_diam, const uint64_t *__restrict__ col_cidx, int64_t ncols,
-    const float *__restrict__ dsq, int n, const uint64_t *__restrict__ bits, int words,
+    int n, int words, const uint4 *__restrict__ nbw, const float *__restrict__ nbd,
     const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
-    unsigned long long *__restrict__ scan_count, int rounds)
+    unsigned long long *__restrict__ scan_count, int rounds,
+    const uint64_t *__restrict__ col_vtx)
 {
     constexpr int CPR = WAVE / G;  // columns per round
     const int lane = threadIdx.x & (WAVE - 1);
@@ -2306,7 +2399,14 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         myv[i] = 0;
     if (myvalid) {
         myd = col_diam[mycol];
-        decode<P>(B, col_cidx[mycol], n, myv);
+        if (P <= 3 && col_vtx) {
+            const uint64_t x = col_vtx[mycol];
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                myv[i] = (int)((x >> (16 * i)) & 0xffffu);
+        } else {
+            decode<P>(B, col_cidx[mycol], n, myv);
+        }
     }
     uint64_t mytau = NONE;
     unsigned long long examined = 0;  // this lane's share of the candidates visited
@@ -2318,16 +2418,6 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         for (int i = 0; i <= P; ++i)
             v[i] = __shfl(myv[i], src, WAVE);
         const bool valid = base + src < ncols;  // uniform in the group
-        const float *row[P + 1];
-#pragma unroll
-        for (int i = 0; i <= P; ++i)
-            row[i] = dsq + (int64_t)v[i] * n;
-        float dv[P + 1][P + 1];
-#pragma unroll
-        for (int a = 0; a <= P; ++a)
-#pragma unroll
-            for (int b = a + 1; b <= P; ++b)
-                dv[a][b] = valid ? row[a][v[b]] : 0.0f;
         int x = -1;  // this lane's hit in the current step
         int hit = -1;
         float e[P + 1];
@@ -2337,12 +2427,15 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         if (valid) {
             for (int top = words - 1; top >= 0; top -= G) {
                 const int word = top - g;
-                uint64_t m = 0;
+                uint64_t m = 0, bw[P + 1];
+                uint32_t pw[P + 1];
                 if (word >= 0) {
                     m = ~0ull;
 #pragma unroll
-                    for (int i = 0; i <= P; ++i)
-                        m &= bits[(int64_t)v[i] * words + word];
+                    for (int i = 0; i <= P; ++i) {
+                        nb_word(nbw, (int64_t)v[i] * words + word, bw[i], pw[i]);
+                        m &= bw[i];
+                    }
                 }
                 unsigned tested = 0;
                 for (uint64_t mm = m; mm;) {
@@ -2352,7 +2445,7 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
                     float t[P + 1];
 #pragma unroll
                     for (int i = 0; i <= P; ++i) {
-                        t[i] = row[i][c];
+                        t[i] = nb_dist(nbd, pw[i], bw[i], b);
                         ok = ok && (t[i] <= d);
                     }
                     ++tested;
@@ -2385,6 +2478,26 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
             ew[i] = __shfl(e[i], hit >= 0 ? hit : lane, WAVE);
         uint64_t tau = NONE;
         if (hit >= 0) {
+            // distances among sigma's vertices, needed only when a vertex of
+            // sigma lies above w (sigma's edges are all within the
+            // threshold: packed-row lookups)
+            bool need = false;
+#pragma unroll
+            for (int j = 0; j <= P; ++j)
+                need = need || v[j] > w;
+            float dv[P + 1][P + 1];
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+#pragma unroll
+                for (int b = a + 1; b <= P; ++b) {
+                    dv[a][b] = 0.0f;
+                    if (need) {
+                        uint64_t wb;
+                        uint32_t wp;
+                        nb_word(nbw, (int64_t)v[a] * words + (v[b] >> 6), wb, wp);
+                        dv[a][b] = nb_dist(nbd, wp, wb, v[b] & 63);
+                    }
+                }
             bool apparent = true;
 #pragma unroll
             for (int j = 0; j <= P; ++j) {
@@ -2426,7 +2539,7 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
 template <int P>
 __global__ __launch_bounds__(256) void k_lows_sparse(
     const uint64_t *__restrict__ na_key, const uint64_t *__restrict__ na_cidx, int64_t ncols,
-    const float *__restrict__ dsq, int n, const uint64_t *__restrict__ bits, int words,
+    const uint4 *__restrict__ nbw, const float *__restrict__ nbd, int n, int words,
     const uint64_t *__restrict__ binom, uint64_t *__restrict__ low_out,
     float *__restrict__ low_diam_out)
 {
@@ -2441,16 +2554,20 @@ __global__ __launch_bounds__(256) void k_lows_sparse(
     float best = INFINITY;
     int bw = -1;
     for (int word = lane; word < words; word += WAVE) {
-        uint64_t m = ~0ull;
+        uint64_t m = ~0ull, wbits[P + 1];
+        uint32_t wpre[P + 1];
 #pragma unroll
-        for (int i = 0; i <= P; ++i)
-            m &= bits[(int64_t)v[i] * words + word];
+        for (int i = 0; i <= P; ++i) {
+            nb_word(nbw, (int64_t)v[i] * words + word, wbits[i], wpre[i]);
+            m &= wbits[i];
+        }
         for (; m; m &= m - 1) {
-            const int x = word * 64 + __ffsll((unsigned long long)m) - 1;
+            const int b = __ffsll((unsigned long long)m) - 1;
+            const int x = word * 64 + b;
             float c = d;
 #pragma unroll
             for (int i = 0; i <= P; ++i)
-                c = fmaxf(c, dsq_at(dsq, n, v[i], x));
+                c = fmaxf(c, nb_dist(nbd, wpre[i], wbits[i], b));
             if (c <= best) {  // ascending x: later (larger) x wins ties
                 best = c;
                 bw = x;
@@ -2474,9 +2591,10 @@ __global__ __launch_bounds__(256) void k_lows_sparse(
 
 template <int P, int G>
 static void launch_apparent_sparse_pg(const float *cd, const uint64_t *cc, int64_t ncols,
-                                      const float *dsq, int n, const uint64_t *bits, int words,
+                                      int n, int words, const uint4 *nbw, const float *nbd,
                                       const uint64_t *binom, uint64_t *tau,
-                                      unsigned long long *sc, hipStream_t s)
+                                      unsigned long long *sc, hipStream_t s,
+                                      const uint64_t *cv)
 {
     // rounds per wave as in the dense kernel: as many as G allows while the
     // grid keeps ~4 waves per SIMD
@@ -2486,20 +2604,20 @@ static void launch_apparent_sparse_pg(const float *cd, const uint64_t *cc, int64
         rounds *= 2;
     const int64_t waves = (ncols + (int64_t)cpr * rounds - 1) / ((int64_t)cpr * rounds);
     dim3 g((unsigned)((waves * WAVE + 255) / 256)), b(256);
-    hipLaunchKernelGGL((k_apparent_sparse<P, G>), g, b, 0, s, cd, cc, ncols, dsq, n, bits, words,
-                       binom, tau, sc, rounds);
+    hipLaunchKernelGGL((k_apparent_sparse<P, G>), g, b, 0, s, cd, cc, ncols, n, words, nbw, nbd,
+                       binom, tau, sc, rounds, cv);
 }
 
 template <int P>
-static void launch_apparent_sparse_p(const float *cd, const uint64_t *cc, int64_t ncols,
-                                     const float *dsq, int n, const uint64_t *bits, int words,
+static void launch_apparent_sparse_p(const float *cd, const uint64_t *cc, int64_t ncols, int n,
+                                     int words, const uint4 *nbw, const float *nbd,
                                      const uint64_t *binom, int group, uint64_t *tau,
-                                     unsigned long long *sc, hipStream_t s)
+                                     unsigned long long *sc, hipStream_t s, const uint64_t *cv)
 {
     switch (group) {
-    case 16: launch_apparent_sparse_pg<P, 16>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
-    case 8: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
-    default: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, dsq, n, bits, words, binom, tau, sc, s); break;
+    case 16: launch_apparent_sparse_pg<P, 16>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
+    case 8: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
+    default: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
     }
 }
 
@@ -2509,35 +2627,42 @@ int sparse_group(int group)
 }
 
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
-                            const float *dsq, int n, int p, const uint64_t *bits, int words,
+                            int n, int p, int words, const uint4 *nbw, const float *nbd,
                             const uint64_t *binom, int group, uint64_t *tau_out,
-                            unsigned long long *scan_count, hipStream_t s)
+                            unsigned long long *scan_count, hipStream_t s,
+                            const uint64_t *col_vtx)
 {
     if (ncols <= 0)
         return;
     group = sparse_group(group);
+    if (p > 3 || n > 65536)
+        col_vtx = nullptr;
+#define RPP_APS(P) launch_apparent_sparse_p<P>(col_diam, col_cidx, ncols, n, words, nbw, nbd, binom, group, tau_out, scan_count, s, col_vtx)
     switch (p) {
-    case 1: launch_apparent_sparse_p<1>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
-    case 2: launch_apparent_sparse_p<2>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
-    case 3: launch_apparent_sparse_p<3>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
-    default: launch_apparent_sparse_p<4>(col_diam, col_cidx, ncols, dsq, n, bits, words, binom, group, tau_out, scan_count, s); break;
+    case 1: RPP_APS(1); break;
+    case 2: RPP_APS(2); break;
+    case 3: RPP_APS(3); break;
+    default: RPP_APS(4); break;
     }
+#undef RPP_APS
 }
 
 void launch_lows_sparse(const uint64_t *na_key, const uint64_t *na_cidx, int64_t ncols,
-                        const float *dsq, int n, int p, const uint64_t *bits, int words,
+                        const uint4 *nbw, const float *nbd, int n, int p, int words,
                         const uint64_t *binom, uint64_t *low_out, float *low_diam_out,
                         hipStream_t s)
 {
     if (ncols <= 0)
         return;
     dim3 g((unsigned)((ncols * WAVE + 255) / 256)), b(256);
+#define RPP_LS(P) hipLaunchKernelGGL(k_lows_sparse<P>, g, b, 0, s, na_key, na_cidx, ncols, nbw, nbd, n, words, binom, low_out, low_diam_out)
     switch (p) {
-    case 1: hipLaunchKernelGGL(k_lows_sparse<1>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
-    case 2: hipLaunchKernelGGL(k_lows_sparse<2>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
-    case 3: hipLaunchKernelGGL(k_lows_sparse<3>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
-    default: hipLaunchKernelGGL(k_lows_sparse<4>, g, b, 0, s, na_key, na_cidx, ncols, dsq, n, bits, words, binom, low_out, low_diam_out); break;
+    case 1: RPP_LS(1); break;
+    case 2: RPP_LS(2); break;
+    case 3: RPP_LS(3); break;
+    default: RPP_LS(4); break;
     }
+#undef RPP_LS
 }
 
 // ===========================================================================
@@ -2628,7 +2753,7 @@ __global__ __launch_bounds__(KT) void k_kruskal(const uint64_t *__restrict__ edg
     }
     __syncthreads();
     for (int64_t base = 0; base < nedges; base += KT) {
-        if (s_merges >= n - 1)
+        if (s_merges >= batch_nv(bt, blockIdx.x, n) - 1)
             break;  // spanning tree complete: no later edge can merge
         const int64_t k = base + tid;
         bool active = k < nedges;
@@ -2735,24 +2860,8 @@ __global__ void k_edge_grad(const float *__restrict__ pts, int n, int d,
         return;
     const int u = (int)(t / d), k = (int)(t % d);
     double acc = 0.0;
-    for (int64_t i = 0; i < nterms; ++i) {
-        const uint64_t e = edges[i];
-        if (e == NONE)
-            continue;
-        int a, b;
-        decode_edge(e, a, b);
-        if (a != u && b != u)
-            continue;
-        const int o = (a == u) ? b : a;
-        double len2 = 0.0;
-        for (int q = 0; q < d; ++q) {
-            const double df = (double)pts[(int64_t)u * d + q] - (double)pts[(int64_t)o * d + q];
-            len2 += df * df;
-        }
-        if (len2 > 0.0)
-            acc += (double)g[i] * ((double)pts[(int64_t)u * d + k] - (double)pts[(int64_t)o * d + k]) /
-                   sqrt(len2);
-    }
+    for (int64_t i = 0; i < nterms; ++i)
+        edge_grad_add(acc, pts, d, u, k, edges[i], g[i]);
     grad[t] = (float)acc;
 }
 

@@ -62,10 +62,14 @@ bool fault_injected(const char *stage, int n);
 // Returns an RPP_* code; on error `err` holds a message.
 int run_pipeline(const RunArgs &a, RunOut &out, std::string &err);
 
-// Several clouds with the same n and maxdim, processed together.
+// Several clouds with the same maxdim, processed together at one size n: a
+// shape bucket pads each cloud's points to n with vertices at infinite
+// distance (finite thresholds only), which no simplex within the threshold
+// contains, so each cloud's pairs and bars are its own.
 struct BatchArgs {
     int count = 0;
-    int n = 0;
+    int n = 0;                                // the group's (padded) number of points
+    const int *nv = nullptr;                  // count clouds' own sizes (<= n), or null: all n
     int maxdim = 0;
     const float *const *dist_dev = nullptr;  // count device pointers
     const float *threshold = nullptr;         // count requested thresholds (host)

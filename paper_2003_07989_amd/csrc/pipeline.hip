@@ -71,9 +71,9 @@ struct Workspace {
     DevBuf dsq, rowmax, scal, binom;
     DevBuf ekey, eval, ekey2, eval2;  // edges for H0
     DevBuf mst, deaths, dedges, ufs;
-    DevBuf tcount, toff, scan, tcount2, toff2;
+    DevBuf tcount, toff, scan;
     DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
-    DevBuf xd, xc;                   // sparse path: all simplices <= thr, top dim
+    DevBuf ndeg, noff, nbw, nbd;     // sparse path: packed neighbour rows
     DevBuf rflags, rexcl, rmat, rvals;  // sparse path: rank-coded diameters
     DevBuf bits;                     // sparse path: neighbour bitsets
     DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
@@ -103,8 +103,8 @@ static std::vector<DevBuf *> device_buffers(Workspace &w)
 {
     return {&w.dsq,     &w.rowmax,  &w.scal,    &w.binom,  &w.ekey,   &w.eval,    &w.ekey2,
             &w.eval2,   &w.mst,     &w.deaths,  &w.dedges, &w.ufs,    &w.tcount,  &w.toff,
-            &w.scan,    &w.tcount2, &w.toff2,   &w.skd[0], &w.skd[1], &w.skc[0],  &w.skc[1],
-            &w.xd,      &w.xc,      &w.rflags,  &w.rexcl,  &w.rmat,   &w.rvals,   &w.bits,
+            &w.scan,    &w.ndeg,    &w.noff,    &w.skd[0], &w.skd[1], &w.skc[0],  &w.skc[1],
+            &w.nbw,     &w.nbd,     &w.rflags,  &w.rexcl,  &w.rmat,   &w.rvals,   &w.bits,
             &w.clr,     &w.clr2,    &w.clrv,    &w.clrv2,  &w.cdiam,  &w.ccidx,   &w.tau,
             &w.akey,    &w.aval,    &w.akey2,   &w.aval2,  &w.nkey,   &w.nval,    &w.nkey2,
             &w.nval2,   &w.clear,   &w.next,    &w.hostpiv, &w.lowc,  &w.lowd,    &w.gedges,
@@ -157,8 +157,6 @@ static void plan_limits(Workspace &w, int n, int maxdim)
     w.tcount.hint = (std::max(tiles, cpre) + 1) * 4;
     w.toff.hint = (std::max(tiles, cpre) + 2) * 8;
     w.scan.hint = (size_t)scan_scratch_words((int64_t)scan_n) * 8;
-    w.tcount2.hint = (tiles + 1) * 4;
-    w.toff2.hint = (tiles + 2) * 8;
     w.cdiam.hint = (cmax + 1) * 4;
     w.ccidx.hint = w.cvtx.hint = (cmax + 1) * 8;
     w.tau.hint = w.akey.hint = w.aval.hint = w.akey2.hint = w.aval2.hint = (cmax + 1) * 8;
@@ -172,8 +170,10 @@ static void plan_limits(Workspace &w, int n, int maxdim)
     if (maxdim >= 1) {  // sparse path
         w.skd[0].hint = w.skd[1].hint = (cpre + 1) * 4;
         w.skc[0].hint = w.skc[1].hint = (cpre + 1) * 8;
-        w.xd.hint = (cmax + 1) * 4;
-        w.xc.hint = (cmax + 1) * 8;
+        w.ndeg.hint = (nn + 1) * 4;
+        w.noff.hint = (nn + 2) * 8;
+        w.nbw.hint = nn * (size_t)words * 16;
+        w.nbd.hint = (2 * E + 1) * 4;
         w.rflags.hint = (E + 1) * 4;
         w.rexcl.hint = (E + 2) * 8;
         w.rmat.hint = nn * nn * 4;
@@ -416,15 +416,15 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
 
 // Sparse enumeration of the p-simplices (p >= 2) from the (p-1)-simplices in
 // ws.skd/skc[cur]: every p-simplex <= threshold, in cidx order, into
-// ws.skd/skc[1-cur] when want_all (the next dimension's prefixes), else into
-// ws.xd/xc; then the clearing filter writes the kept columns, still in cidx
-// order, into ws.cdiam/ccidx.
+// ws.skd/skc[1-cur] when want_all (the next dimension's prefixes), and in the
+// same pass the kept columns -- those not in the sorted clearing set --
+// still in cidx order, into ws.cdiam/ccidx.
 static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *clear,
                             int64_t nclear, bool want_all, int cur, hipStream_t s,
                             int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm)
 {
-    ws.cvtx_ok = false;  // no vertex tuples on this path
-    const int64_t np = ea.npre;
+    ws.cvtx_ok = false;
+    const int64_t np = ea.npre_count;
     ALLOC_TRY(ws.tcount, (size_t)(np + 1) * 4);
     ALLOC_TRY(ws.toff, (size_t)(np + 2) * 8);
     ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(np) * 8);
@@ -438,27 +438,26 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t nall = np ? (int64_t)h[0] : 0;
     *all = nall;
-    DevBuf &bd = want_all ? ws.skd[1 - cur] : ws.xd;
-    DevBuf &bc = want_all ? ws.skc[1 - cur] : ws.xc;
-    ALLOC_TRY(bd, (size_t)(nall + 1) * 4);
-    ALLOC_TRY(bc, (size_t)(nall + 1) * 8);
-    launch_ext_scatter(ea, ws.toff.as<uint64_t>(), bd.as<float>(), bc.as<uint64_t>(), s);
-    // clearing filter, all -> kept
-    const int64_t tiles = compact_tiles(nall);
-    ALLOC_TRY(ws.tcount2, (size_t)(tiles + 1) * 4);
-    ALLOC_TRY(ws.toff2, (size_t)(tiles + 2) * 8);
-    ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(std::max(np, tiles)) * 8);
-    launch_clear_count(bc.as<uint64_t>(), nall, clear, nclear, ws.tcount2.as<uint32_t>(), s);
-    launch_exclusive_scan(ws.tcount2.as<uint32_t>(), tiles, ws.toff2.as<uint64_t>(),
-                          ws.scan.as<uint64_t>(), s);
-    HIP_TRY(hipMemcpyAsync(h, ws.toff2.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    *kept = tiles ? (int64_t)h[0] : 0;
+    if (nclear > nall) {
+        err = "clearing set larger than the simplices it clears";
+        return RPP_E_DEVICE;
+    }
+    *kept = nall - nclear;  // the clearing set is a subset of the extensions
+    if (want_all) {
+        ALLOC_TRY(ws.skd[1 - cur], (size_t)(nall + 1) * 4);
+        ALLOC_TRY(ws.skc[1 - cur], (size_t)(nall + 1) * 8);
+    }
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
-    launch_clear_scatter(bd.as<float>(), bc.as<uint64_t>(), nall, clear, nclear,
-                         ws.toff2.as<uint64_t>(), ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(),
-                         s);
+    const bool vtx = ea.p <= 3 && ea.n <= 65536;  // vertex tuples for the apparent test
+    if (vtx)
+        ALLOC_TRY(ws.cvtx, (size_t)(*kept + 1) * 8);
+    launch_ext_scatter(ea, ws.toff.as<uint64_t>(),
+                       want_all ? ws.skd[1 - cur].as<float>() : nullptr,
+                       want_all ? ws.skc[1 - cur].as<uint64_t>() : nullptr, clear, nclear,
+                       ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), (uint64_t)*kept,
+                       vtx ? ws.cvtx.as<uint64_t>() : nullptr, s);
+    ws.cvtx_ok = vtx;
     if (tm)
         tm->stop();
     return RPP_OK;
@@ -516,9 +515,10 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     if (t_app)
         t_app->start();
     if (words > 0)
-        launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols,
-                               ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
-                               ws.binom.as<uint64_t>(), group, ws.tau.as<uint64_t>(), sc, s);
+        launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols, n, p, words,
+                               ws.nbw.as<uint4>(), ws.nbd.as<float>(), ws.binom.as<uint64_t>(),
+                               group, ws.tau.as<uint64_t>(), sc, s,
+                               ws.cvtx_ok ? ws.cvtx.as<uint64_t>() : nullptr);
     else if (group >= 20000) {
         const int pitch = (n + 3) & ~3;
         if (!ws.dsqp_ready) {
@@ -717,7 +717,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     (void)bstride;
 
     // host copy of the square matrix for the residual reduction (pinned,
-    // grow-only: a DMA copy that overlaps nothing on the host)
+    // grow-only); filled below, once the path is chosen: with rank-coded
+    // diameters it receives the rank matrix instead of the distances
     const float *h_dsq = nullptr;
     if (maxdim >= 1) {
         if (!ws.h_dsq.ensure((size_t)n * n * 4)) {
@@ -725,8 +726,6 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             return RPP_E_NOMEM;
         }
         h_dsq = ws.h_dsq.as<float>();
-        HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.dsq.p, (size_t)n * n * 4, hipMemcpyDeviceToHost,
-                               s));
     }
 
     // ---------------- a2: H0 ---------------------------------------------
@@ -828,6 +827,18 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         nskel = nedges;
         ALLOC_TRY(ws.bits, (size_t)n * words * 8);
         launch_nbr_bits(ws.dsq.as<float>(), n, thr, ws.bits.as<uint64_t>(), words, s);
+        // packed neighbour rows: the 2 * nedges distances under the threshold
+        ALLOC_TRY(ws.ndeg, (size_t)(n + 1) * 4);
+        ALLOC_TRY(ws.noff, (size_t)(n + 2) * 8);
+        ALLOC_TRY(ws.nbw, (size_t)n * words * 16);
+        ALLOC_TRY(ws.nbd, (size_t)(2 * nedges + 1) * 4);
+        ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(n) * 8);
+        launch_nbr_degree(ws.bits.as<uint64_t>(), n, words, ws.ndeg.as<uint32_t>(), s);
+        launch_exclusive_scan(ws.ndeg.as<uint32_t>(), n, ws.noff.as<uint64_t>(),
+                              ws.scan.as<uint64_t>(), s);
+        launch_nbr_pack(ws.dsq.as<float>(), ws.bits.as<uint64_t>(), n, words,
+                        ws.noff.as<uint64_t>(), ws.nbw.as<uint4>(), ws.nbd.as<float>(),
+                        (uint64_t)(2 * nedges), s);
         if (!ws.h_bits.ensure((size_t)n * words * 8)) {
             err = "hipHostMalloc of the host bitset copy failed";
             return RPP_E_NOMEM;
@@ -878,6 +889,9 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             ranks = true;
         }
     }
+    if (maxdim >= 1 && !ranks)
+        HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.dsq.p, (size_t)n * n * 4, hipMemcpyDeviceToHost,
+                               s));
     int rank_bits = 0;
     while (ranks && ((uint64_t)1 << rank_bits) <= (uint64_t)nranks)
         ++rank_bits;
@@ -1002,7 +1016,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             rc = enumerate_dense(ws, ea, s, &ncols, &nthr, &nclr, err, &t_enum, clear_count);
             ncand = (int64_t)nc;
         } else {
-            ExtArgs xa{ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(), words,
+            ExtArgs xa{n, p, words, ws.nbw.as<uint4>(), ws.nbd.as<float>(),
                        ws.binom.as<uint64_t>(), ws.skd[cur].as<float>(),
                        ws.skc[cur].as<uint64_t>(), nskel};
             int64_t nall = 0;
@@ -1072,8 +1086,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         ALLOC_TRY(ws.lowc, (size_t)(nna + 1) * 8);
         ALLOC_TRY(ws.lowd, (size_t)(nna + 1) * 4);
         if (sparse)
-            launch_lows_sparse(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, ws.bits.as<uint64_t>(),
-                               words, ws.binom.as<uint64_t>(), ws.lowc.as<uint64_t>(),
+            launch_lows_sparse(d_nk, d_nv, nna, ws.nbw.as<uint4>(), ws.nbd.as<float>(), n, p, words,
+                               ws.binom.as<uint64_t>(), ws.lowc.as<uint64_t>(),
                                ws.lowd.as<float>(), s);
         else
             launch_lows(d_nk, d_nv, nna, ws.dsq.as<float>(), n, p, thr, ws.binom.as<uint64_t>(),

@@ -122,7 +122,71 @@ def test_many_shapes_evict_and_recreate_workspaces(rpp):
         clouds = [w.condensed_from_points(w.noisy_torus_points(n, 900 + 10 * k + i))
                   for i in range(2)]
         dev = [_dev(d) for d in clouds]
-        out = rpp.barcodes_batch(dev, 2)
+        out = rpp.barcodes_batch(dev, 2, flags=rpp.RPP_BATCH_EXACT_SHAPES)
         for i in range(2):
             _same(out[i], rpp.barcodes_device(dev[i], 2, flags=rpp.RPP_FORCE_DENSE),
                   "shape %d cloud %d" % (n, i))
+
+
+_ALL_COUNTS = ("n_candidates", "n_simplices", "n_thresholded", "n_cleared", "n_kept",
+               "n_apparent", "n_nonapparent", "n_essential", "n_bars")
+# counts that do not depend on the schedule (the single-cloud path clears by
+# the apparent pivots on the device and drops the host pivots' columns later)
+_PATH_FREE = ("n_candidates", "n_simplices", "n_thresholded", "n_essential", "n_bars")
+
+
+def _stats_equal(a, b, label, keys=_ALL_COUNTS):
+    for p in range(len(a.stats)):
+        for k in keys:
+            assert a.stats[p][k] == b.stats[p][k], (label, p, k)
+
+
+@pytest.mark.parametrize("maxdim", [1, 2])
+def test_shape_bucket_mixed_sizes_match_single_and_oracle(rpp, maxdim):
+    """Clouds of 65..128 points share the 128-point bucket (padding vertices
+    at infinite distance): bars, critical edges and every per-dimension count
+    equal the single-cloud path, and the bars equal the oracle's."""
+    sizes = (65, 128, 97, 70, 111, 66) if maxdim == 1 else (65, 90, 77)
+    clouds = [w.condensed_from_points(w.noisy_torus_points(n, 4200 + n)) for n in sizes]
+    thr = [math.inf, float(np.quantile(clouds[1], 0.3))] + [math.inf] * (len(sizes) - 2)
+    dev = [_dev(d) for d in clouds]
+    flags = rpp.RPP_WANT_CRITICAL_EDGES
+    out = rpp.barcodes_batch(dev, maxdim, thr, flags=flags)
+    for i, n in enumerate(sizes):
+        single = rpp.barcodes_device(dev[i], maxdim, thr[i], flags=flags | rpp.RPP_FORCE_DENSE)
+        _same(out[i], single, "n=%d" % n)
+        _stats_equal(out[i], single, "n=%d" % n, _PATH_FREE)
+    exact = rpp.barcodes_batch(dev, maxdim, thr, flags=flags | rpp.RPP_BATCH_EXACT_SHAPES)
+    for i, n in enumerate(sizes):
+        _stats_equal(out[i], exact[i], "n=%d" % n)
+    for i in (0, 2):
+        exp = oracle.barcodes(clouds[i], sizes[i], maxdim, thr[i], clearing=True)
+        for p in range(maxdim + 1):
+            assert np.array_equal(out[i].bars[p][0].view(np.uint32), exp[p][0].view(np.uint32))
+            assert np.array_equal(out[i].bars[p][1].view(np.uint32), exp[p][1].view(np.uint32))
+
+
+def test_shape_bucket_replays_with_new_sizes(rpp):
+    """The bucket's captured graph replays for a different mix of sizes (the
+    sizes live in device memory): each replay equals the exact-shape path."""
+    for rep, sizes in enumerate([(129, 150, 192), (180, 131, 160), (192, 192, 129)]):
+        clouds = [w.condensed_from_points(w.noisy_circle_points(n, seed=500 + 7 * rep + n))
+                  for n in sizes]
+        dev = [_dev(d) for d in clouds]
+        got = rpp.barcodes_batch(dev, 1)
+        ref = rpp.barcodes_batch(dev, 1, flags=rpp.RPP_BATCH_EXACT_SHAPES)
+        for i in range(len(sizes)):
+            _same(got[i], ref[i], "replay %d n=%d" % (rep, sizes[i]))
+            _stats_equal(got[i], ref[i], "replay %d n=%d" % (rep, sizes[i]))
+
+
+def test_no_radius_infinite_threshold_keeps_exact_shape(rpp):
+    """Threshold +inf without the enclosing radius cannot be padded (padding
+    edges would be within it): such requests run at their exact size and
+    still match the single-cloud path."""
+    clouds = [w.condensed_from_points(w.noisy_torus_points(n, 77 + n)) for n in (30, 41)]
+    dev = [_dev(d) for d in clouds]
+    out = rpp.barcodes_batch(dev, 1, flags=rpp.RPP_NO_ENCLOSING_RADIUS)
+    for i in range(2):
+        _same(out[i], rpp.barcodes_device(dev[i], 1, flags=rpp.RPP_NO_ENCLOSING_RADIUS |
+                                          rpp.RPP_FORCE_DENSE), "cloud %d" % i)
