@@ -300,6 +300,24 @@ int rpp_backward(const float *points_dev, int32_t n, int32_t d, int64_t nbars,
                  const float *grad_birth, const float *grad_death, float *grad_points_dev,
                  void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as rpp_backward, with the same arguments and bitwise the same
+ * result, but the bar arrays are staged in a fixed device array of the
+ * library (RPP_NOALLOC_MAX_BARS bars, 24 bytes each: 6 MiB, held on every
+ * GPU the library runs on until the process ends) instead of library-
+ * allocated device memory; the call makes no device or host allocation.
+ * The caller still provides points_dev and grad_points_dev.
+ * nbars > RPP_NOALLOC_MAX_BARS is RPP_E_RANGE, before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the
+ * same GPU (from several threads or streams) race and must be serialised
+ * by the caller.  Returns after completion, so consecutive calls are safe. */
+#define RPP_NOALLOC_MAX_BARS 262144
+int rpp_backward_noalloc(const float *points_dev, int32_t n, int32_t d, int64_t nbars,
+                         const uint64_t *birth_edge, const uint64_t *death_edge,
+                         const float *grad_birth, const float *grad_death,
+                         float *grad_points_dev, void *hip_stream);
+
 /* ---- serving -------------------------------------------------------------
  * A server runs requests on `slots` concurrent slots, each with its own HIP
  * stream and device workspace, so the GPU stages of different requests

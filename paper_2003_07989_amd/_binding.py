@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpp.so")
 
 RPP_MAX_DIM = 4
+RPP_NOALLOC_MAX_BARS = 262144  # bars rpp_backward_noalloc stages at most
 RPP_NO_ENCLOSING_RADIUS = 0x1
 RPP_WANT_PAIRS = 0x2
 RPP_SORTED_PAIR_STORE = 0x4
@@ -120,6 +121,8 @@ def load() -> ctypes.CDLL:
                                  P(ctypes.c_uint64), P(ctypes.c_uint64), P(ctypes.c_float),
                                  P(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
     lib.rpp_backward.restype = ctypes.c_int
+    lib.rpp_backward_noalloc.argtypes = lib.rpp_backward.argtypes
+    lib.rpp_backward_noalloc.restype = ctypes.c_int
     lib.rpp_barcodes_batch.argtypes = [ctypes.c_int32, P(_Request), ctypes.c_void_p,
                                        ctypes.c_uint32, P(P(_Result))]
     lib.rpp_barcodes_batch.restype = ctypes.c_int
@@ -344,10 +347,11 @@ def pdist_device(points: torch.Tensor, out: torch.Tensor = None, stream=None) ->
 
 
 def backward_points(points: torch.Tensor, birth_edge, death_edge, grad_birth, grad_death,
-                    stream=None, out=None) -> torch.Tensor:
+                    stream=None, out=None, noalloc=False) -> torch.Tensor:
     """rpp_backward: gradient w.r.t. (n, d) float32 CUDA coordinates of a
-    loss whose gradient w.r.t. each bar's (birth, death) is given; out: a
-    preallocated (n, d) float32 result."""
+    loss whose gradient w.r.t. each bar's (birth, death) is given.
+    noalloc=True calls rpp_backward_noalloc (bars staged in the library's
+    fixed device array); out: a preallocated (n, d) float32 result."""
     pts = points.contiguous()
     n, d = pts.shape
     be = np.ascontiguousarray(birth_edge, dtype=np.uint64)
@@ -358,7 +362,7 @@ def backward_points(points: torch.Tensor, birth_edge, death_edge, grad_birth, gr
         out = torch.empty_like(pts)
     U64, F32 = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_float)
     lib = load()
-    fn = lib.rpp_backward
+    fn = lib.rpp_backward_noalloc if noalloc else lib.rpp_backward
     _check(fn(ctypes.c_void_p(pts.data_ptr()), int(n), int(d), int(be.size),
               be.ctypes.data_as(U64), de.ctypes.data_as(U64),
               gb.ctypes.data_as(F32), gd.ctypes.data_as(F32),

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librpp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-DEVICE_SOURCES = ["kernels.hip", "pipeline.hip", "batch.hip"]
+DEVICE_SOURCES = ["kernels.hip", "pipeline.hip", "batch.hip", "noalloc.hip"]
 HOST_SOURCES = ["residual.cpp", "capi.cpp", "serve.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -115,7 +115,7 @@ def test_flag_constants_match_the_header():
     for name, val in defs.items():
         v = int(val, 0)
         assert getattr(B, name) == v, name
-        if name != "RPP_MAX_DIM":
+        if name not in ("RPP_MAX_DIM", "RPP_NOALLOC_MAX_BARS"):
             flags.append(v)
     assert all(f and (f & (f - 1)) == 0 for f in flags)
     assert len(set(flags)) == len(flags)
@@ -165,3 +165,29 @@ def test_workspace_bound_covers_every_buffer_at_its_maximum():
         cmax = max(math.comb(n, k) for k in range(2, maxdim + 2))
         need = n * n * 4 + 4 * 8 * E + cmax * (4 + 8 + 8 + 8 + 8 * 8)
         assert rpp.workspace_bytes(n, maxdim) >= need, (n, maxdim)
+
+
+def test_noalloc_backward_rejects_sizes_beyond_its_scratch():
+    """rpp_backward_noalloc refuses more bars than its fixed device array
+    holds, and bad arguments, before any device work (fake device pointers
+    are never touched)."""
+    import ctypes
+    lib = rpp.load()
+    hdr = open(os.path.join(ROOT, "include", "rpp.h")).read()
+    mx = int(re.search(r"#define RPP_NOALLOC_MAX_BARS (\d+)", hdr).group(1))
+    U64, F32 = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_float)
+    m = mx + 1
+    be = np.zeros(m, np.uint64)
+    g = np.zeros(m, np.float32)
+    fake = ctypes.c_void_p(256)
+    args = (be.ctypes.data_as(U64), be.ctypes.data_as(U64), g.ctypes.data_as(F32),
+            g.ctypes.data_as(F32), fake, None)
+    assert lib.rpp_backward_noalloc(fake, 100, 3, m, *args) == -3
+    assert b"RPP_NOALLOC_MAX_BARS" in lib.rpp_last_error()
+    assert lib.rpp_backward_noalloc(fake, 100, 3, -1, *args) == -1
+    assert lib.rpp_backward_noalloc(None, 100, 3, 5, *args) == -1
+    # an edge index past C(n, 2) with a nonzero gradient
+    be2 = np.array([0, 10 ** 6], np.uint64)
+    g2 = np.ones(2, np.float32)
+    assert lib.rpp_backward_noalloc(fake, 100, 3, 2, be2.ctypes.data_as(U64), be2.ctypes.data_as(U64),
+                                    g2.ctypes.data_as(F32), g2.ctypes.data_as(F32), fake, None) == -1
