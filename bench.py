@@ -740,7 +740,7 @@ def bench_cloud(args, name: str, cpu: bool = True) -> dict:
     if kname == "apparent":
         kfull = apparent_kernel_name(top, g)
     elif g < 0:
-        kfull = "k_ext<%d>+k_clear_filter" % top  # sparse enumeration and clearing
+        kfull = "k_ext<%d> (count + scatter with clearing)" % top  # sparse enumeration
     else:
         kfull = "k_enum_count<%d>+k_enum_scatter<%d>" % (top, top)
     traffic = measured_traffic(name, kfull)
