@@ -138,3 +138,40 @@ def test_rank_coded_keys_match_oracle(driver, mode):
         for p in range(1, maxdim + 1):
             assert got_p[p] == exp_p[p], (name, mode, p)
             assert got_e[p] == exp_e[p], (name, mode, p)
+
+
+@pytest.fixture(scope="module")
+def sanitized_driver():
+    """The same driver and reduction built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only; any report aborts)."""
+    out = os.path.join(tempfile.mkdtemp(prefix="rpp_resdrv_asan_"), "residual_driver")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-pthread", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-o", out,
+           os.path.join(HERE, "host", "residual_driver.cpp"),
+           os.path.join(ROOT, "paper_2003_07989_amd", "csrc", "residual.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("no sanitizer runtime: " + r.stderr[-300:])
+    return out
+
+
+@pytest.mark.parametrize("mode,env", [(0, None), (3, None), (19, None), (7, None),
+                                      (51, {"RPP_RANK_KEYS": "1"}),
+                                      (3, {"RPP_WIDE_KEYS": "1"})],
+                         ids=["plain", "late-drops", "bitsets-late-drops",
+                              "late-drops-oblivious", "ranks-bitsets-late-drops", "wide-keys"])
+def test_host_reduction_is_sanitizer_clean(sanitized_driver, mode, env):
+    """Every schedule and key layout of the host reduction under ASan and
+    UBSan, on a dense and a thresholded input: no report, and the oracle's
+    pairs."""
+    for name, build, n, maxdim, thr in (CASES[0], CASES[4]):
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        e = dict(env or {}, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+                 UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+        got_p, got_e = _run(sanitized_driver, d, n, maxdim, thr, mode, env=e)
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, p)
+            assert got_e[p] == exp_e[p], (name, mode, p)
