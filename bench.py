@@ -53,11 +53,14 @@ def algorithmic_bytes_apparent(st: dict, p: int) -> float:
 
 def apparent_kernel_name(p, g):
     """The apparent kernel a dimension ran, from its apparent_group stat:
-    negative for the sparse kernel, 100 K + G for the two-phase kernel,
+    negative for the sparse kernels (-(100 K + G) for the two-phase one),
+    100 K + G for the two-phase kernel,
     10000 + 100 K + G for its workgroup-pooled form, 20000 + 100 NB + G
     for the pooled form with vector reads of its first NB blocks of four
     candidates (NB = 0 meaning 2)."""
     if g < 0:
+        if -g >= 100:
+            return "k_apparent_sparse2<%d,%d,%d>" % (p, -g // 100, -g % 100)
         return "k_apparent_sparse<%d,%d>" % (p, -g)
     if g >= 20000:
         nb = (g - 20000) // 100

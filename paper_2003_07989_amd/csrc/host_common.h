@@ -254,10 +254,46 @@ struct GpuTimer {
     }
 };
 
+// Distances as the host sees them: the n x n matrix, or, on the sparse
+// path, packed neighbour rows -- bits (n x words u64: the neighbours of each
+// vertex), npre (n x words u32: position in nbd of each word's first
+// neighbour) and nbd (the neighbours' distances, row after row, ascending).
+// Packed rows answer only for pairs within the threshold, which is every
+// pair a simplex within the threshold has.
+struct HostDist {
+    const float *dsq = nullptr;
+    int n = 0;
+    const uint64_t *bits = nullptr;
+    const uint32_t *npre = nullptr;
+    const float *nbd = nullptr;
+    int words = 0;
+    float operator()(int a, int b) const
+    {
+        if (!nbd)
+            return dsq[(size_t)a * n + b];
+        if (a == b)
+            return 0.0f;
+        const size_t k = (size_t)a * words + (size_t)(b >> 6);
+        return nbd[npre[k] + (uint32_t)__builtin_popcountll(bits[k] & ((1ull << (b & 63)) - 1))];
+    }
+};
+
+// npre of packed rows from their bitsets: per vertex, a running count of
+// neighbours over the words (out: n * words entries).
+inline void packed_row_prefix(const uint64_t *bits, int n, int words, uint32_t *out)
+{
+    uint32_t run = 0;
+    for (size_t k = 0; k < (size_t)n * words; ++k) {
+        out[k] = run;
+        run += (uint32_t)__builtin_popcountll(bits[k]);
+    }
+}
+
 // Longest edge of the q-simplex c (cidx), the one of largest edge cidx
 // among equally long edges.
-inline uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, uint64_t c, int q)
+inline uint64_t critical_edge(const HostDist &D, const uint64_t *binom, uint64_t c, int q)
 {
+    const int n = D.n;
     int v[8];
     int hi = n;
     for (int pos = 0; pos <= q; ++pos) {
@@ -278,7 +314,7 @@ inline uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, ui
     uint64_t be = UINT64_MAX;
     for (int i = 0; i <= q; ++i)
         for (int j = i + 1; j <= q; ++j) {
-            const float e = dsq[(size_t)v[i] * n + v[j]];
+            const float e = D(v[i], v[j]);
             const uint64_t ec = (uint64_t)v[i] * (v[i] - 1) / 2 + (uint64_t)v[j];  // v[i] > v[j]
             if (e > best || (e == best && ec > be)) {
                 best = e;
@@ -286,6 +322,14 @@ inline uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, ui
             }
         }
     return be;
+}
+
+inline uint64_t critical_edge(const float *dsq, int n, const uint64_t *binom, uint64_t c, int q)
+{
+    HostDist D;
+    D.dsq = dsq;
+    D.n = n;
+    return critical_edge(D, binom, c, q);
 }
 
 inline int bit_length(uint64_t x)

@@ -99,6 +99,15 @@ void launch_enum_count(const EnumArgs &a, uint32_t *tile_counts,
 void launch_enum_scatter(const EnumArgs &a, const uint64_t *tile_offsets, float *out_diam,
                          uint64_t *out_cidx, hipStream_t s, uint64_t *out_vtx = nullptr);
 
+// One pass for a single cloud whose outputs hold every candidate: the kept
+// simplices as launch_enum_scatter writes them, each tile's offset found by
+// a decoupled look-back over the tiles before it (no count pass, no scan).
+// status: tiles + 1 words of scratch (cleared here); *total (device) gets
+// the kept count.  Statistics are not counted.
+void launch_enum_onepass(const EnumArgs &a, unsigned long long *status, uint64_t *total,
+                         float *out_diam, uint64_t *out_cidx, hipStream_t s,
+                         uint64_t *out_vtx = nullptr);
+
 // ---- a5: apparent-pair test -----------------------------------------------
 // tau_out[i] = cidx of the apparent partner of column i, or ~0 when the
 // column is not apparent.  group = lanes cooperating on one column.  When
@@ -222,8 +231,11 @@ void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_di
                         float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
                         uint64_t *kept_vtx, hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
-// neighbours of the column's vertices, scanned from the top, `group` words
-// per step by as many lanes (4, 8 or 16; anything else means 4).
+// neighbours of the column's vertices, scanned from the top.  group = G in
+// {4, 8, 16}: G words per step by as many lanes per column; group = 100 K +
+// G (K in {1, 2, 4}, G in {4, 8}): the two-phase form, each lane alone on
+// its column's top K words first, then G lanes per column still open.
+// Anything else means the default, 404.
 int sparse_group(int group);
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                             int n, int p, int words, const uint4 *nbw, const float *nbd,

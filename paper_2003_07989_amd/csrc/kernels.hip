@@ -621,6 +621,147 @@ __global__ __launch_bounds__(CT) void k_enum_scatter(EnumArgs a0,
     }
 }
 
+// One-pass enumeration (a single cloud whose outputs are sized for every
+// candidate): the scatter pass above with its tile offset found by a
+// decoupled look-back instead of a separate count pass and scan.  A
+// workgroup takes its tile from a ticket counter (status[tiles]), so tiles
+// start in ticket order; it evaluates its candidates, publishes its kept
+// count (flag AGG), then adds up the published counts of the tiles before
+// it, walking back until one that has published its inclusive prefix (flag
+// PRE), publishes its own prefix and writes at its offset.  A tile waits
+// only on tiles with smaller tickets, which are running and publish their
+// counts before they wait on anything, so every wait ends.  status must be
+// zero before the launch; the last tile writes the kept total to *total.
+constexpr uint64_t LB_AGG = 1ull << 62, LB_PRE = 2ull << 62, LB_VAL = (1ull << 62) - 1;
+
+template <int P>
+__global__ __launch_bounds__(CT) void k_enum_onepass(EnumArgs a,
+                                                     unsigned long long *__restrict__ status,
+                                                     int64_t tiles, uint64_t *__restrict__ total,
+                                                     float *__restrict__ out_diam,
+                                                     uint64_t *__restrict__ out_cidx,
+                                                     uint64_t *__restrict__ out_vtx)
+{
+    __shared__ uint32_t wsum[CT / WAVE];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_base;
+    if (threadIdx.x == 0)
+        s_tile = (uint32_t)atomicAdd(&status[tiles], 1ull);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const Binom B{a.binom, a.n + 1};
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const uint64_t c0 = (uint64_t)tile * COMPACT_TILE + (uint64_t)wave * (CI * WAVE) + lane;
+    float dk[CI];
+    uint64_t vk[P <= 3 ? CI : 1];
+    const bool want_vtx = P >= 2 && P <= 3 && out_vtx != nullptr;
+    uint32_t bits = 0;
+    uint32_t cnt = 0;  // kept by the wave
+    if (P == 1) {
+#pragma unroll
+        for (int k = 0; k < CI; ++k) {
+            const uint64_t c = c0 + (uint64_t)k * WAVE;
+            dk[k] = c < a.ncand ? a.dcond[c] + 0.0f : 0.0f;
+        }
+    } else if (c0 < a.ncand) {
+        constexpr int S = EnumChunk<P>::S;
+        EnumWalk<P> wk;
+        decode<P>(B, c0, a.n, wk.v);
+#pragma unroll
+        for (int k0 = 0; k0 < CI; k0 += S) {
+            float d[S];
+            if (P <= 3 && want_vtx) {
+                uint64_t x[S];
+                enum_chunk<P, S, true>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d, x);
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+                    vk[P <= 3 ? k0 + q : 0] = x[q];
+            } else {
+                enum_chunk<P, S>(wk, B, a, c0 + (uint64_t)k0 * WAVE, k0, d);
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                dk[k0 + q] = d[q];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+        const uint64_t c = c0 + (uint64_t)k * WAVE;
+        const bool keep = c < a.ncand && enum_filter(a, c, dk[k]) == 0;
+        bits |= (keep ? 1u : 0u) << k;
+        cnt += (uint32_t)__popcll(__ballot(keep));
+    }
+    if (lane == 0)
+        wsum[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t agg = 0;
+#pragma unroll
+        for (int w = 0; w < CT / WAVE; ++w)
+            agg += wsum[w];
+        uint64_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&status[0], LB_PRE | agg, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[tile], LB_AGG | agg, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int64_t j = (int64_t)tile - 1;;) {
+                const unsigned long long st =
+                    __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if ((st & ~LB_VAL) == 0) {
+                    __builtin_amdgcn_s_sleep(1);  // not yet published
+                    continue;
+                }
+                excl += st & LB_VAL;
+                if (st & LB_PRE)
+                    break;
+                --j;
+            }
+            __hip_atomic_store(&status[tile], LB_PRE | (excl + agg), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if ((int64_t)tile == tiles - 1)
+            *total = excl + agg;
+        s_base = excl;
+    }
+    __syncthreads();
+    uint64_t running = s_base;
+#pragma unroll
+    for (int w = 0; w < CT / WAVE; ++w)
+        running += (w < wave) ? wsum[w] : 0;
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+        const bool keep = (bits >> k) & 1u;
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const uint64_t pos = running + (uint32_t)__popcll(m & lanemask_lt());
+            out_diam[pos] = dk[k];
+            out_cidx[pos] = c0 + (uint64_t)k * WAVE;
+            if (P <= 3 && want_vtx)
+                out_vtx[pos] = vk[P <= 3 ? k : 0];
+        }
+        running += (uint32_t)__popcll(m);
+    }
+}
+
+void launch_enum_onepass(const EnumArgs &a, unsigned long long *status, uint64_t *total,
+                         float *out_diam, uint64_t *out_cidx, hipStream_t s, uint64_t *out_vtx)
+{
+    const int64_t tiles = compact_tiles((int64_t)a.ncand);
+    if (tiles == 0)
+        return;
+    // status: tiles flag words and the ticket counter, all zero
+    launch_fill_u32(reinterpret_cast<uint32_t *>(status), 2 * (tiles + 1), 0u, s);
+    dim3 g((unsigned)tiles), b(CT);
+    switch (a.p) {
+    case 1: hipLaunchKernelGGL(k_enum_onepass<1>, g, b, 0, s, a, status, tiles, total, out_diam, out_cidx, nullptr); break;
+    case 2: hipLaunchKernelGGL(k_enum_onepass<2>, g, b, 0, s, a, status, tiles, total, out_diam, out_cidx, out_vtx); break;
+    case 3: hipLaunchKernelGGL(k_enum_onepass<3>, g, b, 0, s, a, status, tiles, total, out_diam, out_cidx, out_vtx); break;
+    default: hipLaunchKernelGGL(k_enum_onepass<4>, g, b, 0, s, a, status, tiles, total, out_diam, out_cidx, nullptr); break;
+    }
+}
+
 #define RPP_DISPATCH_P(p, F, ...)                                                        \
     switch (p) {                                                                         \
     case 1: F<1> __VA_ARGS__; break;                                                     \
@@ -2359,6 +2500,54 @@ void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_di
                    kept_cidx, kept_cap, kept_vtx)
 }
 
+// Youngest-facet condition of the apparent pairs lemma for sigma (vertices
+// v, diameter d) and its oldest cofacet sigma + {w}, e[i] = d(v_i, w): no
+// facet sigma - {v_j} + {w} with v_j > w (those precede sigma) has diameter
+// d.  The distances among sigma's own vertices (all within the threshold)
+// are read from the packed rows, and only when some v_j lies above w.
+template <int P>
+__device__ __forceinline__ bool apparent_facets_ok(const uint4 *__restrict__ nbw,
+                                                   const float *__restrict__ nbd, int words,
+                                                   const int (&v)[P + 1], float d, int w,
+                                                   const float (&e)[P + 1])
+{
+    bool need = false;
+#pragma unroll
+    for (int j = 0; j <= P; ++j)
+        need = need || v[j] > w;
+    if (!need)
+        return true;
+    float dv[P + 1][P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+#pragma unroll
+        for (int b = a + 1; b <= P; ++b) {
+            uint64_t wb;
+            uint32_t wp;
+            nb_word(nbw, (int64_t)v[a] * words + (v[b] >> 6), wb, wp);
+            dv[a][b] = nb_dist(nbd, wp, wb, v[b] & 63);
+        }
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        if (v[j] > w) {
+            float fd = 0.0f;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {
+                if (a == j)
+                    continue;
+                fd = fmaxf(fd, e[a]);
+#pragma unroll
+                for (int b = a + 1; b <= P; ++b)
+                    if (b != j)
+                        fd = fmaxf(fd, dv[a][b]);
+            }
+            if (fd == d)
+                return false;
+        }
+    }
+    return true;
+}
+
 // Sparse apparent test.  The candidates for sigma's oldest cofacet are the
 // common neighbours of its vertices: the AND of their neighbour bitsets,
 // which leaves out sigma's own vertices.  Layout as in the dense kernel: a
@@ -2536,6 +2725,196 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         tau_out[mycol] = mytau;
 }
 
+// Two-phase sparse apparent test.  Phase 1: every lane takes its own
+// column and scans the top K bitset words of its vertices (all K (P+1)
+// records loaded at once), testing the common neighbours word by word from
+// the top; a column decides there unless none of them passes.  Phase 2: the
+// columns still open (no hit in the K words, words left below) are numbered
+// within the wave and scanned G lanes per column from word words-1-K down,
+// exactly as k_apparent_sparse scans.  One wave owns 64 consecutive columns,
+// so the per-column work of phase 1 (shuffles, facet test, cofacet index)
+// runs once per 64 columns instead of once per 64/G.
+template <int P, int K, int G>
+__global__ __launch_bounds__(256) void k_apparent_sparse2(
+    const float *__restrict__ col_diam, const uint64_t *__restrict__ col_cidx, int64_t ncols,
+    int n, int words, const uint4 *__restrict__ nbw, const float *__restrict__ nbd,
+    const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
+    unsigned long long *__restrict__ scan_count, const uint64_t *__restrict__ col_vtx)
+{
+    constexpr int CPR = WAVE / G;  // open columns per round of phase 2
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = ((blk * blockDim.x + threadIdx.x) / WAVE) * WAVE;
+    if (base >= ncols)
+        return;  // whole waves leave together
+    const Binom B{binom, n + 1};
+    const int64_t mycol = base + lane;
+    const bool myvalid = mycol < ncols;
+    float myd = 0.0f;
+    int myv[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        myv[i] = 0;
+    if (myvalid) {
+        myd = col_diam[mycol];
+        if (P <= 3 && col_vtx) {
+            const uint64_t x = col_vtx[mycol];
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                myv[i] = (int)((x >> (16 * i)) & 0xffffu);
+        } else {
+            decode<P>(B, col_cidx[mycol], n, myv);
+        }
+    }
+    unsigned long long examined = 0;  // this lane's share of the candidates visited
+
+    // ---- phase 1: the top K words of the lane's own column ----
+    int w = -1;
+    float ew[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+        ew[i] = 0.0f;
+    if (myvalid) {
+        uint64_t bw[K][P + 1];
+        uint32_t pw[K][P + 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int word = words - 1 - k;
+#pragma unroll
+            for (int i = 0; i <= P; ++i) {
+                bw[k][i] = 0;
+                pw[k][i] = 0;
+                if (word >= 0)
+                    nb_word(nbw, (int64_t)myv[i] * words + word, bw[k][i], pw[k][i]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int word = words - 1 - k;
+            uint64_t m = ~0ull;
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                m &= bw[k][i];
+            while (m && w < 0) {
+                const int b = 63 - __clzll((long long)m);
+                bool ok = true;
+                float t[P + 1];
+#pragma unroll
+                for (int i = 0; i <= P; ++i) {
+                    t[i] = nb_dist(nbd, pw[k][i], bw[k][i], b);
+                    ok = ok && (t[i] <= myd);
+                }
+                ++examined;
+                if (ok) {
+                    w = word * 64 + b;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i)
+                        ew[i] = t[i];
+                }
+                m &= ~(1ull << b);
+            }
+        }
+    }
+    // open: no hit in the K words and words left below them
+    const bool open = myvalid && w < 0 && words - 1 - K >= 0;
+    const uint64_t omask = __ballot(open);
+
+    // ---- phase 2: open columns, G lanes each, from word words-1-K down ----
+    const int nopen = __popcll(omask);
+    uint64_t tau2 = NONE;  // this lane's tau when its column was open
+    for (int r = 0; r * CPR < nopen; ++r) {
+        const int t = r * CPR + grp;
+        const bool valid = t < nopen;  // uniform in the group
+        const int src = valid ? select_set_bit(omask, t) : lane;
+        const float d = __shfl(myd, src, WAVE);
+        int v[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            v[i] = __shfl(myv[i], src, WAVE);
+        int x = -1;  // this lane's hit in the current step
+        int hit = -1;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = words - 1 - K; top >= 0; top -= G) {
+                const int word = top - g;
+                uint64_t m = 0, bw[P + 1];
+                uint32_t pw[P + 1];
+                if (word >= 0) {
+                    m = ~0ull;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        nb_word(nbw, (int64_t)v[i] * words + word, bw[i], pw[i]);
+                        m &= bw[i];
+                    }
+                }
+                unsigned tested = 0;
+                for (uint64_t mm = m; mm;) {
+                    const int b = 63 - __clzll((long long)mm);
+                    bool ok = true;
+                    float tt[P + 1];
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        tt[i] = nb_dist(nbd, pw[i], bw[i], b);
+                        ok = ok && (tt[i] <= d);
+                    }
+                    ++tested;
+                    if (ok) {
+                        x = word * 64 + b;
+#pragma unroll
+                        for (int i = 0; i <= P; ++i)
+                            e[i] = tt[i];
+                        break;
+                    }
+                    mm &= ~(1ull << b);
+                }
+                const uint64_t hm = __ballot(x >= 0) & gmask;
+                const int hl = hm ? __ffsll((unsigned long long)hm) - 1 - gbase : G;
+                if (scan_count)
+                    examined += g < hl ? (unsigned)__popcll(m) : (g == hl ? tested : 0u);
+                if (hm) {
+                    hit = gbase + hl;
+                    break;
+                }
+            }
+        }
+        const int ww = __shfl(x, hit >= 0 ? hit : lane, WAVE);
+        float eh[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            eh[i] = __shfl(e[i], hit >= 0 ? hit : lane, WAVE);
+        uint64_t tau = NONE;
+        if (hit >= 0 && apparent_facets_ok<P>(nbw, nbd, words, v, d, ww, eh))
+            tau = cofacet_index<P>(B, v, ww);
+        // the owner of open column t is the t-th set lane of omask; group
+        // (t mod CPR)'s first lane holds its tau
+        const int mine = open ? __popcll(omask & lanemask_lt()) : -1;
+        const int from = mine >= 0 ? (mine % CPR) * G : lane;
+        const uint64_t tt = shfl_u64(tau, from);
+        if (mine >= 0 && mine / CPR == r)
+            tau2 = tt;
+    }
+    if (scan_count) {
+        const unsigned long long tot = wave_sum(examined);
+        if (lane == 0)
+            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], tot);
+    }
+    if (!myvalid)
+        return;
+    uint64_t mytau = NONE;
+    if (open)
+        mytau = tau2;
+    else if (w >= 0 && apparent_facets_ok<P>(nbw, nbd, words, myv, myd, w, ew))
+        mytau = cofacet_index<P>(B, myv, w);
+    tau_out[mycol] = mytau;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_lows_sparse(
     const uint64_t *__restrict__ na_key, const uint64_t *__restrict__ na_cidx, int64_t ncols,
@@ -2608,23 +2987,55 @@ static void launch_apparent_sparse_pg(const float *cd, const uint64_t *cc, int64
                        binom, tau, sc, rounds, cv);
 }
 
+template <int P, int K, int G>
+static void launch_apparent_sparse2_pkg(const float *cd, const uint64_t *cc, int64_t ncols, int n,
+                                        int words, const uint4 *nbw, const float *nbd,
+                                        const uint64_t *binom, uint64_t *tau,
+                                        unsigned long long *sc, hipStream_t s,
+                                        const uint64_t *cv)
+{
+    const int64_t waves = (ncols + WAVE - 1) / WAVE;
+    dim3 g((unsigned)((waves * WAVE + 255) / 256)), b(256);
+    hipLaunchKernelGGL((k_apparent_sparse2<P, K, G>), g, b, 0, s, cd, cc, ncols, n, words, nbw,
+                       nbd, binom, tau, sc, cv);
+}
+
 template <int P>
 static void launch_apparent_sparse_p(const float *cd, const uint64_t *cc, int64_t ncols, int n,
                                      int words, const uint4 *nbw, const float *nbd,
                                      const uint64_t *binom, int group, uint64_t *tau,
                                      unsigned long long *sc, hipStream_t s, const uint64_t *cv)
 {
+#define RPP_AS2(K, G) launch_apparent_sparse2_pkg<P, K, G>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv)
     switch (group) {
     case 16: launch_apparent_sparse_pg<P, 16>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
     case 8: launch_apparent_sparse_pg<P, 8>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
+    case 104: RPP_AS2(1, 4); break;
+    case 108: RPP_AS2(1, 8); break;
+    case 204: RPP_AS2(2, 4); break;
+    case 208: RPP_AS2(2, 8); break;
+    case 404: RPP_AS2(4, 4); break;
+    case 408: RPP_AS2(4, 8); break;
     default: launch_apparent_sparse_pg<P, 4>(cd, cc, ncols, n, words, nbw, nbd, binom, tau, sc, s, cv); break;
+    }
+#undef RPP_AS2
+}
+
+// Sparse kernel forms: G in {4, 8, 16} lanes per column (k_apparent_sparse),
+// or 100 K + G, K in {1, 2, 4}, G in {4, 8} (the two-phase
+// k_apparent_sparse2); anything else means the default.
+constexpr int SPARSE_DEFAULT = 404;
+int sparse_group(int group)
+{
+    switch (group) {
+    case 4: case 8: case 16:
+    case 104: case 108: case 204: case 208: case 404: case 408:
+        return group;
+    default:
+        return SPARSE_DEFAULT;
     }
 }
 
-int sparse_group(int group)
-{
-    return (group == 8 || group == 16) ? group : 4;
-}
 
 void launch_apparent_sparse(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
                             int n, int p, int words, const uint4 *nbw, const float *nbd,

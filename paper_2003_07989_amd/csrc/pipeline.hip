@@ -72,8 +72,10 @@ struct Workspace {
     DevBuf ekey, eval, ekey2, eval2;  // edges for H0
     DevBuf mst, deaths, dedges, ufs;
     DevBuf tcount, toff, scan;
+    DevBuf lookback;                 // one-pass enumeration: tile flags + ticket
     DevBuf skd[2], skc[2];           // sparse path: all simplices <= thr, previous dim
     DevBuf ndeg, noff, nbw, nbd;     // sparse path: packed neighbour rows
+    DevBuf hnbd;                     // sparse path: the host's packed rows (rank-coded)
     DevBuf rflags, rexcl, rmat, rvals;  // sparse path: rank-coded diameters
     DevBuf bits;                     // sparse path: neighbour bitsets
     DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
@@ -93,6 +95,8 @@ struct Workspace {
     HostBuf h_app_tau[2], h_app_sigma[2], h_na_key[2], h_na_cidx[2], h_low[2], h_lowd[2];
     HostBuf h_small;
     HostBuf h_dsq, h_bits;           // pinned host copies for the residual reduction
+    HostBuf h_nbd;                   // sparse path: packed rows for the host
+    std::vector<uint32_t> h_npre;    // and their per-word positions
     int binom_n = -1, binom_k = -1;
     std::vector<uint64_t> binom_host;
 };
@@ -103,8 +107,8 @@ static std::vector<DevBuf *> device_buffers(Workspace &w)
 {
     return {&w.dsq,     &w.rowmax,  &w.scal,    &w.binom,  &w.ekey,   &w.eval,    &w.ekey2,
             &w.eval2,   &w.mst,     &w.deaths,  &w.dedges, &w.ufs,    &w.tcount,  &w.toff,
-            &w.scan,    &w.ndeg,    &w.noff,    &w.skd[0], &w.skd[1], &w.skc[0],  &w.skc[1],
-            &w.nbw,     &w.nbd,     &w.rflags,  &w.rexcl,  &w.rmat,   &w.rvals,   &w.bits,
+            &w.scan,    &w.lookback, &w.ndeg,    &w.noff,    &w.skd[0], &w.skd[1], &w.skc[0],  &w.skc[1],
+            &w.nbw,     &w.nbd,     &w.hnbd,    &w.rflags,  &w.rexcl,  &w.rmat,   &w.rvals,   &w.bits,
             &w.clr,     &w.clr2,    &w.clrv,    &w.clrv2,  &w.cdiam,  &w.ccidx,   &w.tau,
             &w.akey,    &w.aval,    &w.akey2,   &w.aval2,  &w.nkey,   &w.nval,    &w.nkey2,
             &w.nval2,   &w.clear,   &w.next,    &w.hostpiv, &w.lowc,  &w.lowd,    &w.gedges,
@@ -157,6 +161,7 @@ static void plan_limits(Workspace &w, int n, int maxdim)
     w.tcount.hint = (std::max(tiles, cpre) + 1) * 4;
     w.toff.hint = (std::max(tiles, cpre) + 2) * 8;
     w.scan.hint = (size_t)scan_scratch_words((int64_t)scan_n) * 8;
+    w.lookback.hint = (std::max(tiles, (uint64_t)compact_tiles((int64_t)E)) + 2) * 8;
     w.cdiam.hint = (cmax + 1) * 4;
     w.ccidx.hint = w.cvtx.hint = (cmax + 1) * 8;
     w.tau.hint = w.akey.hint = w.aval.hint = w.akey2.hint = w.aval2.hint = (cmax + 1) * 8;
@@ -173,7 +178,7 @@ static void plan_limits(Workspace &w, int n, int maxdim)
         w.ndeg.hint = (nn + 1) * 4;
         w.noff.hint = (nn + 2) * 8;
         w.nbw.hint = nn * (size_t)words * 16;
-        w.nbd.hint = (2 * E + 1) * 4;
+        w.nbd.hint = w.hnbd.hint = (2 * E + 1) * 4;
         w.rflags.hint = (E + 1) * 4;
         w.rexcl.hint = (E + 2) * 8;
         w.rmat.hint = nn * nn * 4;
@@ -391,6 +396,28 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
         }
         return RPP_OK;
     };
+    // One pass (decoupled look-back) when the outputs are sized up front and
+    // the thresholded / cleared counts come from the clearing set's size;
+    // RPP_ENUM_TWO_PASS=1 keeps the count + scan + scatter passes.
+    const char *tp = getenv("RPP_ENUM_TWO_PASS");
+    if (upfront && ncleared >= 0 && ea.nbatch <= 1 && !(tp && atoi(tp) != 0)) {
+        ALLOC_TRY(ws.lookback, (size_t)(tiles + 2) * 8);
+        if (tm)
+            tm->start();
+        launch_enum_onepass(ea, ws.lookback.as<unsigned long long>(),
+                            ws.toff.as<uint64_t>() + tiles, ws.cdiam.as<float>(),
+                            ws.ccidx.as<uint64_t>(), s,
+                            ws.cvtx_ok ? ws.cvtx.as<uint64_t>() : nullptr);
+        if (tm)
+            tm->stop();
+        if (tiles == 0) {
+            *kept = 0;
+            *nthr = 0;
+            *nclr = (uint64_t)ncleared;
+            return RPP_OK;
+        }
+        return read_counts();
+    }
     if (tm)
         tm->start();
     launch_enum_count(ea, ws.tcount.as<uint32_t>(), ncleared >= 0 ? nullptr : stats, s);
@@ -716,17 +743,12 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     const int bstride = n + 1;
     (void)bstride;
 
-    // host copy of the square matrix for the residual reduction (pinned,
-    // grow-only); filled below, once the path is chosen: with rank-coded
-    // diameters it receives the rank matrix instead of the distances
+    // The host's view of the distances for the residual reduction, set
+    // once the path is chosen: the square matrix (dense path), or packed
+    // neighbour rows (sparse path; with rank-coded diameters, of the ranks).
     const float *h_dsq = nullptr;
-    if (maxdim >= 1) {
-        if (!ws.h_dsq.ensure((size_t)n * n * 4)) {
-            err = "hipHostMalloc of the host distance copy failed";
-            return RPP_E_NOMEM;
-        }
-        h_dsq = ws.h_dsq.as<float>();
-    }
+    HostDist hdist;
+    hdist.n = n;
 
     // ---------------- a2: H0 ---------------------------------------------
     FAULT_POINT("h0");
@@ -880,8 +902,6 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             launch_rank_matrix(h0_keys, h0_cidx, ws.rflags.as<uint32_t>(),
                                ws.rexcl.as<uint64_t>(), nedges, n, (float)nranks,
                                ws.rmat.as<float>(), ws.rvals.as<float>(), s);
-            HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.rmat.p, (size_t)n * n * 4,
-                                   hipMemcpyDeviceToHost, s));
             rank_vals.resize((size_t)nranks);
             HIP_TRY(hipMemcpyAsync(rank_vals.data(), ws.rvals.p, (size_t)nranks * 4,
                                    hipMemcpyDeviceToHost, s));
@@ -889,9 +909,44 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             ranks = true;
         }
     }
-    if (maxdim >= 1 && !ranks)
-        HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ws.dsq.p, (size_t)n * n * 4, hipMemcpyDeviceToHost,
-                               s));
+    // Host distances.  Sparse path: packed rows, 2E values (2.7 MB on the
+    // 4096-point sphere instead of a 67 MB matrix), which the host's caches
+    // hold; RPP_HOST_MATRIX=1 sends the square matrix instead (comparison).
+    const char *hm_env = getenv("RPP_HOST_MATRIX");
+    const bool host_packed = sparse && !(hm_env && atoi(hm_env) != 0);
+    if (maxdim >= 1 && host_packed) {
+        const float *src = ws.nbd.as<float>();
+        if (ranks) {  // the same rows over the rank matrix
+            ALLOC_TRY(ws.hnbd, (size_t)(2 * nedges + 1) * 4);
+            launch_nbr_pack(ws.rmat.as<float>(), ws.bits.as<uint64_t>(), n, words,
+                            ws.noff.as<uint64_t>(), ws.nbw.as<uint4>(), ws.hnbd.as<float>(),
+                            (uint64_t)(2 * nedges), s);
+            src = ws.hnbd.as<float>();
+        }
+        if (!ws.h_nbd.ensure((size_t)(2 * nedges + 1) * 4)) {
+            err = "hipHostMalloc of the host neighbour rows failed";
+            return RPP_E_NOMEM;
+        }
+        if (nedges)
+            HIP_TRY(hipMemcpyAsync(ws.h_nbd.p, src, (size_t)(2 * nedges) * 4,
+                                   hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the bitsets too, for the positions
+        ws.h_npre.resize((size_t)n * words);
+        packed_row_prefix(h_bits, n, words, ws.h_npre.data());
+        hdist.bits = h_bits;
+        hdist.npre = ws.h_npre.data();
+        hdist.nbd = ws.h_nbd.as<float>();
+        hdist.words = words;
+    } else if (maxdim >= 1) {
+        if (!ws.h_dsq.ensure((size_t)n * n * 4)) {
+            err = "hipHostMalloc of the host distance copy failed";
+            return RPP_E_NOMEM;
+        }
+        h_dsq = ws.h_dsq.as<float>();
+        HIP_TRY(hipMemcpyAsync(ws.h_dsq.p, ranks ? ws.rmat.p : ws.dsq.p, (size_t)n * n * 4,
+                               hipMemcpyDeviceToHost, s));
+        hdist.dsq = h_dsq;
+    }
     int rank_bits = 0;
     while (ranks && ((uint64_t)1 << rank_bits) <= (uint64_t)nranks)
         ++rank_bits;
@@ -964,15 +1019,15 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             if (RR.death[i] > RR.birth[i]) {
                 Dq.birth.push_back(length_of(RR.birth[i]));
                 Dq.death.push_back(length_of(RR.death[i]));
-                Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+                Dq.birth_edge.push_back(critical_edge(hdist, ws.binom_host.data(),
                                                       RR.sigma[i], q));
-                Dq.death_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+                Dq.death_edge.push_back(critical_edge(hdist, ws.binom_host.data(),
                                                       RR.tau[i], q + 1));
             }
         for (size_t i = 0; i < RR.ess_sigma.size(); ++i) {
             Dq.birth.push_back(length_of(RR.ess_birth[i]));
             Dq.death.push_back(INFINITY);
-            Dq.birth_edge.push_back(critical_edge(h_dsq, n, ws.binom_host.data(),
+            Dq.birth_edge.push_back(critical_edge(hdist, ws.binom_host.data(),
                                                   RR.ess_sigma[i], q));
             Dq.death_edge.push_back(UINT64_MAX);
         }
@@ -1179,6 +1234,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         H.P.p = p;
         H.P.thr = thr;
         H.P.dsq = h_dsq;
+        H.P.npre = hdist.npre;
+        H.P.nbd = hdist.nbd;
         H.P.binom = ws.binom_host.data();
         H.P.bits = sparse ? h_bits : nullptr;
         H.P.words = sparse ? words : 0;

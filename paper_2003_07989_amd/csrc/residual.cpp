@@ -754,7 +754,16 @@ struct Ctx {
     }
 
     uint64_t C(int v, int k) const { return P.binom[(int64_t)k * (n + 1) + v]; }
-    float D(int a, int b) const { return P.dsq[(int64_t)a * n + b]; }
+    float D(int a, int b) const
+    {
+        if (!P.nbd)
+            return P.dsq[(int64_t)a * n + b];
+        if (a == b)
+            return 0.0f;
+        const int64_t k = (int64_t)a * P.words + (b >> 6);
+        return P.nbd[P.npre[k] + (uint32_t)__builtin_popcountll(P.bits[k] &
+                                                                 ((1ull << (b & 63)) - 1))];
+    }
 
     // vertices of a simplex with q+1 vertices, decreasing
     void decode(uint64_t c, int q, int *v) const
@@ -843,7 +852,7 @@ struct Ctx {
             }
             const float *rows[8];
             for (int i = 0; i < nv; ++i)
-                rows[i] = P.dsq + (int64_t)v[i] * n;
+                rows[i] = P.nbd ? nullptr : P.dsq + (int64_t)v[i] * n;
             const uint64_t *brow[8];  // C(., k+1) for each gap k
             for (int k = 0; k <= nv; ++k)
                 brow[k] = P.binom + (int64_t)(k + 1) * (n + 1);
@@ -867,6 +876,12 @@ struct Ctx {
                 uint64_t m = bv[0][wd];
                 for (int i = 1; i < nv; ++i)
                     m &= bv[i][wd];
+                // packed rows: each vertex's distances of this word's
+                // neighbours start at its prefix position
+                const float *nrow[8];
+                if (P.nbd && m)
+                    for (int i = 0; i < nv; ++i)
+                        nrow[i] = P.nbd + P.npre[(int64_t)v[i] * P.words + wd];
                 while (m) {
                     const int b = 63 - __builtin_clzll(m);
                     m &= ~(1ull << b);
@@ -874,9 +889,17 @@ struct Ctx {
                     while (k > 0 && u[k - 1] > w)
                         --k;
                     float nd = d;
-                    for (int i = 0; i < nv; ++i) {
-                        const float e = rows[i][w];
-                        nd = e > nd ? e : nd;
+                    if (P.nbd) {
+                        const uint64_t below = (1ull << b) - 1;
+                        for (int i = 0; i < nv; ++i) {
+                            const float e = nrow[i][__builtin_popcountll(bv[i][wd] & below)];
+                            nd = e > nd ? e : nd;
+                        }
+                    } else {
+                        for (int i = 0; i < nv; ++i) {
+                            const float e = rows[i][w];
+                            nd = e > nd ? e : nd;
+                        }
                     }
                     const K key = pack_key<K>(kc, nd, base[k] + brow[k][w]);
                     out[neq] = key;
@@ -996,13 +1019,31 @@ struct Ctx {
                 uint64_t m = ~0ull;
                 for (int i = 0; i <= p; ++i)
                     m &= P.bits[(int64_t)s[i] * P.words + k];
+                if (!m)
+                    continue;
+                // packed rows: this word's distances of each vertex
+                const float *nrow[8];
+                uint64_t nb[8];
+                if (P.nbd)
+                    for (int i = 0; i <= p; ++i) {
+                        const int64_t x = (int64_t)s[i] * P.words + k;
+                        nrow[i] = P.nbd + P.npre[x];
+                        nb[i] = P.bits[x];
+                    }
                 for (; m; m &= m - 1) {
-                    const int w = k * 64 + __builtin_ctzll(m);
+                    const int b = __builtin_ctzll(m);
+                    const int w = k * 64 + b;
                     if (w <= u)
                         continue;
                     bool all = true;
-                    for (int i = 0; i <= p && all; ++i)
-                        all = P.dsq[(int64_t)s[i] * n + w] <= dt;
+                    if (P.nbd) {
+                        const uint64_t below = (1ull << b) - 1;
+                        for (int i = 0; i <= p && all; ++i)
+                            all = nrow[i][__builtin_popcountll(nb[i] & below)] <= dt;
+                    } else {
+                        for (int i = 0; i <= p && all; ++i)
+                            all = P.dsq[(int64_t)s[i] * n + w] <= dt;
+                    }
                     if (all)
                         return false;
                 }

@@ -20,6 +20,12 @@ struct ResidualProblem {
     // when given, cofacets are found among common neighbours only
     const uint64_t *bits = nullptr;
     int words = 0;
+    // optional packed neighbour rows (with bits): npre[v*words + k] is the
+    // position in nbd of v's first neighbour in word k, nbd the neighbours'
+    // distances row after row; when given, dsq is never read (a few MB
+    // instead of n^2 floats: cache-resident where the matrix is not)
+    const uint32_t *npre = nullptr;
+    const float *nbd = nullptr;
     // non-apparent columns in coboundary order (diameter desc, cidx asc);
     // key = ~bits(diameter) in the low 32 bits
     int64_t ncols = 0;

@@ -97,7 +97,7 @@ int main(int argc, char **argv)
     // 3 overlapped with the dropped columns known late: columns park past
     // 2 additions, or with mode & 8 never, so dropped columns end at zero
     // before the gate opens);
-    // mode & 4: oblivious additions
+    // mode & 4: oblivious additions; mode & 64 (with 16): packed rows
     const int mode = atoi(argv[5]);
     const int sched = mode & 3;
     const int n = N;
@@ -289,8 +289,12 @@ int main(int argc, char **argv)
         P.col_low_diam = lowd.data();
         P.napp = napp;
         P.rank_bits = rank_bits;
-        // mode & 16: cofacets from neighbour bitsets (the sparse path)
+        // mode & 16: cofacets from neighbour bitsets (the sparse path);
+        // mode & 64 as well: distances from packed neighbour rows only (the
+        // square matrix is withheld)
         std::vector<uint64_t> bits;
+        std::vector<uint32_t> npre;
+        std::vector<float> nbd;
         if (mode & 16) {
             const int words = (n + 63) / 64;
             bits.assign((size_t)n * words, 0);
@@ -300,6 +304,21 @@ int main(int argc, char **argv)
                         bits[(size_t)a * words + b / 64] |= 1ull << (b % 64);
             P.bits = bits.data();
             P.words = words;
+            if (mode & 64) {
+                npre.assign((size_t)n * words, 0);
+                uint32_t run = 0;
+                for (size_t k = 0; k < (size_t)n * words; ++k) {
+                    npre[k] = run;
+                    run += (uint32_t)__builtin_popcountll(bits[k]);
+                }
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b)
+                        if (a != b && D(a, b) <= thr)
+                            nbd.push_back(D(a, b));
+                P.npre = npre.data();
+                P.nbd = nbd.data();
+                P.dsq = nullptr;
+            }
         }
         P.spec_budget = sched >= 1 ? 2 : 0;
         P.oblivious = (mode & 4) != 0;

@@ -90,6 +90,38 @@ def test_readback_branch_random_order_1500(rpp, monkeypatch):
 
 
 # ---------------------------------------------------------------------------
+# one pass (decoupled look-back) against count + scan + scatter
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", CASES[::2], ids=["op_" + c[0] for c in CASES[::2]])
+def test_one_pass_enumeration_matches_two_passes(rpp, monkeypatch, case):
+    """The one-pass dense enumeration (the default when outputs are sized up
+    front) and the count + scan + scatter passes: the same pairs and every
+    per-dimension count; bars equal the oracle's."""
+    name, d, n, maxdim, thr = case
+    f = rpp.RPP_FORCE_DENSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    monkeypatch.delenv("RPP_ENUM_TWO_PASS", raising=False)
+    a = rpp.barcodes(d, maxdim, thr, flags=f)
+    monkeypatch.setenv("RPP_ENUM_TWO_PASS", "1")
+    b = rpp.barcodes(d, maxdim, thr, flags=f)
+    assert_bars_equal(a.bars, _oracle_bars(d, n, maxdim, thr), name)
+    for p in range(1, maxdim + 1):
+        assert set(zip(*map(list, a.pairs[p]))) == set(zip(*map(list, b.pairs[p]))), (name, p)
+        for k in ("n_candidates", "n_thresholded", "n_cleared", "n_kept", "n_apparent"):
+            assert a.stats[p][k] == b.stats[p][k], (name, p, k)
+
+
+def test_one_pass_enumeration_torus400_and_theorem1(rpp, monkeypatch):
+    monkeypatch.delenv("RPP_ENUM_TWO_PASS", raising=False)
+    head, exp = _golden("torus400")
+    got = rpp.barcodes(w.WORKLOADS["torus400"]["build"](), 2)
+    assert_bars_equal(got.bars, exp, "torus400, one pass")
+    for n, p in ((60, 2), (400, 1), (30, 3)):
+        s, _, ncols = rpp.apparent_pairs(w.all_equal_metric(n), p)
+        assert ncols == math.comb(n, p + 1)
+        assert len(s) == math.comb(n - 1, p + 1)
+
+
+# ---------------------------------------------------------------------------
 # zero distances
 # ---------------------------------------------------------------------------
 def _zero_cases():

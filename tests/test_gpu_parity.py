@@ -356,6 +356,54 @@ def test_sparse_path_matches_oracle(rpp, case):
         assert st["n_simplices"] == oracle.count_simplices(d, n, p, thr)
 
 
+@pytest.mark.parametrize("case", SPARSE_CASES[1::3], ids=["hm_" + c[0] for c in SPARSE_CASES[1::3]])
+def test_host_packed_rows_match_host_matrix(rpp, monkeypatch, case):
+    """The sparse path's host reduction reading packed neighbour rows (the
+    default) and reading the square matrix (RPP_HOST_MATRIX=1): the same
+    bars, critical edges and pairs, with and without rank coding."""
+    name, d, n, maxdim, thr = case
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_WANT_CRITICAL_EDGES
+    for rank in ("0", "1"):
+        monkeypatch.setenv("RPP_RANK_CODING", rank)
+        monkeypatch.delenv("RPP_HOST_MATRIX", raising=False)
+        a = rpp.barcodes(d, maxdim, thr, flags=f)
+        monkeypatch.setenv("RPP_HOST_MATRIX", "1")
+        b = rpp.barcodes(d, maxdim, thr, flags=f)
+        assert_bars_equal(a.bars, b.bars, name)
+        for p in range(maxdim + 1):
+            assert np.array_equal(a.edges[p][0], b.edges[p][0]), (name, rank, p)
+            assert np.array_equal(a.edges[p][1], b.edges[p][1]), (name, rank, p)
+        for p in range(1, maxdim + 1):
+            assert set(zip(*map(list, a.pairs[p]))) == set(zip(*map(list, b.pairs[p])))
+
+
+SPARSE_GROUPS = [4, 8, 16, 104, 108, 204, 208, 404, 408]
+
+
+@pytest.mark.parametrize("case", SPARSE_CASES[::3], ids=["spg_" + c[0] for c in SPARSE_CASES[::3]])
+def test_sparse_apparent_kernel_forms_match_oracle(rpp, monkeypatch, case):
+    """Every sparse apparent-kernel form (G lanes per column; two-phase with
+    the top K words per lane first) gives the oracle's pairs, and the same
+    scan tally."""
+    name, d, n, maxdim, thr = case
+    red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    scans = None
+    monkeypatch.setenv("RPP_COUNT_SCANS", "1")
+    for grp in SPARSE_GROUPS:
+        monkeypatch.setenv("RPP_APPARENT_GROUP", str(grp))
+        g = rpp.barcodes(d, maxdim, thr, flags=f)
+        for p in range(1, maxdim + 1):
+            gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+            es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+            assert gs == es, (name, grp, p)
+            assert g.stats[p]["apparent_group"] == -grp
+        sc = [g.stats[p]["n_scanned"] for p in range(1, maxdim + 1)]
+        if scans is None:
+            scans = sc
+        assert sc == scans, (name, grp)
+
+
 @pytest.mark.parametrize("case", SPARSE_CASES[::2], ids=["rk_" + c[0] for c in SPARSE_CASES[::2]])
 def test_rank_coded_host_keys_match_oracle(rpp, case, monkeypatch):
     """Sparse path with the host reduction on rank-coded diameters and

@@ -77,10 +77,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,build,n,maxdim,thr", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 11, 4, 6, 7, 16, 19],
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 11, 4, 6, 7, 16, 19, 80, 83],
                          ids=["plain", "budget", "overlap", "late-drops", "late-drops-nocap",
                               "oblivious", "overlap-oblivious", "late-drops-oblivious",
-                              "bitsets", "bitsets-late-drops"])
+                              "bitsets", "bitsets-late-drops", "packed", "packed-late-drops"])
 def test_schedules_match_oracle(driver, name, build, n, maxdim, thr, mode):
     d = build()
     if np.isinf(thr):
@@ -121,9 +121,10 @@ def test_wide_keys_match_oracle(driver, mode):
             assert got_e[p] == exp_e[p], (name, mode, p)
 
 
-@pytest.mark.parametrize("mode", [32, 35, 48, 51], ids=["ranks", "ranks-late-drops",
-                                                      "ranks-bitsets",
-                                                      "ranks-bitsets-late-drops"])
+@pytest.mark.parametrize("mode", [32, 35, 48, 51, 115], ids=["ranks", "ranks-late-drops",
+                                                           "ranks-bitsets",
+                                                           "ranks-bitsets-late-drops",
+                                                           "ranks-packed-late-drops"])
 def test_rank_coded_keys_match_oracle(driver, mode):
     """Diameters replaced by the ranks of the distinct edge lengths, and
     keys that pack the rank above a cofacet-index field only as wide as the
@@ -157,9 +158,11 @@ def sanitized_driver():
 
 @pytest.mark.parametrize("mode,env", [(0, None), (3, None), (19, None), (7, None),
                                       (51, {"RPP_RANK_KEYS": "1"}),
+                                      (115, {"RPP_RANK_KEYS": "1"}),
                                       (3, {"RPP_WIDE_KEYS": "1"})],
                          ids=["plain", "late-drops", "bitsets-late-drops",
-                              "late-drops-oblivious", "ranks-bitsets-late-drops", "wide-keys"])
+                              "late-drops-oblivious", "ranks-bitsets-late-drops",
+                              "ranks-packed-late-drops", "wide-keys"])
 def test_host_reduction_is_sanitizer_clean(sanitized_driver, mode, env):
     """Every schedule and key layout of the host reduction under ASan and
     UBSan, on a dense and a thresholded input: no report, and the oracle's
