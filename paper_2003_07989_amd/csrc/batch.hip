@@ -10,7 +10,8 @@
 // and copied back in one transfer; the per-cloud host reductions run in
 // parallel on the worker pool.  The lane-group size of the apparent kernel
 // is chosen per (n, p) by timing the candidates on the first batch
-// (optionally persisted in the JSON file named by RPP_TUNE_CACHE).
+// (optionally persisted in the JSON file named by RPP_TUNE_CACHE), with
+// the rounds per wave and the workgroup size.
 #include "host_common.h"
 #include "kernels.h"
 #include "pipeline.h"
@@ -94,8 +95,19 @@ static unsigned blocks_for(int64_t m)
 }
 
 // ---------------------------------------------------------------------------
-// autotuner cache: (n, p) -> lanes per column of the apparent kernel
+// autotuner cache: (n, p) -> launch configuration of the apparent kernel,
+// one code: G + 100 R + 10000 B, with G lanes per column, R rounds of
+// 64/G columns per wave (0: chosen from the column count) and B wavefronts
+// per workgroup (0: four, i.e. 256 threads)
 // ---------------------------------------------------------------------------
+struct AppCfg {
+    int group, rounds, block;
+};
+static AppCfg app_cfg(int code)
+{
+    const int b = (code / 10000) % 10;
+    return {code % 100, (code / 100) % 100, b ? b * 64 : 256};
+}
 static std::mutex g_tune_mu;
 static std::map<std::pair<int, int>, int> g_tune;
 static bool g_tune_loaded = false;
@@ -111,7 +123,7 @@ static void tune_load_locked()
     FILE *f = fopen(path, "r");
     if (!f)
         return;
-    // format: {"n:p": G, ...}
+    // format: {"n:p": code, ...} (code as app_cfg reads it)
     int n, p, g;
     int ch;
     while ((ch = fgetc(f)) != EOF) {
@@ -329,6 +341,17 @@ static int batch_alloc(BatchWs &W, std::string &err)
     return RPP_OK;
 }
 
+// The apparent kernel of dimension p over the batch's kept columns, with the
+// launch configuration `code` (see app_cfg).
+static void launch_apparent(BatchWs &W, const DimShape &D, const Batch &bk, int code,
+                            hipStream_t s)
+{
+    const AppCfg ac = app_cfg(code);
+    launch_apparent_b(W.cdiam.as<float>(), W.ccidx.as<uint64_t>(), D.cap, W.dsq.as<float>(), W.n,
+                      D.p, W.binom.as<uint64_t>(), ac.group, W.tau.as<uint64_t>(), bk, W.nb, s,
+                      ac.rounds, ac.block);
+}
+
 // The GPU chain of dimension p (and, for p == 1, the staging and H0 stages
 // in front of it).  Fixed shape: suitable for graph capture.  No memset.
 static void enqueue_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags, hipStream_t s)
@@ -391,8 +414,7 @@ static void enqueue_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags
                             W.scan.as<uint64_t>(), s);
     launch_enum_scatter(ea, W.toff.as<uint64_t>(), W.cdiam.as<float>(), W.ccidx.as<uint64_t>(), s);
     Batch bk{W.toff.as<uint64_t>() + D.tiles, D.tiles + 1, D.cap, W.nv.as<int32_t>()};  // kept per cloud
-    launch_apparent_b(W.cdiam.as<float>(), W.ccidx.as<uint64_t>(), D.cap, W.dsq.as<float>(), n, p,
-                      binom, group, W.tau.as<uint64_t>(), bk, nb, s);
+    launch_apparent(W, D, bk, group, s);
     launch_partition_count(W.tau.as<uint64_t>(), D.cap, W.tcount2.as<uint32_t>(), s, bk, nb);
     launch_exclusive_scan_b(W.tcount2.as<uint32_t>(), D.tiles, nb, W.toff2.as<uint64_t>(),
                             W.scan.as<uint64_t>(), s);
@@ -452,29 +474,39 @@ static int launch_dim(BatchWs &W, const DimShape &D, int group, uint32_t flags, 
     return RPP_OK;
 }
 
-// Time each lane-group size on the current batch (eager launches) and keep
+// Tune the apparent kernel's launch on the current batch: after one run of
+// the dimension's chain (its kept columns in place), time the kernel alone
+// (eager, once to warm and once timed; it only rewrites tau) for every lane
+// count G in {4, 8, 16, 32}, rounds per wave R in {chosen from the column
+// count, 1, 2, 4, 8} (R <= G) and workgroup size in {64, 128, 256}, and keep
 // the fastest for (n, p).
 static int autotune(BatchWs &W, const DimShape &D, uint32_t flags, hipStream_t s, int *best,
                     std::string &err)
 {
-    const int cand[] = {4, 8, 16, 32};
+    enqueue_dim(W, D, 8, flags, s);
+    HIP_TRY(hipGetLastError());
+    Batch bk{W.toff.as<uint64_t>() + D.tiles, D.tiles + 1, D.cap, W.nv.as<int32_t>()};
     float best_ms = 1e30f;
     *best = 8;
-    for (int g : cand) {
-        GpuTimer t(s);
-        // the dimension's prerequisites (stages before p) are already in
-        // place; re-running the chain is idempotent
-        enqueue_dim(W, D, g, flags, s);  // warm
-        t.start();
-        enqueue_dim(W, D, g, flags, s);
-        t.stop();
-        HIP_TRY(hipGetLastError());
-        const float ms = t.ms();
-        if (ms < best_ms) {
-            best_ms = ms;
-            *best = g;
+    for (int g : {4, 8, 16, 32})
+        for (int r : {0, 1, 2, 4, 8}) {
+            if (r > g)
+                continue;
+            for (int bw : {4, 1, 2}) {  // wavefronts per workgroup (4: code 0)
+                const int code = g + 100 * r + (bw == 4 ? 0 : 10000 * bw);
+                GpuTimer t(s);
+                launch_apparent(W, D, bk, code, s);  // warm
+                t.start();
+                launch_apparent(W, D, bk, code, s);
+                t.stop();
+                HIP_TRY(hipGetLastError());
+                const float ms = t.ms();
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    *best = code;
+                }
+            }
         }
-    }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[{W.n, D.p}] = *best;
     tune_store_locked();
@@ -707,7 +739,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             Dd.st.n_cleared = (int64_t)st[2 * c + 1];
             Dd.st.n_simplices = own - Dd.st.n_thresholded;
             Dd.st.n_kept = kept;
-            Dd.st.apparent_group = group;
+            Dd.st.apparent_group = app_cfg(group).group;
             Dd.st.n_apparent = napp;
             Dd.st.n_nonapparent = kept - napp;
             Dd.st.n_host_pairs = (int64_t)R.sigma.size();

@@ -133,9 +133,12 @@ void launch_apparent_vec(const float *col_diam, const uint64_t *col_cidx, int64_
                          int group, uint64_t *tau_out, unsigned long long *scan_count,
                          hipStream_t s, const uint64_t *col_vtx = nullptr);
 // Batched: cap = per-cloud capacity (grid size); dsq packed n*n per cloud.
+// rounds (0: from the column count) and block (64, 128 or 256 threads per
+// workgroup) as the autotuner picks them.
 void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
                        const float *dsq, int n, int p, const uint64_t *binom, int group,
-                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s);
+                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s, int rounds = 0,
+                       int block = 256);
 
 // ---- a6: partition --------------------------------------------------------
 // Pass 1: apparent columns per tile.
@@ -230,6 +233,15 @@ void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_di
                         uint64_t *all_cidx, const uint64_t *clear, int64_t nclear,
                         float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
                         uint64_t *kept_vtx, hipStream_t s);
+// The scatter pass with the apparent-pair test of every kept extension fused
+// in (two-phase form; group = 100 K + G as for launch_apparent_sparse):
+// tau_out[kept position] = its apparent partner or NONE; scan_count as for
+// launch_apparent.  No vertex tuples are written.
+void launch_ext_scatter_apparent(const ExtArgs &a, int group, const uint64_t *off_all,
+                                 float *all_diam, uint64_t *all_cidx, const uint64_t *clear,
+                                 int64_t nclear, float *kept_diam, uint64_t *kept_cidx,
+                                 uint64_t kept_cap, uint64_t *tau_out,
+                                 unsigned long long *scan_count, hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
 // neighbours of the column's vertices, scanned from the top.  group = G in
 // {4, 8, 16}: G words per step by as many lanes per column; group = 100 K +

@@ -1782,7 +1782,8 @@ template <int P>
 static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols,
                               const float *dsq, int n, const uint64_t *binom, int group,
                               uint64_t *tau, unsigned long long *sc, hipStream_t s,
-                              Batch bt = Batch(), int nbatch = 1)
+                              Batch bt = Batch(), int nbatch = 1, int rounds_req = 0,
+                              int block = 256)
 {
     if (group >= 100 && nbatch <= 1 && bt.count == nullptr && bt.stride == 0) {
         // two-phase kernel: group = 100 K + G (K candidates alone, then G
@@ -1817,9 +1818,13 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
     int rounds = 1;
     while (rounds < group && total / ((int64_t)cpr * rounds * 2) >= 4096)
         rounds *= 2;
+    if (rounds_req > 0)  // a tuned value (rounds <= group)
+        rounds = rounds_req < group ? rounds_req : group;
+    if (block != 64 && block != 128)
+        block = 256;  // any multiple of 64 up to the kernel's launch bound
     const int64_t waves = (ncols + (int64_t)cpr * rounds - 1) / ((int64_t)cpr * rounds);
     const int64_t threads = waves * WAVE;
-    dim3 g((unsigned)((threads + 255) / 256), nbatch), b(256);
+    dim3 g((unsigned)((threads + block - 1) / block), nbatch), b(block);
     switch (group) {
     case 1: hipLaunchKernelGGL((k_apparent<P, 1>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
     case 4: hipLaunchKernelGGL((k_apparent<P, 4>), g, b, 0, s, cd, cc, ncols, dsq, n, binom, tau, sc, bt, rounds); break;
@@ -1832,16 +1837,19 @@ static void launch_apparent_p(const float *cd, const uint64_t *cc, int64_t ncols
 
 void launch_apparent_b(const float *col_diam, const uint64_t *col_cidx, int64_t cap,
                        const float *dsq, int n, int p, const uint64_t *binom, int group,
-                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s)
+                       uint64_t *tau_out, Batch bt, int nbatch, hipStream_t s, int rounds,
+                       int block)
 {
     if (cap <= 0)
         return;
+#define RPP_AB(P) launch_apparent_p<P>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch, rounds, block)
     switch (p) {
-    case 1: launch_apparent_p<1>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
-    case 2: launch_apparent_p<2>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
-    case 3: launch_apparent_p<3>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
-    default: launch_apparent_p<4>(col_diam, col_cidx, cap, dsq, n, binom, group, tau_out, nullptr, s, bt, nbatch); break;
+    case 1: RPP_AB(1); break;
+    case 2: RPP_AB(2); break;
+    case 3: RPP_AB(3); break;
+    default: RPP_AB(4); break;
     }
+#undef RPP_AB
 }
 
 void launch_apparent(const float *col_diam, const uint64_t *col_cidx, int64_t ncols,
@@ -2408,6 +2416,11 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
         const int word = wb + lane;
         uint64_t m = 0, bw[P];
         uint32_t pw[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            bw[i] = 0;
+            pw[i] = 0;
+        }
         if (word * 64 < limit) {
             m = ~0ull;
 #pragma unroll
@@ -2442,31 +2455,57 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
         }
         const uint64_t km = m & ~cm;
         const uint32_t na = (uint32_t)__popcll(m), nk = (uint32_t)__popcll(km);
-        uint64_t pa = run + (wave_inclusive_scan(na) - na);
-        uint64_t pk = krun + (wave_inclusive_scan(nk) - nk);
-        for (uint64_t r = m; r; r &= r - 1) {
-            const int b = __ffsll((unsigned long long)r) - 1;
-            const int v0 = word * 64 + b;
-            float d = pd;
+        const uint32_t ia = wave_inclusive_scan(na), ik = wave_inclusive_scan(nk);
+        const uint32_t tot = __shfl(ia, WAVE - 1, WAVE), totk = __shfl(ik, WAVE - 1, WAVE);
+        // One extension per lane: lane l of round e0 takes extension e0 + l
+        // of the block (cidx order), found in the word of the first lane
+        // whose inclusive count exceeds it, at the matching set bit; so the
+        // lookups and stores run on every lane however the extensions lie
+        // across the words (a lane walking its own word's bits would leave
+        // most lanes idle where a prefix's extensions crowd a few words).
+        for (uint32_t e0 = 0; e0 < tot; e0 += WAVE) {
+            const uint32_t e = e0 + (uint32_t)lane;
+            int lo = 0;
 #pragma unroll
-            for (int i = 0; i < P; ++i)
-                d = fmaxf(d, nb_dist(a.nbd, pw[i], bw[i], b));
-            const uint64_t c = shifted + (uint64_t)v0;
-            if (all_diam) {
-                all_diam[pa] = d;
-                all_cidx[pa] = c;
-                ++pa;
+            for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                const uint32_t x = __shfl(ia, lo + step - 1, WAVE);
+                lo += x <= e ? step : 0;
             }
-            if (((km >> b) & 1ull) && pk < kept_cap) {  // (the cap only guards the subset property)
-                kept_diam[pk] = d;
-                kept_cidx[pk] = c;
-                if (P <= 3 && kept_vtx)
-                    kept_vtx[pk] = vtx_hi | ((uint64_t)(uint32_t)v0 << (16 * P));
-                ++pk;
+            const uint64_t mw = shfl_u64(m, lo), kw = shfl_u64(km, lo);
+            const uint32_t exa = __shfl(ia - na, lo, WAVE), exk = __shfl(ik - nk, lo, WAVE);
+            uint64_t bl[P];
+            uint32_t pl[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                bl[i] = shfl_u64(bw[i], lo);
+                pl[i] = (uint32_t)__shfl((int)pw[i], lo, WAVE);
+            }
+            if (e < tot) {
+                const int b = select_set_bit(mw, (int)(e - exa));
+                const int v0 = (wb + lo) * 64 + b;
+                float d = pd;
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    d = fmaxf(d, nb_dist(a.nbd, pl[i], bl[i], b));
+                const uint64_t c = shifted + (uint64_t)v0;
+                if (all_diam) {
+                    all_diam[run + e] = d;
+                    all_cidx[run + e] = c;
+                }
+                if ((kw >> b) & 1ull) {
+                    const uint64_t pk =
+                        krun + exk + (uint32_t)__popcll(kw & ((1ull << b) - 1ull));
+                    if (pk < kept_cap) {  // (the cap only guards the subset property)
+                        kept_diam[pk] = d;
+                        kept_cidx[pk] = c;
+                        if (P <= 3 && kept_vtx)
+                            kept_vtx[pk] = vtx_hi | ((uint64_t)(uint32_t)v0 << (16 * P));
+                    }
+                }
             }
         }
-        run += wave_sum(na);
-        krun += wave_sum(nk);
+        run += tot;
+        krun += totk;
     }
 }
 
@@ -2725,6 +2764,106 @@ __global__ __launch_bounds__(256) void k_apparent_sparse(
         tau_out[mycol] = mytau;
 }
 
+// Phase 2 of the two-phase sparse apparent test: the wave's open columns
+// (omask; a lane's own column has vertices myv, diameter myd) numbered in
+// lane order and scanned G lanes per column from word top0 down, as
+// k_apparent_sparse scans.  Returns, on each open column's lane, its tau
+// (NONE when not apparent); adds the candidates visited to `examined` when
+// counting.  Every lane of the wave must call it.
+template <int P, int G>
+__device__ __forceinline__ uint64_t sparse_open_columns(uint64_t omask, const int (&myv)[P + 1],
+                                                        float myd, int top0, int words,
+                                                        const uint4 *__restrict__ nbw,
+                                                        const float *__restrict__ nbd,
+                                                        const Binom &B, bool counting,
+                                                        unsigned long long &examined)
+{
+    constexpr int CPR = WAVE / G;  // open columns per round
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int g = lane & (G - 1);
+    const int grp = lane / G;
+    const int gbase = lane - g;
+    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+    const bool open = (omask >> lane) & 1ull;
+    const int nopen = __popcll(omask);
+    uint64_t tau2 = NONE;
+    for (int r = 0; r * CPR < nopen; ++r) {
+        const int t = r * CPR + grp;
+        const bool valid = t < nopen;  // uniform in the group
+        const int src = valid ? select_set_bit(omask, t) : lane;
+        const float d = __shfl(myd, src, WAVE);
+        int v[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            v[i] = __shfl(myv[i], src, WAVE);
+        int x = -1;  // this lane's hit in the current step
+        int hit = -1;
+        float e[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            e[i] = 0.0f;
+        if (valid) {
+            for (int top = top0; top >= 0; top -= G) {
+                const int word = top - g;
+                uint64_t m = 0, bw[P + 1];
+                uint32_t pw[P + 1];
+                if (word >= 0) {
+                    m = ~0ull;
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        nb_word(nbw, (int64_t)v[i] * words + word, bw[i], pw[i]);
+                        m &= bw[i];
+                    }
+                }
+                unsigned tested = 0;
+                for (uint64_t mm = m; mm;) {
+                    const int b = 63 - __clzll((long long)mm);
+                    bool ok = true;
+                    float tt[P + 1];
+#pragma unroll
+                    for (int i = 0; i <= P; ++i) {
+                        tt[i] = nb_dist(nbd, pw[i], bw[i], b);
+                        ok = ok && (tt[i] <= d);
+                    }
+                    ++tested;
+                    if (ok) {
+                        x = word * 64 + b;
+#pragma unroll
+                        for (int i = 0; i <= P; ++i)
+                            e[i] = tt[i];
+                        break;
+                    }
+                    mm &= ~(1ull << b);
+                }
+                const uint64_t hm = __ballot(x >= 0) & gmask;
+                const int hl = hm ? __ffsll((unsigned long long)hm) - 1 - gbase : G;
+                if (counting)
+                    examined += g < hl ? (unsigned)__popcll(m) : (g == hl ? tested : 0u);
+                if (hm) {
+                    hit = gbase + hl;
+                    break;
+                }
+            }
+        }
+        const int ww = __shfl(x, hit >= 0 ? hit : lane, WAVE);
+        float eh[P + 1];
+#pragma unroll
+        for (int i = 0; i <= P; ++i)
+            eh[i] = __shfl(e[i], hit >= 0 ? hit : lane, WAVE);
+        uint64_t tau = NONE;
+        if (hit >= 0 && apparent_facets_ok<P>(nbw, nbd, words, v, d, ww, eh))
+            tau = cofacet_index<P>(B, v, ww);
+        // the owner of open column t is the t-th set lane of omask; group
+        // (t mod CPR)'s first lane holds its tau
+        const int mine = open ? __popcll(omask & lanemask_lt()) : -1;
+        const int from = mine >= 0 ? (mine % CPR) * G : lane;
+        const uint64_t tt = shfl_u64(tau, from);
+        if (mine >= 0 && mine / CPR == r)
+            tau2 = tt;
+    }
+    return tau2;
+}
+
 // Two-phase sparse apparent test.  Phase 1: every lane takes its own
 // column and scans the top K bitset words of its vertices (all K (P+1)
 // records loaded at once), testing the common neighbours word by word from
@@ -2741,12 +2880,7 @@ __global__ __launch_bounds__(256) void k_apparent_sparse2(
     const uint64_t *__restrict__ binom, uint64_t *__restrict__ tau_out,
     unsigned long long *__restrict__ scan_count, const uint64_t *__restrict__ col_vtx)
 {
-    constexpr int CPR = WAVE / G;  // open columns per round of phase 2
     const int lane = threadIdx.x & (WAVE - 1);
-    const int g = lane & (G - 1);
-    const int grp = lane / G;
-    const int gbase = lane - g;
-    const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t base = ((blk * blockDim.x + threadIdx.x) / WAVE) * WAVE;
     if (base >= ncols)
@@ -2824,82 +2958,8 @@ __global__ __launch_bounds__(256) void k_apparent_sparse2(
     const uint64_t omask = __ballot(open);
 
     // ---- phase 2: open columns, G lanes each, from word words-1-K down ----
-    const int nopen = __popcll(omask);
-    uint64_t tau2 = NONE;  // this lane's tau when its column was open
-    for (int r = 0; r * CPR < nopen; ++r) {
-        const int t = r * CPR + grp;
-        const bool valid = t < nopen;  // uniform in the group
-        const int src = valid ? select_set_bit(omask, t) : lane;
-        const float d = __shfl(myd, src, WAVE);
-        int v[P + 1];
-#pragma unroll
-        for (int i = 0; i <= P; ++i)
-            v[i] = __shfl(myv[i], src, WAVE);
-        int x = -1;  // this lane's hit in the current step
-        int hit = -1;
-        float e[P + 1];
-#pragma unroll
-        for (int i = 0; i <= P; ++i)
-            e[i] = 0.0f;
-        if (valid) {
-            for (int top = words - 1 - K; top >= 0; top -= G) {
-                const int word = top - g;
-                uint64_t m = 0, bw[P + 1];
-                uint32_t pw[P + 1];
-                if (word >= 0) {
-                    m = ~0ull;
-#pragma unroll
-                    for (int i = 0; i <= P; ++i) {
-                        nb_word(nbw, (int64_t)v[i] * words + word, bw[i], pw[i]);
-                        m &= bw[i];
-                    }
-                }
-                unsigned tested = 0;
-                for (uint64_t mm = m; mm;) {
-                    const int b = 63 - __clzll((long long)mm);
-                    bool ok = true;
-                    float tt[P + 1];
-#pragma unroll
-                    for (int i = 0; i <= P; ++i) {
-                        tt[i] = nb_dist(nbd, pw[i], bw[i], b);
-                        ok = ok && (tt[i] <= d);
-                    }
-                    ++tested;
-                    if (ok) {
-                        x = word * 64 + b;
-#pragma unroll
-                        for (int i = 0; i <= P; ++i)
-                            e[i] = tt[i];
-                        break;
-                    }
-                    mm &= ~(1ull << b);
-                }
-                const uint64_t hm = __ballot(x >= 0) & gmask;
-                const int hl = hm ? __ffsll((unsigned long long)hm) - 1 - gbase : G;
-                if (scan_count)
-                    examined += g < hl ? (unsigned)__popcll(m) : (g == hl ? tested : 0u);
-                if (hm) {
-                    hit = gbase + hl;
-                    break;
-                }
-            }
-        }
-        const int ww = __shfl(x, hit >= 0 ? hit : lane, WAVE);
-        float eh[P + 1];
-#pragma unroll
-        for (int i = 0; i <= P; ++i)
-            eh[i] = __shfl(e[i], hit >= 0 ? hit : lane, WAVE);
-        uint64_t tau = NONE;
-        if (hit >= 0 && apparent_facets_ok<P>(nbw, nbd, words, v, d, ww, eh))
-            tau = cofacet_index<P>(B, v, ww);
-        // the owner of open column t is the t-th set lane of omask; group
-        // (t mod CPR)'s first lane holds its tau
-        const int mine = open ? __popcll(omask & lanemask_lt()) : -1;
-        const int from = mine >= 0 ? (mine % CPR) * G : lane;
-        const uint64_t tt = shfl_u64(tau, from);
-        if (mine >= 0 && mine / CPR == r)
-            tau2 = tt;
-    }
+    const uint64_t tau2 = sparse_open_columns<P, G>(omask, myv, myd, words - 1 - K, words, nbw,
+                                                    nbd, B, scan_count != nullptr, examined);
     if (scan_count) {
         const unsigned long long tot = wave_sum(examined);
         if (lane == 0)
@@ -2913,6 +2973,247 @@ __global__ __launch_bounds__(256) void k_apparent_sparse2(
     else if (w >= 0 && apparent_facets_ok<P>(nbw, nbd, words, myv, myd, w, ew))
         mytau = cofacet_index<P>(B, myv, w);
     tau_out[mycol] = mytau;
+}
+
+// Scatter pass of the sparse enumeration with the apparent-pair test fused
+// in (two-phase, as k_apparent_sparse2): a kept extension sigma = (u, v0) is
+// tested on the lane that holds it, so its column never goes back to memory
+// before the test, and the prefix's bitset records of the top K words --
+// the same for every extension of the wave -- are read once per wave; only
+// v0's records are per lane.  tau_out[kept position] gets the apparent
+// partner or NONE.  Same outputs otherwise as k_ext<P, true> (no vertex
+// tuples: nothing reads them after the test).
+template <int P, int K, int G>
+__global__ __launch_bounds__(256) void k_ext_app(ExtArgs a, const uint64_t *__restrict__ off_all,
+                                                 float *__restrict__ all_diam,
+                                                 uint64_t *__restrict__ all_cidx,
+                                                 const uint64_t *__restrict__ clear,
+                                                 int64_t nclear, float *__restrict__ kept_diam,
+                                                 uint64_t *__restrict__ kept_cidx,
+                                                 uint64_t kept_cap, uint64_t *__restrict__ tau_out,
+                                                 unsigned long long *__restrict__ scan_count)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t pre = (blk * blockDim.x + threadIdx.x) / WAVE;
+    if (pre >= a.npre_count)
+        return;  // whole waves leave together
+    const Binom B{a.binom, a.n + 1};
+    const int words = a.words;
+    int u[P];  // prefix vertices, decreasing; u[P-1] = v_1
+    decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
+    uint64_t shifted = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        shifted += B(u[i], P + 1 - i);
+    const int limit = u[P - 1];
+    const float pd = a.pre_diam[pre];
+    // the prefix's records of the top K words (the same for every lane)
+    uint64_t ub[K][P];
+    uint32_t up[K][P];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            ub[k][i] = 0;
+            up[k][i] = 0;
+            if (words - 1 - k >= 0)
+                nb_word(a.nbw, (int64_t)u[i] * words + (words - 1 - k), ub[k][i], up[k][i]);
+        }
+    unsigned long long examined = 0;
+    uint64_t run = off_all[pre];
+    int64_t cpos = nclear ? wave_lower_bound(clear, nclear, shifted) : 0;
+    uint64_t krun = run - (uint64_t)cpos;
+    for (int wb = 0; wb * 64 < limit; wb += WAVE) {
+        const int word = wb + lane;
+        uint64_t m = 0, bw[P];
+        uint32_t pw[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            bw[i] = 0;
+            pw[i] = 0;
+        }
+        if (word * 64 < limit) {
+            m = ~0ull;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                nb_word(a.nbw, (int64_t)u[i] * words + word, bw[i], pw[i]);
+                m &= bw[i];
+            }
+            const int hi = limit - word * 64;
+            if (hi < 64)
+                m &= (1ull << hi) - 1;
+        }
+        const int blk_end = (wb + WAVE) * 64 < limit ? (wb + WAVE) * 64 : limit;
+        uint64_t cm = 0;
+        for (;;) {
+            const int64_t j = cpos + lane;
+            const uint64_t cv = j < nclear ? clear[j] : ~0ull;
+            const bool in = cv < shifted + (uint64_t)blk_end;
+            const uint64_t bm = __ballot(in);
+            const int c = __popcll(bm);
+            for (int k = 0; k < c; ++k) {
+                const uint64_t x = __shfl(cv, k, WAVE) - shifted;
+                if ((int)(x >> 6) == word)
+                    cm |= 1ull << (x & 63);
+            }
+            cpos += c;
+            if (c < WAVE)
+                break;
+        }
+        const uint64_t km = m & ~cm;
+        const uint32_t na = (uint32_t)__popcll(m), nk = (uint32_t)__popcll(km);
+        const uint32_t ia = wave_inclusive_scan(na), ik = wave_inclusive_scan(nk);
+        const uint32_t tot = __shfl(ia, WAVE - 1, WAVE), totk = __shfl(ik, WAVE - 1, WAVE);
+        for (uint32_t e0 = 0; e0 < tot; e0 += WAVE) {
+            const uint32_t e = e0 + (uint32_t)lane;
+            int lo = 0;
+#pragma unroll
+            for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                const uint32_t x = __shfl(ia, lo + step - 1, WAVE);
+                lo += x <= e ? step : 0;
+            }
+            const uint64_t mw = shfl_u64(m, lo), kw = shfl_u64(km, lo);
+            const uint32_t exa = __shfl(ia - na, lo, WAVE), exk = __shfl(ik - nk, lo, WAVE);
+            uint64_t bl[P];
+            uint32_t pl[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                bl[i] = shfl_u64(bw[i], lo);
+                pl[i] = (uint32_t)__shfl((int)pw[i], lo, WAVE);
+            }
+            bool kept = false;
+            uint64_t pk = 0;
+            int myv[P + 1];
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                myv[i] = 0;
+            float myd = 0.0f;
+            if (e < tot) {
+                const int b = select_set_bit(mw, (int)(e - exa));
+                const int v0 = (wb + lo) * 64 + b;
+                float d = pd;
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    d = fmaxf(d, nb_dist(a.nbd, pl[i], bl[i], b));
+                const uint64_t c = shifted + (uint64_t)v0;
+                if (all_diam) {
+                    all_diam[run + e] = d;
+                    all_cidx[run + e] = c;
+                }
+                if ((kw >> b) & 1ull) {
+                    pk = krun + exk + (uint32_t)__popcll(kw & ((1ull << b) - 1ull));
+                    kept = pk < kept_cap;  // (the cap only guards the subset property)
+                    if (kept) {
+                        kept_diam[pk] = d;
+                        kept_cidx[pk] = c;
+                    }
+                }
+                myd = d;
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    myv[i] = u[i];
+                myv[P] = v0;
+            }
+            // apparent test of the kept columns, phase 1: the top K words
+            int w = -1;
+            float ew[P + 1];
+#pragma unroll
+            for (int i = 0; i <= P; ++i)
+                ew[i] = 0.0f;
+            if (kept) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int wd = words - 1 - k;
+                    if (wd < 0 || w >= 0)
+                        continue;
+                    uint64_t vb;
+                    uint32_t vp;
+                    nb_word(a.nbw, (int64_t)myv[P] * words + wd, vb, vp);
+                    uint64_t mm = vb;
+#pragma unroll
+                    for (int i = 0; i < P; ++i)
+                        mm &= ub[k][i];
+                    while (mm && w < 0) {
+                        const int b = 63 - __clzll((long long)mm);
+                        bool ok = true;
+                        float t[P + 1];
+#pragma unroll
+                        for (int i = 0; i < P; ++i) {
+                            t[i] = nb_dist(a.nbd, up[k][i], ub[k][i], b);
+                            ok = ok && (t[i] <= myd);
+                        }
+                        t[P] = nb_dist(a.nbd, vp, vb, b);
+                        ok = ok && (t[P] <= myd);
+                        ++examined;
+                        if (ok) {
+                            w = wd * 64 + b;
+#pragma unroll
+                            for (int i = 0; i <= P; ++i)
+                                ew[i] = t[i];
+                        }
+                        mm &= ~(1ull << b);
+                    }
+                }
+            }
+            const bool open = kept && w < 0 && words - 1 - K >= 0;
+            const uint64_t omask = __ballot(open);
+            uint64_t tau2 = NONE;
+            if (omask)  // uniform: every lane calls it or none
+                tau2 = sparse_open_columns<P, G>(omask, myv, myd, words - 1 - K, words, a.nbw,
+                                                 a.nbd, B, scan_count != nullptr, examined);
+            if (kept) {
+                uint64_t tau = NONE;
+                if (open)
+                    tau = tau2;
+                else if (w >= 0 && apparent_facets_ok<P>(a.nbw, a.nbd, words, myv, myd, w, ew))
+                    tau = cofacet_index<P>(B, myv, w);
+                tau_out[pk] = tau;
+            }
+        }
+        run += tot;
+        krun += totk;
+    }
+    if (scan_count) {
+        const unsigned long long t = wave_sum(examined);
+        if (lane == 0)
+            atomicAdd(&scan_count[blockIdx.x & (SCAN_COUNTERS - 1)], t);
+    }
+}
+
+template <int P>
+static void launch_ext_app_p(const ExtArgs &a, int group, dim3 g, dim3 b, hipStream_t s,
+                             const uint64_t *off_all, float *all_diam, uint64_t *all_cidx,
+                             const uint64_t *clear, int64_t nclear, float *kept_diam,
+                             uint64_t *kept_cidx, uint64_t kept_cap, uint64_t *tau,
+                             unsigned long long *sc)
+{
+#define RPP_EA(K, G) hipLaunchKernelGGL((k_ext_app<P, K, G>), g, b, 0, s, a, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau, sc)
+    switch (group) {
+    case 104: RPP_EA(1, 4); break;
+    case 108: RPP_EA(1, 8); break;
+    case 204: RPP_EA(2, 4); break;
+    case 208: RPP_EA(2, 8); break;
+    case 408: RPP_EA(4, 8); break;
+    default: RPP_EA(4, 4); break;
+    }
+#undef RPP_EA
+}
+
+void launch_ext_scatter_apparent(const ExtArgs &a, int group, const uint64_t *off_all,
+                                 float *all_diam, uint64_t *all_cidx, const uint64_t *clear,
+                                 int64_t nclear, float *kept_diam, uint64_t *kept_cidx,
+                                 uint64_t kept_cap, uint64_t *tau_out,
+                                 unsigned long long *scan_count, hipStream_t s)
+{
+    if (a.npre_count <= 0)
+        return;
+    dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
+    switch (a.p) {
+    case 2: launch_ext_app_p<2>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
+    case 3: launch_ext_app_p<3>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
+    default: launch_ext_app_p<4>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
+    }
 }
 
 template <int P>

@@ -448,7 +448,8 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
 // still in cidx order, into ws.cdiam/ccidx.
 static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *clear,
                             int64_t nclear, bool want_all, int cur, hipStream_t s,
-                            int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm)
+                            int64_t *kept, int64_t *all, std::string &err, GpuTimer *tm,
+                            int fused_group = 0, unsigned long long *scan_count = nullptr)
 {
     ws.cvtx_ok = false;
     const int64_t np = ea.npre_count;
@@ -476,6 +477,18 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
     }
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+    if (fused_group > 0) {
+        // the apparent test runs in the scatter pass: tau of every kept column
+        ALLOC_TRY(ws.tau, (size_t)(*kept + 1) * 8);
+        launch_ext_scatter_apparent(ea, fused_group, ws.toff.as<uint64_t>(),
+                                    want_all ? ws.skd[1 - cur].as<float>() : nullptr,
+                                    want_all ? ws.skc[1 - cur].as<uint64_t>() : nullptr, clear,
+                                    nclear, ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(),
+                                    (uint64_t)*kept, ws.tau.as<uint64_t>(), scan_count, s);
+        if (tm)
+            tm->stop();
+        return RPP_OK;
+    }
     const bool vtx = ea.p <= 3 && ea.n <= 65536;  // vertex tuples for the apparent test
     if (vtx)
         ALLOC_TRY(ws.cvtx, (size_t)(*kept + 1) * 8);
@@ -496,7 +509,7 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
                                   hipStream_t s, int64_t *napp, std::string &err,
                                   GpuTimer *t_app = nullptr, GpuTimer *t_part = nullptr,
                                   int64_t *scanned = nullptr, int words = 0,
-                                  GpuTimer *t_pre = nullptr)
+                                  GpuTimer *t_pre = nullptr, bool tau_ready = false)
 {
     const int64_t tiles = compact_tiles(ncols);
     ALLOC_TRY(ws.tau, (size_t)(ncols + 1) * 8);
@@ -513,9 +526,11 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     ALLOC_TRY(ws.scan, (size_t)scan_scratch_words(tiles) * 8);
     unsigned long long *sc = nullptr;
     if (scanned) {
+        // (a fused enumeration already counted into it)
         ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
         sc = ws.scancnt.as<unsigned long long>();
-        HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+        if (!tau_ready)
+            HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
     }
     if (t_pre) {
         ws.cvtx_ok = false;  // the columns are reordered below; cvtx is not
@@ -541,7 +556,9 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
     }
     if (t_app)
         t_app->start();
-    if (words > 0)
+    if (tau_ready)
+        ;  // the enumeration ran the test
+    else if (words > 0)
         launch_apparent_sparse(ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), ncols, n, p, words,
                                ws.nbw.as<uint4>(), ws.nbd.as<float>(), ws.binom.as<uint64_t>(),
                                group, ws.tau.as<uint64_t>(), sc, s,
@@ -1062,6 +1079,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         tg.start();
         int64_t ncols = 0, ncand = 0;
         uint64_t nthr = 0, nclr = 0;
+        bool fused = false;  // the apparent test ran inside the enumeration
         int rc;
         FAULT_POINT("enumerate");
         CANCEL_POINT();
@@ -1075,8 +1093,19 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                        ws.binom.as<uint64_t>(), ws.skd[cur].as<float>(),
                        ws.skc[cur].as<uint64_t>(), nskel};
             int64_t nall = 0;
+            // the apparent test fused into the scatter pass (two-phase forms,
+            // columns in cidx order); RPP_SPARSE_UNFUSED=1 runs it apart
+            const int sg = sparse_group(a.apparent_group);
+            const char *uf = getenv("RPP_SPARSE_UNFUSED");
+            fused = sg >= 100 && !(a.flags & RPP_SORT_FIRST) && !(uf && atoi(uf) != 0);
+            unsigned long long *sc = nullptr;
+            if (fused && a.count_scans) {
+                ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);
+                sc = ws.scancnt.as<unsigned long long>();
+                HIP_TRY(hipMemsetAsync(sc, 0, (size_t)SCAN_COUNTERS * 8, s));
+            }
             rc = enumerate_sparse(ws, xa, clear_sorted, nclear_sorted, p < maxdim, cur, s,
-                                  &ncols, &nall, err, &t_enum);
+                                  &ncols, &nall, err, &t_enum, fused ? sg : 0, sc);
             ncand = nall;
             nclr = (uint64_t)(nall - ncols);
             if (p < maxdim) {
@@ -1098,7 +1127,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         FAULT_POINT("apparent");
         rc = apparent_and_partition(ws, ncols, n, p, group, s, &napp, err, &t_app, &t_part,
                                     a.count_scans ? &scanned : nullptr, sparse ? words : 0,
-                                    sort_first ? &t_pre : nullptr);
+                                    sort_first ? &t_pre : nullptr, fused);
         if (rc)
             return rc;
         t_sort.start();
@@ -1219,7 +1248,8 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         D.st.n_simplices = ncand - (int64_t)nthr;
         D.st.n_kept = ncols;
         // negative: the sparse kernel, with that many lanes per column
-        D.st.apparent_group = sparse ? -sparse_group(group) : group;
+        // (fused into the enumeration: -(1000 + the two-phase code))
+        D.st.apparent_group = sparse ? -(sparse_group(group) + (fused ? 1000 : 0)) : group;
         D.st.n_apparent = napp;
         D.st.n_nonapparent = nna;
 

@@ -859,16 +859,8 @@ struct Ctx {
             const uint64_t *bv[8];
             for (int i = 0; i < nv; ++i)
                 bv[i] = P.bits + (int64_t)v[i] * P.words;
-            // count first so the stream is sized exactly
-            size_t cnt = 0;
-            for (int wd = 0; wd < P.words; ++wd) {
-                uint64_t m = bv[0][wd];
-                for (int i = 1; i < nv; ++i)
-                    m &= bv[i][wd];
-                cnt += (size_t)__builtin_popcountll(m);
-            }
-            out = arena.reserve<K>(cnt);
-            arena.commit<K>(cnt);
+            // room for every other vertex; the arena keeps only what is used
+            out = arena.reserve<K>((size_t)n + 16);
             K *gt = gt_scratch<K>();
             size_t neq = 0, ngt = 0;
             int k = nv;  // vertices of sigma below w; w runs downward
@@ -911,6 +903,8 @@ struct Ctx {
             }
             memcpy(out + neq, gt, ngt * sizeof(K));
             ties = neq;
+            const size_t cnt = neq + ngt;
+            arena.commit<K>(cnt);
             return cnt;
         }
         const float *rows[8];

@@ -391,17 +391,23 @@ def test_sparse_apparent_kernel_forms_match_oracle(rpp, monkeypatch, case):
     scans = None
     monkeypatch.setenv("RPP_COUNT_SCANS", "1")
     for grp in SPARSE_GROUPS:
-        monkeypatch.setenv("RPP_APPARENT_GROUP", str(grp))
-        g = rpp.barcodes(d, maxdim, thr, flags=f)
-        for p in range(1, maxdim + 1):
-            gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
-            es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
-            assert gs == es, (name, grp, p)
-            assert g.stats[p]["apparent_group"] == -grp
-        sc = [g.stats[p]["n_scanned"] for p in range(1, maxdim + 1)]
-        if scans is None:
-            scans = sc
-        assert sc == scans, (name, grp)
+        for unfused in ("0", "1"):
+            if unfused == "1" and grp < 100:
+                continue  # the single-phase forms always run apart
+            monkeypatch.setenv("RPP_APPARENT_GROUP", str(grp))
+            monkeypatch.setenv("RPP_SPARSE_UNFUSED", unfused)
+            g = rpp.barcodes(d, maxdim, thr, flags=f)
+            for p in range(1, maxdim + 1):
+                gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+                es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+                assert gs == es, (name, grp, unfused, p)
+                # two-phase forms above dimension 1 run inside the enumeration
+                fused = grp >= 100 and p >= 2 and unfused == "0"
+                assert g.stats[p]["apparent_group"] == -(grp + (1000 if fused else 0))
+            sc = [g.stats[p]["n_scanned"] for p in range(1, maxdim + 1)]
+            if scans is None:
+                scans = sc
+            assert sc == scans, (name, grp, unfused)
 
 
 @pytest.mark.parametrize("case", SPARSE_CASES[::2], ids=["rk_" + c[0] for c in SPARSE_CASES[::2]])
