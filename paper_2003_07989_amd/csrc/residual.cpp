@@ -515,20 +515,224 @@ private:
     size_t mask_ = 0, size_ = 0;
 };
 
+// Radix heap over keys that never fall below the last minimum taken (the
+// low of a column only grows as the reduction adds columns whose low is
+// the current one).  Keys are read in 4-bit digits.  Bucket 0 holds copies
+// of that minimum; a key that first differs from it in digit L, where its
+// own digit is g, sits in bucket 1 + 16 L + g, and every key of a bucket
+// is smaller than every key of a later one.  Taking the next minimum
+// empties the lowest non-empty bucket into lower ones (a key moves at most
+// once per digit, every move a sequential append) -- or, once that bucket
+// is small, sorts it into the front run: distinct keys (pairs cancelled),
+// in order, all below every bucket.  The low is then the run's first key,
+// and a new key within the run's range is toggled into it in place.
+template <class K> struct RadixHeap {
+    static constexpr int DB = 4, DIG = 1 << DB;
+    static constexpr int NB = 8 * (int)sizeof(K) / DB * DIG + 1;
+    static constexpr size_t RUN = 48;  // largest bucket sorted into the run
+    std::vector<K> b[NB];
+    uint64_t busy[(NB + 63) / 64] = {};  // bit i: bucket i is not empty
+    std::vector<K> run;                  // front run: run[rh..] ascending
+    size_t rh = 0;
+    K last = 0;
+    int bucket(K k) const
+    {
+        const K x = k ^ last;
+        if (x == 0)
+            return 0;
+        int hb;  // highest differing bit
+        if (sizeof(K) == 8) {
+            hb = 63 - __builtin_clzll((uint64_t)x);
+        } else {
+            const uint64_t hi = (uint64_t)(x >> 32 >> 32);
+            hb = hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll((uint64_t)x);
+        }
+        const int L = hb / DB;
+        return 1 + L * DIG + (int)((k >> (L * DB)) & (K)(DIG - 1));
+    }
+    void put(K k)
+    {
+        const int i = bucket(k);
+        b[i].push_back(k);
+        busy[i >> 6] |= 1ull << (i & 63);
+    }
+    void drop(int i)
+    {
+        b[i].clear();
+        busy[i >> 6] &= ~(1ull << (i & 63));
+    }
+    // Lowest non-empty bucket above 0, or NB.
+    int first_above_zero() const
+    {
+        for (int w = 0; w < (NB + 63) / 64; ++w) {
+            const uint64_t m = w == 0 ? busy[0] & ~1ull : busy[w];
+            if (m)
+                return 64 * w + __builtin_ctzll(m);
+        }
+        return NB;
+    }
+    bool run_empty() const { return rh == run.size(); }
+    // Z/2 add of k to the run (k within its range): removes an equal key,
+    // else inserts k in order.
+    void toggle(K k)
+    {
+        K *f = run.data() + rh, *e = run.data() + run.size();
+        K *at = std::lower_bound(f, e, k);
+        if (*at == k) {
+            if (at == f) {
+                ++rh;
+            } else {
+                std::move(at + 1, e, at);
+                run.pop_back();
+            }
+            return;
+        }
+        if (rh > 0 && at - f < e - at) {
+            std::move(f, at, f - 1);  // room in front: shift the lower part
+            --rh;
+            *(at - 1) = k;
+        } else {
+            const size_t pos = (size_t)(at - run.data());
+            run.insert(run.begin() + (ptrdiff_t)pos, k);
+        }
+    }
+    void add(K k)
+    {
+        if (!run_empty() && k <= run.back())
+            toggle(k);
+        else
+            put(k);
+    }
+    // Adds keys; one below the last minimum (an addition whose low is older
+    // than the column's) re-buckets everything around it.
+    void push(const K *e, size_t len)
+    {
+        if (len == 0)
+            return;
+        K m = e[0];
+        for (size_t i = 1; i < len; ++i)
+            m = e[i] < m ? e[i] : m;
+        if (m < last)
+            rebase(m);
+        for (size_t i = 0; i < len; ++i)
+            add(e[i]);
+    }
+    // Adds every key of another heap (none lies below its last minimum).
+    void merge(const RadixHeap &o)
+    {
+        if (o.size() == 0)
+            return;
+        if (o.last < last)
+            rebase(o.last);
+        o.for_each([&](K k) { add(k); });
+    }
+    void rebase(K m)
+    {
+        std::vector<K> all(run.begin() + (ptrdiff_t)rh, run.end());
+        run.clear();
+        rh = 0;
+        for (int i = 0; i < NB; ++i) {
+            all.insert(all.end(), b[i].begin(), b[i].end());
+            drop(i);
+        }
+        last = m;
+        for (K k : all)
+            put(k);
+    }
+    // The smallest key present an odd number of times (the low of the Z/2
+    // sum); false when every key cancels.
+    bool low(K &out)
+    {
+        while (true) {
+            if (!run_empty()) {
+                out = run[rh];
+                return true;
+            }
+            if (!b[0].empty()) {
+                if (b[0].size() & 1) {
+                    b[0].resize(1);
+                    out = last;
+                    return true;
+                }
+                drop(0);
+            }
+            const int i = first_above_zero();
+            if (i == NB)
+                return false;
+            std::vector<K> &v = b[i];
+            K m = v[0];
+            for (K k : v)
+                m = k < m ? k : m;
+            last = m;
+            if (v.size() <= RUN) {
+                // sort, keep the keys of odd multiplicity
+                std::sort(v.begin(), v.end());
+                run.clear();
+                rh = 0;
+                for (size_t j = 0; j < v.size();) {
+                    size_t e = j + 1;
+                    while (e < v.size() && v[e] == v[j])
+                        ++e;
+                    if ((e - j) & 1)
+                        run.push_back(v[j]);
+                    j = e;
+                }
+                drop(i);
+                continue;
+            }
+            for (K k : v)
+                put(k);  // lands below i
+            drop(i);
+        }
+    }
+    template <class F> void for_each(F f) const
+    {
+        for (size_t j = rh; j < run.size(); ++j)
+            f(run[j]);
+        for (int i = 0; i < NB; ++i)
+            for (K k : b[i])
+                f(k);
+    }
+    size_t size() const
+    {
+        size_t n = run.size() - rh;
+        for (int i = 0; i < NB; ++i)
+            n += b[i].size();
+        return n;
+    }
+};
+
 // Working column = Z/2 sum of several coboundaries.  Each added coboundary
 // is its own stream; a min-heap over the streams' current fronts yields the
 // sum's entries oldest-first.  Only the entries that reach the front are
-// ever ordered, which is what finding the low needs.
+// ever ordered, which is what finding the low needs.  A column that has
+// taken many additions (an essential class is a long chain of them, each
+// key eventually reaching the front) moves every remaining key into a
+// radix heap instead: the 4-ary heap over thousands of streams costs a
+// cache miss per level per key, the radix heap appends.
 template <class K> class Column {
 public:
     DepthPolicy *policy = nullptr;  // shared by the columns of one reduction
     const KeyCodec *codec = nullptr;  // key layout of that reduction
+    static size_t radix_at()
+    {
+        static const size_t v = [] {
+            const char *e = getenv("RPP_RADIX_STREAMS");
+            const long x = e ? atol(e) : 512;
+            return x > 0 ? (size_t)x : ~(size_t)0;  // <= 0: never
+        }();
+        return v;
+    }
     // Adds the coboundary in e[0..len) (arena storage) as a new stream; its
     // first `ties` keys are already in ascending order.
     void push_stream(K *e, size_t len, size_t ties)
     {
         if (len == 0)
             return;
+        if (rh) {
+            rh->push(e, len);
+            return;
+        }
         streams.emplace_back();
         Stream<K> &st = streams.back();
         st.e = e;
@@ -537,12 +741,27 @@ public:
         if (policy)
             policy->streams.fetch_add(1, std::memory_order_relaxed);
         top_push(st.front(), (uint32_t)(streams.size() - 1));
+        if (streams.size() >= radix_at())
+            to_radix();
     }
     // Add another column's current contents: its streams hold exactly its
     // Z/2 sum (cancelled pairs were removed together).  The remaining keys
     // are copied, since both columns reorder their streams as they go.
     void add(const Column &o, Arena &arena)
     {
+        if (o.rh && !rh)
+            to_radix();  // a stream holds distinct keys; the other's buckets
+                         // may still hold pairs that have not cancelled
+        if (rh) {
+            if (o.rh) {
+                rh->merge(*o.rh);
+                return;
+            }
+            for (const Stream<K> &src : o.streams)
+                if (!src.empty())
+                    rh->push(src.e + src.pos, src.len - src.pos);
+            return;
+        }
         for (const Stream<K> &src : o.streams) {
             if (src.empty())
                 continue;
@@ -559,6 +778,8 @@ public:
             dst.chunk = src.chunk;
             top_push(dst.front(), (uint32_t)(streams.size() - 1));
         }
+        if (streams.size() >= radix_at())
+            to_radix();
     }
     // Low of the sum over Z/2: keys present in an even number of streams
     // cancel.  In the min-heap every copy of the minimum lies in a subtree
@@ -566,6 +787,13 @@ public:
     // holds it; pairs are dropped until the minimum is unique.
     bool low(Entry &out)
     {
+        if (rh) {
+            K k;
+            if (!rh->low(k))
+                return false;
+            out = unpack_key<K>(*codec, k);
+            return true;
+        }
         while (!hk.empty()) {
             const K e = hk[0];
             const size_t m = hk.size();
@@ -584,6 +812,23 @@ public:
     }
 
 private:
+    // Every remaining key of every stream into a radix heap based at the
+    // current minimum (each stream's unordered rest lies above its ordered
+    // prefix, so the heap root is the smallest key present).
+    void to_radix()
+    {
+        rh.reset(new RadixHeap<K>());
+        rh->last = hk.empty() ? K(0) : hk[0];
+        for (const Stream<K> &st : streams)
+            if (!st.empty())
+                rh->push(st.e + st.pos, st.len - st.pos);
+        streams.clear();
+        streams.shrink_to_fit();
+        hk.clear();
+        hk.shrink_to_fit();
+        hs.clear();
+        hs.shrink_to_fit();
+    }
     // 4-ary min-heap, keys and stream ids in separate arrays: half the
     // levels of a binary heap, a node's four child keys share a cache line,
     // and the smallest child is picked without branches.
@@ -652,6 +897,7 @@ private:
     std::vector<Stream<K>> streams;
     std::vector<K> hk;
     std::vector<uint32_t> hs;
+    std::unique_ptr<RadixHeap<K>> rh;  // set once the column goes radix
 };
 
 // ---------------------------------------------------------------------------
