@@ -373,6 +373,8 @@ def _fd_check(rpp, pts, batched, grads, full=False, h=1e-4, chunk=32, clouds=Non
                 checked += 1
                 worst = max(worst, err / (1e-4 + 1e-3 * abs(fd)))
                 bad += err > 1e-4 + 1e-3 * abs(fd)
+        print("fd check: cloud %d done (%d coordinates checked, %d skipped, %d failures so far)"
+              % (ci, checked, skipped, bad), file=sys.stderr, flush=True)
     return {"clouds": len(cloud_ids), "coords_checked": checked,
             "coords_skipped_near_ties": skipped, "failures": int(bad),
             "worst_err_over_tol": round(worst, 4), "h": h, "tol": "abs 1e-4 + rel 1e-3",
@@ -702,6 +704,8 @@ def bench_cloud(args, name: str, cpu: bool = True) -> dict:
     rpp.load()
 
     flags = rpp.RPP_SORT_FIRST if args.sort_first else 0
+    if args.oblivious:
+        flags |= rpp.RPP_OBLIVIOUS_REDUCTION
     # scan tally for the apparent kernel's algorithmic bytes (outside timing)
     os.environ["RPP_COUNT_SCANS"] = "1"
     tally = rpp.barcodes_device(dist, maxdim, thr, flags=flags, stream=stream)
@@ -786,6 +790,7 @@ def bench_cloud(args, name: str, cpu: bool = True) -> dict:
         "data": "synthetic",
         "config": {"workload": name, "n": n, "maxdim": maxdim,
                    "stage_order": "sort-first" if args.sort_first else "sort-after",
+                   "reduction": "oblivious" if args.oblivious else "reduction-matrix",
                    "threshold": "inf" if math.isinf(thr) else thr,
                    "threshold_used": last.threshold_used,
                    "simplices_per_step": simplices},
@@ -845,6 +850,9 @@ def main():
     ap.add_argument("--sort-first", action="store_true",
                     help="the paper's stage order: sort every kept column before the "
                          "apparent test (default: sort only the non-apparent ones after it)")
+    ap.add_argument("--oblivious", action="store_true",
+                    help="host reduction in the oblivious form (add a pivot's unreduced "
+                         "coboundary) instead of the reduction-matrix form")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rates", default="0.8",
                     help="serving: arrival rates as multiples of the plain capacity")

@@ -694,36 +694,59 @@ __global__ __launch_bounds__(CT) void k_enum_onepass(EnumArgs a,
     if (lane == 0)
         wsum[wave] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave == 0) {
+        // Look-back by the whole first wave: lane l reads the flag word of
+        // tile (j - l), so one round trip covers 64 predecessors.  The
+        // nearest one holding its inclusive prefix ends the walk; every
+        // tile between must have published at least its aggregate (they
+        // all hold a ticket below ours, so they are running and publish it
+        // without waiting on anyone).  A flag word carries its value, and
+        // nothing else written by the tile is read before the kernel ends,
+        // so the loads and stores are relaxed (device scope): acquire and
+        // release at device scope would invalidate and write back this
+        // XCD's whole L2 on every poll and publication, under the feet of
+        // every other tile reading the distances through it.
         uint64_t agg = 0;
 #pragma unroll
         for (int w = 0; w < CT / WAVE; ++w)
             agg += wsum[w];
         uint64_t excl = 0;
         if (tile == 0) {
-            __hip_atomic_store(&status[0], LB_PRE | agg, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&status[0], LB_PRE | agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&status[tile], LB_AGG | agg, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], LB_AGG | agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             for (int64_t j = (int64_t)tile - 1;;) {
+                const int64_t idx = j - lane;
                 const unsigned long long st =
-                    __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if ((st & ~LB_VAL) == 0) {
-                    __builtin_amdgcn_s_sleep(1);  // not yet published
+                    idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : LB_PRE;  // before tile 0: an empty prefix
+                const uint64_t pre = __ballot((st & LB_PRE) != 0);
+                const uint64_t none = __ballot((st & ~LB_VAL) == 0);
+                const int first = pre ? __ffsll((long long)pre) - 1 : WAVE;
+                const uint64_t upto = first >= WAVE - 1 ? ~0ull : (2ull << first) - 1;
+                if (none & upto) {
+                    __builtin_amdgcn_s_sleep(1);  // a tile in the window not yet published
                     continue;
                 }
-                excl += st & LB_VAL;
-                if (st & LB_PRE)
+                excl += wave_sum<uint64_t>(lane <= first ? (uint64_t)(st & LB_VAL) : 0ull);
+                if (pre)
                     break;
-                --j;
+                j -= WAVE;
             }
-            __hip_atomic_store(&status[tile], LB_PRE | (excl + agg), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], LB_PRE | (excl + agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        if ((int64_t)tile == tiles - 1)
-            *total = excl + agg;
-        s_base = excl;
+        if (lane == 0) {
+            if ((int64_t)tile == tiles - 1)
+                *total = excl + agg;
+            s_base = excl;
+        }
     }
     __syncthreads();
     uint64_t running = s_base;

@@ -619,6 +619,14 @@ static int64_t open_cap()
     const char *e = getenv("RPP_OPEN_CAP");
     return e ? std::max<int64_t>(1, atoll(e)) : OPEN_CAP;
 }
+// Additions per slice of a parked column while the gate is closed and the
+// frontier waits on it (RPP_PARK_SLICE overrides it; 0: it waits idle).
+constexpr int64_t PARK_SLICE = 256;
+static int64_t park_slice()
+{
+    const char *e = getenv("RPP_PARK_SLICE");
+    return e ? std::max<int64_t>(0, atoll(e)) : PARK_SLICE;
+}
 
 // 100 K + G selects the two-phase kernel (K candidates per lane alone,
 // then G lanes per column still open), 10000 + that its form with the open
@@ -1278,6 +1286,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         H.P.app_tau = sorted_store ? ws.h_app_tau[hb].as<uint64_t>() : nullptr;
         H.P.app_sigma = sorted_store ? ws.h_app_sigma[hb].as<uint64_t>() : nullptr;
         H.P.spec_budget = SPEC_BUDGET;
+        H.P.park_slice = park_slice();
         if (ranks) {
             H.P.rank_bits = rank_bits;
             H.P.thr = (float)(nranks - 1);
@@ -1305,7 +1314,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         // on its own thread; the gate waits for them when they are needed.
         HostDim *prevp = p > 1 ? &hd[(size_t)p - 1] : nullptr;
         const int64_t cap = open_cap();
-        H.th = std::thread([&H, prevp, cap, &since] {
+        H.th = std::thread([&H, prevp, cap, &since, trace] {
             struct PrevGate final : DropGate {
                 HostDim &prev, &cur;
                 bool have = false;
@@ -1351,8 +1360,12 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             } catch (const std::exception &) {
                 H.failed = true;
             }
+            const auto f0 = std::chrono::steady_clock::now();
             H.spec.reset();
             const auto b1 = std::chrono::steady_clock::now();
+            if (trace)
+                fprintf(stderr, "rpp trace:   p=%d exact phase state freed in %.3f ms\n", H.P.p,
+                        std::chrono::duration<float, std::milli>(b1 - f0).count());
             H.ms_exact = std::chrono::duration<float, std::milli>(b1 - b0).count();
             H.t_exact_end = since(b1);
             {

@@ -25,6 +25,7 @@
 #include <type_traits>
 #include <condition_variable>
 #include <functional>
+#include <chrono>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -714,6 +715,13 @@ template <class K> class Column {
 public:
     DepthPolicy *policy = nullptr;  // shared by the columns of one reduction
     const KeyCodec *codec = nullptr;  // key layout of that reduction
+    // RPP_RADIX_STREAMS set: every column goes radix at that many streams,
+    // whatever share of its keys has been taken (tests)
+    static bool radix_forced()
+    {
+        static const bool v = getenv("RPP_RADIX_STREAMS") != nullptr;
+        return v;
+    }
     static size_t radix_at()
     {
         static const size_t v = [] {
@@ -741,8 +749,7 @@ public:
         if (policy)
             policy->streams.fetch_add(1, std::memory_order_relaxed);
         top_push(st.front(), (uint32_t)(streams.size() - 1));
-        if (streams.size() >= radix_at())
-            to_radix();
+        maybe_radix();
     }
     // Add another column's current contents: its streams hold exactly its
     // Z/2 sum (cancelled pairs were removed together).  The remaining keys
@@ -778,8 +785,7 @@ public:
             dst.chunk = src.chunk;
             top_push(dst.front(), (uint32_t)(streams.size() - 1));
         }
-        if (streams.size() >= radix_at())
-            to_radix();
+        maybe_radix();
     }
     // Low of the sum over Z/2: keys present in an even number of streams
     // cancel.  In the min-heap every copy of the minimum lies in a subtree
@@ -812,6 +818,24 @@ public:
     }
 
 private:
+    // At radix_at() streams, and each doubling after: go radix when an
+    // eighth of the keys added so far have already reached the front (the
+    // sphere's essential chain: a fifth at 512 streams, and in the end all
+    // of them), not when the streams are long and mostly untouched (dense
+    // coboundaries and edges' coboundaries, 1-4% taken).
+    void maybe_radix()
+    {
+        if (streams.size() < next_check)
+            return;
+        next_check = streams.size() >= (~(size_t)0 >> 1) ? ~(size_t)0 : 2 * streams.size();
+        uint64_t taken = 0, total = 0;
+        for (const Stream<K> &st : streams) {
+            taken += st.pos;
+            total += st.len;
+        }
+        if (radix_forced() || 8 * taken >= total)
+            to_radix();
+    }
     // Every remaining key of every stream into a radix heap based at the
     // current minimum (each stream's unordered rest lies above its ordered
     // prefix, so the heap root is the smallest key present).
@@ -898,6 +922,7 @@ private:
     std::vector<K> hk;
     std::vector<uint32_t> hs;
     std::unique_ptr<RadixHeap<K>> rh;  // set once the column goes radix
+    size_t next_check = radix_at();    // stream count of the next radix check
 };
 
 // ---------------------------------------------------------------------------
@@ -1525,9 +1550,16 @@ private:
         std::atomic<int64_t> look_app{0};
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
         const int64_t budget = P.spec_budget;
+        // One thread at a time may take a column past the budget while
+        // columns are still unclaimed: a long chain (an essential class)
+        // then starts here, beside the other columns, instead of after them;
+        // the phase ends as soon as every column is claimed, and the column
+        // resumes in the exact phase.
+        std::atomic<int> extender{0};
         auto phase_a = [&](int) {
             Ctx X(P, &sink, codec);
             int64_t looks = 0;
+            bool extending = false;
             while (true) {
                 const int64_t j0 = next.fetch_add(chunk);
                 if (j0 >= ncols)
@@ -1563,8 +1595,14 @@ private:
                         if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
                             break;
                         if (budget > 0 && adds >= budget) {
-                            cut = true;  // low still apparent: phase B goes on
-                            break;
+                            if (!extending && P.parallel) {
+                                int idle = 0;
+                                extending = extender.compare_exchange_strong(idle, 1);
+                            }
+                            if (!extending || next.load(std::memory_order_relaxed) >= ncols) {
+                                cut = true;  // low still apparent: phase B goes on
+                                break;
+                            }
                         }
                     }
                     spec_low[j] = lo;
@@ -1572,6 +1610,10 @@ private:
                     spec_adds[j] = adds;
                     spec_cut[j] = cut ? 1 : 0;
                     state[j] = std::move(col);
+                    if (extending) {
+                        extending = false;
+                        extender.store(0);
+                    }
                 }
             }
             look_app += looks;
@@ -1681,8 +1723,30 @@ private:
 
         // The dropped columns are known: drop them, classify the open zero
         // columns, and resume the parked ones.
+        // RPP_TRACE: when the gate opened, the slices run before it, and the
+        // longest round of the exact phase
+        static const bool trace = [] {
+            const char *e = getenv("RPP_TRACE");
+            return e && atoi(e) != 0;
+        }();
+        const auto t0 = std::chrono::steady_clock::now();
+        auto ms_since = [&t0]() {
+            return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                .count();
+        };
+        int64_t nslices = 0, nrounds = 0, longest_size = 0;
+        double longest_ms = 0.0, slice_ms = 0.0;
+        std::mutex trace_mu;
+        int64_t trace_adds = 0;  // the call with the most additions, and its times
+        double trace_tm[4] = {0, 0, 0, 0};
         auto learn = [&]() {
+            const double w0 = trace ? ms_since() : 0.0;
             drop = gate.wait();
+            if (trace)
+                fprintf(stderr,
+                        "rpp trace:   p=%d exact phase: gate open at %.3f ms (waited %.3f ms, "
+                        "%lld slices of parked columns before it, %.3f ms)\n",
+                        P.p, ms_since(), ms_since() - w0, (long long)nslices, slice_ms);
             known = true;
             if (drop)
                 for (int64_t j = 0; j < ncols; ++j)
@@ -1708,6 +1772,7 @@ private:
         // the pivot store and the finished columns; safe to run concurrently).
         std::atomic<int64_t> look_hash{0}, look_app_b{0};
         bool open = !known;  // read by advance(); set before each round
+        int64_t cap_now = cap;  // the additions a column may reach while open
         auto advance = [&](Ctx &Xc, int64_t j) {
             if (drop && drop[j])
                 return;  // dropped after it was queued
@@ -1721,8 +1786,19 @@ private:
             Entry lo = spec_low[j];
             int64_t adds = 0, lh = 0, la = 0;
             bool nz = true;
+            // RPP_TRACE: where the longest call's time goes
+            double tm[4] = {0, 0, 0, 0};  // pivot adds, apparent lookups, coboundaries, lows
+            auto tick = [](std::chrono::steady_clock::time_point &t) {
+                const auto u = std::chrono::steady_clock::now();
+                const double d = std::chrono::duration<double, std::milli>(u - t).count();
+                t = u;
+                return d;
+            };
+            std::chrono::steady_clock::time_point tt;
+            if (trace)
+                tt = std::chrono::steady_clock::now();
             while (true) {
-                if (open && cap > 0 && spec_adds[j] + adds >= cap) {
+                if (open && cap_now > 0 && spec_adds[j] + adds >= cap_now) {
                     parked[j] = 1;  // resumes once the dropped columns are known
                     break;
                 }
@@ -1736,17 +1812,34 @@ private:
                         col->add(*reduced[k], Xc.arena);
                     else
                         Xc.add_coboundary(*col, R.sigma[k], R.birth[k]);
+                    if (trace)
+                        tm[0] += tick(tt);
                 } else {
                     uint64_t other = 0;
                     ++la;
-                    if (!apparent_lookup(Xc, lo.cidx, lo.diam, &other))
+                    const bool app = apparent_lookup(Xc, lo.cidx, lo.diam, &other);
+                    if (trace)
+                        tm[1] += tick(tt);
+                    if (!app)
                         break;
                     Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
+                    if (trace)
+                        tm[2] += tick(tt);
                 }
                 ++adds;
                 nz = col->low(lo);
+                if (trace)
+                    tm[3] += tick(tt);
                 if (!nz)
                     break;
+            }
+            if (trace) {
+                std::lock_guard<std::mutex> lk(trace_mu);
+                if (adds > trace_adds) {
+                    trace_adds = adds;
+                    for (int q = 0; q < 4; ++q)
+                        trace_tm[q] = tm[q];
+                }
             }
             spec_low[j] = lo;
             spec_nz[j] = nz ? 1 : 0;
@@ -1769,12 +1862,37 @@ private:
                 // the frontier waits on a parked column: only the gate helps
                 if (known)
                     throw std::logic_error("residual reduction: frontier stalled");
+                if (!parked_list.empty() && P.park_slice > 0 && !gate.ready()) {
+                    // Nothing can move until the dropped columns are known.
+                    // Instead of waiting idle, take the parked column nearest
+                    // the frontier a slice of additions further (its work is
+                    // lost only if the gate then drops it), and look at the
+                    // gate again.
+                    auto it = std::min_element(parked_list.begin(), parked_list.end());
+                    const int64_t j = *it;
+                    parked_list.erase(it);
+                    parked[j] = 0;
+                    open = true;
+                    cap_now = spec_adds[j] + P.park_slice;
+                    const double s0 = trace ? ms_since() : 0.0;
+                    advance(X, j);
+                    if (trace)
+                        slice_ms += ms_since() - s0;
+                    ++nslices;
+                    cap_now = cap;
+                    if (parked[j])
+                        parked_list.push_back(j);
+                    else if (spec_nz[j])
+                        wait_on(j);
+                    continue;
+                }
                 learn();
                 continue;
             }
             open = !known;
             round.swap(work);
             work.clear();
+            const double r0 = trace ? ms_since() : 0.0;
             if (round.size() == 1 || !P.parallel) {
                 for (int64_t j : round)
                     advance(X, j);
@@ -1786,6 +1904,11 @@ private:
                         advance(Xw, round[i]);
                 });
             }
+            ++nrounds;
+            if (trace && ms_since() - r0 > longest_ms) {
+                longest_ms = ms_since() - r0;
+                longest_size = (int64_t)round.size();
+            }
             for (int64_t j : round) {
                 pending[j] = 0;
                 if (parked[j])
@@ -1796,6 +1919,13 @@ private:
         }
         if (!known)
             learn();  // classifies the zero columns still open
+        if (trace)
+            fprintf(stderr,
+                    "rpp trace:   p=%d exact phase: %lld rounds, longest %.3f ms (%lld columns), "
+                    "done at %.3f ms; longest column call %lld additions: pivot adds %.3f ms, "
+                    "apparent lookups %.3f ms, coboundaries %.3f ms, lows %.3f ms\n",
+                    P.p, (long long)nrounds, longest_ms, (long long)longest_size, ms_since(),
+                    (long long)trace_adds, trace_tm[0], trace_tm[1], trace_tm[2], trace_tm[3]);
         R.lookups_hash += look_hash.load();
         R.lookups_apparent += look_app_b.load();
     }

@@ -322,6 +322,10 @@ int main(int argc, char **argv)
         }
         P.spec_budget = sched >= 1 ? 2 : 0;
         P.oblivious = (mode & 4) != 0;
+        // RPP_TEST_PARK_SLICE: additions per slice of a parked column while
+        // the gate is closed (0: parked columns wait idle)
+        if (const char *e = getenv("RPP_TEST_PARK_SLICE"))
+            P.park_slice = atoll(e);
         ResidualResult R;
         if (sched >= 2) {
             std::unordered_set<uint64_t> ph(prev_host.begin(), prev_host.end());
@@ -334,13 +338,16 @@ int main(int argc, char **argv)
                 // the dropped columns become known only after a few polls:
                 // the reduction runs open, parks columns past 2 additions,
                 // and classifies its zero columns late
+                // (RPP_TEST_GATE_POLLS of them, default 5)
                 struct Late final : DropGate {
                     const uint8_t *d;
-                    int polls = 0;
-                    bool ready() override { return ++polls > 5; }
+                    int polls = 0, after = 5;
+                    bool ready() override { return ++polls > after; }
                     const uint8_t *wait() override { return d; }
                 } gate;
                 gate.d = drop.data();
+                if (const char *e = getenv("RPP_TEST_GATE_POLLS"))
+                    gate.after = atoi(e);
                 residual_speculate(P)->finish_gated(gate, (mode & 8) ? 1000000 : 2, R);
             }
         } else {

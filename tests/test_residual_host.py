@@ -166,6 +166,30 @@ def test_radix_columns_match_oracle(driver, mode, env, streams):
             assert got_e[p] == exp_e[p], (name, mode, streams, p)
 
 
+@pytest.mark.parametrize("slice_,polls", [(0, 5), (1, 5), (1, 100000), (3, 100000),
+                                          (256, 100000)])
+@pytest.mark.parametrize("mode", [3, 7, 19, 83], ids=["late-drops", "late-drops-oblivious",
+                                                      "bitsets-late-drops",
+                                                      "packed-late-drops"])
+def test_parked_slices_match_oracle(driver, mode, slice_, polls):
+    """While the dropped columns are unknown and every other column waits
+    on them, the parked column nearest the frontier goes on `slice_`
+    additions at a time (0: parked columns wait idle); with the gate opening
+    after a few polls or only once nothing else can run, the same pairs and
+    classes -- a column the gate then drops ends as no pair and no class,
+    whatever its slices did."""
+    for name, build, n, maxdim, thr in CASES:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        e = {"RPP_TEST_PARK_SLICE": str(slice_), "RPP_TEST_GATE_POLLS": str(polls)}
+        got_p, got_e = _run(driver, d, n, maxdim, thr, mode, env=e)
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, slice_, polls, p)
+            assert got_e[p] == exp_e[p], (name, mode, slice_, polls, p)
+
+
 @pytest.fixture(scope="module")
 def sanitized_driver():
     """The same driver and reduction built with AddressSanitizer and
@@ -186,11 +210,13 @@ def sanitized_driver():
                                       (115, {"RPP_RANK_KEYS": "1"}),
                                       (3, {"RPP_WIDE_KEYS": "1"}),
                                       (7, {"RPP_RADIX_STREAMS": "2"}),
+                                      (3, {"RPP_TEST_PARK_SLICE": "1",
+                                           "RPP_TEST_GATE_POLLS": "100000"}),
                                       (3, {"RPP_RADIX_STREAMS": "2", "RPP_WIDE_KEYS": "1"})],
                          ids=["plain", "late-drops", "bitsets-late-drops",
                               "late-drops-oblivious", "ranks-bitsets-late-drops",
                               "ranks-packed-late-drops", "wide-keys", "radix-oblivious",
-                              "radix-wide-keys"])
+                              "park-slices", "radix-wide-keys"])
 def test_host_reduction_is_sanitizer_clean(sanitized_driver, mode, env):
     """Every schedule and key layout of the host reduction under ASan and
     UBSan, on a dense and a thresholded input: no report, and the oracle's
