@@ -3018,13 +3018,18 @@ __global__ __launch_bounds__(256) void k_ext_app(ExtArgs a, const uint64_t *__re
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t pre = (blk * blockDim.x + threadIdx.x) / WAVE;
+    // the wave's prefix, made wave-uniform so that everything derived from
+    // it (its vertices, bitset records, offsets) sits in scalar registers
+    const int pre = __builtin_amdgcn_readfirstlane((int)((blk * blockDim.x + threadIdx.x) / WAVE));
     if (pre >= a.npre_count)
         return;  // whole waves leave together
     const Binom B{a.binom, a.n + 1};
     const int words = a.words;
     int u[P];  // prefix vertices, decreasing; u[P-1] = v_1
     decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        u[i] = __builtin_amdgcn_readfirstlane(u[i]);
     uint64_t shifted = 0;
 #pragma unroll
     for (int i = 0; i < P; ++i)

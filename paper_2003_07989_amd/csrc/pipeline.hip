@@ -396,11 +396,14 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
         }
         return RPP_OK;
     };
-    // One pass (decoupled look-back) when the outputs are sized up front and
-    // the thresholded / cleared counts come from the clearing set's size;
-    // RPP_ENUM_TWO_PASS=1 keeps the count + scan + scatter passes.
-    const char *tp = getenv("RPP_ENUM_TWO_PASS");
-    if (upfront && ncleared >= 0 && ea.nbatch <= 1 && !(tp && atoi(tp) != 0)) {
+    // RPP_ENUM_ONE_PASS=1: one pass (decoupled look-back) when the outputs
+    // are sized up front and the thresholded / cleared counts come from the
+    // clearing set's size.  Not the default: the look-back's round trips
+    // between thousands of concurrent tiles cost more than the count pass
+    // and the scan they replace (torus dimension 2: 112 against 91 us per
+    // stage; sphere dimension 1: 63 against 44).
+    const char *op = getenv("RPP_ENUM_ONE_PASS");
+    if (upfront && ncleared >= 0 && ea.nbatch <= 1 && op && atoi(op) != 0) {
         ALLOC_TRY(ws.lookback, (size_t)(tiles + 2) * 8);
         if (tm)
             tm->start();

@@ -26,6 +26,7 @@
 #include <condition_variable>
 #include <functional>
 #include <chrono>
+#include <cmath>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -1037,23 +1038,41 @@ struct Ctx {
     }
 
     // vertices of a simplex with q+1 vertices, decreasing
+    // Vertex v[pos] is the largest v < (the previous one) with C(v, k) <= c,
+    // k = q + 1 - pos.  Started from the real root of v^k / k! = c (exact
+    // for k <= 2 up to rounding) and stepped to the exact answer on the
+    // binomial table, so the guess's accuracy only affects the steps taken.
     void decode(uint64_t c, int q, int *v) const
     {
         int hi = n;
         for (int pos = 0; pos <= q; ++pos) {
             const int k = q + 1 - pos;
-            int lo = k - 1, h = hi - 1;
-            while (lo < h) {
-                int mid = (lo + h + 1) >> 1;
-                if (C(mid, k) <= c)
-                    lo = mid;
-                else
-                    h = mid - 1;
-            }
-            v[pos] = lo;
-            c -= C(lo, k);
-            hi = lo;
+            const int lo = k - 1;
+            double x;
+            if (k == 1)
+                x = (double)c;
+            else if (k == 2)
+                x = 0.5 * (1.0 + std::sqrt(1.0 + 8.0 * (double)c));
+            else if (k == 3)
+                x = std::cbrt(6.0 * (double)c) + 1.0;
+            else
+                x = std::pow((double)c * factorial(k), 1.0 / k) + 0.5 * (k - 1);
+            int g = x >= (double)(hi - 1) ? hi - 1 : (x <= (double)lo ? lo : (int)x);
+            while (g > lo && C(g, k) > c)
+                --g;
+            while (g + 1 < hi && C(g + 1, k) <= c)
+                ++g;
+            v[pos] = g;
+            c -= C(g, k);
+            hi = g;
         }
+    }
+    static double factorial(int k)
+    {
+        double f = 1.0;
+        for (int i = 2; i <= k; ++i)
+            f *= i;
+        return f;
     }
 
     // cidx of sigma + {w} (w not in sigma, v decreasing)
@@ -1074,6 +1093,75 @@ struct Ctx {
         if (!placed)
             c += C(w, r + 1);
         return c;
+    }
+
+    // Sparse coboundary from the neighbour bitsets and packed neighbour rows
+    // (sigma's NV vertices ascending in u): the common neighbours w are
+    // listed first, word by word without a branch per neighbour (up to four
+    // per word, the rarer rest in a loop), then each gets its diameter and
+    // key in a loop of known length.  w ascends, so the cofacets of sigma's
+    // own diameter come out in descending key order and are reversed; the
+    // others follow them.  Returns the count; out needs n + 16 slots.
+    template <class K, int NV>
+    size_t cob_packed(const int *u, float d, const uint64_t *base, K *out, size_t &ties) const
+    {
+        const int W = P.words;
+        const uint64_t *bv[NV];
+        const uint32_t *pre[NV];
+        for (int i = 0; i < NV; ++i) {
+            bv[i] = P.bits + (int64_t)u[i] * W;
+            pre[i] = P.npre + (int64_t)u[i] * W;
+        }
+        int *ws = w_scratch();
+        int cnt = 0;
+        for (int wd = 0; wd < W; ++wd) {
+            uint64_t m = bv[0][wd];
+            for (int i = 1; i < NV; ++i)
+                m &= bv[i][wd];
+            const int w0 = wd << 6;
+            for (int t = 0; t < 4; ++t) {
+                ws[cnt] = w0 + (m ? __builtin_ctzll(m) : 0);
+                cnt += m ? 1 : 0;
+                m &= m - 1;
+            }
+            while (m) {
+                ws[cnt++] = w0 + __builtin_ctzll(m);
+                m &= m - 1;
+            }
+        }
+        K *gt = gt_scratch<K>();
+        size_t neq = 0, ngt = 0;
+        int k = 0;  // vertices of sigma below w
+        for (int t = 0; t < cnt; ++t) {
+            const int w = ws[t];
+            while (k < NV && u[k] < w)
+                ++k;
+            const int wd = w >> 6;
+            const uint64_t below = (1ull << (w & 63)) - 1;
+            float nd = d;
+            for (int i = 0; i < NV; ++i) {
+                const float e = P.nbd[pre[i][wd] + (uint32_t)__builtin_popcountll(bv[i][wd] & below)];
+                nd = e > nd ? e : nd;
+            }
+            const K key = pack_key<K>(kc, nd, base[k] + C(w, k + 1));
+            out[neq] = key;
+            gt[ngt] = key;
+            const bool tie = !(nd > d);
+            neq += tie ? 1 : 0;
+            ngt += tie ? 0 : 1;
+        }
+        std::reverse(out, out + neq);
+        memcpy(out + neq, gt, ngt * sizeof(K));
+        ties = neq;
+        return neq + ngt;
+    }
+    // Scratch for the common neighbours of one coboundary, n + 64 ints.
+    int *w_scratch() const
+    {
+        thread_local std::vector<int> buf;
+        if (buf.size() < (size_t)n + 64)
+            buf.resize((size_t)n + 64);
+        return buf.data();
     }
 
     // Adds sigma's coboundary to col as a new stream.
@@ -1120,6 +1208,17 @@ struct Ctx {
                 for (int i = 0; i < nv; ++i)
                     b += i < k ? C(u[i], i + 1) : C(u[i], i + 2);
                 base[k] = b;
+            }
+            if (P.nbd && nv >= 2 && nv <= 4) {
+                out = arena.reserve<K>((size_t)n + 16);
+                size_t cnt = 0;
+                switch (nv) {
+                case 2: cnt = cob_packed<K, 2>(u, d, base, out, ties); break;
+                case 3: cnt = cob_packed<K, 3>(u, d, base, out, ties); break;
+                default: cnt = cob_packed<K, 4>(u, d, base, out, ties); break;
+                }
+                arena.commit<K>(cnt);
+                return cnt;
             }
             const float *rows[8];
             for (int i = 0; i < nv; ++i)
@@ -1550,16 +1649,9 @@ private:
         std::atomic<int64_t> look_app{0};
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(16, ncols / (8 * workers)));
         const int64_t budget = P.spec_budget;
-        // One thread at a time may take a column past the budget while
-        // columns are still unclaimed: a long chain (an essential class)
-        // then starts here, beside the other columns, instead of after them;
-        // the phase ends as soon as every column is claimed, and the column
-        // resumes in the exact phase.
-        std::atomic<int> extender{0};
         auto phase_a = [&](int) {
             Ctx X(P, &sink, codec);
             int64_t looks = 0;
-            bool extending = false;
             while (true) {
                 const int64_t j0 = next.fetch_add(chunk);
                 if (j0 >= ncols)
@@ -1595,14 +1687,8 @@ private:
                         if (!apparent_lookup(X, lo.cidx, lo.diam, &other))
                             break;
                         if (budget > 0 && adds >= budget) {
-                            if (!extending && P.parallel) {
-                                int idle = 0;
-                                extending = extender.compare_exchange_strong(idle, 1);
-                            }
-                            if (!extending || next.load(std::memory_order_relaxed) >= ncols) {
-                                cut = true;  // low still apparent: phase B goes on
-                                break;
-                            }
+                            cut = true;  // low still apparent: phase B goes on
+                            break;
                         }
                     }
                     spec_low[j] = lo;
@@ -1610,10 +1696,6 @@ private:
                     spec_adds[j] = adds;
                     spec_cut[j] = cut ? 1 : 0;
                     state[j] = std::move(col);
-                    if (extending) {
-                        extending = false;
-                        extender.store(0);
-                    }
                 }
             }
             look_app += looks;

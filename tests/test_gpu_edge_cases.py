@@ -94,14 +94,14 @@ def test_readback_branch_random_order_1500(rpp, monkeypatch):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("case", CASES[::2], ids=["op_" + c[0] for c in CASES[::2]])
 def test_one_pass_enumeration_matches_two_passes(rpp, monkeypatch, case):
-    """The one-pass dense enumeration (the default when outputs are sized up
-    front) and the count + scan + scatter passes: the same pairs and every
-    per-dimension count; bars equal the oracle's."""
+    """The one-pass dense enumeration (RPP_ENUM_ONE_PASS=1, taken when
+    outputs are sized up front) and the count + scan + scatter passes: the
+    same pairs and every per-dimension count; bars equal the oracle's."""
     name, d, n, maxdim, thr = case
     f = rpp.RPP_FORCE_DENSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
-    monkeypatch.delenv("RPP_ENUM_TWO_PASS", raising=False)
+    monkeypatch.setenv("RPP_ENUM_ONE_PASS", "1")
     a = rpp.barcodes(d, maxdim, thr, flags=f)
-    monkeypatch.setenv("RPP_ENUM_TWO_PASS", "1")
+    monkeypatch.delenv("RPP_ENUM_ONE_PASS", raising=False)
     b = rpp.barcodes(d, maxdim, thr, flags=f)
     assert_bars_equal(a.bars, _oracle_bars(d, n, maxdim, thr), name)
     for p in range(1, maxdim + 1):
@@ -111,7 +111,7 @@ def test_one_pass_enumeration_matches_two_passes(rpp, monkeypatch, case):
 
 
 def test_one_pass_enumeration_torus400_and_theorem1(rpp, monkeypatch):
-    monkeypatch.delenv("RPP_ENUM_TWO_PASS", raising=False)
+    monkeypatch.setenv("RPP_ENUM_ONE_PASS", "1")
     head, exp = _golden("torus400")
     got = rpp.barcodes(w.WORKLOADS["torus400"]["build"](), 2)
     assert_bars_equal(got.bars, exp, "torus400, one pass")
