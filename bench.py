@@ -242,6 +242,8 @@ def bench_circles(args):
     P = [torch.from_numpy(p).cuda() for p in pts]
     D = [torch.from_numpy(d).cuda() for d in dists]
     flags = rpp.RPP_WANT_CRITICAL_EDGES
+    if args.oblivious:
+        flags |= rpp.RPP_OBLIVIOUS_REDUCTION
     for _ in range(args.warmup):
         rpp.barcodes_batch(D, 1, flags=flags)
         for d in D[:4]:
