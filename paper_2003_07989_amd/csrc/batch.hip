@@ -692,6 +692,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
         // per-cloud host reductions, in parallel over clouds
         std::vector<ResidualResult> RR(nb);
         auto h0 = std::chrono::steady_clock::now();
+        const double kr = keep_ratio();
         parallel_for(nb, [&](int64_t c) {
             ResidualProblem P;
             P.n = n;
@@ -706,6 +707,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             P.col_low_diam = hld.data() + off[c];
             P.parallel = false;
             P.oblivious = (a.flags & RPP_OBLIVIOUS_REDUCTION) != 0;
+            P.keep_ratio = kr;
             residual_reduce(P, RR[c]);
         });
         auto h1 = std::chrono::steady_clock::now();

@@ -241,7 +241,12 @@ void launch_ext_scatter_apparent(const ExtArgs &a, int group, const uint64_t *of
                                  float *all_diam, uint64_t *all_cidx, const uint64_t *clear,
                                  int64_t nclear, float *kept_diam, uint64_t *kept_cidx,
                                  uint64_t kept_cap, uint64_t *tau_out,
-                                 unsigned long long *scan_count, hipStream_t s);
+                                 unsigned long long *scan_count, hipStream_t s,
+                                 const int64_t *cpos = nullptr);
+// cpos[pre] = entries of the sorted clearing set below prefix pre's first
+// extension (what the fused scatter otherwise searches for itself).
+void launch_clear_pos(const ExtArgs &a, const uint64_t *clear, int64_t nclear, int64_t *cpos,
+                      hipStream_t s);
 // Apparent test and lows for the sparse path: candidates are the common
 // neighbours of the column's vertices, scanned from the top.  group = G in
 // {4, 8, 16}: G words per step by as many lanes per column; group = 100 K +

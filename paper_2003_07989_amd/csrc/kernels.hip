@@ -2998,6 +2998,48 @@ __global__ __launch_bounds__(256) void k_apparent_sparse2(
     tau_out[mycol] = mytau;
 }
 
+// Cleared entries below each prefix's first extension (the clearing set is
+// sorted): one thread per prefix and a plain binary search, so the fused
+// scatter below reads one word instead of searching with a whole wave at
+// its start.
+template <int P>
+__global__ __launch_bounds__(256) void k_clear_pos(ExtArgs a, const uint64_t *__restrict__ clear,
+                                                   int64_t nclear, int64_t *__restrict__ cpos_out)
+{
+    const int64_t pre = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pre >= a.npre_count)
+        return;
+    const Binom B{a.binom, a.n + 1};
+    int u[P];
+    decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
+    uint64_t shifted = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        shifted += B(u[i], P + 1 - i);
+    int64_t lo = 0, hi = nclear;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (clear[mid] < shifted)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    cpos_out[pre] = lo;
+}
+
+void launch_clear_pos(const ExtArgs &a, const uint64_t *clear, int64_t nclear, int64_t *cpos,
+                      hipStream_t s)
+{
+    if (a.npre_count <= 0)
+        return;
+    dim3 g((unsigned)((a.npre_count + 255) / 256)), b(256);
+    switch (a.p) {
+    case 2: hipLaunchKernelGGL(k_clear_pos<2>, g, b, 0, s, a, clear, nclear, cpos); break;
+    case 3: hipLaunchKernelGGL(k_clear_pos<3>, g, b, 0, s, a, clear, nclear, cpos); break;
+    default: hipLaunchKernelGGL(k_clear_pos<4>, g, b, 0, s, a, clear, nclear, cpos); break;
+    }
+}
+
 // Scatter pass of the sparse enumeration with the apparent-pair test fused
 // in (two-phase, as k_apparent_sparse2): a kept extension sigma = (u, v0) is
 // tested on the lane that holds it, so its column never goes back to memory
@@ -3006,15 +3048,21 @@ __global__ __launch_bounds__(256) void k_apparent_sparse2(
 // v0's records are per lane.  tau_out[kept position] gets the apparent
 // partner or NONE.  Same outputs otherwise as k_ext<P, true> (no vertex
 // tuples: nothing reads them after the test).
-template <int P, int K, int G>
-__global__ __launch_bounds__(256) void k_ext_app(ExtArgs a, const uint64_t *__restrict__ off_all,
+// W: the waves per SIMD the register allocation must allow (1: the
+// compiler's choice, 100 VGPRs and four waves for P = 2; more trades
+// spills for occupancy).  The default form takes 5 (96 VGPRs, 3 spilled):
+// on the 4096-point sphere 1.38 -> 1.20 ms per stage; 6 (80 VGPRs, 25
+// spilled) gives 1.35 and 8 (64, 48 spilled) 1.64.
+template <int P, int K, int G, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_ext_app(ExtArgs a, const uint64_t *__restrict__ off_all,
                                                  float *__restrict__ all_diam,
                                                  uint64_t *__restrict__ all_cidx,
                                                  const uint64_t *__restrict__ clear,
                                                  int64_t nclear, float *__restrict__ kept_diam,
                                                  uint64_t *__restrict__ kept_cidx,
                                                  uint64_t kept_cap, uint64_t *__restrict__ tau_out,
-                                                 unsigned long long *__restrict__ scan_count)
+                                                 unsigned long long *__restrict__ scan_count,
+                                                 const int64_t *__restrict__ cpos_all)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -3050,7 +3098,8 @@ __global__ __launch_bounds__(256) void k_ext_app(ExtArgs a, const uint64_t *__re
         }
     unsigned long long examined = 0;
     uint64_t run = off_all[pre];
-    int64_t cpos = nclear ? wave_lower_bound(clear, nclear, shifted) : 0;
+    int64_t cpos = cpos_all ? cpos_all[pre]
+                            : (nclear ? wave_lower_bound(clear, nclear, shifted) : 0);
     uint64_t krun = run - (uint64_t)cpos;
     for (int wb = 0; wb * 64 < limit; wb += WAVE) {
         const int word = wb + lane;
@@ -3214,16 +3263,29 @@ static void launch_ext_app_p(const ExtArgs &a, int group, dim3 g, dim3 b, hipStr
                              const uint64_t *off_all, float *all_diam, uint64_t *all_cidx,
                              const uint64_t *clear, int64_t nclear, float *kept_diam,
                              uint64_t *kept_cidx, uint64_t kept_cap, uint64_t *tau,
-                             unsigned long long *sc)
+                             unsigned long long *sc, const int64_t *cpos)
 {
-#define RPP_EA(K, G) hipLaunchKernelGGL((k_ext_app<P, K, G>), g, b, 0, s, a, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau, sc)
+#define RPP_EA(K, G, W) hipLaunchKernelGGL((k_ext_app<P, K, G, W>), g, b, 0, s, a, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau, sc, cpos)
+    // RPP_EXT_APP_WAVES (1, 5, 6 or 8): the default form compiled for that
+    // many waves per SIMD (a tuning knob; 5 unless set)
+    const char *we = getenv("RPP_EXT_APP_WAVES");
+    const int waves = we ? atoi(we) : 5;
     switch (group) {
-    case 104: RPP_EA(1, 4); break;
-    case 108: RPP_EA(1, 8); break;
-    case 204: RPP_EA(2, 4); break;
-    case 208: RPP_EA(2, 8); break;
-    case 408: RPP_EA(4, 8); break;
-    default: RPP_EA(4, 4); break;
+    case 104: RPP_EA(1, 4, 1); break;
+    case 108: RPP_EA(1, 8, 1); break;
+    case 204: RPP_EA(2, 4, 1); break;
+    case 208: RPP_EA(2, 8, 1); break;
+    case 408: RPP_EA(4, 8, 1); break;
+    default:
+        if (waves == 5)
+            RPP_EA(4, 4, 5);
+        else if (waves == 6)
+            RPP_EA(4, 4, 6);
+        else if (waves == 8)
+            RPP_EA(4, 4, 8);
+        else
+            RPP_EA(4, 4, 1);
+        break;
     }
 #undef RPP_EA
 }
@@ -3232,15 +3294,16 @@ void launch_ext_scatter_apparent(const ExtArgs &a, int group, const uint64_t *of
                                  float *all_diam, uint64_t *all_cidx, const uint64_t *clear,
                                  int64_t nclear, float *kept_diam, uint64_t *kept_cidx,
                                  uint64_t kept_cap, uint64_t *tau_out,
-                                 unsigned long long *scan_count, hipStream_t s)
+                                 unsigned long long *scan_count, hipStream_t s,
+                                 const int64_t *cpos)
 {
     if (a.npre_count <= 0)
         return;
     dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
     switch (a.p) {
-    case 2: launch_ext_app_p<2>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
-    case 3: launch_ext_app_p<3>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
-    default: launch_ext_app_p<4>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count); break;
+    case 2: launch_ext_app_p<2>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count, cpos); break;
+    case 3: launch_ext_app_p<3>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count, cpos); break;
+    default: launch_ext_app_p<4>(a, group, g, b, s, off_all, all_diam, all_cidx, clear, nclear, kept_diam, kept_cidx, kept_cap, tau_out, scan_count, cpos); break;
     }
 }
 

@@ -102,5 +102,7 @@ std::vector<uint64_t> binomial_table(int n, int kmax);
 uint64_t binom_sat(int n, int k);
 
 size_t workspace_bytes(int n, int maxdim);
+// ResidualProblem::keep_ratio for every host reduction (RPP_KEEP_RATIO).
+double keep_ratio();
 
 }  // namespace rpp

@@ -79,6 +79,7 @@ struct Workspace {
     DevBuf rflags, rexcl, rmat, rvals;  // sparse path: rank-coded diameters
     DevBuf bits;                     // sparse path: neighbour bitsets
     DevBuf clr, clr2, clrv, clrv2;   // sparse path: sorted cleared cidx
+    DevBuf cpos;                     // sparse path: cleared entries below each prefix
     DevBuf cdiam, ccidx, tau;
     DevBuf akey, aval, akey2, aval2;  // apparent pairs
     DevBuf nkey, nval, nkey2, nval2;  // non-apparent columns
@@ -112,7 +113,7 @@ static std::vector<DevBuf *> device_buffers(Workspace &w)
             &w.clr,     &w.clr2,    &w.clrv,    &w.clrv2,  &w.cdiam,  &w.ccidx,   &w.tau,
             &w.akey,    &w.aval,    &w.akey2,   &w.aval2,  &w.nkey,   &w.nval,    &w.nkey2,
             &w.nval2,   &w.clear,   &w.next,    &w.hostpiv, &w.lowc,  &w.lowd,    &w.gedges,
-            &w.gvals,   &w.rscratch, &w.scancnt, &w.dsqp,  &w.cvtx};
+            &w.gvals,   &w.rscratch, &w.scancnt, &w.dsqp,  &w.cvtx,   &w.cpos};
 }
 
 Workspace::Workspace()
@@ -185,6 +186,7 @@ static void plan_limits(Workspace &w, int n, int maxdim)
         w.rvals.hint = (E + 1) * 4;
         w.bits.hint = nn * (size_t)words * 8;
         w.clr.hint = w.clr2.hint = w.clrv.hint = w.clrv2.hint = (cpre + 1) * 8;
+        w.cpos.hint = (cpre + 1) * 8;
     }
 }
 
@@ -483,11 +485,20 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
     if (fused_group > 0) {
         // the apparent test runs in the scatter pass: tau of every kept column
         ALLOC_TRY(ws.tau, (size_t)(*kept + 1) * 8);
+        // RPP_NO_CLEAR_POS=1: the fused scatter searches the clearing set
+        // itself (each wave at its start) instead
+        const char *ncp = getenv("RPP_NO_CLEAR_POS");
+        int64_t *cpos = nullptr;
+        if (nclear > 0 && !(ncp && atoi(ncp) != 0)) {
+            ALLOC_TRY(ws.cpos, (size_t)(np + 1) * 8);
+            cpos = ws.cpos.as<int64_t>();
+            launch_clear_pos(ea, clear, nclear, cpos, s);
+        }
         launch_ext_scatter_apparent(ea, fused_group, ws.toff.as<uint64_t>(),
                                     want_all ? ws.skd[1 - cur].as<float>() : nullptr,
                                     want_all ? ws.skc[1 - cur].as<uint64_t>() : nullptr, clear,
                                     nclear, ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(),
-                                    (uint64_t)*kept, ws.tau.as<uint64_t>(), scan_count, s);
+                                    (uint64_t)*kept, ws.tau.as<uint64_t>(), scan_count, s, cpos);
         if (tm)
             tm->stop();
         return RPP_OK;
@@ -621,6 +632,14 @@ static int64_t open_cap()
 {
     const char *e = getenv("RPP_OPEN_CAP");
     return e ? std::max<int64_t>(1, atoll(e)) : OPEN_CAP;
+}
+// Reduction-matrix form: a kept R_k with more than this many times the
+// keys of its own coboundary is added as D_k (RPP_KEEP_RATIO; 0: never).
+constexpr double KEEP_RATIO = 0.0;
+double keep_ratio()
+{
+    const char *e = getenv("RPP_KEEP_RATIO");
+    return e ? std::max(0.0, atof(e)) : KEEP_RATIO;
 }
 // Additions per slice of a parked column while the gate is closed and the
 // frontier waits on it (RPP_PARK_SLICE overrides it; 0: it waits idle).
@@ -1295,6 +1314,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             H.P.thr = (float)(nranks - 1);
         }
         H.P.oblivious = (a.flags & RPP_OBLIVIOUS_REDUCTION) != 0;
+        H.P.keep_ratio = keep_ratio();
         H.napp = napp;
         H.app_tau = ws.h_app_tau[hb].as<uint64_t>();
         H.app_sigma = ws.h_app_sigma[hb].as<uint64_t>();

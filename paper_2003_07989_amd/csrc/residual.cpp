@@ -818,6 +818,19 @@ public:
         return false;
     }
 
+    // Keys still held (what adding this column copies), and the length of
+    // its first stream (its own coboundary), 0 once it went radix.
+    size_t remaining() const
+    {
+        if (rh)
+            return rh->size();
+        size_t r = 0;
+        for (const Stream<K> &st : streams)
+            r += st.len - st.pos;
+        return r;
+    }
+    size_t first_len() const { return rh || streams.empty() ? 0 : streams[0].len; }
+
 private:
     // At radix_at() streams, and each doubling after: go radix when an
     // eighth of the keys added so far have already reached the front (the
@@ -1792,6 +1805,14 @@ private:
             // oblivious: nothing is kept, a later column adds D_k instead
             reduced.push_back(spec_adds[j] && !P.oblivious ? std::move(state[j]) : nullptr);
             state[j].reset();
+            if (const Column<K> *rk = reduced.back().get()) {
+                // R_k holding many more keys than D_k: a later column adds
+                // D_k and reduces it again lazily rather than copying R_k
+                const size_t d0 = rk->first_len();
+                if (P.keep_ratio > 0.0 && d0 > 0 &&
+                    (double)rk->remaining() > P.keep_ratio * (double)d0)
+                    reduced.back().reset();
+            }
             const int64_t *it = whead.find(lo.cidx);
             if (!it)
                 return;

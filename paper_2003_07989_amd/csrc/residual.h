@@ -61,6 +61,11 @@ struct ResidualProblem {
     // on oblivious reduction makes the pairs and classes identical; the
     // oblivious form needs less memory and may need more additions.
     bool oblivious = false;
+    // > 0, with the reduction-matrix form: a kept R_k whose remaining keys
+    // exceed keep_ratio times the length of its own coboundary D_k is added
+    // as D_k instead (the same result by the paper's lemma on oblivious
+    // reduction, chosen per addition by its cost); 0: always R_k
+    double keep_ratio = 0.0;
     // > 0: every diameter in this problem -- dsq, col_key, col_low_diam,
     // thr -- is an integer rank below 2^rank_bits (<= 24) held as a float
     // (ranks of the distinct edge lengths, ascending), so keys can pack the

@@ -326,6 +326,10 @@ int main(int argc, char **argv)
         // the gate is closed (0: parked columns wait idle)
         if (const char *e = getenv("RPP_TEST_PARK_SLICE"))
             P.park_slice = atoll(e);
+        // RPP_TEST_KEEP_RATIO: add D_k for kept R_k holding more than this
+        // many times D_k's keys (0: always R_k)
+        if (const char *e = getenv("RPP_TEST_KEEP_RATIO"))
+            P.keep_ratio = atof(e);
         ResidualResult R;
         if (sched >= 2) {
             std::unordered_set<uint64_t> ph(prev_host.begin(), prev_host.end());

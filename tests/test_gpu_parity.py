@@ -410,6 +410,31 @@ def test_sparse_apparent_kernel_forms_match_oracle(rpp, monkeypatch, case):
             assert sc == scans, (name, grp, unfused)
 
 
+@pytest.mark.parametrize("waves,search", [("1", "0"), ("6", "0"), ("8", "0"), ("5", "1")])
+def test_fused_sparse_kernel_occupancy_forms_match_oracle(rpp, monkeypatch, waves, search):
+    """The fused sparse enumeration + apparent kernel compiled for 1 (the
+    compiler's choice), 6 or 8 waves per SIMD instead of the default 5
+    (registers spilled to reach them), and with each wave
+    searching the clearing set itself instead of reading its precomputed
+    position: the oracle's pairs and the default form's scan tally."""
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    monkeypatch.setenv("RPP_COUNT_SCANS", "1")
+    monkeypatch.delenv("RPP_APPARENT_GROUP", raising=False)
+    for name, d, n, maxdim, thr in SPARSE_CASES[::3]:
+        red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+        monkeypatch.delenv("RPP_EXT_APP_WAVES", raising=False)
+        monkeypatch.delenv("RPP_NO_CLEAR_POS", raising=False)
+        base = rpp.barcodes(d, maxdim, thr, flags=f)
+        monkeypatch.setenv("RPP_EXT_APP_WAVES", waves)
+        monkeypatch.setenv("RPP_NO_CLEAR_POS", search)
+        g = rpp.barcodes(d, maxdim, thr, flags=f)
+        for p in range(1, maxdim + 1):
+            gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+            es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+            assert gs == es, (name, waves, p)
+            assert g.stats[p]["n_scanned"] == base.stats[p]["n_scanned"], (name, waves, p)
+
+
 @pytest.mark.parametrize("case", SPARSE_CASES[::2], ids=["rk_" + c[0] for c in SPARSE_CASES[::2]])
 def test_rank_coded_host_keys_match_oracle(rpp, case, monkeypatch):
     """Sparse path with the host reduction on rank-coded diameters and

@@ -190,6 +190,25 @@ def test_parked_slices_match_oracle(driver, mode, slice_, polls):
             assert got_e[p] == exp_e[p], (name, mode, slice_, polls, p)
 
 
+@pytest.mark.parametrize("ratio", ["0.01", "1", "4"])
+@pytest.mark.parametrize("mode", [0, 3, 19, 83], ids=["plain", "late-drops", "bitsets-late-drops",
+                                                      "packed-late-drops"])
+def test_keep_ratio_matches_oracle(driver, mode, ratio):
+    """The reduction-matrix form choosing per pivot column between its kept
+    R_k and its coboundary D_k (D_k when R_k holds more than `ratio` times
+    D_k's keys; 0.01 takes D_k almost always, a mixed choice in between):
+    the same pairs and classes as the oracle, whatever the mix."""
+    for name, build, n, maxdim, thr in CASES:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        got_p, got_e = _run(driver, d, n, maxdim, thr, mode, env={"RPP_TEST_KEEP_RATIO": ratio})
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, ratio, p)
+            assert got_e[p] == exp_e[p], (name, mode, ratio, p)
+
+
 @pytest.fixture(scope="module")
 def sanitized_driver():
     """The same driver and reduction built with AddressSanitizer and
