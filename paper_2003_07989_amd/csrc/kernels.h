@@ -232,7 +232,8 @@ void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s);
 void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
                         uint64_t *all_cidx, const uint64_t *clear, int64_t nclear,
                         float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
-                        uint64_t *kept_vtx, hipStream_t s);
+                        uint64_t *kept_vtx, hipStream_t s,
+                        const int64_t *cpos = nullptr);
 // The scatter pass with the apparent-pair test of every kept extension fused
 // in (two-phase form; group = 100 K + G as for launch_apparent_sparse):
 // tau_out[kept position] = its apparent partner or NONE; scan_count as for

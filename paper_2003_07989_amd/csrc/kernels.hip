@@ -2384,16 +2384,22 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
                                              const uint64_t *__restrict__ clear, int64_t nclear,
                                              float *__restrict__ kept_diam,
                                              uint64_t *__restrict__ kept_cidx, uint64_t kept_cap,
-                                             uint64_t *__restrict__ kept_vtx)
+                                             uint64_t *__restrict__ kept_vtx,
+                                             const int64_t *__restrict__ cpos_all)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t pre = (blk * blockDim.x + threadIdx.x) / WAVE;
+    // the wave's prefix, wave-uniform: what derives from it sits in scalar
+    // registers
+    const int pre = __builtin_amdgcn_readfirstlane((int)((blk * blockDim.x + threadIdx.x) / WAVE));
     if (pre >= a.npre_count)
         return;  // whole waves leave together
     const Binom B{a.binom, a.n + 1};
     int u[P];  // prefix vertices, decreasing; u[P-1] = v_1
     decode<P - 1>(B, a.pre_cidx[pre], a.n, u);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        u[i] = __builtin_amdgcn_readfirstlane(u[i]);
     // cidx of (u, v0) = sum_i C(u_i, P+1-i) + v0
     uint64_t shifted = 0;
 #pragma unroll
@@ -2433,7 +2439,8 @@ __global__ __launch_bounds__(256) void k_ext(ExtArgs a, uint32_t *__restrict__ c
     uint64_t run = off_all[pre];
     // cleared entries below this prefix's first extension: the kept entries
     // of the prefix start that many places before its extensions
-    int64_t cpos = nclear ? wave_lower_bound(clear, nclear, shifted) : 0;
+    int64_t cpos = cpos_all ? cpos_all[pre]
+                            : (nclear ? wave_lower_bound(clear, nclear, shifted) : 0);
     uint64_t krun = run - (uint64_t)cpos;
     for (int wb = 0; wb * 64 < limit; wb += WAVE) {
         const int word = wb + lane;
@@ -2545,13 +2552,13 @@ void launch_ext_count(const ExtArgs &a, uint32_t *cnt_all, hipStream_t s)
         return;
     dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
     RPP_EXT_LAUNCH(false, cnt_all, nullptr, nullptr, nullptr, nullptr, (int64_t)0, nullptr,
-                   nullptr, (uint64_t)0, nullptr)
+                   nullptr, (uint64_t)0, nullptr, nullptr)
 }
 
 void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_diam,
                         uint64_t *all_cidx, const uint64_t *clear, int64_t nclear,
                         float *kept_diam, uint64_t *kept_cidx, uint64_t kept_cap,
-                        uint64_t *kept_vtx, hipStream_t s)
+                        uint64_t *kept_vtx, hipStream_t s, const int64_t *cpos)
 {
     if (a.npre_count <= 0)
         return;
@@ -2559,7 +2566,7 @@ void launch_ext_scatter(const ExtArgs &a, const uint64_t *off_all, float *all_di
         kept_vtx = nullptr;
     dim3 g((unsigned)((a.npre_count * WAVE + 255) / 256)), b(256);
     RPP_EXT_LAUNCH(true, nullptr, off_all, all_diam, all_cidx, clear, nclear, kept_diam,
-                   kept_cidx, kept_cap, kept_vtx)
+                   kept_cidx, kept_cap, kept_vtx, cpos)
 }
 
 // Youngest-facet condition of the apparent pairs lemma for sigma (vertices

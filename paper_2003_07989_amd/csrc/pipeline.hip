@@ -482,18 +482,19 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
     }
     ALLOC_TRY(ws.cdiam, (size_t)(*kept + 1) * 4);
     ALLOC_TRY(ws.ccidx, (size_t)(*kept + 1) * 8);
+    // each prefix's place in the clearing set, found beforehand by one
+    // thread per prefix; RPP_NO_CLEAR_POS=1: each scatter wave searches the
+    // clearing set itself at its start instead
+    const char *ncp = getenv("RPP_NO_CLEAR_POS");
+    int64_t *cpos = nullptr;
+    if (nclear > 0 && !(ncp && atoi(ncp) != 0)) {
+        ALLOC_TRY(ws.cpos, (size_t)(np + 1) * 8);
+        cpos = ws.cpos.as<int64_t>();
+        launch_clear_pos(ea, clear, nclear, cpos, s);
+    }
     if (fused_group > 0) {
         // the apparent test runs in the scatter pass: tau of every kept column
         ALLOC_TRY(ws.tau, (size_t)(*kept + 1) * 8);
-        // RPP_NO_CLEAR_POS=1: the fused scatter searches the clearing set
-        // itself (each wave at its start) instead
-        const char *ncp = getenv("RPP_NO_CLEAR_POS");
-        int64_t *cpos = nullptr;
-        if (nclear > 0 && !(ncp && atoi(ncp) != 0)) {
-            ALLOC_TRY(ws.cpos, (size_t)(np + 1) * 8);
-            cpos = ws.cpos.as<int64_t>();
-            launch_clear_pos(ea, clear, nclear, cpos, s);
-        }
         launch_ext_scatter_apparent(ea, fused_group, ws.toff.as<uint64_t>(),
                                     want_all ? ws.skd[1 - cur].as<float>() : nullptr,
                                     want_all ? ws.skc[1 - cur].as<uint64_t>() : nullptr, clear,
@@ -510,7 +511,7 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
                        want_all ? ws.skd[1 - cur].as<float>() : nullptr,
                        want_all ? ws.skc[1 - cur].as<uint64_t>() : nullptr, clear, nclear,
                        ws.cdiam.as<float>(), ws.ccidx.as<uint64_t>(), (uint64_t)*kept,
-                       vtx ? ws.cvtx.as<uint64_t>() : nullptr, s);
+                       vtx ? ws.cvtx.as<uint64_t>() : nullptr, s, cpos);
     ws.cvtx_ok = vtx;
     if (tm)
         tm->stop();
@@ -1123,11 +1124,14 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                        ws.binom.as<uint64_t>(), ws.skd[cur].as<float>(),
                        ws.skc[cur].as<uint64_t>(), nskel};
             int64_t nall = 0;
-            // the apparent test fused into the scatter pass (two-phase forms,
-            // columns in cidx order); RPP_SPARSE_UNFUSED=1 runs it apart
+            // RPP_SPARSE_FUSED=1: the apparent test fused into the scatter
+            // pass (two-phase forms, columns in cidx order).  Not the
+            // default: with one wave per prefix about half the lanes idle
+            // in the test, and the standalone kernel after the scatter is
+            // faster (sphere dimension 2: 0.50 + 0.43 ms apart, 1.23 fused)
             const int sg = sparse_group(a.apparent_group);
-            const char *uf = getenv("RPP_SPARSE_UNFUSED");
-            fused = sg >= 100 && !(a.flags & RPP_SORT_FIRST) && !(uf && atoi(uf) != 0);
+            const char *fu = getenv("RPP_SPARSE_FUSED");
+            fused = sg >= 100 && !(a.flags & RPP_SORT_FIRST) && fu && atoi(fu) != 0;
             unsigned long long *sc = nullptr;
             if (fused && a.count_scans) {
                 ALLOC_TRY(ws.scancnt, (size_t)SCAN_COUNTERS * 8);

@@ -392,10 +392,10 @@ def test_sparse_apparent_kernel_forms_match_oracle(rpp, monkeypatch, case):
     monkeypatch.setenv("RPP_COUNT_SCANS", "1")
     for grp in SPARSE_GROUPS:
         for unfused in ("0", "1"):
-            if unfused == "1" and grp < 100:
+            if unfused == "0" and grp < 100:
                 continue  # the single-phase forms always run apart
             monkeypatch.setenv("RPP_APPARENT_GROUP", str(grp))
-            monkeypatch.setenv("RPP_SPARSE_UNFUSED", unfused)
+            monkeypatch.setenv("RPP_SPARSE_FUSED", "0" if unfused == "1" else "1")
             g = rpp.barcodes(d, maxdim, thr, flags=f)
             for p in range(1, maxdim + 1):
                 gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
@@ -419,6 +419,7 @@ def test_fused_sparse_kernel_occupancy_forms_match_oracle(rpp, monkeypatch, wave
     position: the oracle's pairs and the default form's scan tally."""
     f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
     monkeypatch.setenv("RPP_COUNT_SCANS", "1")
+    monkeypatch.setenv("RPP_SPARSE_FUSED", "1")
     monkeypatch.delenv("RPP_APPARENT_GROUP", raising=False)
     for name, d, n, maxdim, thr in SPARSE_CASES[::3]:
         red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
