@@ -346,6 +346,46 @@ static size_t upfront_limit()
     return e ? (size_t)strtoull(e, nullptr, 10) : ((size_t)1 << 30);
 }
 
+// Waits for the work queued on s by polling an event for up to 2 ms (most
+// waits in a call are for a few hundred microseconds of kernels), then in
+// the runtime's blocking wait.  The blocking wait alone left, about once in
+// 60 calls, a 6-7 ms gap between two stages of a dimension: the thread woke
+// that late after the GPU had finished (torus, 124 calls with the polling:
+// none).  RPP_SPIN_SYNC=0: the blocking wait only; =2: poll without limit.
+static hipError_t stream_wait(hipStream_t s)
+{
+    static const int mode = [] {
+        const char *e = getenv("RPP_SPIN_SYNC");
+        return e ? atoi(e) : 1;
+    }();
+    if (mode == 0)
+        return hipStreamSynchronize(s);
+    thread_local hipEvent_t ev = nullptr;
+    thread_local int ev_dev = -1;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (!ev || ev_dev != dev) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return e;
+        ev_dev = dev;
+    }
+    e = hipEventRecord(ev, s);
+    if (e != hipSuccess)
+        return e;
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned polls = 0;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+        __builtin_ia32_pause();
+        if (mode == 1 && (++polls & 255u) == 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+            return hipStreamSynchronize(s);
+    }
+    return e;
+}
+
 // Stable compaction of the p-simplices (dense enumeration) into ws.cdiam /
 // ws.ccidx; returns the kept count through *kept and the counters.
 // ncleared: the number of set bits of ea.clear, all of them candidates
@@ -388,7 +428,7 @@ static int enumerate_dense(Workspace &ws, const EnumArgs &ea, hipStream_t s, int
     auto read_counts = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(h + 1, stats, 16, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(stream_wait(s));
         *kept = tiles ? (int64_t)h[0] : 0;
         *nthr = h[1];
         *nclr = h[2];
@@ -468,7 +508,7 @@ static int enumerate_sparse(Workspace &ws, const ExtArgs &ea, const uint64_t *cl
                           ws.scan.as<uint64_t>(), s);
     uint64_t *h = ws.h_small.as<uint64_t>();
     HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + np, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     const int64_t nall = np ? (int64_t)h[0] : 0;
     *all = nall;
     if (nclear > nall) {
@@ -608,7 +648,7 @@ static int apparent_and_partition(Workspace &ws, int64_t ncols, int n, int p, in
         t_part->stop();
     uint64_t *h = ws.h_small.as<uint64_t>();
     HIP_TRY(hipMemcpyAsync(h, ws.toff.as<uint64_t>() + tiles, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     *napp = ncols > 0 ? (int64_t)h[0] : 0;
     if (scanned) {
         std::vector<unsigned long long> c(SCAN_COUNTERS);
@@ -689,7 +729,7 @@ static int choose_group(Workspace &ws, int64_t ncols, int n, int p, hipStream_t 
                     ws.binom.as<uint64_t>(), 8, ws.tau.as<uint64_t>(), sc, s);
     std::vector<unsigned long long> c(SCAN_COUNTERS);
     HIP_TRY(hipMemcpyAsync(c.data(), sc, (size_t)SCAN_COUNTERS * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     double tot = 0;
     for (unsigned long long x : c)
         tot += (double)x;
@@ -766,7 +806,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     launch_min(ws.rowmax.as<float>(), n, radius, s);
     uint32_t *hs = ws.h_small.as<uint32_t>();
     HIP_TRY(hipMemcpyAsync(hs, ws.scal.p, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     if (hs[0]) {
         err = "distance matrix holds a NaN, infinite or negative entry";
         return RPP_E_DATA;
@@ -835,7 +875,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
                        ws.dedges.as<uint64_t>(), counters, ws.ufs.as<int>(), s);
         int hc[2];
         HIP_TRY(hipMemcpyAsync(hc, counters, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(stream_wait(s));
         mst_edges = hc[1];
         DimOut &d0 = out.dims[0];
         d0.death.resize(hc[0]);
@@ -943,7 +983,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             uint64_t *hs = ws.h_small.as<uint64_t>();
             HIP_TRY(hipMemcpyAsync(hs, ws.rexcl.as<uint64_t>() + nedges, 8,
                                    hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(stream_wait(s));
             nranks = (int64_t)hs[0];
             ALLOC_TRY(ws.rmat, (size_t)n * n * 4);
             ALLOC_TRY(ws.rvals, (size_t)(nranks + 1) * 4);
@@ -953,7 +993,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             rank_vals.resize((size_t)nranks);
             HIP_TRY(hipMemcpyAsync(rank_vals.data(), ws.rvals.p, (size_t)nranks * 4,
                                    hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(stream_wait(s));
             ranks = true;
         }
     }
@@ -978,7 +1018,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         if (nedges)
             HIP_TRY(hipMemcpyAsync(ws.h_nbd.p, src, (size_t)(2 * nedges) * 4,
                                    hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));  // the bitsets too, for the positions
+        HIP_TRY(stream_wait(s));  // the bitsets too, for the positions
         ws.h_npre.resize((size_t)n * words);
         packed_row_prefix(h_bits, n, words, ws.h_npre.data());
         hdist.bits = h_bits;
@@ -1058,9 +1098,11 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
         Dq.st.ms_host = H.ms_spec + H.ms_exact;
         if (trace)
             fprintf(stderr,
-                    "rpp trace: dim %d gpu %.3f ms | speculative %.3f ms | exact %.3f ms "
+                    "rpp trace: dim %d gpu %.3f ms (enumerate %.3f, apparent %.3f, partition "
+                    "%.3f, sort %.3f) | speculative %.3f ms | exact %.3f ms "
                     "(from %.3f to %.3f ms) | joined at %.3f ms | %lld columns, %lld dropped\n",
-                    q, Dq.st.ms_gpu, H.ms_spec, H.ms_exact, H.t_exact_start, H.t_exact_end,
+                    q, Dq.st.ms_gpu, Dq.st.ms_enumerate, Dq.st.ms_apparent, Dq.st.ms_partition,
+                    Dq.st.ms_sort, H.ms_spec, H.ms_exact, H.t_exact_start, H.t_exact_end,
                     since(std::chrono::steady_clock::now()), (long long)H.P.ncols,
                     (long long)H.ndrop);
         for (size_t i = 0; i < RR.sigma.size(); ++i)
@@ -1269,7 +1311,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
             }
         }
         tg.stop();
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(stream_wait(s));
         D.st.ms_gpu = tg.ms();
         D.st.ms_enumerate = t_enum.ms();
         D.st.ms_apparent = t_app.ms();
@@ -1410,7 +1452,7 @@ int run_pipeline(const RunArgs &a, RunOut &out, std::string &err)
     if (trace)
         fprintf(stderr, "rpp trace: n %d maxdim %d done at %.3f ms\n", n, maxdim,
                 since(std::chrono::steady_clock::now()));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     return RPP_OK;
 }
 
@@ -1418,7 +1460,7 @@ int run_pdist(const float *pts, int n, int d, float *dist, hipStream_t s, std::s
 {
     launch_pdist(pts, n, d, dist, s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     return RPP_OK;
 }
 
@@ -1436,7 +1478,7 @@ int run_backward(const float *pts, int n, int d, const std::vector<uint64_t> &ed
     }
     launch_edge_grad(pts, n, d, ws.gedges.as<uint64_t>(), ws.gvals.as<float>(), m, grad, s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     return RPP_OK;
 }
 
@@ -1459,7 +1501,7 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
     ws.dsqp_ready = false;
     uint32_t hb = 0;
     HIP_TRY(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     if (hb) {
         err = "distance matrix holds a NaN, infinite or negative entry";
         return RPP_E_DATA;
@@ -1506,7 +1548,7 @@ int run_apparent_only(const float *dcond_dev, int n, int p, float threshold, hip
                                    hipMemcpyDeviceToHost, s));
         }
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     if (st) {
         memset(st, 0, sizeof(*st));
         st->n_candidates = (int64_t)ncand;
