@@ -626,7 +626,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             HIP_TRY(hipMemcpyAsync(W.h_dsq.p, W.dsq.p, (size_t)nb * n * n * 4,
                                    hipMemcpyDeviceToHost, s));
         }
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(stream_wait(s));
         const float gpu_ms = tg.ms();
         if (p == 1) {
             for (int c = 0; c < nb; ++c)
@@ -687,7 +687,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             HIP_TRY(hipMemcpyAsync(hv.data(), W.pcidx.p, (size_t)tot * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(hl.data(), W.plow.p, (size_t)tot * 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(hld.data(), W.plowd.p, (size_t)tot * 4, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(stream_wait(s));
         }
         // per-cloud host reductions, in parallel over clouds
         std::vector<ResidualResult> RR(nb);
@@ -771,7 +771,7 @@ int run_batch(const BatchArgs &a, std::vector<RunOut> &outs, std::string &err)
             }
         }
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(stream_wait(s));
     return RPP_OK;
 }
 

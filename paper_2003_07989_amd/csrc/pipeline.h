@@ -104,5 +104,8 @@ uint64_t binom_sat(int n, int k);
 size_t workspace_bytes(int n, int maxdim);
 // ResidualProblem::keep_ratio for every host reduction (RPP_KEEP_RATIO).
 double keep_ratio();
+// Waits for the work queued on s: polls an event for up to 2 ms, then the
+// runtime's blocking wait (RPP_SPIN_SYNC=0: the blocking wait only).
+hipError_t stream_wait(hipStream_t s);
 
 }  // namespace rpp

@@ -352,7 +352,7 @@ static size_t upfront_limit()
 // 60 calls, a 6-7 ms gap between two stages of a dimension: the thread woke
 // that late after the GPU had finished (torus, 124 calls with the polling:
 // none).  RPP_SPIN_SYNC=0: the blocking wait only; =2: poll without limit.
-static hipError_t stream_wait(hipStream_t s)
+hipError_t stream_wait(hipStream_t s)
 {
     static const int mode = [] {
         const char *e = getenv("RPP_SPIN_SYNC");
