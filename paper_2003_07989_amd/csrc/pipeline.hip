@@ -684,7 +684,10 @@ double keep_ratio()
 }
 // Additions per slice of a parked column while the gate is closed and the
 // frontier waits on it (RPP_PARK_SLICE overrides it; 0: it waits idle).
-constexpr int64_t PARK_SLICE = 256;
+// Off: on the torus the slices go to columns the gate then drops and slow
+// the previous dimension's reduction beside them (9.0 against 9.4 ms per
+// step); on the sphere they change nothing measurable.
+constexpr int64_t PARK_SLICE = 0;
 static int64_t park_slice()
 {
     const char *e = getenv("RPP_PARK_SLICE");

@@ -51,7 +51,7 @@ struct ResidualProblem {
     // finish_gated: while the gate is closed and every other column waits
     // on it, the parked column nearest the frontier goes on this many
     // additions at a time instead of idling (0: parked columns wait)
-    int64_t park_slice = 256;
+    int64_t park_slice = 0;
     // How a column adds a host pivot column k (paper, "Reduction Matrix vs.
     // Oblivious Matrix Reduction").  false: k's reduced column R_k, kept from
     // k's own reduction as the streams of the coboundaries it summed (the
