@@ -436,6 +436,28 @@ def test_fused_sparse_kernel_occupancy_forms_match_oracle(rpp, monkeypatch, wave
             assert g.stats[p]["n_scanned"] == base.stats[p]["n_scanned"], (name, waves, p)
 
 
+@pytest.mark.parametrize("search", ["0", "1"])
+def test_sparse_scatter_clearing_positions_match_oracle(rpp, monkeypatch, search):
+    """The sparse extension scatter with each prefix's place in the clearing
+    set read from the precomputed positions (default) or searched by the
+    wave itself (RPP_NO_CLEAR_POS=1): the oracle's pairs, and the same kept
+    and cleared counts."""
+    f = rpp.RPP_FORCE_SPARSE | rpp.RPP_WANT_PAIRS | rpp.RPP_NO_ENCLOSING_RADIUS
+    monkeypatch.delenv("RPP_SPARSE_FUSED", raising=False)
+    for name, d, n, maxdim, thr in SPARSE_CASES:
+        red = oracle.reduce(d, n, maxdim, thr, clearing=n > 33)
+        monkeypatch.setenv("RPP_NO_CLEAR_POS", search)
+        g = rpp.barcodes(d, maxdim, thr, flags=f)
+        monkeypatch.setenv("RPP_NO_CLEAR_POS", "1" if search == "0" else "0")
+        h = rpp.barcodes(d, maxdim, thr, flags=f)
+        for p in range(1, maxdim + 1):
+            gs = set(zip(g.pairs[p][0].tolist(), g.pairs[p][1].tolist()))
+            es = set(zip(red[p]["sigma"].tolist(), red[p]["tau"].tolist()))
+            assert gs == es, (name, search, p)
+            for k in ("n_kept", "n_cleared", "n_candidates"):
+                assert g.stats[p][k] == h.stats[p][k], (name, search, p, k)
+
+
 @pytest.mark.parametrize("case", SPARSE_CASES[::2], ids=["rk_" + c[0] for c in SPARSE_CASES[::2]])
 def test_rank_coded_host_keys_match_oracle(rpp, case, monkeypatch):
     """Sparse path with the host reduction on rank-coded diameters and
