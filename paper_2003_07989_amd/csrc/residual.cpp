@@ -339,6 +339,12 @@ public:
     {
         used_ += (count * sizeof(K) + 63) & ~(size_t)63;
     }
+    // Takes back the last commit (its keys stay readable until the next
+    // reserve).
+    template <class K> void uncommit(size_t count)
+    {
+        used_ -= (count * sizeof(K) + 63) & ~(size_t)63;
+    }
 
 private:
     BlockSink *sink_;
@@ -687,6 +693,22 @@ template <class K> struct RadixHeap {
             drop(i);
         }
     }
+    // Keys just above the low, usually the next lows: up to w of the run
+    // behind it, then, when the run holds fewer, the lowest bucket if it
+    // holds at most bmax keys (unordered; out has room for w + bmax).
+    size_t ahead(K *out, size_t w, size_t bmax) const
+    {
+        size_t c = 0;
+        for (size_t j = rh + 1; j < run.size() && c < w; ++j)
+            out[c++] = run[j];
+        if (c < w) {
+            const int i = first_above_zero();
+            if (i < NB && b[i].size() <= bmax)
+                for (K k : b[i])
+                    out[c++] = k;
+        }
+        return c;
+    }
     template <class F> void for_each(F f) const
     {
         for (size_t j = rh; j < run.size(); ++j)
@@ -830,6 +852,9 @@ public:
         return r;
     }
     size_t first_len() const { return rh || streams.empty() ? 0 : streams[0].len; }
+    bool radix() const { return (bool)rh; }
+    // Radix columns: keys just above the low (RadixHeap::ahead); 0 otherwise.
+    size_t ahead(K *out, size_t w, size_t bmax) const { return rh ? rh->ahead(out, w, bmax) : 0; }
 
 private:
     // At radix_at() streams, and each doubling after: go radix when an
@@ -1495,6 +1520,36 @@ private:
         const std::function<void(int)> *fn = nullptr;
         int active = 0;  // threads inside fn, the caller excluded
     };
+
+public:
+    // A job the caller does not take part in: launch() offers fn(tid) to the
+    // workers (those idle join), join() closes it and waits until every
+    // thread that entered fn has left it.
+    class Async {
+        friend class Pool;
+        Job job;
+        std::function<void(int)> fn;
+    };
+    void launch(Async &a, std::function<void(int)> fn)
+    {
+        a.fn = std::move(fn);
+        a.job.fn = &a.fn;
+        if (workers_.empty())
+            return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            open_.push_back(&a.job);
+        }
+        cv_.notify_all();
+    }
+    void join(Async &a)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        close_locked(&a.job);
+        done_.wait(lk, [&] { return a.job.active == 0; });
+    }
+
+private:
     // Threads: the CPUs this process may use (affinity mask, and the
     // cgroup CPU quota when one is set), less one for the thread that
     // enqueues GPU work while the pool is busy, at most 16.
@@ -1582,6 +1637,176 @@ private:
     std::vector<Job *> open_;
     bool stop_ = false;
 };
+
+// Look-ahead for one long column, a chain of additions whose every step
+// waits on the previous one's low (the essential class of a sphere: ~19,000
+// additions, almost all of them apparent partners).  Such a column's next
+// lows are usually among the keys just above its current low, so helper
+// threads take those keys as they appear, find their apparent partners and
+// generate the partners' coboundaries ahead of the column's thread, which
+// uses a result when its low has one and otherwise computes as before.
+// Both sides compute the same pure function of the key, so the additions
+// are the ones the column would make alone.  64-bit keys only.
+//
+// Requests: a ring of keys written by the column's thread only; a helper
+// that falls behind skips the oldest (a skipped key is computed by the
+// column's thread if it becomes a low).  Results: direct-mapped slots under
+// a sequence lock (odd while a helper writes one), every field a relaxed
+// atomic; the reader copies a slot and keeps it only if the sequence number
+// did not move meanwhile.
+struct ChainAssist {
+    static constexpr size_t RING = 256;
+    static constexpr size_t NSLOT = 64;
+    static constexpr size_t CAP = 256;  // longest coboundary handed over
+    static constexpr uint64_t NOT_APPARENT = ~0ull;
+    struct Slot {
+        std::atomic<uint32_t> seq{0};
+        std::atomic<uint64_t> tau{~0ull};
+        std::atomic<uint64_t> sigma{0};
+        std::atomic<uint32_t> len{0}, ties{0};
+        std::atomic<uint64_t> keys[CAP];
+    };
+    std::atomic<uint64_t> ring[RING];
+    std::atomic<uint64_t> head{0}, claim{0};
+    std::atomic<uint64_t> finished{0};  // requests answered or skipped
+    std::atomic<int> helping{0};         // helpers inside help()
+    std::atomic<bool> stop{false};
+    std::unique_ptr<Slot[]> slots{new Slot[NSLOT]};
+    uint64_t asked[256];  // the column thread's recent requests
+
+    ChainAssist()
+    {
+        for (auto &r : ring)
+            r.store(0, std::memory_order_relaxed);
+        for (auto &a : asked)
+            a = ~0ull;
+    }
+    static size_t slot_of(uint64_t tau) { return (size_t)((tau * 0x9E3779B97F4A7C15ull) >> 58); }
+
+    // Column thread: ask for key k (skipped when asked recently).
+    void publish(uint64_t k)
+    {
+        const size_t a = (size_t)((k * 0xC2B2AE3D27D4EB4Full) >> 56);
+        if (asked[a] == k)
+            return;
+        asked[a] = k;
+        const uint64_t h = head.load(std::memory_order_relaxed);
+        ring[h % RING].store(k, std::memory_order_relaxed);
+        head.store(h + 1, std::memory_order_release);
+    }
+    // Column thread: the result for cofacet tau, if a helper has one:
+    // sigma (NOT_APPARENT when tau has no apparent partner) and its
+    // coboundary in buf[0..len), the first `ties` keys ascending.
+    bool take(uint64_t tau, uint64_t &sigma, uint64_t *buf, size_t &len, size_t &ties) const
+    {
+        const Slot &s = slots[slot_of(tau)];
+        const uint32_t s1 = s.seq.load(std::memory_order_acquire);
+        if ((s1 & 1) || s1 == 0 || s.tau.load(std::memory_order_relaxed) != tau)
+            return false;
+        sigma = s.sigma.load(std::memory_order_relaxed);
+        len = s.len.load(std::memory_order_relaxed);
+        ties = s.ties.load(std::memory_order_relaxed);
+        if (len > CAP || ties > len)
+            return false;
+        for (size_t i = 0; i < len; ++i)
+            buf[i] = s.keys[i].load(std::memory_order_relaxed);
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return s.seq.load(std::memory_order_relaxed) == s1;
+    }
+    // Helper thread, until stop: compute(k, tau, sigma, e, len, ties) for
+    // each requested key; false from it means nothing to hand over.
+    template <class F> void help(F compute)
+    {
+        helping.fetch_add(1, std::memory_order_relaxed);
+        while (!stop.load(std::memory_order_acquire)) {
+            uint64_t c = claim.load(std::memory_order_relaxed);
+            const uint64_t h = head.load(std::memory_order_acquire);
+            if (c >= h) {
+                _mm_pause();
+                continue;
+            }
+            if (h - c > RING / 2) {  // far behind: only recent keys matter
+                if (claim.compare_exchange_weak(c, h - RING / 4, std::memory_order_relaxed))
+                    finished.fetch_add(h - RING / 4 - c, std::memory_order_release);
+                continue;
+            }
+            if (!claim.compare_exchange_weak(c, c + 1, std::memory_order_relaxed))
+                continue;
+            answer(ring[c % RING].load(std::memory_order_relaxed), compute);
+            finished.fetch_add(1, std::memory_order_release);
+        }
+    }
+    template <class F> void answer(uint64_t k, F &compute)
+    {
+        uint64_t tau = 0, sigma = NOT_APPARENT;
+        const uint64_t *e = nullptr;
+        size_t len = 0, ties = 0;
+        if (!compute(k, tau, sigma, e, len, ties) || len > CAP)
+            return;
+        Slot &s = slots[slot_of(tau)];
+        uint32_t q = s.seq.load(std::memory_order_relaxed);
+        if ((q & 1) || !s.seq.compare_exchange_strong(q, q + 1, std::memory_order_relaxed))
+            return;  // another helper is writing this slot
+        std::atomic_thread_fence(std::memory_order_release);
+        s.tau.store(tau, std::memory_order_relaxed);
+        s.sigma.store(sigma, std::memory_order_relaxed);
+        s.len.store((uint32_t)len, std::memory_order_relaxed);
+        s.ties.store((uint32_t)ties, std::memory_order_relaxed);
+        for (size_t i = 0; i < len; ++i)
+            s.keys[i].store(e[i], std::memory_order_relaxed);
+        s.seq.store(q + 2, std::memory_order_release);
+    }
+    // Tests: let the helpers answer every request so far (none when no
+    // helper has joined; bounded).
+    void settle(int64_t spins) const
+    {
+        while (helping.load(std::memory_order_relaxed) > 0 &&
+               finished.load(std::memory_order_acquire) < head.load(std::memory_order_relaxed) &&
+               spins-- > 0)
+            _mm_pause();
+    }
+    // Already answered (a slot holds tau): the helper skips it.
+    bool has(uint64_t tau) const
+    {
+        const Slot &s = slots[slot_of(tau)];
+        return !(s.seq.load(std::memory_order_acquire) & 1) &&
+               s.tau.load(std::memory_order_relaxed) == tau;
+    }
+};
+
+// Helper threads a long column's look-ahead may take: RPP_CHAIN_HELPERS
+// (0: none), default 2.
+int chain_helpers()
+{
+    static const int v = [] {
+        const char *e = getenv("RPP_CHAIN_HELPERS");
+        const int x = e ? atoi(e) : 2;
+        return std::max(0, std::min(x, 8));
+    }();
+    return v;
+}
+// Tests: RPP_TEST_CHAIN_SETTLE=1 has a column wait (boundedly) after each
+// request for the helpers' answers, so that handed-over coboundaries are
+// used even on small inputs.
+bool chain_test_settle()
+{
+    static const bool v = [] {
+        const char *e = getenv("RPP_TEST_CHAIN_SETTLE");
+        return e && atoi(e) != 0;
+    }();
+    return v;
+}
+// Additions a column makes in one call before it takes helpers (once it is
+// a radix column): RPP_CHAIN_AFTER (tests), default 128.
+int64_t chain_assist_after()
+{
+    static const int64_t v = [] {
+        const char *e = getenv("RPP_CHAIN_AFTER");
+        const long x = e ? atol(e) : 128;
+        return (int64_t)std::max(0L, x);
+    }();
+    return v;
+}
 
 }  // namespace
 
@@ -1876,6 +2101,55 @@ private:
         std::atomic<int64_t> look_hash{0}, look_app_b{0};
         bool open = !known;  // read by advance(); set before each round
         int64_t cap_now = cap;  // the additions a column may reach while open
+        std::atomic<int64_t> n_handed{0}, n_assisted{0};  // RPP_TRACE counts
+        // Look-ahead helpers for a long column (64-bit keys): at most
+        // chain_helpers() idle workers, once a call has made ASSIST_AFTER
+        // additions on a radix column.
+        const int64_t ASSIST_AFTER = chain_assist_after();
+        const int helpers =
+            sizeof(K) == 8 && P.parallel ? std::min(chain_helpers(), pool.size() - 1) : 0;
+        struct Assisted {  // stops and joins the helpers on every way out
+            Pool &pool;
+            std::unique_ptr<ChainAssist> as;
+            Pool::Async job;
+            std::vector<uint64_t> buf;  // a handed-over coboundary
+            explicit Assisted(Pool &p) : pool(p), as(new ChainAssist()), buf(ChainAssist::CAP) {}
+            ~Assisted()
+            {
+                as->stop.store(true, std::memory_order_release);
+                pool.join(job);
+            }
+        };
+        auto start_assist = [&](std::unique_ptr<Assisted> &A) {
+            A.reset(new Assisted(pool));
+            ChainAssist *as = A->as.get();
+            auto joined = std::make_shared<std::atomic<int>>(0);
+            pool.launch(A->job, [this, as, joined, helpers, &pivots](int) {
+                if (joined->fetch_add(1) >= helpers)
+                    return;
+                Ctx Xh(P, &sink, codec);
+                as->help([&](uint64_t k, uint64_t &tau, uint64_t &sigma, const uint64_t *&e,
+                             size_t &len, size_t &ties) {
+                    const Entry t = unpack_key<K>(codec, (K)k);
+                    tau = t.cidx;
+                    if (as->has(tau) || pivots.find(tau))
+                        return false;  // answered, or a host pivot
+                    uint64_t other = 0;
+                    if (!apparent_lookup(Xh, t.cidx, t.diam, &other)) {
+                        sigma = ChainAssist::NOT_APPARENT;
+                        return true;
+                    }
+                    K *out = nullptr;
+                    size_t tl = 0;
+                    len = Xh.coboundary<K>(other, t.diam, out, tl);
+                    Xh.arena.uncommit<K>(len);  // copied out before the next one
+                    sigma = other;
+                    ties = tl;
+                    e = reinterpret_cast<const uint64_t *>(out);
+                    return true;
+                });
+            });
+        };
         auto advance = [&](Ctx &Xc, int64_t j) {
             if (drop && drop[j])
                 return;  // dropped after it was queued
@@ -1900,7 +2174,14 @@ private:
             std::chrono::steady_clock::time_point tt;
             if (trace)
                 tt = std::chrono::steady_clock::now();
+            std::unique_ptr<Assisted> A;  // declared after col: joined before col may go
+            ChainAssist *as = nullptr;
             while (true) {
+                if (!as && adds >= ASSIST_AFTER && helpers > 0 && col->radix()) {
+                    start_assist(A);
+                    as = A->as.get();
+                    ++n_assisted;
+                }
                 if (open && cap_now > 0 && spec_adds[j] + adds >= cap_now) {
                     parked[j] = 1;  // resumes once the dropped columns are known
                     break;
@@ -1920,12 +2201,23 @@ private:
                 } else {
                     uint64_t other = 0;
                     ++la;
-                    const bool app = apparent_lookup(Xc, lo.cidx, lo.diam, &other);
+                    size_t alen = 0, aties = 0;
+                    bool app, handed = false;
+                    if (as && as->take(lo.cidx, other, A->buf.data(), alen, aties)) {
+                        handed = true;
+                        ++n_handed;
+                        app = other != ChainAssist::NOT_APPARENT;
+                    } else {
+                        app = apparent_lookup(Xc, lo.cidx, lo.diam, &other);
+                    }
                     if (trace)
                         tm[1] += tick(tt);
                     if (!app)
                         break;
-                    Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
+                    if (handed)  // a radix column copies the keys in
+                        col->push_stream(reinterpret_cast<K *>(A->buf.data()), alen, aties);
+                    else
+                        Xc.add_coboundary(*col, other, lo.diam);  // diameter of its tau
                     if (trace)
                         tm[2] += tick(tt);
                 }
@@ -1935,6 +2227,14 @@ private:
                     tm[3] += tick(tt);
                 if (!nz)
                     break;
+                if (as) {  // ask for the keys just above the new low
+                    K ah[8 + 16];
+                    const size_t m = col->ahead(ah, 8, 16);
+                    for (size_t i = 0; i < m; ++i)
+                        as->publish((uint64_t)ah[i]);
+                    if (chain_test_settle())
+                        as->settle(1000000);
+                }
             }
             if (trace) {
                 std::lock_guard<std::mutex> lk(trace_mu);
@@ -2026,9 +2326,10 @@ private:
             fprintf(stderr,
                     "rpp trace:   p=%d exact phase: %lld rounds, longest %.3f ms (%lld columns), "
                     "done at %.3f ms; longest column call %lld additions: pivot adds %.3f ms, "
-                    "apparent lookups %.3f ms, coboundaries %.3f ms, lows %.3f ms\n",
+                    "apparent lookups %.3f ms, coboundaries %.3f ms, lows %.3f ms; look-ahead: %lld columns, %lld handed over\n",
                     P.p, (long long)nrounds, longest_ms, (long long)longest_size, ms_since(),
-                    (long long)trace_adds, trace_tm[0], trace_tm[1], trace_tm[2], trace_tm[3]);
+                    (long long)trace_adds, trace_tm[0], trace_tm[1], trace_tm[2], trace_tm[3],
+                    (long long)n_assisted.load(), (long long)n_handed.load());
         R.lookups_hash += look_hash.load();
         R.lookups_apparent += look_app_b.load();
     }

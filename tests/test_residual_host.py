@@ -209,6 +209,105 @@ def test_keep_ratio_matches_oracle(driver, mode, ratio):
             assert got_e[p] == exp_e[p], (name, mode, ratio, p)
 
 
+# Look-ahead helpers on every radix column from its first addition; with
+# RPP_TEST_CHAIN_SETTLE the column waits for the helpers' answers, so that it
+# takes handed-over coboundaries even on small inputs.
+_LOOKAHEAD = {"RPP_RADIX_STREAMS": "1", "RPP_CHAIN_AFTER": "0"}
+# the void of a 120-point sphere survives radius 1.0: an essential class
+# whose column is a chain of apparent additions, as on the large sphere
+SPHERE = ("sphere120_thr", lambda: w.condensed_from_points(w.noisy_sphere_points(120, seed=7)),
+          120, 2, 1.0)
+
+
+@pytest.mark.parametrize("settle", ["0", "1"], ids=["racing", "settled"])
+@pytest.mark.parametrize("helpers", ["1", "3"])
+@pytest.mark.parametrize("mode,env", [(0, None), (3, None), (7, None), (11, None), (15, None),
+                                      (19, None), (83, None), (91, None),
+                                      (123, {"RPP_RANK_KEYS": "1"})],
+                         ids=["plain", "late-drops", "late-drops-oblivious", "never-parked",
+                              "never-parked-oblivious", "bitsets-late-drops",
+                              "packed-late-drops", "packed-never-parked",
+                              "ranks-packed-never-parked"])
+def test_chain_lookahead_matches_oracle(driver, mode, env, helpers, settle):
+    """Helper threads that look ahead of a long column (its next lows'
+    apparent partners and their coboundaries, handed over when the column
+    reaches them): the oracle's pairs and classes, and the same number of
+    additions per dimension as without helpers (a handed-over coboundary is
+    the one the column would have generated)."""
+    for name, build, n, maxdim, thr in CASES + [SPHERE]:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        e = dict(env or {}, RPP_TEST_CHAIN_SETTLE=settle, **_LOOKAHEAD)
+        got_p, got_e, got_a = _run(driver, d, n, maxdim, thr, mode, with_additions=True,
+                                   env=dict(e, RPP_CHAIN_HELPERS=helpers))
+        _, _, alone_a = _run(driver, d, n, maxdim, thr, mode, with_additions=True,
+                             env=dict(e, RPP_CHAIN_HELPERS="0"))
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, helpers, p)
+            assert got_e[p] == exp_e[p], (name, mode, helpers, p)
+        assert got_a == alone_a, (name, mode, helpers)
+
+
+def test_chain_lookahead_hands_over(driver):
+    """The settled look-ahead on the sphere's essential chain does hand
+    coboundaries over (what the tests above then check is the hand-over
+    path, not only the column's own)."""
+    name, build, n, maxdim, thr = SPHERE
+    with tempfile.NamedTemporaryFile(suffix=".f32", delete=False) as f:
+        np.ascontiguousarray(build(), dtype=np.float32).tofile(f)
+        path = f.name
+    try:
+        r = subprocess.run([driver, path, str(n), str(maxdim), repr(float(thr)), "91"],
+                           check=True, capture_output=True, text=True,
+                           env=dict(os.environ, RPP_TRACE="1", RPP_CHAIN_HELPERS="2",
+                                    RPP_TEST_CHAIN_SETTLE="1", **_LOOKAHEAD))
+    finally:
+        os.unlink(path)
+    handed = [int(line.split("look-ahead:")[1].split(",")[1].split()[0])
+              for line in r.stderr.splitlines() if "look-ahead:" in line]
+    assert handed and max(handed) > 100, r.stderr[-2000:]
+
+
+@pytest.fixture(scope="module")
+def tsan_driver():
+    """The driver and reduction built with ThreadSanitizer (host code)."""
+    out = os.path.join(tempfile.mkdtemp(prefix="rpp_resdrv_tsan_"), "residual_driver")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-pthread", "-fsanitize=thread", "-o", out,
+           os.path.join(HERE, "host", "residual_driver.cpp"),
+           os.path.join(ROOT, "paper_2003_07989_amd", "csrc", "residual.cpp")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("no thread sanitizer runtime: " + r.stderr[-300:])
+    return out
+
+
+@pytest.mark.parametrize("mode,env", [(11, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3",
+                                                RPP_TEST_CHAIN_SETTLE="1")),
+                                      (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3",
+                                                RPP_TEST_CHAIN_SETTLE="1")),
+                                      (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3")),
+                                      (3, None)],
+                         ids=["lookahead-settled", "lookahead-packed-settled",
+                              "lookahead-packed-racing", "late-drops"])
+def test_host_reduction_is_race_free(tsan_driver, mode, env):
+    """The threaded schedules (worker pool, overlapped gate, look-ahead
+    helpers with their sequence-locked hand-over) under ThreadSanitizer: no
+    report, and the oracle's pairs."""
+    cases = (SPHERE,) if env else (CASES[0], CASES[4])
+    for name, build, n, maxdim, thr in cases:
+        d = build()
+        if np.isinf(thr):
+            thr = oracle.enclosing_radius(d, n)
+        e = dict(env or {}, TSAN_OPTIONS="halt_on_error=1:abort_on_error=1")
+        got_p, got_e = _run(tsan_driver, d, n, maxdim, thr, mode, env=e)
+        exp_p, exp_e = _expected(d, n, maxdim, thr)
+        for p in range(1, maxdim + 1):
+            assert got_p[p] == exp_p[p], (name, mode, p)
+            assert got_e[p] == exp_e[p], (name, mode, p)
+
+
 @pytest.fixture(scope="module")
 def sanitized_driver():
     """The same driver and reduction built with AddressSanitizer and
@@ -231,11 +330,13 @@ def sanitized_driver():
                                       (7, {"RPP_RADIX_STREAMS": "2"}),
                                       (3, {"RPP_TEST_PARK_SLICE": "1",
                                            "RPP_TEST_GATE_POLLS": "100000"}),
-                                      (3, {"RPP_RADIX_STREAMS": "2", "RPP_WIDE_KEYS": "1"})],
+                                      (3, {"RPP_RADIX_STREAMS": "2", "RPP_WIDE_KEYS": "1"}),
+                                      (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3",
+                                                RPP_TEST_CHAIN_SETTLE="1"))],
                          ids=["plain", "late-drops", "bitsets-late-drops",
                               "late-drops-oblivious", "ranks-bitsets-late-drops",
                               "ranks-packed-late-drops", "wide-keys", "radix-oblivious",
-                              "park-slices", "radix-wide-keys"])
+                              "park-slices", "radix-wide-keys", "lookahead"])
 def test_host_reduction_is_sanitizer_clean(sanitized_driver, mode, env):
     """Every schedule and key layout of the host reduction under ASan and
     UBSan, on a dense and a thresholded input: no report, and the oracle's
