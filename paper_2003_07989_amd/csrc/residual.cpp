@@ -1659,18 +1659,21 @@ struct ChainAssist {
     static constexpr size_t NSLOT = 64;
     static constexpr size_t CAP = 256;  // longest coboundary handed over
     static constexpr uint64_t NOT_APPARENT = ~0ull;
-    struct Slot {
+    struct alignas(64) Slot {
         std::atomic<uint32_t> seq{0};
         std::atomic<uint64_t> tau{~0ull};
         std::atomic<uint64_t> sigma{0};
         std::atomic<uint32_t> len{0}, ties{0};
         std::atomic<uint64_t> keys[CAP];
     };
-    std::atomic<uint64_t> ring[RING];
-    std::atomic<uint64_t> head{0}, claim{0};
+    // written by the column's thread (one store of head per step)
+    alignas(64) std::atomic<uint64_t> ring[RING];
+    alignas(64) std::atomic<uint64_t> head{0};
+    // written by the helpers, on lines of their own
+    alignas(64) std::atomic<uint64_t> claim{0};
     std::atomic<uint64_t> finished{0};  // requests answered or skipped
     std::atomic<int> helping{0};         // helpers inside help()
-    std::atomic<bool> stop{false};
+    alignas(64) std::atomic<bool> stop{false};
     std::unique_ptr<Slot[]> slots{new Slot[NSLOT]};
     uint64_t asked[256];  // the column thread's recent requests
 
@@ -1683,16 +1686,29 @@ struct ChainAssist {
     }
     static size_t slot_of(uint64_t tau) { return (size_t)((tau * 0x9E3779B97F4A7C15ull) >> 58); }
 
-    // Column thread: ask for key k (skipped when asked recently).
-    void publish(uint64_t k)
+    // Column thread: ask for keys k[0..m) (each skipped when asked
+    // recently).
+    void publish(const uint64_t *k, size_t m)
     {
-        const size_t a = (size_t)((k * 0xC2B2AE3D27D4EB4Full) >> 56);
-        if (asked[a] == k)
-            return;
-        asked[a] = k;
-        const uint64_t h = head.load(std::memory_order_relaxed);
-        ring[h % RING].store(k, std::memory_order_relaxed);
-        head.store(h + 1, std::memory_order_release);
+        const uint64_t h0 = head.load(std::memory_order_relaxed);
+        uint64_t h = h0;
+        for (size_t i = 0; i < m; ++i) {
+            const size_t a = (size_t)((k[i] * 0xC2B2AE3D27D4EB4Full) >> 56);
+            if (asked[a] == k[i])
+                continue;
+            asked[a] = k[i];
+            ring[h++ % RING].store(k[i], std::memory_order_relaxed);
+        }
+        if (h != h0)
+            head.store(h, std::memory_order_release);
+    }
+    // Column thread: start bringing in tau's slot (its header and first
+    // keys), read a little later by take().
+    void prefetch(uint64_t tau) const
+    {
+        const char *p = reinterpret_cast<const char *>(&slots[slot_of(tau)]);
+        for (int i = 0; i < 10; ++i)
+            _mm_prefetch(p + 64 * i, _MM_HINT_T0);
     }
     // Column thread: the result for cofacet tau, if a helper has one:
     // sigma (NOT_APPARENT when tau has no apparent partner) and its
@@ -2228,10 +2244,13 @@ private:
                 if (!nz)
                     break;
                 if (as) {  // ask for the keys just above the new low
+                    as->prefetch(lo.cidx);
                     K ah[8 + 16];
                     const size_t m = col->ahead(ah, 8, 16);
+                    uint64_t ak[8 + 16];
                     for (size_t i = 0; i < m; ++i)
-                        as->publish((uint64_t)ah[i]);
+                        ak[i] = (uint64_t)ah[i];
+                    as->publish(ak, m);
                     if (chain_test_settle())
                         as->settle(1000000);
                 }
