@@ -190,3 +190,57 @@ def test_no_radius_infinite_threshold_keeps_exact_shape(rpp):
     for i in range(2):
         _same(out[i], rpp.barcodes_device(dev[i], 1, flags=rpp.RPP_NO_ENCLOSING_RADIUS |
                                           rpp.RPP_FORCE_DENSE), "cloud %d" % i)
+
+
+_TUNE_CHILD = r"""
+import hashlib, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2003_07989_amd as m
+import workloads as w
+m.load()
+dev = [torch.from_numpy(np.ascontiguousarray(
+           w.condensed_from_points(w.noisy_torus_points(72, 90 + i)), dtype=np.float32)).cuda()
+       for i in range(3)]
+flags = m.RPP_BATCH_AUTOTUNE if sys.argv[2] == "tune" else 0
+out = m.barcodes_batch(dev, 2, flags=flags)
+h = hashlib.sha256()
+for r in out:
+    for b, d in r.bars:
+        h.update(b.view(np.uint32).tobytes()); h.update(d.view(np.uint32).tobytes())
+print("digest", h.hexdigest())
+"""
+
+
+def test_tune_cache_persists_across_processes(rpp, tmp_path):
+    """RPP_TUNE_CACHE: a process that autotunes writes the chosen launch
+    configuration per (n, dimension) to the file; a second process reads it
+    back and runs the batch with it; both give the same barcodes."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, RPP_TUNE_CACHE=str(cache))
+
+    def child(mode):
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root, mode], env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return [l for l in r.stdout.splitlines() if l.startswith("digest")][-1]
+
+    first = child("tune")
+    table = json.loads(cache.read_text())
+    # 72 points share the 128-point shape bucket; one entry per dimension
+    assert {"128:1", "128:2"} <= set(table), table
+    for code in table.values():
+        assert isinstance(code, int) and 0 < code % 100 <= 64, table
+    stamp = os.stat(cache).st_mtime_ns
+    # asked to tune again, the second process finds both entries and
+    # tunes nothing (a tuning run rewrites the file)
+    second = child("tune")
+    assert first == second
+    assert os.stat(cache).st_mtime_ns == stamp
+    assert json.loads(cache.read_text()) == table
+    assert child("plain") == first
