@@ -2117,6 +2117,7 @@ private:
         std::atomic<int64_t> look_hash{0}, look_app_b{0};
         bool open = !known;  // read by advance(); set before each round
         int64_t cap_now = cap;  // the additions a column may reach while open
+        std::vector<int64_t> slice_cap((size_t)ncols, 0);  // a sliced column's own cap
         std::atomic<int64_t> n_handed{0}, n_assisted{0};  // RPP_TRACE counts
         // Look-ahead helpers for a long column (64-bit keys): at most
         // chain_helpers() idle workers, once a call has made ASSIST_AFTER
@@ -2198,7 +2199,8 @@ private:
                     as = A->as.get();
                     ++n_assisted;
                 }
-                if (open && cap_now > 0 && spec_adds[j] + adds >= cap_now) {
+                const int64_t capj = slice_cap[j] ? slice_cap[j] : cap_now;
+                if (open && capj > 0 && spec_adds[j] + adds >= capj) {
                     parked[j] = 1;  // resumes once the dropped columns are known
                     break;
                 }
@@ -2286,26 +2288,41 @@ private:
                     throw std::logic_error("residual reduction: frontier stalled");
                 if (!parked_list.empty() && P.park_slice > 0 && !gate.ready()) {
                     // Nothing can move until the dropped columns are known.
-                    // Instead of waiting idle, take the parked column nearest
-                    // the frontier a slice of additions further (its work is
-                    // lost only if the gate then drops it), and look at the
-                    // gate again.
-                    auto it = std::min_element(parked_list.begin(), parked_list.end());
-                    const int64_t j = *it;
-                    parked_list.erase(it);
-                    parked[j] = 0;
+                    // Instead of waiting idle, take every parked column a
+                    // slice of additions further, in parallel (a column's
+                    // work is lost only if the gate then drops it; the long
+                    // chain the frontier will wait on is among them), and
+                    // look at the gate again.
+                    round.assign(parked_list.begin(), parked_list.end());
+                    parked_list.clear();
+                    for (int64_t j : round) {
+                        parked[j] = 0;
+                        slice_cap[j] = spec_adds[j] + P.park_slice;
+                    }
                     open = true;
-                    cap_now = spec_adds[j] + P.park_slice;
                     const double s0 = trace ? ms_since() : 0.0;
-                    advance(X, j);
+                    if (round.size() == 1 || !P.parallel) {
+                        for (int64_t j : round)
+                            advance(X, j);
+                    } else {
+                        std::atomic<int64_t> nx{0};
+                        pool.run([&](int) {
+                            Ctx Xw(P, &sink, codec);
+                            for (int64_t i = nx.fetch_add(1); i < (int64_t)round.size();
+                                 i = nx.fetch_add(1))
+                                advance(Xw, round[i]);
+                        });
+                    }
                     if (trace)
                         slice_ms += ms_since() - s0;
-                    ++nslices;
-                    cap_now = cap;
-                    if (parked[j])
-                        parked_list.push_back(j);
-                    else if (spec_nz[j])
-                        wait_on(j);
+                    nslices += (int64_t)round.size();
+                    for (int64_t j : round) {
+                        slice_cap[j] = 0;
+                        if (parked[j])
+                            parked_list.push_back(j);
+                        else if (spec_nz[j] && !(drop && drop[j]))
+                            wait_on(j);
+                    }
                     continue;
                 }
                 learn();

@@ -288,9 +288,11 @@ def tsan_driver():
                                       (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3",
                                                 RPP_TEST_CHAIN_SETTLE="1")),
                                       (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3")),
-                                      (3, None)],
+                                      (3, None),
+                                      (3, {"RPP_TEST_PARK_SLICE": "1",
+                                           "RPP_TEST_GATE_POLLS": "100000"})],
                          ids=["lookahead-settled", "lookahead-packed-settled",
-                              "lookahead-packed-racing", "late-drops"])
+                              "lookahead-packed-racing", "late-drops", "park-slices"])
 def test_host_reduction_is_race_free(tsan_driver, mode, env):
     """The threaded schedules (worker pool, overlapped gate, look-ahead
     helpers with their sequence-locked hand-over) under ThreadSanitizer: no
