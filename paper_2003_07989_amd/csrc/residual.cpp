@@ -726,6 +726,379 @@ template <class K> struct RadixHeap {
     }
 };
 
+// Bucket queue over the keys' top bits, for the same long columns: slot
+// (k - base) >> s of a power-of-two table laid over the keys present when
+// it is (re)built (with room for the range to double), keys beyond it in an
+// overflow list that becomes the next table once the front reaches the
+// end.  A slot's keys sit unordered in 14-key chunks until the front
+// reaches it; then they are sorted (pairs cancel) into the front run.  Keys
+// at or below the run's last key are merged into it, a step's keys at once.
+// With diameter ranks in the top bits (the sphere's chain) a slot is about
+// one rank, so each key is moved once and sorted once, where the radix heap
+// refiles it level by level.
+template <class K> struct SlotHeap {
+    static constexpr int CK = 14;
+    struct Chunk {
+        uint32_t next, cnt;
+        K k[CK];
+    };
+    std::vector<Chunk> pool;
+    uint32_t free_head = 0;       // 1-based chunk index, 0: none
+    std::vector<uint32_t> head;   // newest chunk of each slot, 1-based
+    std::vector<uint64_t> occ;    // bit per non-empty slot
+    std::vector<uint64_t> occ2;   // bit per non-zero occ word
+    uint32_t ns = 0;              // slots
+    K base = 0;
+    int s = 0;
+    uint32_t cur = 0;             // slots below cur are empty
+    bool laid = false;
+    std::vector<K> over;          // keys beyond the table
+    std::vector<K> run;           // front run: run[rh..] ascending
+    size_t rh = 0;
+    size_t nslot = 0;             // keys in slots
+    std::vector<K> batch, run2, tmp;
+
+    static int bitlen(K x)
+    {
+        if (sizeof(K) > 8) {
+            const uint64_t hi = (uint64_t)(x >> 32 >> 32);
+            if (hi)
+                return 128 - __builtin_clzll(hi);
+        }
+        const uint64_t lo = (uint64_t)x;
+        return lo ? 64 - __builtin_clzll(lo) : 0;
+    }
+    uint32_t new_chunk()
+    {
+        if (free_head) {
+            const uint32_t c = free_head;
+            free_head = pool[c - 1].next;
+            return c;
+        }
+        pool.emplace_back();
+        return (uint32_t)pool.size();
+    }
+    void mark(uint32_t i)
+    {
+        occ[i >> 6] |= 1ull << (i & 63);
+        occ2[i >> 12] |= 1ull << ((i >> 6) & 63);
+    }
+    void unmark(uint32_t i)
+    {
+        occ[i >> 6] &= ~(1ull << (i & 63));
+        if (!occ[i >> 6])
+            occ2[i >> 12] &= ~(1ull << ((i >> 6) & 63));
+    }
+    void put_slot(uint32_t i, K k)
+    {
+        uint32_t c = head[i];
+        if (!c || pool[c - 1].cnt == CK) {
+            const uint32_t nc = new_chunk();
+            pool[nc - 1].next = c;
+            pool[nc - 1].cnt = 0;
+            head[i] = nc;
+            if (!c)
+                mark(i);
+            c = nc;
+        }
+        Chunk &ch = pool[c - 1];
+        ch.k[ch.cnt++] = k;
+        ++nslot;
+    }
+    bool run_empty() const { return rh == run.size(); }
+    // Z/2 add of one key at or below the run's end.
+    void toggle(K k)
+    {
+        K *f = run.data() + rh, *e = run.data() + run.size();
+        K *at = std::lower_bound(f, e, k);
+        if (at != e && *at == k) {
+            if (at == f) {
+                ++rh;
+            } else {
+                std::move(at + 1, e, at);
+                run.pop_back();
+            }
+            return;
+        }
+        if (rh > 0 && at - f < e - at) {
+            std::move(f, at, f - 1);
+            --rh;
+            *(at - 1) = k;
+        } else {
+            run.insert(run.begin() + (at - run.data()), k);
+        }
+    }
+    // A key above the run's end (or the run empty).
+    void put(K k)
+    {
+        if (!laid) {
+            over.push_back(k);
+            return;
+        }
+        if (k < base) {  // below the table: the run holds the smallest keys
+            if (run_empty()) {
+                run.clear();
+                rh = 0;
+                run.push_back(k);
+            } else {
+                toggle(k);
+            }
+            return;
+        }
+        const K off = (K)(k - base) >> s;
+        if (off >= (K)ns) {
+            over.push_back(k);
+            return;
+        }
+        const uint32_t i = (uint32_t)off;
+        if (i < cur)
+            cur = i;
+        put_slot(i, k);
+    }
+    void push(const K *e, size_t len)
+    {
+        if (run_empty()) {
+            for (size_t i = 0; i < len; ++i)
+                put(e[i]);
+            return;
+        }
+        const K rb = run.back();
+        batch.clear();
+        for (size_t i = 0; i < len; ++i) {
+            if (e[i] <= rb)
+                batch.push_back(e[i]);
+            else
+                put(e[i]);
+        }
+        if (batch.size() <= 4) {
+            for (K k : batch)
+                toggle(k);
+            return;
+        }
+        std::sort(batch.begin(), batch.end());
+        // Z/2 merge of the run and the batch
+        run2.clear();
+        size_t a = rh, b = 0;
+        const size_t ae = run.size(), be = batch.size();
+        while (a < ae && b < be) {
+            const K x = run[a], y = batch[b];
+            if (x < y) {
+                run2.push_back(x);
+                ++a;
+                continue;
+            }
+            size_t q = b + 1;
+            while (q < be && batch[q] == y)
+                ++q;
+            const bool odd = (q - b) & 1;
+            if (y < x) {
+                if (odd)
+                    run2.push_back(y);
+            } else {
+                if (!odd)
+                    run2.push_back(x);
+                ++a;
+            }
+            b = q;
+        }
+        run2.insert(run2.end(), run.begin() + (ptrdiff_t)a, run.end());
+        while (b < be) {
+            const K y = batch[b];
+            size_t q = b + 1;
+            while (q < be && batch[q] == y)
+                ++q;
+            if ((q - b) & 1)
+                run2.push_back(y);
+            b = q;
+        }
+        run.swap(run2);
+        rh = 0;
+    }
+    // Lays a table over the overflow keys (every slot empty).
+    void rebuild()
+    {
+        K m = over[0], M = over[0];
+        for (K k : over) {
+            m = k < m ? k : m;
+            M = k > M ? k : M;
+        }
+        int sb = 8;  // log2 of the slots: about twice the keys, 256 to 2^17
+        while (sb < 17 && ((size_t)1 << sb) < 2 * over.size())
+            ++sb;
+        if (ns != (1u << sb)) {
+            ns = 1u << sb;
+            head.assign(ns, 0);
+            occ.assign(ns / 64, 0);
+            occ2.assign((ns / 64 + 63) / 64, 0);
+        }
+        base = m;
+        laid = true;
+        const int bl = bitlen((K)(M - m));
+        s = bl > sb - 1 ? bl - (sb - 1) : 0;  // the range fills half the table
+        cur = 0;
+        tmp.swap(over);
+        over.clear();
+        for (K k : tmp)
+            put(k);
+        tmp.clear();
+    }
+    // First occupied slot at or above cur, or ns.
+    uint32_t next_slot() const
+    {
+        const uint32_t nw = ns / 64;
+        uint32_t w = cur >> 6;
+        if (w >= nw)
+            return ns;
+        const uint64_t m = occ[w] & (~0ull << (cur & 63));
+        if (m)
+            return (w << 6) | (uint32_t)__builtin_ctzll(m);
+        ++w;
+        if (w >= nw)
+            return ns;
+        uint32_t w2 = w >> 6;
+        uint64_t m2 = occ2[w2] & (~0ull << (w & 63));
+        while (!m2) {
+            if (++w2 >= (uint32_t)occ2.size())
+                return ns;
+            m2 = occ2[w2];
+        }
+        w = (w2 << 6) | (uint32_t)__builtin_ctzll(m2);
+        return (w << 6) | (uint32_t)__builtin_ctzll(occ[w]);
+    }
+    // Slot i's keys into out (appended); the slot becomes empty.
+    void take_slot(uint32_t i, std::vector<K> &out)
+    {
+        for (uint32_t c = head[i]; c;) {
+            Chunk &ch = pool[c - 1];
+            out.insert(out.end(), ch.k, ch.k + ch.cnt);
+            nslot -= ch.cnt;
+            const uint32_t nx = ch.next;
+            ch.next = free_head;
+            free_head = c;
+            c = nx;
+        }
+        head[i] = 0;
+        unmark(i);
+    }
+    bool low(K &out)
+    {
+        while (true) {
+            if (!run_empty()) {
+                out = run[rh];
+                return true;
+            }
+            if (!laid) {
+                if (over.empty())
+                    return false;
+                rebuild();
+                continue;
+            }
+            const uint32_t i = next_slot();
+            if (i == ns) {
+                if (over.empty())
+                    return false;
+                rebuild();
+                continue;
+            }
+            cur = i;
+            tmp.clear();
+            take_slot(i, tmp);
+            std::sort(tmp.begin(), tmp.end());
+            run.clear();
+            rh = 0;
+            for (size_t j = 0; j < tmp.size();) {
+                size_t e = j + 1;
+                while (e < tmp.size() && tmp[e] == tmp[j])
+                    ++e;
+                if ((e - j) & 1)
+                    run.push_back(tmp[j]);
+                j = e;
+            }
+        }
+    }
+    size_t ahead(K *out, size_t w, size_t bmax) const
+    {
+        size_t c = 0;
+        for (size_t j = rh + 1; j < run.size() && c < w; ++j)
+            out[c++] = run[j];
+        if (c < w && laid) {
+            const uint32_t i = next_slot();
+            if (i < ns) {
+                size_t cnt = 0;
+                for (uint32_t ch = head[i]; ch; ch = pool[ch - 1].next)
+                    cnt += pool[ch - 1].cnt;
+                if (cnt <= bmax)
+                    for (uint32_t ch = head[i]; ch; ch = pool[ch - 1].next)
+                        for (uint32_t q = 0; q < pool[ch - 1].cnt; ++q)
+                            out[c++] = pool[ch - 1].k[q];
+            }
+        }
+        return c;
+    }
+    template <class F> void for_each(F f) const
+    {
+        for (size_t j = rh; j < run.size(); ++j)
+            f(run[j]);
+        for (uint32_t i = 0; i < ns; ++i)
+            for (uint32_t ch = head[i]; ch; ch = pool[ch - 1].next)
+                for (uint32_t q = 0; q < pool[ch - 1].cnt; ++q)
+                    f(pool[ch - 1].k[q]);
+        for (K k : over)
+            f(k);
+    }
+    size_t size() const { return run.size() - rh + nslot + over.size(); }
+};
+
+// The ordered store of a long column: the radix heap, or with
+// RPP_SLOT_HEAP=1 the bucket queue above.
+template <class K> struct FrontHeap {
+    static bool slots_wanted()
+    {
+        static const bool v = [] {
+            const char *e = getenv("RPP_SLOT_HEAP");
+            return e && atoi(e) != 0;
+        }();
+        return v;
+    }
+    std::unique_ptr<RadixHeap<K>> r;
+    std::unique_ptr<SlotHeap<K>> q;
+    explicit FrontHeap(K last)
+    {
+        if (slots_wanted()) {
+            q.reset(new SlotHeap<K>());
+        } else {
+            r.reset(new RadixHeap<K>());
+            r->last = last;
+        }
+    }
+    void push(const K *e, size_t len) { r ? r->push(e, len) : q->push(e, len); }
+    void merge(const FrontHeap &o)
+    {
+        if (r && o.r) {
+            r->merge(*o.r);
+            return;
+        }
+        std::vector<K> all;
+        all.reserve(o.size());
+        o.for_each([&](K k) { all.push_back(k); });
+        if (!all.empty())
+            push(all.data(), all.size());
+    }
+    bool low(K &out) { return r ? r->low(out) : q->low(out); }
+    size_t size() const { return r ? r->size() : q->size(); }
+    size_t ahead(K *out, size_t w, size_t bmax) const
+    {
+        return r ? r->ahead(out, w, bmax) : q->ahead(out, w, bmax);
+    }
+    template <class F> void for_each(F f) const
+    {
+        if (r)
+            r->for_each(f);
+        else
+            q->for_each(f);
+    }
+};
+
 // Working column = Z/2 sum of several coboundaries.  Each added coboundary
 // is its own stream; a min-heap over the streams' current fronts yields the
 // sum's entries oldest-first.  Only the entries that reach the front are
@@ -880,8 +1253,7 @@ private:
     // prefix, so the heap root is the smallest key present).
     void to_radix()
     {
-        rh.reset(new RadixHeap<K>());
-        rh->last = hk.empty() ? K(0) : hk[0];
+        rh.reset(new FrontHeap<K>(hk.empty() ? K(0) : hk[0]));
         for (const Stream<K> &st : streams)
             if (!st.empty())
                 rh->push(st.e + st.pos, st.len - st.pos);
@@ -960,7 +1332,7 @@ private:
     std::vector<Stream<K>> streams;
     std::vector<K> hk;
     std::vector<uint32_t> hs;
-    std::unique_ptr<RadixHeap<K>> rh;  // set once the column goes radix
+    std::unique_ptr<FrontHeap<K>> rh;  // set once the column goes radix
     size_t next_check = radix_at();    // stream count of the next radix check
 };
 
