@@ -1049,14 +1049,15 @@ template <class K> struct SlotHeap {
     size_t size() const { return run.size() - rh + nslot + over.size(); }
 };
 
-// The ordered store of a long column: the radix heap, or with
-// RPP_SLOT_HEAP=1 the bucket queue above.
+// The ordered store of a long column: the bucket queue above, or with
+// RPP_SLOT_HEAP=0 the radix heap (on the 4096-point sphere's chain the
+// queue's lows take 9.7 ms against the radix heap's 21.8).
 template <class K> struct FrontHeap {
     static bool slots_wanted()
     {
         static const bool v = [] {
             const char *e = getenv("RPP_SLOT_HEAP");
-            return e && atoi(e) != 0;
+            return !e || atoi(e) != 0;
         }();
         return v;
     }

@@ -141,29 +141,31 @@ def test_rank_coded_keys_match_oracle(driver, mode):
             assert got_e[p] == exp_e[p], (name, mode, p)
 
 
+@pytest.mark.parametrize("heap", ["1", "0"], ids=["slot-queue", "radix-heap"])
 @pytest.mark.parametrize("streams", [1, 3])
 @pytest.mark.parametrize("mode,env", [(0, None), (3, None), (4, None), (7, None), (83, None),
                                       (3, {"RPP_WIDE_KEYS": "1"}),
                                       (115, {"RPP_RANK_KEYS": "1"})],
                          ids=["plain", "late-drops", "oblivious", "late-drops-oblivious",
                               "packed-late-drops", "wide-keys", "ranks-packed-late-drops"])
-def test_radix_columns_match_oracle(driver, mode, env, streams):
-    """Columns that switch from the stream heap to the radix heap after
-    `streams` added coboundaries (normally only long chains such as an
-    essential class's do): with every column switching at once or after a
-    few additions, on every key layout, and with the oblivious form (whose
-    unreduced additions can lie below the column's low and re-base the
-    buckets), the same pairs and classes."""
+def test_radix_columns_match_oracle(driver, mode, env, streams, heap):
+    """Columns that switch from the stream heap to a bucket structure (the
+    slot queue over the keys' top bits, or the radix heap) after `streams`
+    added coboundaries (normally only long chains such as an essential
+    class's do): with every column switching at once or after a few
+    additions, on every key layout, and with the oblivious form (whose
+    unreduced additions can lie below the column's low: below the table, or
+    re-basing the buckets), the same pairs and classes."""
     for name, build, n, maxdim, thr in CASES:
         d = build()
         if np.isinf(thr):
             thr = oracle.enclosing_radius(d, n)
-        e = dict(env or {}, RPP_RADIX_STREAMS=str(streams))
+        e = dict(env or {}, RPP_RADIX_STREAMS=str(streams), RPP_SLOT_HEAP=heap)
         got_p, got_e = _run(driver, d, n, maxdim, thr, mode, env=e)
         exp_p, exp_e = _expected(d, n, maxdim, thr)
         for p in range(1, maxdim + 1):
-            assert got_p[p] == exp_p[p], (name, mode, streams, p)
-            assert got_e[p] == exp_e[p], (name, mode, streams, p)
+            assert got_p[p] == exp_p[p], (name, mode, streams, heap, p)
+            assert got_e[p] == exp_e[p], (name, mode, streams, heap, p)
 
 
 @pytest.mark.parametrize("slice_,polls", [(0, 5), (1, 5), (1, 100000), (3, 100000),
@@ -334,11 +336,15 @@ def sanitized_driver():
                                            "RPP_TEST_GATE_POLLS": "100000"}),
                                       (3, {"RPP_RADIX_STREAMS": "2", "RPP_WIDE_KEYS": "1"}),
                                       (91, dict(_LOOKAHEAD, RPP_CHAIN_HELPERS="3",
-                                                RPP_TEST_CHAIN_SETTLE="1"))],
+                                                RPP_TEST_CHAIN_SETTLE="1")),
+                                      (7, {"RPP_RADIX_STREAMS": "2", "RPP_SLOT_HEAP": "0"}),
+                                      (3, {"RPP_RADIX_STREAMS": "2", "RPP_WIDE_KEYS": "1",
+                                           "RPP_SLOT_HEAP": "0"})],
                          ids=["plain", "late-drops", "bitsets-late-drops",
                               "late-drops-oblivious", "ranks-bitsets-late-drops",
                               "ranks-packed-late-drops", "wide-keys", "radix-oblivious",
-                              "park-slices", "radix-wide-keys", "lookahead"])
+                              "park-slices", "radix-wide-keys", "lookahead",
+                              "radix-heap-oblivious", "radix-heap-wide-keys"])
 def test_host_reduction_is_sanitizer_clean(sanitized_driver, mode, env):
     """Every schedule and key layout of the host reduction under ASan and
     UBSan, on a dense and a thresholded input: no report, and the oracle's
